@@ -1,0 +1,442 @@
+"""Pins of the FP64 oracle against facts it does not compute itself.
+
+Each test fixes one part of the oracle by a closed form, an independent
+numerical route, a textbook table or brute force, so that a dropped term, a
+wrong sign or index, or a transposed operand anywhere in ``oracle/`` fails at
+least one test.  All run on the CPU.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import (Geometry, ZernikeBasis, MonomialBasis, forward, adjoint,
+                    kernel_phase)
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# Zernike basis
+# --------------------------------------------------------------------------
+
+def test_paper_index_facts():
+    facts = json.load(open(os.path.join(GOLD, "paper_basis_facts.json")))
+    for d, nl in facts["ansi_to_nl"].items():
+        assert oracle.ansi_to_nm(int(d)) == tuple(nl)
+    for j, nm in facts["noll_to_nm"].items():
+        assert oracle.noll_to_nm(int(j)) == tuple(nm)
+    # proportionalities stated in the paper, checked at random points
+    rng = np.random.default_rng(1)
+    x, y = rng.uniform(-1.5, 1.5, size=(2, 50))
+    z2 = oracle.zernike_nm(1, 1, x, y)
+    z1 = oracle.zernike_nm(1, -1, x, y)
+    z4 = oracle.zernike_nm(2, 0, x, y)
+    assert np.allclose(z2 / x, z2[0] / x[0])
+    assert np.allclose(z1 / y, z1[0] / y[0])
+    r2 = x ** 2 + y ** 2
+    assert np.allclose(np.polyfit(r2, z4, 1), [2 * math.sqrt(3), -math.sqrt(3)])
+
+
+def test_ansi_roundtrip_and_noll_map():
+    for d in range(66):
+        n, m = oracle.ansi_to_nm(d)
+        assert abs(m) <= n and (n - m) % 2 == 0
+        assert oracle.nm_to_ansi(n, m) == d
+    assert [oracle.noll_to_ansi(j) for j in range(4, 12)] == [4, 3, 5, 7, 8, 6, 9, 12]
+    # every (n, m) up to n = 10 appears exactly once in the Noll ordering
+    seen = {oracle.noll_to_nm(j) for j in range(1, 67)}
+    assert len(seen) == 66
+
+
+TEXTBOOK = {  # Cartesian forms of the orthonormal Zernike polynomials
+    0: lambda x, y: np.ones_like(x),
+    1: lambda x, y: 2 * y,
+    2: lambda x, y: 2 * x,
+    3: lambda x, y: 2 * math.sqrt(6) * x * y,
+    4: lambda x, y: math.sqrt(3) * (2 * (x * x + y * y) - 1),
+    5: lambda x, y: math.sqrt(6) * (x * x - y * y),
+    6: lambda x, y: math.sqrt(8) * (3 * x * x * y - y ** 3),
+    7: lambda x, y: math.sqrt(8) * (3 * (x * x + y * y) - 2) * y,
+    8: lambda x, y: math.sqrt(8) * (3 * (x * x + y * y) - 2) * x,
+    9: lambda x, y: math.sqrt(8) * (x ** 3 - 3 * x * y * y),
+    10: lambda x, y: math.sqrt(10) * (4 * x ** 3 * y - 4 * x * y ** 3),
+    11: lambda x, y: math.sqrt(10) * (4 * (x * x + y * y) - 3) * 2 * x * y,
+    12: lambda x, y: math.sqrt(5) * (6 * (x * x + y * y) ** 2 - 6 * (x * x + y * y) + 1),
+    13: lambda x, y: math.sqrt(10) * (4 * (x * x + y * y) - 3) * (x * x - y * y),
+    14: lambda x, y: math.sqrt(10) * (x ** 4 - 6 * x * x * y * y + y ** 4),
+}
+
+
+def test_zernike_textbook_cartesian():
+    rng = np.random.default_rng(2)
+    x, y = rng.uniform(-1.9, 1.9, size=(2, 400))
+    Z = ZernikeBasis(range(15)).evaluate(x, y)
+    for d, fn in TEXTBOOK.items():
+        np.testing.assert_allclose(Z[d], fn(x, y), rtol=1e-12, atol=1e-12)
+
+
+def test_zernike_jacobi_route():
+    # R_n^m(rho) = (-1)^((n-m)/2) rho^m P_{(n-m)/2}^{(m,0)}(1 - 2 rho^2)
+    from scipy.special import eval_jacobi
+    rng = np.random.default_rng(3)
+    rho = rng.uniform(0, 1.8, 200)
+    ang = rng.uniform(-np.pi, np.pi, 200)
+    x, y = rho * np.cos(ang), rho * np.sin(ang)
+    for d in range(45):
+        n, m = oracle.ansi_to_nm(d)
+        am = abs(m)
+        k = (n - am) // 2
+        R = (-1) ** k * rho ** am * eval_jacobi(k, am, 0, 1 - 2 * rho ** 2)
+        N = math.sqrt(2 * (n + 1) / (2 if m == 0 else 1))
+        ref = N * R * (np.cos(m * ang) if m >= 0 else np.sin(am * ang))
+        np.testing.assert_allclose(oracle.zernike_nm(n, m, x, y), ref,
+                                   rtol=1e-10, atol=1e-10)
+
+
+def test_zernike_orthonormal_quadrature():
+    # Gauss-Legendre in rho (weight rho) x uniform angle: exact for these
+    nr, na = 24, 64
+    t, wt = np.polynomial.legendre.leggauss(nr)
+    rho = 0.5 * (t + 1)
+    wr = 0.5 * wt * rho
+    ang = 2 * np.pi * np.arange(na) / na
+    R, A = np.meshgrid(rho, ang, indexing="ij")
+    Wq = (wr[:, None] * np.ones(na)[None, :]) * (2 * np.pi / na) / np.pi
+    Z = ZernikeBasis(range(28)).evaluate(R * np.cos(A), R * np.sin(A))
+    G = np.einsum("iab,jab,ab->ij", Z, Z, Wq)
+    np.testing.assert_allclose(G, np.eye(28), atol=1e-12)
+
+
+def test_monomial_basis_matches_direct():
+    b = MonomialBasis([(2, 0), (0, 2), (1, 1)], [[1, 0, 0], [0, 1, 0], [0.5, 0.5, 2]])
+    x = np.array([0.3, -1.2]); y = np.array([2.0, 0.1])
+    Z = b.evaluate(x, y)
+    np.testing.assert_allclose(Z[0], x * x)
+    np.testing.assert_allclose(Z[2], 0.5 * x * x + 0.5 * y * y + 2 * x * y)
+
+
+# --------------------------------------------------------------------------
+# Transforms
+# --------------------------------------------------------------------------
+
+def _tilt_w(u, v, geom):
+    return np.stack([np.pi * np.asarray(v) * geom.R / geom.ny,
+                     np.pi * np.asarray(u) * geom.R / geom.nx], axis=1)
+
+
+@pytest.mark.parametrize("nx,ny", [(24, 16), (32, 32), (20, 12)])
+def test_forward_integer_bins_equal_fft(nx, ny):
+    rng = np.random.default_rng(10 + nx)
+    geom = Geometry(nx, ny)
+    u = rng.integers(-nx // 2, nx // 2, size=9)
+    v = rng.integers(-ny // 2, ny // 2, size=9)
+    f = rng.normal(size=(ny, nx)) + 1j * rng.normal(size=(ny, nx))
+    E = forward(f, _tilt_w(u, v, geom), ZernikeBasis([1, 2]), geom)
+    Ff = np.fft.fft2(f)
+    ref = (-1.0) ** (u + v) * Ff[v % ny, u % nx]
+    np.testing.assert_allclose(E, ref, rtol=1e-12, atol=1e-10)
+
+
+def test_forward_odd_sizes_general_phase():
+    nx, ny = 15, 9
+    rng = np.random.default_rng(4)
+    geom = Geometry(nx, ny)            # cx = 7.5, cy = 4.5
+    u = rng.integers(-7, 7, size=6)
+    v = rng.integers(-4, 4, size=6)
+    f = rng.normal(size=(ny, nx)) + 1j * rng.normal(size=(ny, nx))
+    E = forward(f, _tilt_w(u, v, geom), ZernikeBasis([1, 2]), geom)
+    Ff = np.fft.fft2(f)
+    ref = np.exp(2j * np.pi * (u * geom.cx / nx + v * geom.cy / ny)) * Ff[v % ny, u % nx]
+    np.testing.assert_allclose(E, ref, rtol=1e-12, atol=1e-10)
+
+
+def test_adjoint_integer_bins_equal_ifft():
+    nx, ny = 24, 16
+    rng = np.random.default_rng(5)
+    geom = Geometry(nx, ny)
+    # distinct bins so the sparse grid has one entry per spot
+    flat = rng.choice(nx * ny, size=11, replace=False)
+    v, u = np.divmod(flat, nx)
+    u = u - nx // 2
+    v = v - ny // 2
+    y = rng.normal(size=11) + 1j * rng.normal(size=11)
+    g = adjoint(y, _tilt_w(u, v, geom), ZernikeBasis([1, 2]), geom)
+    grid = np.zeros((ny, nx), complex)
+    grid[v % ny, u % nx] = (-1.0) ** (u + v) * y
+    ref = nx * ny * np.fft.ifft2(grid)
+    np.testing.assert_allclose(g, ref, rtol=1e-12, atol=1e-10)
+
+
+def test_dirichlet_off_grid():
+    nx, ny = 40, 28
+    geom = Geometry(nx, ny)
+    rng = np.random.default_rng(6)
+    u = rng.uniform(-nx / 2, nx / 2, 7)
+    v = rng.uniform(-ny / 2, ny / 2, 7)
+    E = forward(np.ones((ny, nx)), _tilt_w(u, v, geom), ZernikeBasis([1, 2]), geom)
+    ref = (np.exp(1j * np.pi * (u / nx + v / ny))
+           * np.sin(np.pi * u) / np.sin(np.pi * u / nx)
+           * np.sin(np.pi * v) / np.sin(np.pi * v / ny))
+    np.testing.assert_allclose(E, ref, rtol=1e-11, atol=1e-10)
+
+
+@pytest.mark.parametrize("n", [8, 64, 256])
+def test_quadratic_gauss_sum(n):
+    # basis {x^2, y^2}, origin 0, R = 1, coefficients 2 pi / n: E = -2 i n
+    geom = Geometry(n, n, cx=0.0, cy=0.0, R=1.0)
+    b = MonomialBasis([(2, 0), (0, 2)], [[1.0, 0.0], [0.0, 1.0]])
+    w = np.array([[2 * np.pi / n, 2 * np.pi / n]])
+    E = forward(np.ones((n, n)), w, b, geom)
+    np.testing.assert_allclose(E, [-2j * n], rtol=1e-10, atol=1e-9 * n)
+
+
+def test_conjugate_hologram_textbook_phase():
+    # one spot; nearfield phase = its own kernel phase built from the
+    # textbook Cartesian polynomials => E = sum A
+    nx, ny = 36, 28
+    geom = Geometry(nx, ny)
+    rng = np.random.default_rng(7)
+    modes = list(range(15))
+    w = rng.normal(0, 2.0, size=(3, 15))
+    jj, ii = np.mgrid[0:ny, 0:nx]
+    xh = (ii - geom.cx) / geom.R
+    yh = (jj - geom.cy) / geom.R
+    amp = rng.uniform(0.2, 1.0, size=(ny, nx))
+    for k in range(3):
+        th = sum(w[k, d] * TEXTBOOK[d](xh, yh) for d in modes)
+        E = forward(amp * np.exp(1j * th), w, ZernikeBasis(modes), geom)
+        assert abs(E[k] - amp.sum()) < 1e-10 * amp.sum()
+
+
+def test_dot_product_adjoint():
+    nx, ny = 30, 22
+    geom = Geometry(nx, ny)
+    rng = np.random.default_rng(8)
+    basis = ZernikeBasis([0, 1, 2, 3, 4, 7, 12])
+    w = rng.normal(0, 3, size=(13, basis.D))
+    f = rng.normal(size=(ny, nx)) + 1j * rng.normal(size=(ny, nx))
+    y = rng.normal(size=13) + 1j * rng.normal(size=13)
+    lhs = np.vdot(y, forward(f, w, basis, geom))        # <F f, y> as y^H F f
+    rhs = np.vdot(adjoint(y, w, basis, geom), f)        # (F* y)^H f
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+
+
+def test_piston_linearity_aliasing_subsets():
+    nx, ny = 26, 18
+    geom = Geometry(nx, ny)
+    rng = np.random.default_rng(9)
+    basis = ZernikeBasis([0, 1, 2, 4, 5])
+    w = rng.normal(0, 2, size=(6, 5))
+    f = rng.normal(size=(ny, nx)) + 1j * rng.normal(size=(ny, nx))
+    h = rng.normal(size=(ny, nx)) + 1j * rng.normal(size=(ny, nx))
+    E = forward(f, w, basis, geom)
+    # piston: Z_0 = 1, so +c on w[:, 0] multiplies E by exp(-i c)
+    w2 = w.copy(); w2[:, 0] += 0.7
+    np.testing.assert_allclose(forward(f, w2, basis, geom), E * np.exp(-0.7j), rtol=1e-12)
+    # linearity
+    a, b = 0.3 - 1.1j, 2.0 + 0.5j
+    np.testing.assert_allclose(forward(a * f + b * h, w, basis, geom),
+                               a * E + b * forward(h, w, basis, geom), rtol=1e-11, atol=1e-11)
+    # aliasing: u -> u + nx is the same kernel on integer pixels (even nx)
+    w3 = w.copy(); w3[:, 2] += np.pi * nx * geom.R / nx
+    np.testing.assert_allclose(forward(f, w3, basis, geom), E, rtol=1e-10, atol=1e-10)
+    # subsets
+    sp = [4, 1]
+    np.testing.assert_allclose(forward(f, w, basis, geom, spots=sp), E[sp], rtol=1e-13)
+    y = rng.normal(size=6) + 1j * rng.normal(size=6)
+    g = adjoint(y, w, basis, geom)
+    px = np.array([0, 17, nx * ny - 1])
+    np.testing.assert_allclose(adjoint(y, w, basis, geom, pixels=px),
+                               g.reshape(-1)[px], rtol=1e-13)
+
+
+def test_threaded_equals_serial():
+    nx, ny = 64, 48
+    geom = Geometry(nx, ny)
+    rng = np.random.default_rng(11)
+    basis = ZernikeBasis(range(10))
+    w = rng.normal(0, 3, size=(40, 10))
+    f = rng.normal(size=(ny, nx)) + 1j * rng.normal(size=(ny, nx))
+    a = forward(f, w, basis, geom, workers=1, chunk=500)
+    b = forward(f, w, basis, geom, workers=4, chunk=500)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_bruteforce_mpmath_8x8():
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 30
+    nx = ny = 8
+    geom = Geometry(nx, ny)
+    rng = np.random.default_rng(12)
+    modes = list(range(15))
+    N = 5
+    w = rng.normal(0, 2.5, size=(N, 15))
+    f = rng.normal(size=(ny, nx)) + 1j * rng.normal(size=(ny, nx))
+    y = rng.normal(size=N) + 1j * rng.normal(size=N)
+
+    def Z(d, x, yv):
+        n, m = oracle.ansi_to_nm(d)
+        am = abs(m)
+        r = mp.sqrt(x * x + yv * yv)
+        ang = mp.atan2(yv, x)
+        k = (n - am) // 2
+        R = (-1) ** k * r ** am * mp.jacobi(k, am, 0, 1 - 2 * r * r)
+        N_ = mp.sqrt(mp.mpf(2 * (n + 1)) / (2 if m == 0 else 1))
+        return N_ * R * (mp.cos(m * ang) if m >= 0 else mp.sin(am * ang))
+
+    E = [mp.mpc(0)] * N
+    g = np.zeros((ny, nx), complex)
+    for j in range(ny):
+        for i in range(nx):
+            x = (mp.mpf(i) - geom.cx) / geom.R
+            yv = (mp.mpf(j) - geom.cy) / geom.R
+            zs = [Z(d, x, yv) for d in modes]
+            acc = mp.mpc(0)
+            for k in range(N):
+                th = mp.fsum(mp.mpf(w[k, d]) * zs[d] for d in modes)
+                E[k] += mp.expj(-th) * mp.mpc(f[j, i].real, f[j, i].imag)
+                acc += mp.expj(th) * mp.mpc(y[k].real, y[k].imag)
+            g[j, i] = complex(acc)
+    Eo = forward(f, w, ZernikeBasis(modes), geom)
+    go = adjoint(y, w, ZernikeBasis(modes), geom)
+    np.testing.assert_allclose(Eo, np.array([complex(e) for e in E]), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(go, g, rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# WGS
+# --------------------------------------------------------------------------
+
+def test_one_spot_wgs_reaches_sum_amp():
+    nx, ny = 32, 24
+    geom = Geometry(nx, ny)
+    rng = np.random.default_rng(13)
+    basis = ZernikeBasis(range(10))
+    w = rng.normal(0, 2, size=(1, 10))
+    amp = rng.uniform(0.1, 1, size=(ny, nx))
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx))
+    phi1, W1, E0, st0 = oracle.wgs_step(phi, [1.0], [1.0], amp, w, basis, geom)
+    _, _, E1, st1 = oracle.wgs_step(phi1, W1, [1.0], amp, w, basis, geom)
+    assert abs(abs(E1[0]) - amp.sum()) < 1e-10 * amp.sum()
+    # efficiency of a single perfect spot: (sum A)^2 / (P sum A^2)
+    assert abs(st1[0] - amp.sum() ** 2 / (amp.size * np.sum(amp ** 2))) < 1e-12
+
+
+def _fft_wgs(phi, W, t, amp, u, v, power):
+    """Independent WGS at integer bins, zero aberration, through numpy FFTs."""
+    ny, nx = amp.shape
+    sgn = (-1.0) ** (u + v)
+    E = sgn * np.fft.fft2(amp * np.exp(1j * phi))[v % ny, u % nx]
+    a = np.abs(E)
+    r = (a / np.linalg.norm(a)) / (t / np.linalg.norm(t))
+    W = W * r ** (-power)
+    W = W / W.mean()
+    grid = np.zeros((ny, nx), complex)
+    grid[v % ny, u % nx] = sgn * W * t * E / a
+    g = nx * ny * np.fft.ifft2(grid)
+    return np.angle(g), W, E
+
+
+@pytest.mark.parametrize("power", [1.0, 0.0])
+def test_wgs_equals_fft_wgs_at_integer_bins(power):
+    nx, ny = 32, 24
+    geom = Geometry(nx, ny)
+    rng = np.random.default_rng(14)
+    flat = rng.choice(nx * ny, size=9, replace=False)
+    v, u = np.divmod(flat, nx)
+    u = u - nx // 2
+    v = v - ny // 2
+    w = _tilt_w(u, v, geom)
+    amp = np.exp(-(((np.arange(nx) - nx / 2) / 10.0) ** 2)[None, :]
+                 - (((np.arange(ny) - ny / 2) / 8.0) ** 2)[:, None])
+    t = rng.uniform(0.5, 1.0, size=9)
+    phi_a = rng.uniform(-np.pi, np.pi, size=(ny, nx))
+    phi_b = phi_a.copy()
+    Wa = np.ones(9)
+    Wb = np.ones(9)
+    for _ in range(6):
+        phi_a, Wa, Ea, _ = oracle.wgs_step(phi_a, Wa, t, amp, w, ZernikeBasis([1, 2]), geom, power)
+        phi_b, Wb, Eb = _fft_wgs(phi_b, Wb, t, amp, u, v, power)
+        np.testing.assert_allclose(Ea, Eb, rtol=1e-9, atol=1e-9)
+        np.testing.assert_allclose(Wa, Wb, rtol=1e-9)
+        d = np.angle(np.exp(1j * (phi_a - phi_b)))
+        assert np.max(np.abs(d)) < 1e-8
+    if power == 0.0:
+        np.testing.assert_array_equal(Wa, np.ones(9))
+
+
+def test_wgs_stats_definitions():
+    E = np.array([3 + 4j, 0 + 1j, 2 + 0j])
+    t = np.array([1.0, 1.0, 2.0])
+    amp = np.ones((2, 3))
+    st = oracle.wgs_stats(E, t, amp)
+    I = np.array([25.0, 1.0, 1.0])
+    assert st[0] == pytest.approx(30.0 / (6 * 6))
+    assert st[1] == pytest.approx(1 - 24 / 26)
+    assert st[2] == pytest.approx(np.std(I) / np.mean(I))
+    assert st[3] == pytest.approx(30.0)
+
+
+# --------------------------------------------------------------------------
+# Loss and gradient
+# --------------------------------------------------------------------------
+
+def _grad_case(nx=20, ny=14, N=7, seed=15):
+    geom = Geometry(nx, ny)
+    rng = np.random.default_rng(seed)
+    basis = ZernikeBasis([1, 2, 3, 4, 5, 7, 12])
+    w = rng.normal(0, 2, size=(N, basis.D))
+    amp = rng.uniform(0.2, 1, size=(ny, nx))
+    t = rng.uniform(0.5, 1, size=N)
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx))
+    return geom, basis, w, amp, t, phi
+
+
+def test_gradient_matches_torch_autograd_dense_kernel():
+    torch = pytest.importorskip("torch")
+    geom, basis, w, amp, t, phi = _grad_case()
+    g, L, _ = oracle.loss_grad(phi, amp, t, w, basis, geom, lam=0.3, eps=1e-2)
+    # independent route: cached dense kernel matrix + autograd (float64)
+    idx = np.arange(geom.P)
+    K = torch.tensor(np.exp(-1j * kernel_phase(w, basis, geom, idx)))
+    ph = torch.tensor(phi, requires_grad=True)
+    A = torch.tensor(amp)
+    f = (A * torch.exp(1j * ph)).reshape(-1)
+    E = K @ f
+    s = math.sqrt(geom.P * float(np.sum(amp ** 2)) / len(t))
+    Ls = torch.sum((torch.abs(E / s) ** 2 - torch.tensor(t)) ** 2)
+
+    def wrap(d):
+        return torch.remainder(d + math.pi, 2 * math.pi) - math.pi
+    dx = torch.zeros_like(ph); dy = torch.zeros_like(ph)
+    dx = torch.cat([wrap(ph[:, 1:] - ph[:, :-1]), torch.zeros(geom.ny, 1, dtype=ph.dtype)], 1)
+    dy = torch.cat([wrap(ph[1:, :] - ph[:-1, :]), torch.zeros(1, geom.nx, dtype=ph.dtype)], 0)
+    TV = torch.sum(torch.sqrt(dx ** 2 + dy ** 2 + 1e-4)) / geom.P
+    Lt = Ls + 0.3 * TV
+    Lt.backward()
+    assert abs(L - float(Lt.detach())) < 1e-12 * abs(L)
+    np.testing.assert_allclose(g, ph.grad.numpy(), rtol=1e-10, atol=1e-12)
+
+
+def test_fd_update_equals_full_recompute_and_analytic():
+    geom, basis, w, amp, t, phi = _grad_case(seed=16)
+    lam, eps, h = 0.3, 1e-2, 1e-4
+    pix = [0, 5, geom.nx + 3, geom.P - 1, geom.P // 2]
+    fd = oracle.fd_grad(phi, pix, amp, t, w, basis, geom, h=h, lam=lam, eps=eps)
+    full = []
+    for p in pix:
+        j, i = divmod(p, geom.nx)
+        vals = []
+        for s in (+h, -h):
+            q = phi.copy(); q[j, i] += s
+            vals.append(oracle.total_loss(q, amp, t, w, basis, geom, lam, eps)[0])
+        full.append((vals[0] - vals[1]) / (2 * h))
+    np.testing.assert_allclose(fd, full, rtol=1e-7, atol=1e-10)
+    g, _, _ = oracle.loss_grad(phi, amp, t, w, basis, geom, lam=lam, eps=eps)
+    ga = g.reshape(-1)[pix]
+    np.testing.assert_allclose(fd, ga, rtol=1e-6, atol=1e-8 * np.max(np.abs(g)))
