@@ -1,0 +1,196 @@
+/*
+ * ash.h -- C ABI of the aberration-space holography hot path on MI355X.
+ *
+ * The library computes, for N target spots with per-spot kernel
+ * coefficients w[n][d] over a basis {Z_d} of D pupil functions,
+ *
+ *   kernel phase  theta_n(x) = sum_d w[n][d] Z_d(xh, yh)           (radians)
+ *   forward       E_n  = sum_x f(x) exp(-i theta_n(x))
+ *   adjoint       g(x) = sum_n y_n exp(+i theta_n(x))
+ *
+ * over every SLM pixel x = (i, j) (i = column, the fastest index), which is
+ * the compressed spot-holography transform pair with generalised "Zernike
+ * kernels" (paper: "Aberration-Space Holography", compressed-sum equations
+ * and modal-expansion paragraph), with kernels generated on the fly from a
+ * monomial expansion of the basis and the N x D coefficient matrix
+ * (paper: Methods, "Computational Scaling").  A weighted Gerchberg-Saxton
+ * loop runs both transforms on the device ("A Full-Field 2D Tweezer Array",
+ * WGS paragraph).
+ *
+ * Conventions
+ *   - Normalised pupil coordinates xh = (i - cx)/R, yh = (j - cy)/R.
+ *   - Transforms are unnormalised; the adjoint is the exact conjugate
+ *     transpose of the forward.  With the orthonormal Zernike tilts
+ *     Z_2 = 2 xh and Z_1 = 2 yh, integer-bin tilts w = pi u R / nx reproduce
+ *     numpy's fft2 bins up to the factor exp(2 pi i (u cx/nx + v cy/ny)).
+ *   - Complex arrays are interleaved (re, im) float pairs (torch complex64).
+ *   - Pixel arrays are row-major [ny][nx] float32 (phase, amplitude) or
+ *     [ny][nx][2] (complex field).
+ *   - Arithmetic: FP32 with the phase kept in turns and range-reduced before
+ *     the hardware sine/cosine; per-spot constant and tilt terms are wrapped
+ *     per pixel tile in FP64 when spots are set, and the basis table is
+ *     evaluated in FP64 and rounded once to FP32.  Sums are blocked and
+ *     compensated; results are bitwise deterministic for fixed inputs.
+ *
+ * Ownership and threading
+ *   - Every *_dev pointer is a device pointer owned by the caller, on the
+ *     context's device, contiguous, and must stay valid until the enqueued
+ *     work that uses it has finished.  *_host arrays are read before the
+ *     call returns.
+ *   - The library owns the context and all scratch memory.  Scratch is
+ *     allocated only by ash_set_basis / ash_set_spots (and batched set-up),
+ *     never by ash_forward, ash_adjoint or ash_wgs_iterate.
+ *   - Compute calls are asynchronous on the context's stream.  A context is
+ *     not thread-safe: use one context per host thread / stream.
+ *
+ * Errors
+ *   Every call returns ASH_OK (0) or a negative ASH_E* code.  Argument
+ *   errors are detected before any work is enqueued and leave the context
+ *   unchanged.  HIP runtime errors return ASH_EHIP with the runtime's
+ *   message in ash_last_error().  The library never aborts or prints.
+ */
+#ifndef ASH_H
+#define ASH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ASH_OK 0
+#define ASH_EINVAL (-1)       /* null / negative / non-finite argument     */
+#define ASH_ESHAPE (-2)       /* sizes inconsistent with the context       */
+#define ASH_ENOTREADY (-3)    /* basis or spots not set yet                */
+#define ASH_EUNSUPPORTED (-4) /* outside the supported limits below        */
+#define ASH_ENOMEM (-5)       /* device or host allocation failed          */
+#define ASH_EHIP (-6)         /* HIP runtime error (see ash_last_error)    */
+
+#define ASH_MAX_MODES 32       /* D                                          */
+#define ASH_MAX_NONLINEAR 28   /* modes with a term of total degree >= 2     */
+#define ASH_MAX_MONOMIALS 128  /* n_mono                                     */
+#define ASH_MAX_DEGREE 12      /* p + q of any monomial x^p y^q              */
+#define ASH_MAX_SIDE 65536     /* nx, ny                                     */
+#define ASH_MAX_SPOTS 1048576  /* N                                          */
+
+typedef struct ash_ctx ash_ctx;
+
+/* Weighted-GS parameters (the paper cites weighted GS without a formula;
+ * the reading implemented is, per iteration:
+ *   a_k = |E_k|,  r_k = (a_k/||a||) / (t_k/||t||),
+ *   W_k <- W_k r_k^(-power) where a_k > 0, then W <- W / mean(W),
+ *   y_k = W_k t_k E_k / a_k  (W_k t_k where a_k = 0),
+ *   phi <- arg(F_c^{-1} y)   with arg(0) = 0.)                             */
+typedef struct ash_wgs_params {
+  float power; /* weight exponent p; 1 = classic WGS, 0 = plain GS         */
+  int32_t reserved;
+} ash_wgs_params;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int ash_version(void);
+
+/* Human-readable text for a status code (static storage). */
+const char* ash_strerror(int code);
+
+/* Detail of the last error on ctx (static per context; "" if none). */
+const char* ash_last_error(const ash_ctx* ctx);
+
+/* Create a context on HIP device `device`, enqueueing on `stream` (a
+ * hipStream_t, NULL = the device's null stream).  *out receives the handle. */
+int ash_create(ash_ctx** out, int device, void* stream);
+
+/* Release the context and its device memory (synchronises its stream). */
+int ash_destroy(ash_ctx* ctx);
+
+/* Change the stream later calls enqueue on. */
+int ash_set_stream(ash_ctx* ctx, void* stream);
+
+/* Block until all work enqueued by ctx has finished. */
+int ash_sync(ash_ctx* ctx);
+
+/* Expand the orthonormal Zernike polynomial with ANSI index `ansi` into
+ * monomials: Z(xh, yh) = sum_k coef_out[k] xh^pow_out[2k] yh^pow_out[2k+1].
+ * Host-only, no device needed.  Writes at most `cap` terms; returns the
+ * number of terms (>= 0) or a negative code (ASH_EINVAL for ansi < 0 or
+ * null outputs, ASH_EUNSUPPORTED if the radial order exceeds
+ * ASH_MAX_DEGREE or the expansion needs more than cap terms).
+ * Paper: the modal-expansion paragraph (ANSI indexing) and Methods,
+ * "Computational Scaling" (basis given by monomial coefficients). */
+int ash_zernike_monomials(int ansi, int cap, int32_t* pow_out,
+                          double* coef_out);
+
+/* Define the SLM and the basis.
+ *   nx, ny     SLM size in pixels (1 .. ASH_MAX_SIDE).
+ *   cx, cy, R  pupil centre (pixels) and unit radius (pixels, > 0).
+ *   D          number of basis modes (1 .. ASH_MAX_MODES).
+ *   n_mono     number of distinct monomials (1 .. ASH_MAX_MONOMIALS).
+ *   mono_pow   host [n_mono][2] int32 exponents (p, q) of xh^p yh^q,
+ *              p, q >= 0, p + q <= ASH_MAX_DEGREE.
+ *   mono_coef  host [D][n_mono] float64: Z_d = sum_k mono_coef[d][k] mono_k.
+ *   amp_dev    device [ny][nx] float32 source amplitude A(x) >= 0 (copied
+ *              into the context), or NULL for A = 1.
+ * Replaces any previous basis; clears the spots (call ash_set_spots again).
+ * Paper: Methods, "Computational Scaling" (Z_d as a monomial sum evaluated
+ * per pixel) and the source amplitude measured in "A Full-Field 2D
+ * Tweezer Array".  Errors: ASH_EINVAL, ASH_EUNSUPPORTED, ASH_ENOMEM,
+ * ASH_EHIP. */
+int ash_set_basis(ash_ctx* ctx, int nx, int ny, double cx, double cy,
+                  double R, int D, int n_mono, const int32_t* mono_pow,
+                  const double* mono_coef, const float* amp_dev);
+
+/* Set the N spots.
+ *   w_host       host [N][D] float64 kernel coefficients in radians (the
+ *                aberration-space coordinates w_d^(n) of each spot).
+ *   target_host  host [N] float32 target amplitudes t_n > 0, or NULL for 1.
+ * May be called between iterations without touching pixel data (paper:
+ * Methods, "Computational Scaling", agile spot updates).  Runs an FP64
+ * device kernel that wraps each spot's constant and tilt terms per pixel
+ * tile.  Errors: ASH_ENOTREADY (no basis), ASH_EINVAL (N < 1, null w,
+ * non-finite values, t <= 0), ASH_EUNSUPPORTED, ASH_ENOMEM, ASH_EHIP. */
+int ash_set_spots(ash_ctx* ctx, int N, const double* w_host,
+                  const float* target_host);
+
+/* Forward transform E_n = sum_x f(x) exp(-i theta_n(x)).
+ * Exactly one input is non-NULL:
+ *   phase_dev  device [ny][nx] float32 phase; f = A exp(i phase), or
+ *   field_dev  device [ny][nx][2] float32 complex nearfield f (A unused).
+ *   E_dev      device [N][2] float32 output (unnormalised).
+ * Paper: "Aberration-Space Holography", compressed forward sum.
+ * Errors: ASH_EINVAL, ASH_ENOTREADY, ASH_EHIP. */
+int ash_forward(ash_ctx* ctx, const float* phase_dev, const float* field_dev,
+                float* E_dev);
+
+/* Adjoint transform g(x) = sum_n y_n exp(+i theta_n(x)).
+ *   y_dev          device [N][2] float32 spot fields.
+ *   g_dev          device [ny][nx][2] float32 output, or NULL.
+ *   phase_out_dev  device [ny][nx] float32 output arg g in (-pi, pi]
+ *                  (arg 0 = 0), or NULL.  At least one output non-NULL.
+ * Paper: "Aberration-Space Holography", compressed adjoint sum; the
+ * phase output is the GS nearfield projection.
+ * Errors: ASH_EINVAL, ASH_ENOTREADY, ASH_EHIP. */
+int ash_adjoint(ash_ctx* ctx, const float* y_dev, float* g_dev,
+                float* phase_out_dev);
+
+/* n_iter weighted-GS iterations, all on the device without host sync.
+ *   phase_dev    device [ny][nx] float32, in: start phase, out: final.
+ *   weights_dev  device [N] float32 spot weights W, in/out (start with 1).
+ *   params       see ash_wgs_params (NULL = power 1).
+ *   E_dev        device [N][2] float32: fields of the last iteration's
+ *                forward transform (before its phase update), or NULL.
+ *   stats_dev    device [n_iter][4] float32 per-iteration figures of the
+ *                forward fields: efficiency sum|E|^2/(P sum A^2),
+ *                uniformity 1-(max-min)/(max+min) of |E|^2/t^2, its
+ *                std/mean, and sum|E|^2; or NULL.
+ * Paper: "A Full-Field 2D Tweezer Array" (weighted GS) and the GS
+ * description in "Aberration-Space Holography".
+ * Errors: ASH_EINVAL (n_iter < 0, null phase/weights, power not finite),
+ * ASH_ENOTREADY, ASH_EHIP. */
+int ash_wgs_iterate(ash_ctx* ctx, float* phase_dev, float* weights_dev,
+                    int n_iter, const ash_wgs_params* params, float* E_dev,
+                    float* stats_dev);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASH_H */

@@ -1,0 +1,14 @@
+"""Aberration-space holography hot path on MI355X (gfx950).
+
+Per-spot propagation kernels exp(-i sum_d w_d^(n) Z_d(x)) merged into one
+SLM hologram: the compressed forward/adjoint transforms and the weighted
+Gerchberg-Saxton loop, as hand-written HIP kernels behind a C ABI
+(include/ash.h).  This package is the thin Python binding.
+"""
+
+from ._lib import AshError, LIB_PATH, lib
+from .basis import zernike_monomials, zernike_table
+from .context import Context
+
+__all__ = ["AshError", "Context", "LIB_PATH", "lib", "zernike_monomials",
+           "zernike_table"]

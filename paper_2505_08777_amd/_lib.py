@@ -1,0 +1,80 @@
+"""ctypes loader for libash.so (the HIP library built in-tree).
+
+The product path has no CPU fallback: if the library is missing or does not
+load, importing this module raises.
+"""
+
+import ctypes
+import os
+
+# torch brings its own copy of the HIP runtime.  Loading it before libash
+# makes libash's libamdhip64 dependency resolve to that same, already loaded
+# runtime; two HIP runtimes in one process do not share the device.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libash.so")
+
+OK = 0
+EINVAL, ESHAPE, ENOTREADY, EUNSUPPORTED, ENOMEM, EHIP = -1, -2, -3, -4, -5, -6
+
+MAX_MODES = 32
+MAX_MONOMIALS = 128
+
+
+class AshError(RuntimeError):
+    def __init__(self, code, where, detail=""):
+        self.code = code
+        msg = "%s failed: %s (%d)" % (where, strerror(code), code)
+        if detail:
+            msg += ": " + detail
+        super().__init__(msg)
+
+
+class WgsParams(ctypes.Structure):
+    _fields_ = [("power", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            "libash.so is not built; run `python -m paper_2505_08777_amd.build` "
+            "(hipcc for gfx950) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    D = ctypes.c_double
+    sig = {
+        "ash_version": (I, []),
+        "ash_strerror": (ctypes.c_char_p, [I]),
+        "ash_last_error": (ctypes.c_char_p, [P]),
+        "ash_create": (I, [ctypes.POINTER(P), I, P]),
+        "ash_destroy": (I, [P]),
+        "ash_set_stream": (I, [P, P]),
+        "ash_sync": (I, [P]),
+        "ash_zernike_monomials": (I, [I, I, P, P]),
+        "ash_set_basis": (I, [P, I, I, D, D, D, I, I, P, P, P]),
+        "ash_set_spots": (I, [P, I, P, P]),
+        "ash_forward": (I, [P, P, P, P]),
+        "ash_adjoint": (I, [P, P, P, P]),
+        "ash_wgs_iterate": (I, [P, P, P, I, ctypes.POINTER(WgsParams), P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def strerror(code):
+    return lib.ash_strerror(code).decode()
+
+
+def check(code, where, ctx=None):
+    if code != OK:
+        detail = lib.ash_last_error(ctx).decode() if ctx else ""
+        raise AshError(code, where, detail)
+    return code

@@ -1,0 +1,168 @@
+"""Python binding of libash: argument marshalling around the C ABI.
+
+Every transform, reduction and update runs in the library's HIP kernels;
+torch supplies device memory (tensors) and the stream.  Pixel arrays are
+[ny, nx] float32 (phase, amplitude) or complex64 (fields); spot arrays are
+[N] complex64 (fields) or float32 (targets, weights).
+"""
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from ._lib import lib, check, AshError, WgsParams
+from .basis import zernike_table
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype, shape, name, device):
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError("%s must be on cuda:%d" % (name, device))
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s"
+                         % (name, tuple(shape), tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+class Context:
+    """One library context on one device, enqueueing on torch's stream."""
+
+    def __init__(self, device=0):
+        self.device = int(device)
+        self._h = ctypes.c_void_p()
+        rc = lib.ash_create(ctypes.byref(self._h), self.device, None)
+        if rc != 0:
+            raise AshError(rc, "ash_create", lib.ash_last_error(None).decode())
+        self.nx = self.ny = self.N = self.D = None
+        self.modes = None
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if self._h:
+            lib.ash_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        check(lib.ash_set_stream(self._h, ctypes.c_void_p(s)), "ash_set_stream")
+
+    def sync(self):
+        check(lib.ash_sync(self._h), "ash_sync", self._h)
+
+    # -- set-up -----------------------------------------------------------
+    def set_basis(self, nx, ny, modes=None, mono_pow=None, mono_coef=None,
+                  amp=None, cx=None, cy=None, R=None):
+        """Zernike modes (ANSI list) or an explicit monomial table."""
+        if modes is not None:
+            mono_pow, mono_coef = zernike_table(modes)
+            self.modes = list(modes)
+        mono_pow = np.ascontiguousarray(mono_pow, dtype=np.int32)
+        mono_coef = np.ascontiguousarray(mono_coef, dtype=np.float64)
+        cx = nx / 2.0 if cx is None else cx
+        cy = ny / 2.0 if cy is None else cy
+        R = min(nx, ny) / 2.0 if R is None else R
+        if amp is not None:
+            amp = _dev(amp, torch.float32, (ny, nx), "amp", self.device)
+        self._stream()
+        check(lib.ash_set_basis(self._h, int(nx), int(ny), float(cx),
+                                float(cy), float(R), mono_coef.shape[0],
+                                mono_pow.shape[0], mono_pow.ctypes.data,
+                                mono_coef.ctypes.data, _ptr(amp)),
+              "ash_set_basis", self._h)
+        self.nx, self.ny, self.D = int(nx), int(ny), mono_coef.shape[0]
+        self.N = None
+
+    def set_spots(self, w, target=None):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        if w.ndim != 2 or w.shape[1] != self.D:
+            raise ValueError("w must be [N, %s]" % self.D)
+        t = None
+        if target is not None:
+            t = np.ascontiguousarray(target, dtype=np.float32)
+            if t.shape != (w.shape[0],):
+                raise ValueError("target must be [N]")
+        self._stream()
+        check(lib.ash_set_spots(self._h, w.shape[0], w.ctypes.data,
+                                t.ctypes.data if t is not None else None),
+              "ash_set_spots", self._h)
+        self.N = w.shape[0]
+
+    # -- transforms ---------------------------------------------------------
+    def forward(self, phase=None, field=None, out=None):
+        """E_n = sum_x f(x) exp(-i theta_n(x)); f = A exp(i phase) or field."""
+        if (phase is None) == (field is None):
+            raise ValueError("give exactly one of phase, field")
+        P = (self.ny, self.nx)
+        if phase is not None:
+            _dev(phase, torch.float32, P, "phase", self.device)
+        else:
+            _dev(field, torch.complex64, P, "field", self.device)
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.complex64,
+                              device="cuda:%d" % self.device)
+        _dev(out, torch.complex64, (self.N,), "out", self.device)
+        self._stream()
+        check(lib.ash_forward(self._h, _ptr(phase), _ptr(field), _ptr(out)),
+              "ash_forward", self._h)
+        return out
+
+    def adjoint(self, y, field=True, phase=False):
+        """g(x) = sum_n y_n exp(+i theta_n(x)); returns g and/or arg g."""
+        _dev(y, torch.complex64, (self.N,), "y", self.device)
+        if not (field or phase):
+            raise ValueError("request at least one output")
+        dev = "cuda:%d" % self.device
+        g = torch.empty((self.ny, self.nx), dtype=torch.complex64,
+                        device=dev) if field else None
+        ph = torch.empty((self.ny, self.nx), dtype=torch.float32,
+                         device=dev) if phase else None
+        self._stream()
+        check(lib.ash_adjoint(self._h, _ptr(y), _ptr(g), _ptr(ph)),
+              "ash_adjoint", self._h)
+        if field and phase:
+            return g, ph
+        return g if field else ph
+
+    def wgs(self, phase, n_iter, weights=None, power=1.0, want_E=True,
+            want_stats=True):
+        """n_iter weighted-GS iterations; phase is updated in place.
+
+        Returns (phase, weights, E_last, stats[n_iter, 4])."""
+        _dev(phase, torch.float32, (self.ny, self.nx), "phase", self.device)
+        dev = "cuda:%d" % self.device
+        if weights is None:
+            weights = torch.ones(self.N, dtype=torch.float32, device=dev)
+        _dev(weights, torch.float32, (self.N,), "weights", self.device)
+        E = torch.empty(self.N, dtype=torch.complex64, device=dev) \
+            if want_E else None
+        st = torch.empty((max(n_iter, 1), 4), dtype=torch.float32,
+                         device=dev) if want_stats else None
+        params = WgsParams(float(power), 0)
+        self._stream()
+        check(lib.ash_wgs_iterate(self._h, _ptr(phase), _ptr(weights),
+                                  int(n_iter), ctypes.byref(params), _ptr(E),
+                                  _ptr(st)), "ash_wgs_iterate", self._h)
+        if st is not None:
+            st = st[:n_iter]
+        return phase, weights, E, st

@@ -1,0 +1,115 @@
+// Internal state and kernel launchers of libash (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "ash.h"
+
+namespace ash {
+
+// Pixel tile: 64 columns x 16 rows.  Tiles are stored tile-major, pixels
+// row-major inside a tile, ragged tiles padded with zero-amplitude pixels.
+constexpr int kTileW = 64;
+constexpr int kTileH = 16;
+constexpr int kTile = kTileW * kTileH;
+constexpr int kBlock = 256;  // threads per block for the transforms
+constexpr int kWave = 64;
+
+// Nonlinear-mode counts with a compiled kernel; other counts are padded up.
+int pad_nonlinear(int nl);
+
+struct Basis {
+  int nx = 0, ny = 0;
+  double cx = 0, cy = 0, R = 1;
+  int D = 0;
+  int nl = 0;      // modes with a monomial of total degree >= 2
+  int nl_pad = 0;  // nl rounded up to a compiled kernel
+  int rec = 0;     // floats per pixel record: 2 + nl_pad rounded up to 4
+  int tiles_x = 0, tiles_y = 0, n_tiles = 0;
+  std::vector<int> nl_mode;   // [nl] original mode index of nonlinear slot
+  std::vector<double> aff;    // [D][3] coefficient of 1, xh, yh in Z_d
+  double amp_sum2 = 0;        // sum over pixels of A^2 (host, FP64)
+};
+
+struct Spots {
+  int N = 0;
+  int srec = 0;        // floats per spot record (== basis rec)
+  double t_norm2 = 0;  // sum t^2 (host, FP64)
+};
+
+struct Buffers {
+  float* pixtab = nullptr;   // [n_tiles][kTile][rec]: di, dj, Rm_0 ...
+  float* amp_t = nullptr;    // [n_tiles][kTile]
+  float* field_t = nullptr;  // [n_tiles][kTile][2]
+  double* tilez = nullptr;   // [n_tiles][nl][3] Z^nl, d/di, d/dj at origins
+  float* spotrec = nullptr;  // [N][rec]: 0, 0, c_0 ... (turns)
+  float* offtab = nullptr;   // [n_tiles][N][4] wrapped offset, a, b, 0
+  float* target = nullptr;   // [N]
+  float* y = nullptr;        // [N][2]
+  float* Ebuf = nullptr;     // [N][2] fields of the last WGS forward
+  double* w64 = nullptr;     // [N][D] staged coefficients (radians)
+  double* spot64 = nullptr;  // [N][3] FP64 constant, alpha, beta (turns)
+  double* aff_dev = nullptr; // [D][3] affine coefficients of each mode
+  int* nlmode_dev = nullptr; // [nl]
+  float* partial = nullptr;  // [groups][N][2]
+  float* red = nullptr;      // [slices][N][2]
+  size_t cap_spots = 0, cap_w = 0, cap_off = 0, cap_partial = 0, cap_red = 0;
+};
+
+struct FwdPlan {
+  int groups = 0;           // tile groups (forward partial rows)
+  int tiles_per_group = 0;
+  int slices = 0;           // second-level reduction rows
+  int rows_per_slice = 0;
+};
+
+FwdPlan plan_forward(int n_tiles, int N);
+
+// ---- launchers (kernels.hip) ----
+hipError_t launch_build_pixtab(const Basis& b, const int32_t* d_pow,
+                               const double* d_nlcoef, int n_mono,
+                               const float* amp_dev, float* pixtab,
+                               float* amp_t, double* tilez, hipStream_t s);
+hipError_t launch_prep_spots(const Basis& b, int N, const double* d_w,
+                             const double* d_aff, const int* d_nlmode,
+                             const double* tilez, float* spotrec,
+                             float* offtab, double* spot64, hipStream_t s);
+hipError_t launch_make_field(const Basis& b, const float* phase,
+                             const float* field, const float* amp_t,
+                             float* field_t, hipStream_t s);
+hipError_t launch_forward(const Basis& b, int N, const FwdPlan& p,
+                          const float* pixtab, const float* field_t,
+                          const float* spotrec, const float* offtab,
+                          float* partial, hipStream_t s);
+hipError_t launch_reduce(int N, const FwdPlan& p, const float* partial,
+                         float* red, hipStream_t s);
+hipError_t launch_finish_E(int N, const FwdPlan& p, const float* red,
+                           float* E, hipStream_t s);
+hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
+                             const float* target, float t_norm, float* W,
+                             float power, float eff_denom, float* y,
+                             float* Ebuf, float* E_extra, float* stats_row,
+                             hipStream_t s);
+enum AdjOut { kOutG = 1, kOutPhase = 2, kOutField = 4 };
+hipError_t launch_adjoint(const Basis& b, int N, const float* pixtab,
+                          const float* spotrec, const float* offtab,
+                          const float* y, const float* amp_t, int outs,
+                          float* g, float* phase, float* field_t,
+                          hipStream_t s);
+
+}  // namespace ash
+
+struct ash_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool has_basis = false, has_spots = false;
+  ash::Basis basis;
+  ash::Spots spots;
+  ash::Buffers buf;
+  ash::FwdPlan plan;
+};

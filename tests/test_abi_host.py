@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol
+that include/ash.h declares, expands Zernike polynomials exactly and
+rejects bad arguments with the documented codes.  No GPU compute."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ash.h")
+
+A = pytest.importorskip("paper_2505_08777_amd")
+from paper_2505_08777_amd import _lib  # noqa: E402
+import oracle  # noqa: E402
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ash_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    syms = declared_symbols()
+    assert "ash_forward" in syms and "ash_wgs_iterate" in syms
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_status_codes_match_header():
+    src = open(HEADER).read()
+    codes = dict((m.group(1), int(m.group(2))) for m in
+                 re.finditer(r"#define (ASH_E[A-Z]+) \((-\d+)\)", src))
+    assert codes == {"ASH_EINVAL": _lib.EINVAL, "ASH_ESHAPE": _lib.ESHAPE,
+                     "ASH_ENOTREADY": _lib.ENOTREADY,
+                     "ASH_EUNSUPPORTED": _lib.EUNSUPPORTED,
+                     "ASH_ENOMEM": _lib.ENOMEM, "ASH_EHIP": _lib.EHIP}
+    for c in list(codes.values()) + [0]:
+        assert _lib.strerror(c) != "unknown error"
+    assert _lib.strerror(-99) == "unknown error"
+
+
+@pytest.mark.parametrize("ansi", range(0, 66))
+def test_zernike_expansion_matches_radial_formula(ansi):
+    pw, cf = A.zernike_monomials(ansi)
+    rng = np.random.default_rng(ansi)
+    x, y = rng.uniform(-1.9, 1.9, size=(2, 64))
+    val = sum(c * x ** p * y ** q for (p, q), c in zip(pw, cf))
+    n, m = oracle.ansi_to_nm(ansi)
+    ref = oracle.zernike_nm(n, m, x, y)
+    np.testing.assert_allclose(val, ref, rtol=1e-10, atol=1e-9)
+
+
+def test_zernike_table_union():
+    pw, cf = A.zernike_table([1, 2, 4, 12])
+    assert cf.shape == (4, pw.shape[0])
+    x, y = 0.3, -0.7
+    mono = np.array([x ** p * y ** q for p, q in pw])
+    np.testing.assert_allclose(cf @ mono, [oracle.zernike_nm(*oracle.ansi_to_nm(d), x, y)
+                                           for d in [1, 2, 4, 12]], rtol=1e-12)
+
+
+def test_zernike_expansion_errors():
+    lib = _lib.lib
+    pw = np.zeros((4, 2), np.int32)
+    cf = np.zeros(4)
+    assert lib.ash_zernike_monomials(-1, 4, pw.ctypes.data, cf.ctypes.data) == _lib.EINVAL
+    assert lib.ash_zernike_monomials(3, 4, None, None) == _lib.EINVAL
+    # Z_12 has 6 terms: a cap of 4 is too small
+    assert lib.ash_zernike_monomials(12, 4, pw.ctypes.data, cf.ctypes.data) == _lib.EUNSUPPORTED
+    # radial order 13 exceeds the supported degree
+    assert lib.ash_zernike_monomials(13 * 15 // 2 + 1, 4, pw.ctypes.data, cf.ctypes.data) == _lib.EUNSUPPORTED
+
+
+def test_null_context_and_arguments():
+    lib = _lib.lib
+    assert lib.ash_create(None, 0, None) == _lib.EINVAL
+    assert lib.ash_destroy(None) == _lib.EINVAL
+    assert lib.ash_sync(None) == _lib.EINVAL
+    assert lib.ash_set_spots(None, 1, None, None) == _lib.EINVAL
+    assert lib.ash_forward(None, None, None, None) == _lib.EINVAL
+    assert lib.ash_adjoint(None, None, None, None) == _lib.EINVAL
+    assert lib.ash_wgs_iterate(None, None, None, 1, None, None, None) == _lib.EINVAL
+    assert lib.ash_last_error(None) == b"null context"  # after ash_create(NULL)
+    assert lib.ash_version() >= 100
+
+
+def test_create_without_gpu_reports_hip_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert _lib.lib.ash_create(ctypes.byref(h), 0, None) == _lib.EHIP
