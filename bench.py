@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Throughput of the weighted Gerchberg-Saxton hologram loop on one MI355X.
+
+A step is one call of the library's WGS loop: the workload's iterations of
+forward transform -> farfield weight update -> adjoint transform -> phase
+projection, on synthetic inputs already resident in HBM.  The default
+workload is the full-field 2D stand-in (1024 x 1024 SLM, 400 spots from 50
+bilinearly interpolated isoplanatic patches x 8 Zernike modes, 100 WGS
+iterations per step).
+
+Printed (one JSON line): spot x pixel kernel evaluations per second over
+forward + adjoint (value), WGS iterations per second, the fraction of the
+FP32 vector peak, the roofline of the dominant kernel from HIP events on
+the library's stream, and the FP64 CPU oracle timed on a bounded sample of
+the same workload on the host cores (with the GPU's error against it).
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X FP32 vector, AMD specification
+METRIC = ("spot·pixel kernel evals/s (fwd+adj) and WGS iters/s; "
+          "% FP32 VALU peak")
+
+
+def flops_per_eval(D):
+    # D phase multiply-adds (2 flops each), range reduction (1), sin and
+    # cos (1 each), complex multiply-accumulate as 4 FMAs (8 flops)
+    return 2 * D + 11
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="field1024",
+                    choices=["plain256", "field1024", "volume1920"])
+    ap.add_argument("--iters", type=int, default=None,
+                    help="WGS iterations per step (default: the workload's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(ctx, d, pix_sample):
+    """The FP64 oracle on a bounded sample of the same workload.
+
+    Sample: one full forward transform (all spots, all pixels) at the
+    workload's seeded start phase, and the adjoint at a fixed set of pixels
+    for the farfield projection y = t E/|E| of the oracle's fields.  The GPU
+    runs the same two transforms on the same inputs; its errors against the
+    oracle are returned beside the timing."""
+    import numpy as np
+    import torch
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from tolerance import field_errors
+    geom = oracle.Geometry(d["nx"], d["ny"])
+    basis = oracle.ZernikeBasis(d["modes"])
+    cores = len(os.sched_getaffinity(0))
+    amp32 = d["amp"].astype(np.float32).astype(np.float64)
+    phi32 = d["phi0"].astype(np.float32)
+    N, P = d["w"].shape[0], geom.P
+    t0 = time.perf_counter()
+    Eref = oracle.forward(amp32 * np.exp(1j * phi32.astype(np.float64)),
+                          d["w"], basis, geom, workers=cores)
+    t1 = time.perf_counter()
+    y = (d["t"] * Eref / np.abs(Eref)).astype(np.complex64)
+    gref = oracle.adjoint(y.astype(np.complex128), d["w"], basis, geom,
+                          pixels=pix_sample, workers=cores)
+    t2 = time.perf_counter()
+    evals = N * P + N * len(pix_sample)
+    dev = torch.device("cuda:0")
+    E = ctx.forward(phase=torch.tensor(phi32, device=dev)).cpu().numpy()
+    g = ctx.adjoint(torch.tensor(y, device=dev)).reshape(-1)
+    g_s = g[torch.tensor(pix_sample, device=dev)].cpu().numpy()
+    fe = field_errors(E, Eref)
+    ge = field_errors(g_s, gref)
+    obj = {"value": evals / (t2 - t0), "unit": "evals/s", "cores": cores,
+           "kind": "oracle",
+           "sample": "one forward transform over all %d spots x %d pixels "
+                     "(%.2f s) plus the adjoint at %d pixels x %d spots "
+                     "(%.2f s), FP64 numpy on %d threads"
+                     % (N, P, t1 - t0, len(pix_sample), N, t2 - t1, cores)}
+    parity = {"forward_max_rel": fe[0], "forward_norm_rel": fe[1],
+              "adjoint_max_rel": ge[0], "adjoint_norm_rel": ge[1],
+              "bar": 1e-4}
+    return obj, parity
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(each GPU would run its own pixel slab; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads
+    import paper_2505_08777_amd as A
+
+    d = workloads.make(args.workload)
+    n_iter = args.iters or d["n_iter"]
+    nx, ny = d["nx"], d["ny"]
+    N, D = d["w"].shape
+    P = nx * ny
+    dev = torch.device("cuda:0")
+    ctx = A.Context(0)
+    ctx.set_basis(nx, ny, modes=d["modes"],
+                  amp=torch.tensor(d["amp"], dtype=torch.float32, device=dev))
+    ctx.set_spots(d["w"], d["t"])
+    phase = torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
+    weights = torch.ones(N, dtype=torch.float32, device=dev)
+
+    for _ in range(args.warmup):
+        ctx.wgs(phase, n_iter, weights=weights, want_E=False, want_stats=False)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, every kernel bracketed by HIP events
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.wgs(phase, n_iter, weights=weights, want_E=False,
+                want_stats=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+
+    # the same loop without events, for the event overhead
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.wgs(phase, n_iter, weights=weights, want_E=False,
+                want_stats=False)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+
+    T = t1 - t0
+    ms_step = 1e3 * T / args.steps
+    evals_step = 2.0 * N * P * n_iter
+    value = evals_step * args.steps / T
+    F = flops_per_eval(D)
+    # dominant kernel: the transform with the larger total time
+    dom = max(("forward", "adjoint"), key=lambda k: prof[k][0])
+    ms_avg = prof[dom][0] / max(prof[dom][1], 1)
+    achieved = N * P * F / (ms_avg * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "k_%s" % dom,
+                "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                "traffic": None,
+                "avg_launch_ms": ms_avg, "launches": prof[dom][1],
+                "flops_per_eval": F, "evals_per_launch": N * P}
+    kernels = {k: {"total_ms": v[0], "launches": v[1],
+                   "avg_ms": v[0] / v[1] if v[1] else None}
+               for k, v in prof.items()}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "slm": "%dx%d" % (nx, ny),
+                   "spots": N, "modes": D, "wgs_iters_per_step": n_iter},
+        "wgs_iters_per_s": n_iter * args.steps / T,
+        "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
+        "ms_per_step_without_events": 1e3 * (t3 - t2) / args.steps,
+        "roofline": roofline, "kernels": kernels,
+    }
+
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(12345)
+        pix = np.sort(rng.choice(P, size=min(P, 65536), replace=False))
+        out["cpu_baseline"], out["parity"] = cpu_baseline(ctx, d, pix)
+        out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

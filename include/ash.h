@@ -189,6 +189,23 @@ int ash_wgs_iterate(ash_ctx* ctx, float* phase_dev, float* weights_dev,
                     int n_iter, const ash_wgs_params* params, float* E_dev,
                     float* stats_dev);
 
+/* Kernel timing, for measurement.  While enabled, every kernel the context
+ * enqueues is bracketed by HIP events on the context's stream.  Categories:
+ *   ASH_PROF_FORWARD   forward transform kernel
+ *   ASH_PROF_ADJOINT   adjoint transform kernel (with its epilogue)
+ *   ASH_PROF_REDUCE    partial-sum reductions and the weighted-GS update
+ *   ASH_PROF_FIELD     nearfield preparation A exp(i phase)
+ * ash_profile_read synchronises the stream, writes the summed milliseconds
+ * and the launch count of each category into ms_out[4] / launches_out[4]
+ * (either may be NULL) and clears the record.  Enabling allocates events;
+ * disabled (the default), nothing is recorded. */
+#define ASH_PROF_FORWARD 0
+#define ASH_PROF_ADJOINT 1
+#define ASH_PROF_REDUCE 2
+#define ASH_PROF_FIELD 3
+int ash_profile_enable(ash_ctx* ctx, int enable);
+int ash_profile_read(ash_ctx* ctx, double* ms_out, int64_t* launches_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,8 @@ def _load():
         "ash_forward": (I, [P, P, P, P]),
         "ash_adjoint": (I, [P, P, P, P]),
         "ash_wgs_iterate": (I, [P, P, P, I, ctypes.POINTER(WgsParams), P, P]),
+        "ash_profile_enable": (I, [P, I]),
+        "ash_profile_read": (I, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

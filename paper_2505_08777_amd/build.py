@@ -1,6 +1,8 @@
 """Build libash.so in-tree with hipcc for gfx950.
 
-Usage: python -m paper_2505_08777_amd.build [-v]
+Usage: python paper_2505_08777_amd/build.py [-v]
+(run by path, so that the package, and with it a stale library, is not
+imported before the build)
 """
 
 import os

@@ -67,6 +67,20 @@ class Context:
         s = torch.cuda.current_stream(self.device).cuda_stream
         check(lib.ash_set_stream(self._h, ctypes.c_void_p(s)), "ash_set_stream")
 
+    def profile(self, enable=True):
+        """Bracket every enqueued kernel with HIP events (see profile_read)."""
+        check(lib.ash_profile_enable(self._h, 1 if enable else 0),
+              "ash_profile_enable", self._h)
+
+    def profile_read(self):
+        """{category: (total ms, launches)} since the last read; syncs."""
+        ms = np.zeros(4, dtype=np.float64)
+        n = np.zeros(4, dtype=np.int64)
+        check(lib.ash_profile_read(self._h, ms.ctypes.data, n.ctypes.data),
+              "ash_profile_read", self._h)
+        names = ("forward", "adjoint", "reduce", "field")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(names)}
+
     def sync(self):
         check(lib.ash_sync(self._h), "ash_sync", self._h)
 

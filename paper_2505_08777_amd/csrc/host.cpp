@@ -57,6 +57,45 @@ int use_device(ash_ctx* c) {
   return ASH_OK;
 }
 
+hipEvent_t prof_event(ash_ctx* c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// Enqueue `launch` bracketed by events of category `cat` when profiling.
+template <typename F>
+hipError_t timed(ash_ctx* c, int cat, F&& launch) {
+  if (!c->prof_on) return launch();
+  hipEvent_t a = prof_event(c), b = prof_event(c);
+  if (a) (void)hipEventRecord(a, c->stream);
+  hipError_t e = launch();
+  if (a && b) {
+    (void)hipEventRecord(b, c->stream);
+    c->prof.push_back({cat, a, b});
+  } else {
+    if (a) c->prof_pool.push_back(a);
+    if (b) c->prof_pool.push_back(b);
+  }
+  return e;
+}
+
+void prof_release(ash_ctx* c) {
+  for (auto& r : c->prof) {
+    c->prof_pool.push_back(r.start);
+    c->prof_pool.push_back(r.stop);
+  }
+  c->prof.clear();
+}
+
 template <typename T>
 void dfree(T*& p) {
   if (p) (void)hipFree(p);
@@ -243,6 +282,9 @@ int ash_create(ash_ctx** out, int device, void* stream) {
 int ash_destroy(ash_ctx* c) {
   if (!c) return ASH_EINVAL;
   if (use_device(c) == ASH_OK) (void)hipStreamSynchronize(c->stream);
+  prof_release(c);
+  for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+  c->prof_pool.clear();
   free_basis(c);
   delete c;
   return ASH_OK;
@@ -508,12 +550,20 @@ int ash_forward(ash_ctx* c, const float* phase_dev, const float* field_dev,
   const Basis& b = c->basis;
   Buffers& B = c->buf;
   const int N = c->spots.N;
-  HIPCHK(c, launch_make_field(b, phase_dev, field_dev, B.amp_t, B.field_t,
-                              c->stream), "make_field");
-  HIPCHK(c, launch_forward(b, N, c->plan, B.pixtab, B.field_t, B.spotrec,
-                           B.offtab, B.partial, c->stream), "forward");
-  HIPCHK(c, launch_reduce(N, c->plan, B.partial, B.red, c->stream), "reduce");
-  HIPCHK(c, launch_finish_E(N, c->plan, B.red, E_dev, c->stream), "finish");
+  HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
+           return launch_make_field(b, phase_dev, field_dev, B.amp_t,
+                                    B.field_t, c->stream);
+         }), "make_field");
+  HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
+           return launch_forward(b, N, c->plan, B.pixtab, B.field_t,
+                                 B.spotrec, B.offtab, B.partial, c->stream);
+         }), "forward");
+  HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+           return launch_reduce(N, c->plan, B.partial, B.red, c->stream);
+         }), "reduce");
+  HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+           return launch_finish_E(N, c->plan, B.red, E_dev, c->stream);
+         }), "finish");
   return ASH_OK;
 }
 
@@ -528,10 +578,12 @@ int ash_adjoint(ash_ctx* c, const float* y_dev, float* g_dev,
   int rc = use_device(c);
   if (rc) return rc;
   const int outs = (g_dev ? kOutG : 0) | (phase_out_dev ? kOutPhase : 0);
-  HIPCHK(c, launch_adjoint(c->basis, c->spots.N, c->buf.pixtab,
-                           c->buf.spotrec, c->buf.offtab, y_dev, c->buf.amp_t,
-                           outs, g_dev, phase_out_dev, nullptr, c->stream),
-         "adjoint");
+  HIPCHK(c, timed(c, ASH_PROF_ADJOINT, [&] {
+           return launch_adjoint(c->basis, c->spots.N, c->buf.pixtab,
+                                 c->buf.spotrec, c->buf.offtab, y_dev,
+                                 c->buf.amp_t, outs, g_dev, phase_out_dev,
+                                 nullptr, c->stream);
+         }), "adjoint");
   return ASH_OK;
 }
 
@@ -554,25 +606,61 @@ int ash_wgs_iterate(ash_ctx* c, float* phase_dev, float* weights_dev,
   const int N = c->spots.N;
   const float t_norm = (float)sqrt(c->spots.t_norm2);
   const float eff_denom = (float)((double)b.nx * b.ny * b.amp_sum2);
-  HIPCHK(c, launch_make_field(b, phase_dev, nullptr, B.amp_t, B.field_t,
-                              c->stream), "make_field");
+  HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
+           return launch_make_field(b, phase_dev, nullptr, B.amp_t,
+                                    B.field_t, c->stream);
+         }), "make_field");
   for (int it = 0; it < n_iter; ++it) {
     const bool last = it == n_iter - 1;
-    HIPCHK(c, launch_forward(b, N, c->plan, B.pixtab, B.field_t, B.spotrec,
-                             B.offtab, B.partial, c->stream), "forward");
-    HIPCHK(c, launch_reduce(N, c->plan, B.partial, B.red, c->stream),
-           "reduce");
-    HIPCHK(c, launch_wgs_update(N, c->plan, B.red, B.target, t_norm,
-                                weights_dev, power, eff_denom, B.y, B.Ebuf,
-                                last ? E_dev : nullptr,
-                                stats_dev ? stats_dev + 4 * (size_t)it
-                                          : nullptr,
-                                c->stream), "wgs_update");
-    HIPCHK(c, launch_adjoint(b, N, B.pixtab, B.spotrec, B.offtab, B.y,
-                             B.amp_t, last ? kOutPhase : kOutField, nullptr,
-                             last ? phase_dev : nullptr,
-                             last ? nullptr : B.field_t, c->stream),
-           "adjoint");
+    HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
+             return launch_forward(b, N, c->plan, B.pixtab, B.field_t,
+                                   B.spotrec, B.offtab, B.partial, c->stream);
+           }), "forward");
+    HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+             return launch_reduce(N, c->plan, B.partial, B.red, c->stream);
+           }), "reduce");
+    HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+             return launch_wgs_update(
+                 N, c->plan, B.red, B.target, t_norm, weights_dev, power,
+                 eff_denom, B.y, B.Ebuf, last ? E_dev : nullptr,
+                 stats_dev ? stats_dev + 4 * (size_t)it : nullptr, c->stream);
+           }), "wgs_update");
+    HIPCHK(c, timed(c, ASH_PROF_ADJOINT, [&] {
+             return launch_adjoint(b, N, B.pixtab, B.spotrec, B.offtab, B.y,
+                                   B.amp_t, last ? kOutPhase : kOutField,
+                                   nullptr, last ? phase_dev : nullptr,
+                                   last ? nullptr : B.field_t, c->stream);
+           }), "adjoint");
+  }
+  return ASH_OK;
+}
+
+int ash_profile_enable(ash_ctx* c, int enable) {
+  if (!c) return ASH_EINVAL;
+  c->prof_on = enable != 0;
+  return ASH_OK;
+}
+
+int ash_profile_read(ash_ctx* c, double* ms_out, int64_t* launches_out) {
+  if (!c) return ASH_EINVAL;
+  int rc = use_device(c);
+  if (rc) return rc;
+  double ms[4] = {0, 0, 0, 0};
+  int64_t n[4] = {0, 0, 0, 0};
+  hipError_t e = hipStreamSynchronize(c->stream);
+  for (auto& r : c->prof) {
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.start, r.stop);
+    if (r.cat >= 0 && r.cat < 4) {
+      ms[r.cat] += t;
+      n[r.cat] += 1;
+    }
+  }
+  prof_release(c);
+  if (e != hipSuccess) return hip_fail(c, e, "reading kernel timings");
+  for (int k = 0; k < 4; ++k) {
+    if (ms_out) ms_out[k] = ms[k];
+    if (launches_out) launches_out[k] = n[k];
   }
   return ASH_OK;
 }

@@ -103,8 +103,16 @@ hipError_t launch_adjoint(const Basis& b, int N, const float* pixtab,
 
 }  // namespace ash
 
+struct ash_prof_rec {
+  int cat;
+  hipEvent_t start, stop;
+};
+
 struct ash_ctx {
   int device = 0;
+  bool prof_on = false;
+  std::vector<ash_prof_rec> prof;    // recorded pairs (in use)
+  std::vector<hipEvent_t> prof_pool; // free events
   hipStream_t stream = nullptr;
   std::string err;
   bool has_basis = false, has_spots = false;
