@@ -47,7 +47,23 @@ def parse():
     ap.add_argument("--iters", type=int, default=None,
                     help="WGS iterations per step (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many "
+                         "MiB (for scaling HBM byte counters), then exit")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    """A plain copy of known size: reads and writes mib MiB once each."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}),
+          flush=True)
 
 
 def cpu_baseline(ctx, d, pix_sample):
@@ -98,6 +114,9 @@ def cpu_baseline(ctx, d, pix_sample):
 
 def main():
     args = parse()
+    if args.calibrate_copy_mib:
+        calibrate_copy(args.calibrate_copy_mib)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(each GPU would run its own pixel slab; see DESIGN.md)",

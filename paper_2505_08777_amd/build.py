@@ -19,9 +19,11 @@ SOURCES = ["host.cpp", "kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for all device code: hipcc -O3 would
-# otherwise form v_pk_fma/add/mul_f32 from ordinary float code.
+# otherwise form v_pk_fma/add/mul_f32 from ordinary float code.  Matrix-core
+# results are kept in VGPRs (no accumulation-register copies).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-I", INCLUDE, "-I", CSRC]
 
 

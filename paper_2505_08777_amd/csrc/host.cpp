@@ -270,10 +270,18 @@ int ash_create(ash_ctx** out, int device, void* stream) {
   if (strcmp(arch, "9.5") != 0)
     return create_fail(ASH_EUNSUPPORTED,
                        std::string("needs gfx950, device reports ") + arch);
+  int n_cu = 0;
+  e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount,
+                            device);
+  if (e != hipSuccess || n_cu <= 0) {
+    (void)hipGetLastError();
+    return create_fail(ASH_EHIP, "device query: compute unit count");
+  }
   ash_ctx* c = new (std::nothrow) ash_ctx();
   if (!c) return create_fail(ASH_ENOMEM, "host allocation");
   g_create_err.clear();
   c->device = device;
+  c->n_cu = n_cu;
   c->stream = reinterpret_cast<hipStream_t>(stream);
   *out = c;
   return ASH_OK;
@@ -361,8 +369,8 @@ int ash_set_basis(ash_ctx* c, int nx, int ny, double cx, double cy, double R,
   b.nl = (int)b.nl_mode.size();
   if (b.nl > ASH_MAX_NONLINEAR)
     return fail(c, ASH_EUNSUPPORTED, "too many non-linear modes");
-  b.nl_pad = pad_nonlinear(b.nl);
-  b.rec = (b.nl_pad + 2 + 3) & ~3;
+  b.kh = half_k(b.nl);
+  b.rec = 2 * b.kh;
   b.tiles_x = (nx + kTileW - 1) / kTileW;
   b.tiles_y = (ny + kTileH - 1) / kTileH;
   b.n_tiles = b.tiles_x * b.tiles_y;
@@ -457,7 +465,8 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
   }
   int rc = use_device(c);
   if (rc) return rc;
-  const FwdPlan plan = plan_forward(b.n_tiles, N);
+  const FwdPlan plan = plan_forward(b.n_tiles, N,
+                                    forward_blocks_per_cu(b.kh), c->n_cu);
   Buffers& B = c->buf;
   const size_t n_off = (size_t)b.n_tiles * N * 4;
   const size_t n_part = (size_t)plan.groups * N * 2;
@@ -578,9 +587,12 @@ int ash_adjoint(ash_ctx* c, const float* y_dev, float* g_dev,
   int rc = use_device(c);
   if (rc) return rc;
   const int outs = (g_dev ? kOutG : 0) | (phase_out_dev ? kOutPhase : 0);
+  HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+           return launch_to_polar(c->spots.N, y_dev, c->buf.y, c->stream);
+         }), "to_polar");
   HIPCHK(c, timed(c, ASH_PROF_ADJOINT, [&] {
            return launch_adjoint(c->basis, c->spots.N, c->buf.pixtab,
-                                 c->buf.spotrec, c->buf.offtab, y_dev,
+                                 c->buf.spotrec, c->buf.offtab, c->buf.y,
                                  c->buf.amp_t, outs, g_dev, phase_out_dev,
                                  nullptr, c->stream);
          }), "adjoint");

@@ -19,16 +19,16 @@ constexpr int kTile = kTileW * kTileH;
 constexpr int kBlock = 256;  // threads per block for the transforms
 constexpr int kWave = 64;
 
-// Nonlinear-mode counts with a compiled kernel; other counts are padded up.
-int pad_nonlinear(int nl);
+// Half of the padded contraction length 2 KH >= 4 + nl (one MFMA per pair).
+int half_k(int nl);
 
 struct Basis {
   int nx = 0, ny = 0;
   double cx = 0, cy = 0, R = 1;
   int D = 0;
   int nl = 0;      // modes with a monomial of total degree >= 2
-  int nl_pad = 0;  // nl rounded up to a compiled kernel
-  int rec = 0;     // floats per pixel record: 2 + nl_pad rounded up to 4
+  int kh = 0;      // half_k(nl): MFMAs per 32x32 block
+  int rec = 0;     // floats per pixel / spot record: 2 kh
   int tiles_x = 0, tiles_y = 0, n_tiles = 0;
   std::vector<int> nl_mode;   // [nl] original mode index of nonlinear slot
   std::vector<double> aff;    // [D][3] coefficient of 1, xh, yh in Z_d
@@ -42,14 +42,14 @@ struct Spots {
 };
 
 struct Buffers {
-  float* pixtab = nullptr;   // [n_tiles][kTile][rec]: di, dj, Rm_0 ...
+  float* pixtab = nullptr;   // [n_tiles][kTile][rec]: 1, di, dj, Rm_s (split)
   float* amp_t = nullptr;    // [n_tiles][kTile]
-  float* field_t = nullptr;  // [n_tiles][kTile][2]
+  float* field_t = nullptr;  // [n_tiles][kTile][2] nearfield (A, phi turns)
   double* tilez = nullptr;   // [n_tiles][nl][3] Z^nl, d/di, d/dj at origins
-  float* spotrec = nullptr;  // [N][rec]: 0, 0, c_0 ... (turns)
+  float* spotrec = nullptr;  // [N][rec]: 0, 0, 0, c_s in turns (split)
   float* offtab = nullptr;   // [n_tiles][N][4] wrapped offset, a, b, 0
   float* target = nullptr;   // [N]
-  float* y = nullptr;        // [N][2]
+  float* y = nullptr;        // [N][2] spot fields (|y|, psi turns)
   float* Ebuf = nullptr;     // [N][2] fields of the last WGS forward
   double* w64 = nullptr;     // [N][D] staged coefficients (radians)
   double* spot64 = nullptr;  // [N][3] FP64 constant, alpha, beta (turns)
@@ -61,13 +61,14 @@ struct Buffers {
 };
 
 struct FwdPlan {
-  int groups = 0;           // tile groups (forward partial rows)
-  int tiles_per_group = 0;
+  int groups = 0;           // pixel-block ranges (forward partial rows)
   int slices = 0;           // second-level reduction rows
   int rows_per_slice = 0;
 };
 
-FwdPlan plan_forward(int n_tiles, int N);
+// Resident forward blocks per CU for a compiled contraction length.
+int forward_blocks_per_cu(int kh);
+FwdPlan plan_forward(int n_tiles, int N, int blocks_per_cu, int n_cu);
 
 // ---- launchers (kernels.hip) ----
 hipError_t launch_build_pixtab(const Basis& b, const int32_t* d_pow,
@@ -81,6 +82,8 @@ hipError_t launch_prep_spots(const Basis& b, int N, const double* d_w,
 hipError_t launch_make_field(const Basis& b, const float* phase,
                              const float* field, const float* amp_t,
                              float* field_t, hipStream_t s);
+hipError_t launch_to_polar(int N, const float* y, float* ypol,
+                           hipStream_t s);
 hipError_t launch_forward(const Basis& b, int N, const FwdPlan& p,
                           const float* pixtab, const float* field_t,
                           const float* spotrec, const float* offtab,
@@ -97,7 +100,7 @@ hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
 enum AdjOut { kOutG = 1, kOutPhase = 2, kOutField = 4 };
 hipError_t launch_adjoint(const Basis& b, int N, const float* pixtab,
                           const float* spotrec, const float* offtab,
-                          const float* y, const float* amp_t, int outs,
+                          const float* ypol, const float* amp_t, int outs,
                           float* g, float* phase, float* field_t,
                           hipStream_t s);
 
@@ -110,6 +113,7 @@ struct ash_prof_rec {
 
 struct ash_ctx {
   int device = 0;
+  int n_cu = 0;
   bool prof_on = false;
   std::vector<ash_prof_rec> prof;    // recorded pairs (in use)
   std::vector<hipEvent_t> prof_pool; // free events

@@ -17,21 +17,38 @@
 // and linear term at the anchor.  Only the small in-tile quantities
 // enter FP32, so the FP32 phase stays within a few tens of turns wherever
 // the kernels respect the Nyquist limit.  The hardware v_sin_f32 and
-// v_cos_f32 take their argument in turns; tau is reduced to [0, 1) first.
+// v_cos_f32 take their argument in turns; phases are reduced to [0, 1)
+// first.
+//
+// Nearfield values and spot fields are kept in polar form (magnitude,
+// phase in turns).  The phase of the multiplier joins the contraction as
+// one more term, so the forward sums A(x) exp(-2 pi i (tau - phi(x))) and
+// the adjoint |y_k| exp(2 pi i (tau + psi_k)), two FMAs per evaluation:
+//
+//   theta = sum_k S[spot][k] X[k][pixel],  k = 0 .. 2 KH - 1, with
+//     k = 0            S: off        X: 1
+//     k = 1, 2         S: a, b       X: di, dj
+//     k = 3 .. 2+nl    S: c_s        X: Rm_s
+//     k = 2 KH - 1     S: -1 | psi   X: phi | 1     (forward | adjoint)
+//   and zeros in between.
 #include <math.h>
 
 #include "internal.h"
 
 namespace ash {
 
-int pad_nonlinear(int nl) {
-  if (nl <= 16) return nl;
-  if (nl <= 20) return 20;
-  if (nl <= 24) return 24;
-  return 28;
+int half_k(int nl) {
+  // anchor offset, two slopes, the non-linear modes and the multiplier phase
+  const int k = 4 + nl;
+  return (k + 1) / 2;
 }
 
-__host__ __device__ constexpr int rec_of(int nl) { return (nl + 2 + 3) & ~3; }
+// Records hold k = 0 .. 2 KH - 1 split by parity: entry (k & 1) KH + k / 2.
+__host__ __device__ constexpr int slot(int k, int kh) {
+  return (k & 1) * kh + (k >> 1);
+}
+
+constexpr float kInv2Pi = 0.15915494309189533577f;
 
 // Anchor of a tile: offsets di in [-32, 31], dj in [-8, 7].
 constexpr int kAnchorI = kTileW / 2;
@@ -90,20 +107,20 @@ __global__ void k_build_pixtab(int nx, int ny, double cx, double cy,
   const int di = pix % kTileW - kAnchorI, dj = pix / kTileW - kAnchorJ;
   const int i = i0 + di, j = j0 + dj;
   const bool valid = i < nx && j < ny;
+  const int kh = rec / 2;
   float* r = pixtab + gid * rec;
-  r[0] = (float)di;
-  r[1] = (float)dj;
+  for (int k = 0; k < rec; ++k) r[k] = 0.0f;
+  r[slot(0, kh)] = 1.0f;
+  r[slot(1, kh)] = (float)di;
+  r[slot(2, kh)] = (float)dj;
+  r[slot(2 * kh - 1, kh)] = 1.0f;  // multiplier phase term (adjoint)
   const double xh = (i - cx) * invR, yh = (j - cy) * invR;
   const double x0 = (i0 - cx) * invR, y0 = (j0 - cy) * invR;
-  for (int s = 0; s < rec - 2; ++s) {
-    double rem = 0.0;
-    if (s < nl && valid) {
-      double v, gx, gy, v0, g0x, g0y;
-      eval_nl(s, n_mono, pw, nlcoef, invR, xh, yh, &v, &gx, &gy);
-      eval_nl(s, n_mono, pw, nlcoef, invR, x0, y0, &v0, &g0x, &g0y);
-      rem = v - v0 - g0x * di - g0y * dj;
-    }
-    r[2 + s] = (float)rem;
+  for (int s = 0; s < nl && valid; ++s) {
+    double v, gx, gy, v0, g0x, g0y;
+    eval_nl(s, n_mono, pw, nlcoef, invR, xh, yh, &v, &gx, &gy);
+    eval_nl(s, n_mono, pw, nlcoef, invR, x0, y0, &v0, &g0x, &g0y);
+    r[slot(3 + s, kh)] = (float)(v - v0 - g0x * di - g0y * dj);
   }
   amp_t[gid] = valid ? (amp ? amp[(long)j * nx + i] : 1.0f) : 0.0f;
 }
@@ -167,11 +184,12 @@ __global__ void k_spot_records(int N, int D, int nl, int rec, double invR,
     a += wd * aff[3 * d + 1];
     bb += wd * aff[3 * d + 2];
   }
+  const int kh = rec / 2;
   float* r = spotrec + (long)k * rec;
-  r[0] = 0.0f;
-  r[1] = 0.0f;
-  for (int s = 0; s < rec - 2; ++s)
-    r[2 + s] = s < nl ? (float)(w[(long)k * D + nlmode[s]] * inv2pi) : 0.0f;
+  for (int e = 0; e < rec; ++e) r[e] = 0.0f;  // slots 0..2: per tile
+  for (int s = 0; s < nl; ++s)
+    r[slot(3 + s, kh)] = (float)(w[(long)k * D + nlmode[s]] * inv2pi);
+  r[slot(2 * kh - 1, kh)] = -1.0f;  // multiplier phase term (forward)
   spot64[3 * (long)k] = o * inv2pi;
   spot64[3 * (long)k + 1] = a * inv2pi * invR;
   spot64[3 * (long)k + 2] = bb * inv2pi * invR;
@@ -222,13 +240,14 @@ hipError_t launch_prep_spots(const Basis& b, int N, const double* d_w,
 }
 
 // ---------------------------------------------------------------------------
-// Nearfield in tile-major order: f = A exp(i phase), or a copied field.
+// Nearfield in tile-major polar form (A, phi in turns) from a phase with the
+// basis amplitude, or from a complex field; spot fields in polar form.
 // ---------------------------------------------------------------------------
 __global__ void k_make_field(int nx, int ny, int tiles_x, long total,
                              const float* __restrict__ phase,
                              const float2* __restrict__ field,
                              const float* __restrict__ amp_t,
-                             float2* __restrict__ field_t) {
+                             float2* __restrict__ nf_t) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= total) return;
   const int tile = (int)(gid / kTile), pix = (int)(gid % kTile);
@@ -238,15 +257,13 @@ __global__ void k_make_field(int nx, int ny, int tiles_x, long total,
   if (i < nx && j < ny) {
     const long p = (long)j * nx + i;
     if (phase) {
-      float sn, cs;
-      sincosf(phase[p], &sn, &cs);
-      const float a = amp_t[gid];
-      v = make_float2(a * cs, a * sn);
+      v = make_float2(amp_t[gid], phase[p] * kInv2Pi);
     } else {
-      v = field[p];
+      const float2 f = field[p];
+      v = make_float2(hypotf(f.x, f.y), atan2f(f.y, f.x) * kInv2Pi);
     }
   }
-  field_t[gid] = v;
+  nf_t[gid] = v;
 }
 
 hipError_t launch_make_field(const Basis& b, const float* phase,
@@ -260,92 +277,214 @@ hipError_t launch_make_field(const Basis& b, const float* phase,
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Forward transform.  One lane per spot, 64 spots per wave; the pixel record
-// and the nearfield value are wave-uniform and come through scalar loads.
-// Each wave walks `tpg` consecutive tiles; per 64 pixels the block sum is
-// added into a Kahan-compensated running total.  Output: partial[g][k].
-// ---------------------------------------------------------------------------
-template <int NL>
-__global__ __launch_bounds__(kBlock) void k_forward(
-    int N, int n_tiles, int tpg, const float* __restrict__ pixtab,
-    const float2* __restrict__ field_t, const float* __restrict__ spotrec,
-    const float4* __restrict__ offtab, float2* __restrict__ partial) {
-  constexpr int E = NL + 2;
-  constexpr int REC = rec_of(NL);
-  const int lane = threadIdx.x & (kWave - 1);
-  const int sg = blockIdx.y * (kBlock / kWave) + (threadIdx.x / kWave);
-  if (sg * kWave >= N) return;  // wave-uniform exit; no barriers below
-  const int k = sg * kWave + lane;
-  const int kc = k < N ? k : N - 1;
-  float c[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) c[e] = spotrec[(long)kc * REC + e];
-  const int g = blockIdx.x;
-  const int t0 = g * tpg;
-  const int t1 = min(t0 + tpg, n_tiles);
-  float sr = 0.0f, si = 0.0f, cr = 0.0f, ci = 0.0f;
-  for (int t = t0; t < t1; ++t) {
-    const float4 ot = offtab[(long)t * N + kc];
-    c[0] = ot.y;  // tile slopes take the di, dj slots of the record
-    c[1] = ot.z;
-    const float off = ot.x;
-    const float* __restrict__ rt = pixtab + (long)t * kTile * REC;
-    const float2* __restrict__ ft = field_t + (long)t * kTile;
-    for (int pb = 0; pb < kTile; pb += 64) {
-      float br = 0.0f, bi = 0.0f;
-#pragma unroll 4
-      for (int p = pb; p < pb + 64; ++p) {
-        const float* __restrict__ r = rt + p * REC;
-        float tau = off;
-#pragma unroll
-        for (int e = 0; e < E; ++e) tau = fmaf(c[e], r[e], tau);
-        tau = __builtin_amdgcn_fractf(tau);
-        const float sn = __builtin_amdgcn_sinf(tau);
-        const float cs = __builtin_amdgcn_cosf(tau);
-        const float2 f = ft[p];
-        // f * exp(-i theta) = (fr c + fi s) + i (fi c - fr s)
-        br = fmaf(f.x, cs, br);
-        br = fmaf(f.y, sn, br);
-        bi = fmaf(f.y, cs, bi);
-        bi = fmaf(-f.x, sn, bi);
-      }
-      kahan_add(sr, cr, br);
-      kahan_add(si, ci, bi);
-    }
-  }
-  if (k < N) partial[(long)g * N + k] = make_float2(sr, si);
+__global__ void k_to_polar(int N, const float2* __restrict__ y,
+                           float2* __restrict__ ypol) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const float2 v = y[k];
+  ypol[k] = make_float2(hypotf(v.x, v.y), atan2f(v.y, v.x) * kInv2Pi);
 }
 
-template <int NL>
-static hipError_t fwd_nl(dim3 grid, hipStream_t s, int N, int n_tiles, int tpg,
-                         const float* pixtab, const float* field_t,
+hipError_t launch_to_polar(int N, const float* y, float* ypol,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_to_polar, dim3((N + 255) / 256), dim3(256), 0, s, N,
+                     reinterpret_cast<const float2*>(y),
+                     reinterpret_cast<float2*>(ypol));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Transforms on the matrix cores.
+//
+// For a block of 32 spots x 32 pixels the phases form the product
+// theta = S X of the spot records S[32][2 KH] and the pixel records
+// X[2 KH][32] (layout at the top of this file), one
+// v_mfma_f32_32x32x2_f32 per pair of k.  Operand lane l carries item l%32
+// and k = 2j + l/32, which is why records are stored split by the parity of
+// k.  Result lane l holds the 16 phases of column n = l%32 and rows
+// m = 8(i/4) + 4(l/32) + i%4, i = 0..15.  The VALU then range-reduces,
+// takes the hardware sine and cosine and multiply-accumulates: the forward
+// keeps 16 spots per lane and sums over pixel columns, the adjoint
+// (theta^T = X^T S^T) keeps 16 pixels per lane and sums over spot columns.
+// At the end a butterfly over the 32 lanes of each half-wave finishes the
+// column sums, leaving one (re, im) result in every pair of lanes.
+// ---------------------------------------------------------------------------
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// One butterfly step over lane bit `mask` (< 32): of the 2*half complex
+// values per lane keep the lower or upper `half` (by the lane's bit) and add
+// the partner's copy of them.
+template <int HALF>
+__device__ __forceinline__ void bfly_step(float* re, float* im, int q,
+                                          int mask) {
+  const bool up = (q & mask) != 0;
+#pragma unroll
+  for (int i = 0; i < HALF; ++i) {
+    const float sr = up ? re[i] : re[i + HALF];
+    const float si = up ? im[i] : im[i + HALF];
+    const float kr = up ? re[i + HALF] : re[i];
+    const float ki = up ? im[i + HALF] : im[i];
+    re[i] = kr + __shfl_xor(sr, mask, kWave);
+    im[i] = ki + __shfl_xor(si, mask, kWave);
+  }
+}
+
+// Sum 16 complex values per lane over the 32 lanes of the half-wave.  On
+// return re[0], im[0] hold the total of value index bfly_index(q).
+__device__ __forceinline__ void bfly_reduce(float* re, float* im, int q) {
+  bfly_step<8>(re, im, q, 16);
+  bfly_step<4>(re, im, q, 8);
+  bfly_step<2>(re, im, q, 4);
+  bfly_step<1>(re, im, q, 2);
+  re[0] += __shfl_xor(re[0], 1, kWave);
+  im[0] += __shfl_xor(im[0], 1, kWave);
+}
+
+__device__ __forceinline__ int bfly_index(int q) {
+  return 8 * ((q >> 4) & 1) + 4 * ((q >> 3) & 1) + 2 * ((q >> 2) & 1) +
+         ((q >> 1) & 1);
+}
+
+// row of the 32x32 result held in value i by a lane of half h
+__device__ __forceinline__ int mfma_row(int i, int h) {
+  return 8 * (i >> 2) + 4 * h + (i & 3);
+}
+
+// Range reduction, hardware sine / cosine and the multiply-accumulate of
+// one 32x32 block of phases (16 per lane) with the lane's magnitude m:
+// sr += m cos(2 pi theta), si += sgn m sin(2 pi theta).
+template <bool kNegSin>
+__device__ __forceinline__ void accumulate(const floatx16& th, float m,
+                                           float* sr, float* si) {
+  const float ms = kNegSin ? -m : m;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const float r = __builtin_amdgcn_fractf(th[i]);
+    sr[i] = fmaf(m, __builtin_amdgcn_cosf(r), sr[i]);
+    si[i] = fmaf(ms, __builtin_amdgcn_sinf(r), si[i]);
+  }
+}
+
+template <int KH>
+__device__ __forceinline__ floatx16 phase_block(const float* a,
+                                                const float* b) {
+  floatx16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+#pragma unroll
+  for (int j = 0; j < KH; ++j) acc = mfma32(a[j], b[j], acc);
+  return acc;
+}
+
+// Forward: wave = 32 spots x a contiguous range of 32-pixel blocks (tile
+// order); the ranges split the pixel blocks of the SLM evenly over the
+// groups.  E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))).
+template <int KH>
+__global__ __launch_bounds__(kBlock) void k_forward(
+    int N, long n_blk, int groups, const float* __restrict__ pixtab,
+    const float2* __restrict__ nf_t, const float* __restrict__ spotrec,
+    const float4* __restrict__ offtab, float2* __restrict__ partial) {
+  constexpr int R2 = 2 * KH;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int h = lane >> 5, q = lane & 31;
+  const int mb = blockIdx.y * (kBlock / kWave) + (threadIdx.x / kWave);
+  if (mb * 32 >= N) return;  // wave-uniform exit; no barriers below
+  const int k = mb * 32 + q;
+  const bool live = k < N;
+  const int kc = live ? k : N - 1;
+  float S[KH];
+#pragma unroll
+  for (int j = 0; j < KH; ++j)
+    S[j] = live ? spotrec[(long)kc * R2 + h * KH + j] : 0.0f;
+  const float s1 = S[1];
+  const int g = blockIdx.x;
+  const long b0 = n_blk * g / groups;
+  const long b1 = n_blk * (g + 1) / groups;
+  float er[16], ei[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) er[i] = ei[i] = 0.0f;
+  long tcur = -1;
+  for (long b = b0; b < b1; ++b) {
+    const long t = b >> 5;  // 32 blocks per tile
+    if (t != tcur) {        // wave-uniform
+      tcur = t;
+      const float4 ot = offtab[t * N + kc];
+      S[0] = live ? (h ? ot.y : ot.x) : 0.0f;
+      S[1] = h ? s1 : (live ? ot.z : 0.0f);
+    }
+    const long px = b * 32 + q;  // tile-major pixel of this lane's column
+    float X[KH];
+    const float* __restrict__ xr = pixtab + px * R2 + h * KH;
+#pragma unroll
+    for (int j = 0; j < KH; ++j) X[j] = xr[j];
+    const float2 nf = nf_t[px];
+    if (h) X[KH - 1] = nf.y;  // k = 2 KH - 1: the nearfield phase
+    const floatx16 th = phase_block<KH>(S, X);
+    accumulate<true>(th, nf.x, er, ei);
+  }
+  bfly_reduce(er, ei, q);
+  const int ko = mb * 32 + mfma_row(bfly_index(q), h);
+  if ((q & 1) == 0 && ko < N)
+    partial[(long)g * N + ko] = make_float2(er[0], ei[0]);
+}
+
+template <int KH>
+static hipError_t fwd_kh(int n_mb, int groups, hipStream_t s, int N,
+                         long n_blk, const float* pixtab, const float* field_t,
                          const float* spotrec, const float* offtab,
                          float* partial) {
-  hipLaunchKernelGGL(k_forward<NL>, grid, dim3(kBlock), 0, s, N, n_tiles, tpg,
-                     pixtab, reinterpret_cast<const float2*>(field_t), spotrec,
-                     reinterpret_cast<const float4*>(offtab),
+  const int waves_per_block = kBlock / kWave;
+  dim3 grid(groups, (n_mb + waves_per_block - 1) / waves_per_block);
+  hipLaunchKernelGGL(k_forward<KH>, grid, dim3(kBlock), 0, s, N, n_blk,
+                     groups, pixtab, reinterpret_cast<const float2*>(field_t),
+                     spotrec, reinterpret_cast<const float4*>(offtab),
                      reinterpret_cast<float2*>(partial));
   return hipGetLastError();
 }
 
-#define ASH_NL_CASES(X) \
-  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) \
-  X(14) X(15) X(16) X(20) X(24) X(28)
+template <int KH>
+static int fwd_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_forward<KH>, kBlock,
+                                                   0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n > 0 ? n : 1;
+}
+
+#define ASH_KH_CASES(X) \
+  X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) \
+  X(15) X(16)
+
+int forward_blocks_per_cu(int kh) {
+  switch (kh) {
+#define X(n) \
+  case n:    \
+    return fwd_blocks_per_cu<n>();
+    ASH_KH_CASES(X)
+#undef X
+    default:
+      return 1;
+  }
+}
 
 hipError_t launch_forward(const Basis& b, int N, const FwdPlan& p,
                           const float* pixtab, const float* field_t,
                           const float* spotrec, const float* offtab,
                           float* partial, hipStream_t s) {
-  const int n_sg = (N + kWave - 1) / kWave;
-  const int waves_per_block = kBlock / kWave;
-  dim3 grid(p.groups, (n_sg + waves_per_block - 1) / waves_per_block);
-  switch (b.nl_pad) {
-#define X(n)                                                                 \
-  case n:                                                                    \
-    return fwd_nl<n>(grid, s, N, b.n_tiles, p.tiles_per_group, pixtab,       \
-                     field_t, spotrec, offtab, partial);
-    ASH_NL_CASES(X)
+  const int n_mb = (N + 31) / 32;
+  const long n_blk = (long)b.n_tiles * (kTile / 32);
+  switch (b.kh) {
+#define X(n)                                                                \
+  case n:                                                                   \
+    return fwd_kh<n>(n_mb, p.groups, s, N, n_blk, pixtab, field_t, spotrec, \
+                     offtab, partial);
+    ASH_KH_CASES(X)
 #undef X
     default:
       return hipErrorInvalidValue;
@@ -485,10 +624,8 @@ __global__ __launch_bounds__(kUpd) void k_wgs_update(
     const float wk = W[k] / mean_w;
     W[k] = wk;
     const float2 e = Ebuf[k];
-    const float a = sqrtf(e.x * e.x + e.y * e.y);
-    const float amp = wk * t[k];
-    y[k] = a > 0.0f ? make_float2(amp * (e.x / a), amp * (e.y / a))
-                    : make_float2(amp, 0.0f);
+    // y = W t E/|E| in polar form (W t, arg E / 2 pi); arg 0 = 0
+    y[k] = make_float2(wk * t[k], atan2f(e.y, e.x) * kInv2Pi);
   }
   if (stats && tid == 0) {
     stats[0] = eff_denom > 0.0f ? sum_a2 / eff_denom : 0.0f;
@@ -512,98 +649,77 @@ hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Adjoint transform.  One block per tile, four pixels per lane; the spot
-// record, y_k and the tile offset are wave-uniform (scalar loads).  Per 64
-// spots the block sum is added into a Kahan-compensated total.  Epilogue:
-// g, arg g, and/or the next nearfield A g/|g| in tile order.
-// ---------------------------------------------------------------------------
-constexpr int kAdjPx = kTile / kBlock;  // 4
+// Adjoint: wave = 32 pixels of one tile x all spots.
+// g(x) = sum_k |y_k| exp(2 pi i (tau_k(x) + psi_k)); the epilogue writes g,
+// arg g and/or the next nearfield (A, arg g / 2 pi) in tile order.
+constexpr int kAdjWavesPerTile = kTile / 32;  // 32
 
-template <int NL>
+template <int KH>
 __global__ __launch_bounds__(kBlock) void k_adjoint(
     int N, int nx, int ny, int tiles_x, const float* __restrict__ pixtab,
     const float* __restrict__ spotrec, const float4* __restrict__ offtab,
-    const float2* __restrict__ y, const float* __restrict__ amp_t, int outs,
-    float2* __restrict__ g, float* __restrict__ phase,
-    float2* __restrict__ field_t) {
-  constexpr int E = NL + 2;
-  constexpr int REC = rec_of(NL);
-  const int tile = blockIdx.x;
-  const int tid = threadIdx.x;
-  float z[kAdjPx][E];
+    const float2* __restrict__ ypol, const float* __restrict__ amp_t,
+    int outs, float2* __restrict__ g, float* __restrict__ phase,
+    float2* __restrict__ nf_t) {
+  constexpr int R2 = 2 * KH;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int h = lane >> 5, q = lane & 31;
+  const int wv = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+  const int tile = wv / kAdjWavesPerTile;
+  const int p0 = (wv % kAdjWavesPerTile) * 32;  // first pixel of the block
+  float X[KH];
+  const float* __restrict__ xr =
+      pixtab + ((long)tile * kTile + p0 + q) * R2 + h * KH;
 #pragma unroll
-  for (int q = 0; q < kAdjPx; ++q) {
-    const float* r = pixtab + ((long)tile * kTile + tid + kBlock * q) * REC;
+  for (int j = 0; j < KH; ++j) X[j] = xr[j];
+  const float4* __restrict__ orow = offtab + (long)tile * N;
+  float gr[16], gi[16];
 #pragma unroll
-    for (int e = 0; e < E; ++e) z[q][e] = r[e];
+  for (int i = 0; i < 16; ++i) gr[i] = gi[i] = 0.0f;
+  for (int n0 = 0; n0 < N; n0 += 32) {
+    const int n = n0 + q;
+    const bool live = n < N;
+    const int nc = live ? n : N - 1;
+    float S[KH];
+    const float* __restrict__ sr = spotrec + (long)nc * R2 + h * KH;
+#pragma unroll
+    for (int j = 0; j < KH; ++j) S[j] = sr[j];
+    const float4 ot = orow[nc];
+    const float2 yp = ypol[nc];
+    S[0] = h ? ot.y : ot.x;
+    if (!h) S[1] = ot.z;
+    if (h) S[KH - 1] = yp.y;  // k = 2 KH - 1: the spot-field phase
+    const floatx16 th = phase_block<KH>(X, S);
+    accumulate<false>(th, live ? yp.x : 0.0f, gr, gi);
   }
-  float gr[kAdjPx], gi[kAdjPx], cr[kAdjPx], ci[kAdjPx];
-#pragma unroll
-  for (int q = 0; q < kAdjPx; ++q) gr[q] = gi[q] = cr[q] = ci[q] = 0.0f;
-  const float4* __restrict__ offrow = offtab + (long)tile * N;
-  for (int k0 = 0; k0 < N; k0 += 64) {
-    const int k1 = min(k0 + 64, N);
-    float br[kAdjPx], bi[kAdjPx];
-#pragma unroll
-    for (int q = 0; q < kAdjPx; ++q) br[q] = bi[q] = 0.0f;
-#pragma unroll 2
-    for (int k = k0; k < k1; ++k) {
-      const float* __restrict__ sr = spotrec + (long)k * REC;
-      const float2 yk = y[k];
-      const float4 ot = offrow[k];
-#pragma unroll
-      for (int q = 0; q < kAdjPx; ++q) {
-        float tau = fmaf(ot.y, z[q][0], ot.x);
-        tau = fmaf(ot.z, z[q][1], tau);
-#pragma unroll
-        for (int e = 2; e < E; ++e) tau = fmaf(sr[e], z[q][e], tau);
-        tau = __builtin_amdgcn_fractf(tau);
-        const float sn = __builtin_amdgcn_sinf(tau);
-        const float cs = __builtin_amdgcn_cosf(tau);
-        // y * exp(+i theta) = (yr c - yi s) + i (yr s + yi c)
-        br[q] = fmaf(yk.x, cs, br[q]);
-        br[q] = fmaf(-yk.y, sn, br[q]);
-        bi[q] = fmaf(yk.x, sn, bi[q]);
-        bi[q] = fmaf(yk.y, cs, bi[q]);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kAdjPx; ++q) {
-      kahan_add(gr[q], cr[q], br[q]);
-      kahan_add(gi[q], ci[q], bi[q]);
-    }
-  }
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
-#pragma unroll
-  for (int q = 0; q < kAdjPx; ++q) {
-    const int pix = tid + kBlock * q;
-    const int i = tx * kTileW + pix % kTileW;
-    const int j = ty * kTileH + pix / kTileW;
-    if (outs & kOutField) {
-      const float a = amp_t[(long)tile * kTile + pix];
-      const float m = hypotf(gr[q], gi[q]);
-      field_t[(long)tile * kTile + pix] =
-          m > 0.0f ? make_float2(a * (gr[q] / m), a * (gi[q] / m))
-                   : make_float2(a, 0.0f);
-    }
-    if (i < nx && j < ny) {
-      const long p = (long)j * nx + i;
-      if (outs & kOutG) g[p] = make_float2(gr[q], gi[q]);
-      if (outs & kOutPhase) phase[p] = atan2f(gi[q], gr[q]);
-    }
+  bfly_reduce(gr, gi, q);
+  if (q & 1) return;  // the pair partner holds the same result
+  const int pix = p0 + mfma_row(bfly_index(q), h);
+  const int i = (tile % tiles_x) * kTileW + pix % kTileW;
+  const int j = (tile / tiles_x) * kTileH + pix / kTileW;
+  const float vr = gr[0], vi = gi[0];
+  const float ang = atan2f(vi, vr);  // atan2(0, 0) = 0
+  if (outs & kOutField)
+    nf_t[(long)tile * kTile + pix] =
+        make_float2(amp_t[(long)tile * kTile + pix], ang * kInv2Pi);
+  if (i < nx && j < ny) {
+    const long p = (long)j * nx + i;
+    if (outs & kOutG) g[p] = make_float2(vr, vi);
+    if (outs & kOutPhase) phase[p] = ang;
   }
 }
 
-template <int NL>
-static hipError_t adj_nl(const Basis& b, int N, const float* pixtab,
+template <int KH>
+static hipError_t adj_kh(const Basis& b, int N, const float* pixtab,
                          const float* spotrec, const float* offtab,
-                         const float* y, const float* amp_t, int outs, float* g,
-                         float* phase, float* field_t, hipStream_t s) {
-  hipLaunchKernelGGL(k_adjoint<NL>, dim3(b.n_tiles), dim3(kBlock), 0, s, N,
-                     b.nx, b.ny, b.tiles_x, pixtab, spotrec,
+                         const float* ypol, const float* amp_t, int outs,
+                         float* g, float* phase, float* field_t,
+                         hipStream_t s) {
+  const int blocks = b.n_tiles * kAdjWavesPerTile / (kBlock / kWave);
+  hipLaunchKernelGGL(k_adjoint<KH>, dim3(blocks), dim3(kBlock), 0, s, N, b.nx,
+                     b.ny, b.tiles_x, pixtab, spotrec,
                      reinterpret_cast<const float4*>(offtab),
-                     reinterpret_cast<const float2*>(y), amp_t, outs,
+                     reinterpret_cast<const float2*>(ypol), amp_t, outs,
                      reinterpret_cast<float2*>(g), phase,
                      reinterpret_cast<float2*>(field_t));
   return hipGetLastError();
@@ -611,30 +727,31 @@ static hipError_t adj_nl(const Basis& b, int N, const float* pixtab,
 
 hipError_t launch_adjoint(const Basis& b, int N, const float* pixtab,
                           const float* spotrec, const float* offtab,
-                          const float* y, const float* amp_t, int outs,
+                          const float* ypol, const float* amp_t, int outs,
                           float* g, float* phase, float* field_t,
                           hipStream_t s) {
-  switch (b.nl_pad) {
-#define X(n)                                                                  \
-  case n:                                                                     \
-    return adj_nl<n>(b, N, pixtab, spotrec, offtab, y, amp_t, outs, g, phase, \
-                     field_t, s);
-    ASH_NL_CASES(X)
+  switch (b.kh) {
+#define X(n)                                                              \
+  case n:                                                                 \
+    return adj_kh<n>(b, N, pixtab, spotrec, offtab, ypol, amp_t, outs, g, \
+                     phase, field_t, s);
+    ASH_KH_CASES(X)
 #undef X
     default:
       return hipErrorInvalidValue;
   }
 }
 
-FwdPlan plan_forward(int n_tiles, int N) {
+FwdPlan plan_forward(int n_tiles, int N, int blocks_per_cu, int n_cu) {
   FwdPlan p;
-  const int n_sg = (N + kWave - 1) / kWave;
-  // about 8192 waves in flight: 8 per SIMD on 256 CUs x 4 SIMDs
-  long want = 8192 / (long)n_sg;
+  const int n_mb = (N + 31) / 32;
+  const long n_blk = (long)n_tiles * (kTile / 32);
+  // one full round of resident waves, each wave a range of pixel blocks
+  const long waves = (long)blocks_per_cu * (kBlock / kWave) * n_cu;
+  long want = waves / n_mb;
   if (want < 1) want = 1;
-  if (want > n_tiles) want = n_tiles;
-  p.tiles_per_group = (int)((n_tiles + want - 1) / want);
-  p.groups = (n_tiles + p.tiles_per_group - 1) / p.tiles_per_group;
+  if (want > n_blk) want = n_blk;
+  p.groups = (int)want;
   p.rows_per_slice = 32;
   p.slices = (p.groups + p.rows_per_slice - 1) / p.rows_per_slice;
   return p;
