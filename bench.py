@@ -137,6 +137,7 @@ def main():
     ctx.set_basis(nx, ny, modes=d["modes"],
                   amp=torch.tensor(d["amp"], dtype=torch.float32, device=dev))
     ctx.set_spots(d["w"], d["t"])
+    info = ctx.info()
     phase = torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
     weights = torch.ones(N, dtype=torch.float32, device=dev)
 
@@ -195,7 +196,7 @@ def main():
         "wgs_iters_per_s": n_iter * args.steps / T,
         "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
         "ms_per_step_without_events": 1e3 * (t3 - t2) / args.steps,
-        "roofline": roofline, "kernels": kernels,
+        "roofline": roofline, "kernels": kernels, "layout": info,
     }
 
     if not args.no_cpu_baseline:

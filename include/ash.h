@@ -26,11 +26,15 @@
  *   - Complex arrays are interleaved (re, im) float pairs (torch complex64).
  *   - Pixel arrays are row-major [ny][nx] float32 (phase, amplitude) or
  *     [ny][nx][2] (complex field).
- *   - Arithmetic: FP32 with the phase kept in turns and range-reduced before
- *     the hardware sine/cosine; per-spot constant and tilt terms are wrapped
- *     per pixel tile in FP64 when spots are set, and the basis table is
- *     evaluated in FP64 and rounded once to FP32.  Sums are blocked and
- *     compensated; results are bitwise deterministic for fixed inputs.
+ *   - Arithmetic: phases in turns, range-reduced before the hardware
+ *     sine/cosine.  Per-spot constant and tilt terms are wrapped per pixel
+ *     tile in FP64 when spots are set, and the basis is evaluated in FP64
+ *     as a small remainder about each tile anchor.  The in-tile phase is a
+ *     dot product evaluated on the matrix cores from exact bf16 pieces of
+ *     these FP64/FP32 values with FP32 accumulation (see
+ *     ash_set_precision); magnitudes and sums are FP32, with compensated
+ *     reductions across the SLM.  Results are bitwise deterministic for
+ *     fixed inputs.
  *
  * Ownership and threading
  *   - Every *_dev pointer is a device pointer owned by the caller, on the
@@ -188,6 +192,31 @@ int ash_adjoint(ash_ctx* ctx, const float* y_dev, float* g_dev,
 int ash_wgs_iterate(ash_ctx* ctx, float* phase_dev, float* weights_dev,
                     int n_iter, const ash_wgs_params* params, float* E_dev,
                     float* stats_dev);
+
+/* Precision of the in-tile remainder terms.  The phase is a sum of
+ * products of bf16 pieces.  ASH_PRECISION_AUTO (default) carries the basis
+ * remainders and their coefficients in 2 pieces (relative error below
+ * 2^-16 of the remainder phase) when, for every tile and spot,
+ * sum_s |c_s| max|Rm_s| <= 1/2 turn, and in 3 pieces (~2^-24) otherwise;
+ * ASH_PRECISION_FULL always uses 3 pieces.  Takes effect at the next
+ * ash_set_spots.  Errors: ASH_EINVAL. */
+#define ASH_PRECISION_AUTO 0
+#define ASH_PRECISION_FULL 1
+int ash_set_precision(ash_ctx* ctx, int mode);
+
+/* Shape of the current set-up, for measurement and tests. */
+typedef struct ash_info {
+  int32_t n_tiles;       /* 32 x 16 pixel tiles                           */
+  int32_t nonlinear;     /* modes with a monomial of degree >= 2          */
+  int32_t pieces;        /* bf16 pieces of remainders / coefficients      */
+  int32_t groups;        /* 16-slot groups = matrix-core ops per 32x32    */
+  int32_t fwd_ranges;    /* pixel-block ranges of the forward transform   */
+  float rm_bound;        /* max over tiles/spots of sum |c_s| max|Rm_s|   */
+  float theta_bound;     /* bound on |phase| (turns) of any spot-pixel pair */
+  int32_t range_reduce;  /* 1: phases reduced to one turn before sin/cos,
+                            0: bound <= 64 turns, the hardware reduces    */
+} ash_info;
+int ash_get_info(const ash_ctx* ctx, ash_info* out);
 
 /* Kernel timing, for measurement.  While enabled, every kernel the context
  * enqueues is bracketed by HIP events on the context's stream.  Categories:

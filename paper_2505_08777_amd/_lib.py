@@ -35,6 +35,18 @@ class WgsParams(ctypes.Structure):
     _fields_ = [("power", ctypes.c_float), ("reserved", ctypes.c_int32)]
 
 
+class Info(ctypes.Structure):
+    _fields_ = [("n_tiles", ctypes.c_int32), ("nonlinear", ctypes.c_int32),
+                ("pieces", ctypes.c_int32), ("groups", ctypes.c_int32),
+                ("fwd_ranges", ctypes.c_int32), ("rm_bound", ctypes.c_float),
+                ("theta_bound", ctypes.c_float),
+                ("range_reduce", ctypes.c_int32)]
+
+
+PRECISION_AUTO = 0
+PRECISION_FULL = 1
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -58,6 +70,8 @@ def _load():
         "ash_forward": (I, [P, P, P, P]),
         "ash_adjoint": (I, [P, P, P, P]),
         "ash_wgs_iterate": (I, [P, P, P, I, ctypes.POINTER(WgsParams), P, P]),
+        "ash_set_precision": (I, [P, I]),
+        "ash_get_info": (I, [P, ctypes.POINTER(Info)]),
         "ash_profile_enable": (I, [P, I]),
         "ash_profile_read": (I, [P, P, P]),
     }

@@ -12,7 +12,7 @@ import math
 import numpy as np
 import torch
 
-from ._lib import lib, check, AshError, WgsParams
+from ._lib import lib, check, AshError, WgsParams, Info, PRECISION_AUTO, PRECISION_FULL
 from .basis import zernike_table
 
 
@@ -80,6 +80,19 @@ class Context:
               "ash_profile_read", self._h)
         names = ("forward", "adjoint", "reduce", "field")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(names)}
+
+    def set_precision(self, full=False):
+        """3 bf16 pieces for every remainder term (full) or the automatic
+        choice; takes effect at the next set_spots."""
+        check(lib.ash_set_precision(self._h, PRECISION_FULL if full
+                                    else PRECISION_AUTO),
+              "ash_set_precision", self._h)
+
+    def info(self):
+        out = Info()
+        check(lib.ash_get_info(self._h, ctypes.byref(out)), "ash_get_info",
+              self._h)
+        return {f: getattr(out, f) for f, _ in Info._fields_}
 
     def sync(self):
         check(lib.ash_sync(self._h), "ash_sync", self._h)

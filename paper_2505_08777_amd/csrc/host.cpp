@@ -125,9 +125,11 @@ void free_spots(ash_ctx* c) {
   dfree(b.Ebuf);
   dfree(b.w64);
   dfree(b.spot64);
+  dfree(b.bound);
   dfree(b.partial);
   dfree(b.red);
-  b.cap_spots = b.cap_w = b.cap_off = b.cap_partial = b.cap_red = 0;
+  b.cap_spots = b.cap_spotrec = b.cap_w = b.cap_off = b.cap_partial =
+      b.cap_red = 0;
   c->has_spots = false;
   c->spots = Spots();
 }
@@ -141,8 +143,43 @@ void free_basis(ash_ctx* c) {
   dfree(b.aff_dev);
   dfree(b.nlmode_dev);
   dfree(b.tilez);
+  dfree(b.rmax);
+  dfree(b.d_pow);
+  dfree(b.d_nlcoef);
+  b.cap_pixtab = 0;
   c->has_basis = false;
   c->basis = Basis();
+}
+
+// (Re)build the pixel table for the geometry's record shape; the tile-order
+// amplitude is written only when `with_amp` (from amp_dev, or 1 if NULL).
+int build_pixtab(ash_ctx* c, const float* amp_dev, bool with_amp) {
+  Buffers& B = c->buf;
+  const Geom& g = c->basis.g;
+  const size_t need = (size_t)g.n_tiles * g.groups * 2 * kTile * 8;
+  if (need > B.cap_pixtab) {
+    dfree(B.pixtab);
+    B.cap_pixtab = 0;
+    int rc = dalloc(c, &B.pixtab, need, "basis table");
+    if (rc) return rc;
+    B.cap_pixtab = need;
+  }
+  HIPCHK(c, launch_build_pixtab(g, B.d_pow, B.d_nlcoef, c->basis.n_mono,
+                                amp_dev, B.pixtab,
+                                with_amp ? B.amp_t : nullptr, c->stream),
+         "building basis table");
+  return ASH_OK;
+}
+
+template <typename T>
+int grow(ash_ctx* c, T** p, size_t* cap, size_t need, const char* what) {
+  if (need <= *cap) return ASH_OK;
+  dfree(*p);
+  *cap = 0;
+  int rc = dalloc(c, p, need, what);
+  if (rc) return rc;
+  *cap = need;
+  return ASH_OK;
 }
 
 // binomial coefficient (exact in double for the degrees allowed)
@@ -158,6 +195,14 @@ double fact(int n) {
   for (int i = 2; i <= n; ++i) r *= i;
   return r;
 }
+
+// Remainder phases below this bound (turns) use 2 bf16 pieces: the dropped
+// piece products stay below 2^-16 of it, 7.6e-6 turns.
+constexpr float kTwoPieceBound = 0.5f;
+
+// Phases bounded by this many turns skip the explicit range reduction: the
+// hardware sine and cosine reduce exactly over |x| <= 256 turns.
+constexpr float kNoReduceBound = 64.0f;
 
 }  // namespace
 
@@ -340,12 +385,14 @@ int ash_set_basis(ash_ctx* c, int nx, int ny, double cx, double cy, double R,
       return fail(c, ASH_EINVAL, "non-finite basis coefficient");
 
   Basis b;
-  b.nx = nx;
-  b.ny = ny;
-  b.cx = cx;
-  b.cy = cy;
-  b.R = R;
-  b.D = D;
+  Geom& g = b.g;
+  g.nx = nx;
+  g.ny = ny;
+  g.cx = cx;
+  g.cy = cy;
+  g.R = R;
+  g.D = D;
+  b.n_mono = n_mono;
   b.aff.assign(3 * D, 0.0);
   std::vector<double> nlcoef;  // [nl][n_mono], affine terms zeroed
   for (int d = 0; d < D; ++d) {
@@ -366,14 +413,14 @@ int ash_set_basis(ash_ctx* c, int nx, int ny, double cx, double cy, double R,
       }
     }
   }
-  b.nl = (int)b.nl_mode.size();
-  if (b.nl > ASH_MAX_NONLINEAR)
+  g.nl = (int)b.nl_mode.size();
+  if (g.nl > ASH_MAX_NONLINEAR)
     return fail(c, ASH_EUNSUPPORTED, "too many non-linear modes");
-  b.kh = half_k(b.nl);
-  b.rec = 2 * b.kh;
-  b.tiles_x = (nx + kTileW - 1) / kTileW;
-  b.tiles_y = (ny + kTileH - 1) / kTileH;
-  b.n_tiles = b.tiles_x * b.tiles_y;
+  g.pieces = 2;
+  g.groups = groups_for(g.nl, g.pieces);
+  g.tiles_x = (nx + kTileW - 1) / kTileW;
+  g.tiles_y = (ny + kTileH - 1) / kTileH;
+  g.n_tiles = g.tiles_x * g.tiles_y;
 
   int rc = use_device(c);
   if (rc) return rc;
@@ -397,49 +444,75 @@ int ash_set_basis(ash_ctx* c, int nx, int ny, double cx, double cy, double R,
   b.amp_sum2 = s2;
 
   free_basis(c);
+  c->basis = b;
   Buffers& B = c->buf;
-  const size_t npix = (size_t)b.n_tiles * kTile;
-  if ((rc = dalloc(c, &B.pixtab, npix * b.rec, "basis table")) ||
-      (rc = dalloc(c, &B.amp_t, npix, "amplitude")) ||
-      (rc = dalloc(c, &B.field_t, 2 * npix, "nearfield")) ||
+  const size_t npix = (size_t)g.n_tiles * kTile;
+  const size_t nl1 = (size_t)std::max(g.nl, 1);
+  if ((rc = dalloc(c, &B.amp_t, npix, "amplitude")) ||
+      (rc = dalloc(c, &B.field_t, 4 * npix, "nearfield")) ||
       (rc = dalloc(c, &B.aff_dev, 3 * (size_t)D, "basis affine terms")) ||
-      (rc = dalloc(c, &B.nlmode_dev, (size_t)std::max(b.nl, 1), "modes")) ||
-      (rc = dalloc(c, &B.tilez, 3 * (size_t)b.n_tiles * std::max(b.nl, 1),
-                   "tile basis"))) {
+      (rc = dalloc(c, &B.nlmode_dev, nl1, "modes")) ||
+      (rc = dalloc(c, &B.tilez, 3 * (size_t)g.n_tiles * nl1, "tile basis")) ||
+      (rc = dalloc(c, &B.rmax, (size_t)g.n_tiles * nl1, "tile bounds")) ||
+      (rc = dalloc(c, &B.d_pow, 2 * (size_t)n_mono, "monomials")) ||
+      (rc = dalloc(c, &B.d_nlcoef, std::max(nlcoef.size(), (size_t)1),
+                   "monomial coefficients"))) {
     free_basis(c);
     return rc;
   }
-  int32_t* d_pow = nullptr;
-  double* d_nl = nullptr;
-  if ((rc = dalloc(c, &d_pow, 2 * (size_t)n_mono, "monomials")) ||
-      (rc = dalloc(c, &d_nl, nlcoef.size(), "monomial coefficients"))) {
-    dfree(d_pow);
-    free_basis(c);
-    return rc;
-  }
-  hipError_t e = hipMemcpyAsync(d_pow, mono_pow, 2 * n_mono * sizeof(int32_t),
+  hipError_t e = hipMemcpyAsync(B.d_pow, mono_pow,
+                                2 * n_mono * sizeof(int32_t),
                                 hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && !nlcoef.empty())
-    e = hipMemcpyAsync(d_nl, nlcoef.data(), nlcoef.size() * sizeof(double),
-                       hipMemcpyHostToDevice, c->stream);
+    e = hipMemcpyAsync(B.d_nlcoef, nlcoef.data(),
+                       nlcoef.size() * sizeof(double), hipMemcpyHostToDevice,
+                       c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(B.aff_dev, b.aff.data(), 3 * D * sizeof(double),
                        hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess && b.nl > 0)
-    e = hipMemcpyAsync(B.nlmode_dev, b.nl_mode.data(), b.nl * sizeof(int),
+  if (e == hipSuccess && g.nl > 0)
+    e = hipMemcpyAsync(B.nlmode_dev, b.nl_mode.data(), g.nl * sizeof(int),
                        hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
-    e = launch_build_pixtab(b, d_pow, d_nl, n_mono, amp_dev, B.pixtab,
-                            B.amp_t, B.tilez, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  dfree(d_pow);
-  dfree(d_nl);
+    e = launch_build_tilebasis(g, B.d_pow, B.d_nlcoef, n_mono, B.tilez,
+                               B.rmax, c->stream);
   if (e != hipSuccess) {
     free_basis(c);
     return hip_fail(c, e, "building basis table");
   }
-  c->basis = b;
+  rc = build_pixtab(c, amp_dev, true);
+  if (rc == ASH_OK) {
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = hip_fail(c, e, "building basis table");
+  }
+  if (rc) {
+    std::string msg = c->err;
+    free_basis(c);
+    c->err = msg;
+    return rc;
+  }
   c->has_basis = true;
+  return ASH_OK;
+}
+
+int ash_set_precision(ash_ctx* c, int mode) {
+  if (!c) return ASH_EINVAL;
+  if (mode != ASH_PRECISION_AUTO && mode != ASH_PRECISION_FULL)
+    return fail(c, ASH_EINVAL, "unknown precision mode");
+  c->precision = mode;
+  return ASH_OK;
+}
+
+int ash_get_info(const ash_ctx* c, ash_info* out) {
+  if (!c || !out) return ASH_EINVAL;
+  out->n_tiles = c->basis.g.n_tiles;
+  out->nonlinear = c->basis.g.nl;
+  out->pieces = c->basis.g.pieces;
+  out->groups = c->basis.g.groups;
+  out->fwd_ranges = c->plan.groups;
+  out->rm_bound = c->spots.rm_bound;
+  out->theta_bound = c->spots.theta_bound;
+  out->range_reduce = c->basis.g.reduce;
   return ASH_OK;
 }
 
@@ -450,8 +523,8 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
   if (!c->has_basis) return fail(c, ASH_ENOTREADY, "set the basis first");
   if (N < 1 || !w_host) return fail(c, ASH_EINVAL, "N >= 1 and w required");
   if (N > ASH_MAX_SPOTS) return fail(c, ASH_EUNSUPPORTED, "too many spots");
-  const Basis& b = c->basis;
-  const size_t nw = (size_t)N * b.D;
+  Geom& g = c->basis.g;
+  const size_t nw = (size_t)N * g.D;
   for (size_t k = 0; k < nw; ++k)
     if (!isfinite(w_host[k]))
       return fail(c, ASH_EINVAL, "non-finite spot coefficient");
@@ -465,85 +538,93 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
   }
   int rc = use_device(c);
   if (rc) return rc;
-  const FwdPlan plan = plan_forward(b.n_tiles, N,
-                                    forward_blocks_per_cu(b.kh), c->n_cu);
+  c->has_spots = false;
   Buffers& B = c->buf;
-  const size_t n_off = (size_t)b.n_tiles * N * 4;
-  const size_t n_part = (size_t)plan.groups * N * 2;
-  const size_t n_red = (size_t)plan.slices * N * 2;
-  // grow-only allocations (state is rebuilt below in any case)
-  if ((size_t)N > B.cap_spots) {
-    dfree(B.spotrec);
+  const size_t n_blk32 = ((size_t)N + 31) / 32;
+  if ((size_t)N > B.cap_spots) {  // per-spot buffers share one capacity
     dfree(B.target);
     dfree(B.y);
     dfree(B.Ebuf);
     dfree(B.spot64);
     B.cap_spots = 0;
-    if ((rc = dalloc(c, &B.spotrec, (size_t)N * b.rec, "spot records")) ||
-        (rc = dalloc(c, &B.target, (size_t)N, "targets")) ||
-        (rc = dalloc(c, &B.y, 2 * (size_t)N, "spot fields")) ||
+    if ((rc = dalloc(c, &B.target, (size_t)N, "targets")) ||
+        (rc = dalloc(c, &B.y, 4 * (size_t)N, "spot fields")) ||
         (rc = dalloc(c, &B.Ebuf, 2 * (size_t)N, "spot fields")) ||
-        (rc = dalloc(c, &B.spot64, 3 * (size_t)N, "spot offsets"))) {
-      free_spots(c);
-      return rc;
-    }
+        (rc = dalloc(c, &B.spot64, 3 * (size_t)N, "spot offsets")))
+      goto fail_alloc;
     B.cap_spots = N;
   }
-  if (nw > B.cap_w) {
-    dfree(B.w64);
-    B.cap_w = 0;
-    if ((rc = dalloc(c, &B.w64, nw, "coefficients"))) {
-      free_spots(c);
-      return rc;
+  if (!B.bound && (rc = dalloc(c, &B.bound, 2, "bound"))) goto fail_alloc;
+  if ((rc = grow(c, &B.w64, &B.cap_w, nw, "coefficients")) ||
+      (rc = grow(c, &B.offtab, &B.cap_off, (size_t)g.n_tiles * 2 * N * 4,
+                 "tile offsets")) ||
+      (rc = grow(c, &B.spotrec, &B.cap_spotrec,
+                 n_blk32 * kMaxGroups * 2 * 32 * 8, "spot records")))
+    goto fail_alloc;
+  {
+    hipError_t e = hipMemcpyAsync(B.w64, w_host, nw * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(B.target, t.data(), N * sizeof(float),
+                         hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(B.bound, 0, 8, c->stream);
+    if (e == hipSuccess)
+      e = launch_prep_spots(g, N, B.w64, B.aff_dev, B.nlmode_dev, B.tilez,
+                            B.rmax, B.spotrec, B.spot64, B.offtab, B.bound,
+                            c->stream);
+    unsigned bound_bits[2] = {0u, 0u};
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(bound_bits, B.bound, 8, hipMemcpyDeviceToHost,
+                         c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "preparing spots");
+    float bound, theta_bound;
+    memcpy(&bound, &bound_bits[0], 4);
+    memcpy(&theta_bound, &bound_bits[1], 4);
+    g.reduce = theta_bound <= kNoReduceBound ? 0 : 1;
+    const int pieces =
+        (c->precision == ASH_PRECISION_AUTO && bound <= kTwoPieceBound) ? 2
+                                                                        : 3;
+    if (pieces != g.pieces) {
+      // a different record shape: rebuild the basis table and the records
+      Geom g2 = g;
+      g2.pieces = pieces;
+      g2.groups = groups_for(g.nl, pieces);
+      if (g2.groups > kMaxGroups)
+        return fail(c, ASH_EUNSUPPORTED, "record too long");
+      const Geom old = g;
+      g = g2;
+      if ((rc = build_pixtab(c, nullptr, false))) {
+        g = old;
+        return rc;
+      }
+      e = launch_prep_spots(g, N, B.w64, B.aff_dev, B.nlmode_dev, B.tilez,
+                            B.rmax, B.spotrec, B.spot64, B.offtab, B.bound,
+                            c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "preparing spots");
     }
-    B.cap_w = nw;
+    c->spots.rm_bound = bound;
+    c->spots.theta_bound = theta_bound;
   }
-  if (n_off > B.cap_off) {
-    dfree(B.offtab);
-    B.cap_off = 0;
-    if ((rc = dalloc(c, &B.offtab, n_off, "tile offsets"))) {
-      free_spots(c);
-      return rc;
-    }
-    B.cap_off = n_off;
-  }
-  if (n_part > B.cap_partial) {
-    dfree(B.partial);
-    B.cap_partial = 0;
-    if ((rc = dalloc(c, &B.partial, n_part, "partial sums"))) {
-      free_spots(c);
-      return rc;
-    }
-    B.cap_partial = n_part;
-  }
-  if (n_red > B.cap_red) {
-    dfree(B.red);
-    B.cap_red = 0;
-    if ((rc = dalloc(c, &B.red, n_red, "partial sums"))) {
-      free_spots(c);
-      return rc;
-    }
-    B.cap_red = n_red;
-  }
-  hipError_t e = hipMemcpyAsync(B.w64, w_host, nw * sizeof(double),
-                                hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(B.target, t.data(), N * sizeof(float),
-                       hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess)
-    e = launch_prep_spots(b, N, B.w64, B.aff_dev, B.nlmode_dev, B.tilez,
-                          B.spotrec, B.offtab, B.spot64, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) {
-    c->has_spots = false;
-    return hip_fail(c, e, "preparing spots");
+  {
+    const FwdPlan plan = plan_forward(g.n_tiles, N,
+                                      forward_blocks_per_cu(g.groups),
+                                      c->n_cu);
+    if ((rc = grow(c, &B.partial, &B.cap_partial,
+                   (size_t)plan.groups * N * 2, "partial sums")) ||
+        (rc = grow(c, &B.red, &B.cap_red, (size_t)plan.slices * N * 2,
+                   "partial sums")))
+      goto fail_alloc;
+    c->plan = plan;
   }
   c->spots.N = N;
-  c->spots.srec = b.rec;
   c->spots.t_norm2 = tn2;
-  c->plan = plan;
   c->has_spots = true;
   return ASH_OK;
+fail_alloc:
+  free_spots(c);
+  return rc;
 }
 
 int ash_forward(ash_ctx* c, const float* phase_dev, const float* field_dev,
@@ -556,15 +637,15 @@ int ash_forward(ash_ctx* c, const float* phase_dev, const float* field_dev,
     return fail(c, ASH_EINVAL, "exactly one of phase/field, and E, required");
   int rc = use_device(c);
   if (rc) return rc;
-  const Basis& b = c->basis;
+  const Geom& g = c->basis.g;
   Buffers& B = c->buf;
   const int N = c->spots.N;
   HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
-           return launch_make_field(b, phase_dev, field_dev, B.amp_t,
+           return launch_make_field(g, phase_dev, field_dev, B.amp_t,
                                     B.field_t, c->stream);
          }), "make_field");
   HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
-           return launch_forward(b, N, c->plan, B.pixtab, B.field_t,
+           return launch_forward(g, N, c->plan, B.pixtab, B.field_t,
                                  B.spotrec, B.offtab, B.partial, c->stream);
          }), "forward");
   HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
@@ -586,15 +667,15 @@ int ash_adjoint(ash_ctx* c, const float* y_dev, float* g_dev,
     return fail(c, ASH_EINVAL, "y and at least one output required");
   int rc = use_device(c);
   if (rc) return rc;
+  Buffers& B = c->buf;
   const int outs = (g_dev ? kOutG : 0) | (phase_out_dev ? kOutPhase : 0);
   HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
-           return launch_to_polar(c->spots.N, y_dev, c->buf.y, c->stream);
+           return launch_to_polar(c->spots.N, y_dev, B.y, c->stream);
          }), "to_polar");
   HIPCHK(c, timed(c, ASH_PROF_ADJOINT, [&] {
-           return launch_adjoint(c->basis, c->spots.N, c->buf.pixtab,
-                                 c->buf.spotrec, c->buf.offtab, c->buf.y,
-                                 c->buf.amp_t, outs, g_dev, phase_out_dev,
-                                 nullptr, c->stream);
+           return launch_adjoint(c->basis.g, c->spots.N, B.pixtab, B.spotrec,
+                                 B.offtab, B.y, B.amp_t, outs, g_dev,
+                                 phase_out_dev, nullptr, c->stream);
          }), "adjoint");
   return ASH_OK;
 }
@@ -613,19 +694,19 @@ int ash_wgs_iterate(ash_ctx* c, float* phase_dev, float* weights_dev,
   if (n_iter == 0) return ASH_OK;
   int rc = use_device(c);
   if (rc) return rc;
-  const Basis& b = c->basis;
+  const Geom& g = c->basis.g;
   Buffers& B = c->buf;
   const int N = c->spots.N;
   const float t_norm = (float)sqrt(c->spots.t_norm2);
-  const float eff_denom = (float)((double)b.nx * b.ny * b.amp_sum2);
+  const float eff_denom = (float)((double)g.nx * g.ny * c->basis.amp_sum2);
   HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
-           return launch_make_field(b, phase_dev, nullptr, B.amp_t,
+           return launch_make_field(g, phase_dev, nullptr, B.amp_t,
                                     B.field_t, c->stream);
          }), "make_field");
   for (int it = 0; it < n_iter; ++it) {
     const bool last = it == n_iter - 1;
     HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
-             return launch_forward(b, N, c->plan, B.pixtab, B.field_t,
+             return launch_forward(g, N, c->plan, B.pixtab, B.field_t,
                                    B.spotrec, B.offtab, B.partial, c->stream);
            }), "forward");
     HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
@@ -638,7 +719,7 @@ int ash_wgs_iterate(ash_ctx* c, float* phase_dev, float* weights_dev,
                  stats_dev ? stats_dev + 4 * (size_t)it : nullptr, c->stream);
            }), "wgs_update");
     HIPCHK(c, timed(c, ASH_PROF_ADJOINT, [&] {
-             return launch_adjoint(b, N, B.pixtab, B.spotrec, B.offtab, B.y,
+             return launch_adjoint(g, N, B.pixtab, B.spotrec, B.offtab, B.y,
                                    B.amp_t, last ? kOutPhase : kOutField,
                                    nullptr, last ? phase_dev : nullptr,
                                    last ? nullptr : B.field_t, c->stream);

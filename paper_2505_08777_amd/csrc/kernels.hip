@@ -14,51 +14,106 @@
 //   tau_k(x) = off[t][k] + a[t][k] di + b[t][k] dj + sum_s c_k,s Rm_s(x)
 //
 // where off (wrapped into [0, 1) in FP64), a and b collect every constant
-// and linear term at the anchor.  Only the small in-tile quantities
-// enter FP32, so the FP32 phase stays within a few tens of turns wherever
-// the kernels respect the Nyquist limit.  The hardware v_sin_f32 and
-// v_cos_f32 take their argument in turns; phases are reduced to [0, 1)
-// first.
+// and linear term at the anchor.  Only the small in-tile quantities enter
+// the single-precision sum, so it stays within a few tens of turns wherever
+// the kernels respect the Nyquist limit.
 //
 // Nearfield values and spot fields are kept in polar form (magnitude,
-// phase in turns).  The phase of the multiplier joins the contraction as
-// one more term, so the forward sums A(x) exp(-2 pi i (tau - phi(x))) and
-// the adjoint |y_k| exp(2 pi i (tau + psi_k)), two FMAs per evaluation:
+// phase in turns); the phase of the multiplier joins the sum, so the
+// forward adds A(x) exp(-2 pi i (tau - phi(x))) and the adjoint
+// |y_k| exp(2 pi i (tau + psi_k)): two FMAs per evaluation after the
+// hardware v_sin_f32 / v_cos_f32 (argument in turns, reduced to [0, 1)).
 //
-//   theta = sum_k S[spot][k] X[k][pixel],  k = 0 .. 2 KH - 1, with
-//     k = 0            S: off        X: 1
-//     k = 1, 2         S: a, b       X: di, dj
-//     k = 3 .. 2+nl    S: c_s        X: Rm_s
-//     k = 2 KH - 1     S: -1 | psi   X: phi | 1     (forward | adjoint)
-//   and zeros in between.
+// The sum is a dot product theta = sum_f S[spot][f] X[f][pixel] over slots
+// f, evaluated on the matrix cores in bf16 with FP32 accumulation.  Every
+// FP32 / FP64 quantity is carried as an exact sum of bf16 pieces
+// (v = v_h + v_m + v_l, each the bf16 rounding of what remains), and each
+// product becomes a few products of pieces:
+//   mode s, 2 pieces:  c_h Rm_h + c_h Rm_m + c_m Rm_h               (3 slots)
+//   mode s, 3 pieces:  + c_h Rm_l + c_l Rm_h + c_m Rm_m              (6 slots)
+//   fixed 12 slots at the end of the last 16-slot group:
+//     p 4..6    S: -1 -1 -1 | psi_h psi_m psi_l   X: phi_h phi_m phi_l | 1 1 1
+//               (forward | adjoint)
+//     p 7..9    S: off_h off_m off_l              X: 1 1 1
+//     p 10..12  S: a_h a_m a_l                    X: di di di
+//     p 13..15  S: b_h b_m b_l                    X: dj dj dj
+// Products of 8-bit-mantissa pieces are exact, so the error is that of the
+// FP32 accumulation plus the dropped piece products: below 2^-16 |c Rm|
+// with 2 pieces (used only while that stays negligible) and ~2^-24
+// otherwise.  One v_mfma_f32_32x32x16_bf16 takes 16 slots.
 #include <math.h>
 
 #include "internal.h"
 
 namespace ash {
 
-int half_k(int nl) {
-  // anchor offset, two slopes, the non-linear modes and the multiplier phase
-  const int k = 4 + nl;
-  return (k + 1) / 2;
-}
-
-// Records hold k = 0 .. 2 KH - 1 split by parity: entry (k & 1) KH + k / 2.
-__host__ __device__ constexpr int slot(int k, int kh) {
-  return (k & 1) * kh + (k >> 1);
-}
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr float kInv2Pi = 0.15915494309189533577f;
+constexpr double kInv2PiD = 0.15915494309189533577;
 
-// Anchor of a tile: offsets di in [-32, 31], dj in [-8, 7].
+// Anchor of a tile: offsets di in [-16, 15], dj in [-8, 7].
 constexpr int kAnchorI = kTileW / 2;
 constexpr int kAnchorJ = kTileH / 2;
 
-__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
-  const float yv = x - c;
-  const float t = s + yv;
-  c = (t - s) - yv;
-  s = t;
+constexpr unsigned kBf16One = 0x3F80u;
+constexpr unsigned kBf16MinusOne = 0xBF80u;
+
+__host__ __device__ int slots_per_mode(int pieces) {
+  return pieces == 2 ? 3 : 6;
+}
+
+int groups_for(int nl, int pieces) {
+  const int f = slots_per_mode(pieces) * nl + 12;
+  return (f + 15) / 16;
+}
+
+// ---------------------------------------------------------------------------
+// bf16 pieces
+// ---------------------------------------------------------------------------
+__device__ inline unsigned bf16_bits(float x) {  // round to nearest even
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+__device__ inline float bf16_val(unsigned b) { return __uint_as_float(b << 16); }
+
+// v = h + m + l + O(2^-27 |v|); each piece is the bf16 rounding of the rest
+__device__ inline void split3(double v, unsigned* p) {
+  p[0] = bf16_bits((float)v);
+  const double r1 = v - (double)bf16_val(p[0]);
+  p[1] = bf16_bits((float)r1);
+  const double r2 = r1 - (double)bf16_val(p[1]);
+  p[2] = bf16_bits((float)r2);
+}
+
+__device__ inline void split3f(float v, unsigned* p) {
+  p[0] = bf16_bits(v);
+  const float r1 = v - bf16_val(p[0]);  // exact (Sterbenz)
+  p[1] = bf16_bits(r1);
+  const float r2 = r1 - bf16_val(p[1]);
+  p[2] = bf16_bits(r2);
+}
+
+// Polar value with its phase in pieces, as one 16-byte record:
+// {magnitude bits, phase_h | phase_m << 16, phase_l | tail << 16, 0}
+__device__ inline u32x4 polar_record(float mag, float turns, unsigned tail) {
+  unsigned p[3];
+  split3f(turns, p);
+  u32x4 r;
+  r[0] = __float_as_uint(mag);
+  r[1] = p[0] | (p[1] << 16);
+  r[2] = p[2] | (tail << 16);
+  r[3] = 0u;
+  return r;
+}
+
+// Slot f of a record of 16-slot groups: group f / 16, lane half (f % 16)/8,
+// entry f % 8.
+__device__ inline void put_slot(unsigned short* rec, int f, unsigned v) {
+  rec[(f / 16) * 16 + ((f % 16) / 8) * 8 + (f % 8)] = (unsigned short)v;
 }
 
 __device__ __forceinline__ double ipow(double x, int p) {
@@ -67,8 +122,15 @@ __device__ __forceinline__ double ipow(double x, int p) {
   return r;
 }
 
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+  const float yv = x - c;
+  const float t = s + yv;
+  c = (t - s) - yv;
+  s = t;
+}
+
 // ---------------------------------------------------------------------------
-// Basis table, FP64 evaluation rounded once to FP32.
+// Basis table (FP64, rounded once into bf16 pieces).
 // ---------------------------------------------------------------------------
 // Value and pixel-index gradient of the non-linear part of slot s at (x, y)
 // (normalised coordinates).
@@ -91,92 +153,159 @@ __device__ void eval_nl(int s, int n_mono, const int32_t* __restrict__ pw,
   *dj = sy * invR;
 }
 
-__global__ void k_build_pixtab(int nx, int ny, double cx, double cy,
-                               double invR, int tiles_x, long total, int rec,
-                               int nl, int n_mono,
+__device__ inline bool pixel_ij(const Geom& b, int tile, int pix, int* i,
+                                int* j) {
+  *i = (tile % b.tiles_x) * kTileW + pix % kTileW;
+  *j = (tile / b.tiles_x) * kTileH + pix / kTileW;
+  return *i < b.nx && *j < b.ny;
+}
+
+// Remainder Rm_s at one pixel of a tile (FP64); 0 outside the SLM.
+__device__ double remainder_at(const Geom& b, int s, int n_mono,
+                               const int32_t* __restrict__ pw,
+                               const double* __restrict__ nlcoef, int tile,
+                               int pix) {
+  int i, j;
+  if (!pixel_ij(b, tile, pix, &i, &j)) return 0.0;
+  const double invR = 1.0 / b.R;
+  const int i0 = (tile % b.tiles_x) * kTileW + kAnchorI;
+  const int j0 = (tile / b.tiles_x) * kTileH + kAnchorJ;
+  double v, gx, gy, v0, g0x, g0y;
+  eval_nl(s, n_mono, pw, nlcoef, invR, (i - b.cx) * invR, (j - b.cy) * invR,
+          &v, &gx, &gy);
+  eval_nl(s, n_mono, pw, nlcoef, invR, (i0 - b.cx) * invR,
+          (j0 - b.cy) * invR, &v0, &g0x, &g0y);
+  return v - v0 - g0x * (i - i0) - g0y * (j - j0);
+}
+
+// One thread per pixel: the pixel's record, scattered as
+// [tile][group][half][pixel][8 bf16] so that lanes read 16 consecutive bytes.
+__global__ void k_build_pixtab(Geom b, long total, int n_mono,
                                const int32_t* __restrict__ pw,
                                const double* __restrict__ nlcoef,
                                const float* __restrict__ amp,
-                               float* __restrict__ pixtab,
+                               unsigned short* __restrict__ pixtab,
                                float* __restrict__ amp_t) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= total) return;
   const int tile = (int)(gid / kTile), pix = (int)(gid % kTile);
-  const int i0 = (tile % tiles_x) * kTileW + kAnchorI;
-  const int j0 = (tile / tiles_x) * kTileH + kAnchorJ;
-  const int di = pix % kTileW - kAnchorI, dj = pix / kTileW - kAnchorJ;
-  const int i = i0 + di, j = j0 + dj;
-  const bool valid = i < nx && j < ny;
-  const int kh = rec / 2;
-  float* r = pixtab + gid * rec;
-  for (int k = 0; k < rec; ++k) r[k] = 0.0f;
-  r[slot(0, kh)] = 1.0f;
-  r[slot(1, kh)] = (float)di;
-  r[slot(2, kh)] = (float)dj;
-  r[slot(2 * kh - 1, kh)] = 1.0f;  // multiplier phase term (adjoint)
-  const double xh = (i - cx) * invR, yh = (j - cy) * invR;
-  const double x0 = (i0 - cx) * invR, y0 = (j0 - cy) * invR;
-  for (int s = 0; s < nl && valid; ++s) {
-    double v, gx, gy, v0, g0x, g0y;
-    eval_nl(s, n_mono, pw, nlcoef, invR, xh, yh, &v, &gx, &gy);
-    eval_nl(s, n_mono, pw, nlcoef, invR, x0, y0, &v0, &g0x, &g0y);
-    r[slot(3 + s, kh)] = (float)(v - v0 - g0x * di - g0y * dj);
+  const int G = b.groups;
+  unsigned short rec[16 * kMaxGroups];
+  for (int e = 0; e < 16 * G; ++e) rec[e] = 0;
+  const int spm = slots_per_mode(b.pieces);
+  for (int s = 0; s < b.nl; ++s) {
+    unsigned p[3];
+    split3(remainder_at(b, s, n_mono, pw, nlcoef, tile, pix), p);
+    const int f = spm * s;  // pixel side of the piece products
+    put_slot(rec, f + 0, p[0]);
+    put_slot(rec, f + 1, p[1]);
+    put_slot(rec, f + 2, p[0]);
+    if (spm == 6) {
+      put_slot(rec, f + 3, p[2]);
+      put_slot(rec, f + 4, p[0]);
+      put_slot(rec, f + 5, p[1]);
+    }
   }
-  amp_t[gid] = valid ? (amp ? amp[(long)j * nx + i] : 1.0f) : 0.0f;
+  const int di = pix % kTileW - kAnchorI, dj = pix / kTileW - kAnchorJ;
+  const int base = 16 * (G - 1);
+  const unsigned bdi = bf16_bits((float)di), bdj = bf16_bits((float)dj);
+  for (int r = 0; r < 3; ++r) {
+    put_slot(rec, base + 4 + r, kBf16One);  // multiplier phase (adjoint)
+    put_slot(rec, base + 7 + r, kBf16One);
+    put_slot(rec, base + 10 + r, bdi);
+    put_slot(rec, base + 13 + r, bdj);
+  }
+  for (int g = 0; g < G; ++g)
+    for (int h = 0; h < 2; ++h) {
+      unsigned short* dst =
+          pixtab + ((((long)tile * G + g) * 2 + h) * kTile + pix) * 8;
+      for (int e = 0; e < 8; ++e) dst[e] = rec[g * 16 + h * 8 + e];
+    }
+  if (amp_t) {
+    int i, j;
+    const bool valid = pixel_ij(b, tile, pix, &i, &j);
+    amp_t[gid] = valid ? (amp ? amp[(long)j * b.nx + i] : 1.0f) : 0.0f;
+  }
 }
 
-// Value and gradient of every non-linear slot at every tile origin (FP64).
-__global__ void k_build_tilebasis(double cx, double cy, double invR,
-                                  int tiles_x, int n_tiles, int nl, int n_mono,
-                                  const int32_t* __restrict__ pw,
-                                  const double* __restrict__ nlcoef,
-                                  double* __restrict__ tilez) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= n_tiles * nl) return;
-  const int tile = gid / nl, s = gid % nl;
-  const double x0 = ((tile % tiles_x) * kTileW + kAnchorI - cx) * invR;
-  const double y0 = ((tile / tiles_x) * kTileH + kAnchorJ - cy) * invR;
-  double v, gx, gy;
-  eval_nl(s, n_mono, pw, nlcoef, invR, x0, y0, &v, &gx, &gy);
-  tilez[3 * (long)gid] = v;
-  tilez[3 * (long)gid + 1] = gx;
-  tilez[3 * (long)gid + 2] = gy;
+// Value and gradient of every non-linear slot at every tile anchor, and the
+// largest |Rm_s| over the tile's pixels (one block of 256 per tile).
+__global__ __launch_bounds__(256) void k_build_tilebasis(
+    Geom b, int n_mono, const int32_t* __restrict__ pw,
+    const double* __restrict__ nlcoef, double* __restrict__ tilez,
+    float* __restrict__ rmax) {
+  __shared__ double sh[256];
+  const int tile = blockIdx.x;
+  const double invR = 1.0 / b.R;
+  const double x0 = ((tile % b.tiles_x) * kTileW + kAnchorI - b.cx) * invR;
+  const double y0 = ((tile / b.tiles_x) * kTileH + kAnchorJ - b.cy) * invR;
+  for (int s = 0; s < b.nl; ++s) {
+    if (threadIdx.x == 0) {
+      double v, gx, gy;
+      eval_nl(s, n_mono, pw, nlcoef, invR, x0, y0, &v, &gx, &gy);
+      tilez[3 * ((long)tile * b.nl + s)] = v;
+      tilez[3 * ((long)tile * b.nl + s) + 1] = gx;
+      tilez[3 * ((long)tile * b.nl + s) + 2] = gy;
+    }
+    double m = 0.0;
+    for (int pix = threadIdx.x; pix < kTile; pix += 256)
+      m = fmax(m, fabs(remainder_at(b, s, n_mono, pw, nlcoef, tile, pix)));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w)
+        sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) rmax[(long)tile * b.nl + s] = (float)sh[0];
+    __syncthreads();
+  }
 }
 
-hipError_t launch_build_pixtab(const Basis& b, const int32_t* d_pow,
+hipError_t launch_build_tilebasis(const Geom& b, const int32_t* d_pow,
+                                  const double* d_nlcoef, int n_mono,
+                                  double* tilez, float* rmax, hipStream_t s) {
+  if (b.nl == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_tilebasis, dim3(b.n_tiles), dim3(256), 0, s, b,
+                     n_mono, d_pow, d_nlcoef, tilez, rmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_pixtab(const Geom& b, const int32_t* d_pow,
                                const double* d_nlcoef, int n_mono,
-                               const float* amp_dev, float* pixtab,
-                               float* amp_t, double* tilez, hipStream_t s) {
+                               const float* amp_dev, unsigned short* pixtab,
+                               float* amp_t, hipStream_t s) {
   const long total = (long)b.n_tiles * kTile;
-  const int threads = 256;
-  const long blocks = (total + threads - 1) / threads;
-  hipLaunchKernelGGL(k_build_pixtab, dim3((unsigned)blocks), dim3(threads), 0,
-                     s, b.nx, b.ny, b.cx, b.cy, 1.0 / b.R, b.tiles_x, total,
-                     b.rec, b.nl, n_mono, d_pow, d_nlcoef, amp_dev, pixtab,
-                     amp_t);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || b.nl == 0) return e;
-  const int nt = b.n_tiles * b.nl;
-  hipLaunchKernelGGL(k_build_tilebasis, dim3((nt + 255) / 256), dim3(256), 0,
-                     s, b.cx, b.cy, 1.0 / b.R, b.tiles_x, b.n_tiles, b.nl,
-                     n_mono, d_pow, d_nlcoef, tilez);
+  hipLaunchKernelGGL(k_build_pixtab, dim3((unsigned)((total + 255) / 256)),
+                     dim3(256), 0, s, b, total, n_mono, d_pow, d_nlcoef,
+                     amp_dev, pixtab, amp_t);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Spot preparation (FP64): per-spot non-linear coefficients in turns, and
-// for every (tile, spot) the wrapped phase and the phase slopes of all
-// constant and linear terms at the tile origin.
+// Spot preparation (FP64): per-spot records of the non-linear coefficients
+// (turns, in pieces), and for every (tile, spot) the wrapped phase and the
+// phase slopes of all constant and linear terms at the tile anchor.
 // ---------------------------------------------------------------------------
-__global__ void k_spot_records(int N, int D, int nl, int rec, double invR,
-                               const double* __restrict__ w,
+__global__ void k_spot_records(Geom b, int N, const double* __restrict__ w,
                                const double* __restrict__ aff,
                                const int* __restrict__ nlmode,
-                               float* __restrict__ spotrec,
+                               unsigned short* __restrict__ spotrec,
                                double* __restrict__ spot64) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= N) return;
-  const double inv2pi = 0.15915494309189533577;
+  const int G = b.groups;
+  const long blk = k / 32, q = k % 32;
+  if (k >= N) {  // padding to a whole spot block: zero records
+    if (k < (N + 31) / 32 * 32)
+      for (int g = 0; g < G; ++g)
+        for (int h = 0; h < 2; ++h) {
+          unsigned short* dst =
+              spotrec + (((blk * G + g) * 2 + h) * 32 + q) * 8;
+          for (int e = 0; e < 8; ++e) dst[e] = 0;
+        }
+    return;
+  }
+  const int D = b.D;
   double o = 0.0, a = 0.0, bb = 0.0;
   for (int d = 0; d < D; ++d) {
     const double wd = w[(long)k * D + d];
@@ -184,112 +313,159 @@ __global__ void k_spot_records(int N, int D, int nl, int rec, double invR,
     a += wd * aff[3 * d + 1];
     bb += wd * aff[3 * d + 2];
   }
-  const int kh = rec / 2;
-  float* r = spotrec + (long)k * rec;
-  for (int e = 0; e < rec; ++e) r[e] = 0.0f;  // slots 0..2: per tile
-  for (int s = 0; s < nl; ++s)
-    r[slot(3 + s, kh)] = (float)(w[(long)k * D + nlmode[s]] * inv2pi);
-  r[slot(2 * kh - 1, kh)] = -1.0f;  // multiplier phase term (forward)
-  spot64[3 * (long)k] = o * inv2pi;
-  spot64[3 * (long)k + 1] = a * inv2pi * invR;
-  spot64[3 * (long)k + 2] = bb * inv2pi * invR;
+  unsigned short rec[16 * kMaxGroups];
+  for (int e = 0; e < 16 * G; ++e) rec[e] = 0;
+  const int spm = slots_per_mode(b.pieces);
+  for (int s = 0; s < b.nl; ++s) {
+    unsigned p[3];
+    split3(w[(long)k * D + nlmode[s]] * kInv2PiD, p);
+    const int f = spm * s;  // spot side of the piece products
+    put_slot(rec, f + 0, p[0]);
+    put_slot(rec, f + 1, p[0]);
+    put_slot(rec, f + 2, p[1]);
+    if (spm == 6) {
+      put_slot(rec, f + 3, p[0]);
+      put_slot(rec, f + 4, p[2]);
+      put_slot(rec, f + 5, p[1]);
+    }
+  }
+  const int base = 16 * (G - 1);
+  for (int r = 0; r < 3; ++r) put_slot(rec, base + 4 + r, kBf16MinusOne);
+  // scatter: [spot block of 32][group][half][32 spots][8]
+  for (int g = 0; g < G; ++g)
+    for (int h = 0; h < 2; ++h) {
+      unsigned short* dst = spotrec + (((blk * G + g) * 2 + h) * 32 + q) * 8;
+      for (int e = 0; e < 8; ++e) dst[e] = rec[g * 16 + h * 8 + e];
+    }
+  spot64[3 * (long)k] = o * kInv2PiD;
+  spot64[3 * (long)k + 1] = a * kInv2PiD / b.R;
+  spot64[3 * (long)k + 2] = bb * kInv2PiD / b.R;
 }
 
-__global__ void k_spot_offsets(int N, int D, int nl, int tiles_x, long total,
-                               double cx, double cy,
+// One thread per (tile, spot).  Output [tile][half][spot][8 bf16]: the last
+// 16-slot group's per-tile slots (p 7 in half 0, p 8..15 in half 1), zero
+// elsewhere, to be OR-ed into the static spot record.  Also the largest
+// bound sum_s |c_s| max|Rm_s| (turns) of the in-tile remainder phase.
+__global__ void k_spot_offsets(Geom b, int N, long total,
                                const double* __restrict__ spot64,
                                const double* __restrict__ w,
                                const int* __restrict__ nlmode,
                                const double* __restrict__ tilez,
-                               float4* __restrict__ offtab) {
+                               const float* __restrict__ rmax,
+                               u32x4* __restrict__ offtab,
+                               unsigned* __restrict__ bound_bits) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= total) return;
   const int tile = (int)(gid / N), k = (int)(gid % N);
-  const double inv2pi = 0.15915494309189533577;
-  const double i0 = (double)((tile % tiles_x) * kTileW + kAnchorI) - cx;
-  const double j0 = (double)((tile / tiles_x) * kTileH + kAnchorJ) - cy;
+  const int nl = b.nl;
+  const double i0 = (double)((tile % b.tiles_x) * kTileW + kAnchorI) - b.cx;
+  const double j0 = (double)((tile / b.tiles_x) * kTileH + kAnchorJ) - b.cy;
   const double al = spot64[3 * (long)k + 1], be = spot64[3 * (long)k + 2];
   double t = spot64[3 * (long)k] + al * i0 + be * j0;
-  double a = al, b = be;
+  double a = al, bs = be, bound = 0.0;
   const double* tz = tilez + 3 * (long)tile * nl;
   for (int s = 0; s < nl; ++s) {
-    const double c = w[(long)k * D + nlmode[s]] * inv2pi;
+    const double c = w[(long)k * b.D + nlmode[s]] * kInv2PiD;
     t += c * tz[3 * s];
     a += c * tz[3 * s + 1];
-    b += c * tz[3 * s + 2];
+    bs += c * tz[3 * s + 2];
+    bound += fabs(c) * (double)rmax[(long)tile * nl + s];
   }
   t -= floor(t);
-  offtab[gid] = make_float4((float)t, (float)a, (float)b, 0.0f);
+  // |theta| over the tile: offset, slopes times the largest distance from
+  // the anchor, remainder, and the two record phases of at most 1/2 each
+  const double mag = 2.0 + kAnchorI * fabs(a) + kAnchorJ * fabs(bs) + bound;
+  unsigned po[3], pa[3], pb[3];
+  split3(t, po);
+  split3(a, pa);
+  split3(bs, pb);
+  u32x4 h0, h1;
+  h0[0] = h0[1] = h0[2] = 0u;
+  h0[3] = po[0] << 16;            // p 7
+  h1[0] = po[1] | (po[2] << 16);  // p 8, 9
+  h1[1] = pa[0] | (pa[1] << 16);  // p 10, 11
+  h1[2] = pa[2] | (pb[0] << 16);  // p 12, 13
+  h1[3] = pb[1] | (pb[2] << 16);  // p 14, 15
+  offtab[((long)tile * 2 + 0) * N + k] = h0;
+  offtab[((long)tile * 2 + 1) * N + k] = h1;
+  // non-negative floats order like their bit patterns
+  atomicMax(bound_bits, __float_as_uint((float)bound));
+  atomicMax(bound_bits + 1, __float_as_uint((float)mag));
 }
 
-hipError_t launch_prep_spots(const Basis& b, int N, const double* d_w,
+hipError_t launch_prep_spots(const Geom& b, int N, const double* d_w,
                              const double* d_aff, const int* d_nlmode,
-                             const double* tilez, float* spotrec,
-                             float* offtab, double* spot64, hipStream_t s) {
-  hipLaunchKernelGGL(k_spot_records, dim3((N + 255) / 256), dim3(256), 0, s,
-                     N, b.D, b.nl, b.rec, 1.0 / b.R, d_w, d_aff, d_nlmode,
-                     spotrec, spot64);
+                             const double* tilez, const float* rmax,
+                             unsigned short* spotrec, double* spot64,
+                             unsigned* offtab, unsigned* bound_bits,
+                             hipStream_t s) {
+  const int n_pad = (N + 31) / 32 * 32;
+  hipLaunchKernelGGL(k_spot_records, dim3((n_pad + 255) / 256), dim3(256), 0,
+                     s, b, N, d_w, d_aff, d_nlmode, spotrec, spot64);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long total = (long)b.n_tiles * N;
   hipLaunchKernelGGL(k_spot_offsets, dim3((unsigned)((total + 255) / 256)),
-                     dim3(256), 0, s, N, b.D, b.nl, b.tiles_x, total, b.cx,
-                     b.cy, spot64, d_w, d_nlmode, tilez,
-                     reinterpret_cast<float4*>(offtab));
+                     dim3(256), 0, s, b, N, total, spot64, d_w, d_nlmode,
+                     tilez, rmax, reinterpret_cast<u32x4*>(offtab),
+                     bound_bits);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Nearfield in tile-major polar form (A, phi in turns) from a phase with the
-// basis amplitude, or from a complex field; spot fields in polar form.
+// Nearfield records in tile order, {A, phase pieces | 1 (p 7)}, from a phase
+// with the basis amplitude or from a complex field; spot-field records
+// {|y|, phase pieces}.
 // ---------------------------------------------------------------------------
-__global__ void k_make_field(int nx, int ny, int tiles_x, long total,
+__global__ void k_make_field(Geom b, long total,
                              const float* __restrict__ phase,
                              const float2* __restrict__ field,
                              const float* __restrict__ amp_t,
-                             float2* __restrict__ nf_t) {
+                             u32x4* __restrict__ nf_t) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= total) return;
   const int tile = (int)(gid / kTile), pix = (int)(gid % kTile);
-  const int i = (tile % tiles_x) * kTileW + pix % kTileW;
-  const int j = (tile / tiles_x) * kTileH + pix / kTileW;
-  float2 v = make_float2(0.0f, 0.0f);
-  if (i < nx && j < ny) {
-    const long p = (long)j * nx + i;
+  int i, j;
+  float mag = 0.0f, turns = 0.0f;
+  if (pixel_ij(b, tile, pix, &i, &j)) {
+    const long p = (long)j * b.nx + i;
     if (phase) {
-      v = make_float2(amp_t[gid], phase[p] * kInv2Pi);
+      mag = amp_t[gid];
+      turns = phase[p] * kInv2Pi;
+      turns -= rintf(turns);  // any phase: reduce to [-1/2, 1/2]
     } else {
       const float2 f = field[p];
-      v = make_float2(hypotf(f.x, f.y), atan2f(f.y, f.x) * kInv2Pi);
+      mag = hypotf(f.x, f.y);
+      turns = atan2f(f.y, f.x) * kInv2Pi;
     }
   }
-  nf_t[gid] = v;
+  nf_t[gid] = polar_record(mag, turns, kBf16One);
 }
 
-hipError_t launch_make_field(const Basis& b, const float* phase,
+hipError_t launch_make_field(const Geom& b, const float* phase,
                              const float* field, const float* amp_t,
-                             float* field_t, hipStream_t s) {
+                             unsigned* nf_t, hipStream_t s) {
   const long total = (long)b.n_tiles * kTile;
   hipLaunchKernelGGL(k_make_field, dim3((unsigned)((total + 255) / 256)),
-                     dim3(256), 0, s, b.nx, b.ny, b.tiles_x, total, phase,
+                     dim3(256), 0, s, b, total, phase,
                      reinterpret_cast<const float2*>(field), amp_t,
-                     reinterpret_cast<float2*>(field_t));
+                     reinterpret_cast<u32x4*>(nf_t));
   return hipGetLastError();
 }
 
 __global__ void k_to_polar(int N, const float2* __restrict__ y,
-                           float2* __restrict__ ypol) {
+                           u32x4* __restrict__ ypol) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
   const float2 v = y[k];
-  ypol[k] = make_float2(hypotf(v.x, v.y), atan2f(v.y, v.x) * kInv2Pi);
+  ypol[k] = polar_record(hypotf(v.x, v.y), atan2f(v.y, v.x) * kInv2Pi, 0u);
 }
 
-hipError_t launch_to_polar(int N, const float* y, float* ypol,
+hipError_t launch_to_polar(int N, const float* y, unsigned* ypol,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_to_polar, dim3((N + 255) / 256), dim3(256), 0, s, N,
                      reinterpret_cast<const float2*>(y),
-                     reinterpret_cast<float2*>(ypol));
+                     reinterpret_cast<u32x4*>(ypol));
   return hipGetLastError();
 }
 
@@ -297,11 +473,10 @@ hipError_t launch_to_polar(int N, const float* y, float* ypol,
 // Transforms on the matrix cores.
 //
 // For a block of 32 spots x 32 pixels the phases form the product
-// theta = S X of the spot records S[32][2 KH] and the pixel records
-// X[2 KH][32] (layout at the top of this file), one
-// v_mfma_f32_32x32x2_f32 per pair of k.  Operand lane l carries item l%32
-// and k = 2j + l/32, which is why records are stored split by the parity of
-// k.  Result lane l holds the 16 phases of column n = l%32 and rows
+// theta = S X of the spot records S[32][16 G] and the pixel records
+// X[16 G][32]: G v_mfma_f32_32x32x16_bf16.  Operand lane l carries item
+// l%32 and slots 8 (l/32) .. 8 (l/32) + 7 of each 16-slot group.  Result
+// lane l holds the 16 phases of column n = l%32 and rows
 // m = 8(i/4) + 4(l/32) + i%4, i = 0..15.  The VALU then range-reduces,
 // takes the hardware sine and cosine and multiply-accumulates: the forward
 // keeps 16 spots per lane and sums over pixel columns, the adjoint
@@ -309,10 +484,21 @@ hipError_t launch_to_polar(int N, const float* y, float* ypol,
 // At the end a butterfly over the 32 lanes of each half-wave finishes the
 // column sums, leaving one (re, im) result in every pair of lanes.
 // ---------------------------------------------------------------------------
-typedef float floatx16 __attribute__((ext_vector_type(16)));
+__device__ __forceinline__ floatx16 mfma_bf16(u32x4 a, u32x4 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+      __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0,
+      0);
+}
 
-__device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+template <int G>
+__device__ __forceinline__ floatx16 phase_block(const u32x4* a,
+                                                const u32x4* b) {
+  floatx16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+#pragma unroll
+  for (int g = 0; g < G; ++g) acc = mfma_bf16(a[g], b[g], acc);
+  return acc;
 }
 
 // One butterfly step over lane bit `mask` (< 32): of the 2*half complex
@@ -356,135 +542,147 @@ __device__ __forceinline__ int mfma_row(int i, int h) {
 
 // Range reduction, hardware sine / cosine and the multiply-accumulate of
 // one 32x32 block of phases (16 per lane) with the lane's magnitude m:
-// sr += m cos(2 pi theta), si += sgn m sin(2 pi theta).
-template <bool kNegSin>
+// sr += m cos(2 pi theta), si += sgn m sin(2 pi theta).  The hardware
+// sine and cosine take turns and reduce exactly by themselves over
+// |theta| <= 256; kReduce = false skips the explicit fract where the host
+// has bounded every phase of the set-up well inside that domain.
+template <bool kNegSin, bool kReduce>
 __device__ __forceinline__ void accumulate(const floatx16& th, float m,
                                            float* sr, float* si) {
   const float ms = kNegSin ? -m : m;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    const float r = __builtin_amdgcn_fractf(th[i]);
+    const float r = kReduce ? __builtin_amdgcn_fractf(th[i]) : th[i];
     sr[i] = fmaf(m, __builtin_amdgcn_cosf(r), sr[i]);
     si[i] = fmaf(ms, __builtin_amdgcn_sinf(r), si[i]);
   }
 }
 
-template <int KH>
-__device__ __forceinline__ floatx16 phase_block(const float* a,
-                                                const float* b) {
-  floatx16 acc;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
-#pragma unroll
-  for (int j = 0; j < KH; ++j) acc = mfma32(a[j], b[j], acc);
-  return acc;
-}
-
 // Forward: wave = 32 spots x a contiguous range of 32-pixel blocks (tile
-// order); the ranges split the pixel blocks of the SLM evenly over the
-// groups.  E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))).
-template <int KH>
+// rows, tile order); the ranges split the pixel blocks of the SLM evenly.
+// Blocks are handed to the XCDs round-robin by linear id; range r belongs
+// to XCD r % 8, and the waves of one XCD enumerate (range, spot block)
+// pairs with the spot block fastest, so all spot blocks of a range run on
+// one XCD at neighbouring slots and its L2 serves the range's records to
+// all of them.  E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))).
+template <int G, bool kReduce>
 __global__ __launch_bounds__(kBlock) void k_forward(
-    int N, long n_blk, int groups, const float* __restrict__ pixtab,
-    const float2* __restrict__ nf_t, const float* __restrict__ spotrec,
-    const float4* __restrict__ offtab, float2* __restrict__ partial) {
-  constexpr int R2 = 2 * KH;
+    int N, long n_blk, int groups, const u32x4* __restrict__ pixtab,
+    const u32x4* __restrict__ nf_t, const u32x4* __restrict__ spotrec,
+    const u32x4* __restrict__ offtab, float2* __restrict__ partial) {
   const int lane = threadIdx.x & (kWave - 1);
   const int h = lane >> 5, q = lane & 31;
-  const int mb = blockIdx.y * (kBlock / kWave) + (threadIdx.x / kWave);
-  if (mb * 32 >= N) return;  // wave-uniform exit; no barriers below
+  const int n_mb = (N + 31) / 32;
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const long v = (long)slot * (kBlock / kWave) + threadIdx.x / kWave;
+  if (v >= (long)(groups / kXcds) * n_mb) return;  // wave-uniform exit
+  const int gi = (int)(v / n_mb) * kXcds + xcd;  // pixel range
+  const int mb = (int)(v % n_mb);                // spot block
   const int k = mb * 32 + q;
-  const bool live = k < N;
-  const int kc = live ? k : N - 1;
-  float S[KH];
+  const int kc = k < N ? k : N - 1;
+  u32x4 S[G];
 #pragma unroll
-  for (int j = 0; j < KH; ++j)
-    S[j] = live ? spotrec[(long)kc * R2 + h * KH + j] : 0.0f;
-  const float s1 = S[1];
-  const int g = blockIdx.x;
-  const long b0 = n_blk * g / groups;
-  const long b1 = n_blk * (g + 1) / groups;
+  for (int g = 0; g < G; ++g)
+    S[g] = spotrec[(((long)mb * G + g) * 2 + h) * 32 + q];
+  const u32x4 s_last = S[G - 1];
+  const long b0 = n_blk * gi / groups;
+  const long b1 = n_blk * (gi + 1) / groups;
   float er[16], ei[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) er[i] = ei[i] = 0.0f;
-  long tcur = -1;
-  for (long b = b0; b < b1; ++b) {
-    const long t = b >> 5;  // 32 blocks per tile
-    if (t != tcur) {        // wave-uniform
-      tcur = t;
-      const float4 ot = offtab[t * N + kc];
-      S[0] = live ? (h ? ot.y : ot.x) : 0.0f;
-      S[1] = h ? s1 : (live ? ot.z : 0.0f);
-    }
-    const long px = b * 32 + q;  // tile-major pixel of this lane's column
-    float X[KH];
-    const float* __restrict__ xr = pixtab + px * R2 + h * KH;
+  // records of pixel block b: pixel pieces, nearfield, tile slots of spot k
+  auto load = [&](long b, u32x4* X, u32x4& nf, u32x4& ot) {
+    const long t = b / kBlkPerTile;
+    const int pix = (int)(b % kBlkPerTile) * 32 + q;
 #pragma unroll
-    for (int j = 0; j < KH; ++j) X[j] = xr[j];
-    const float2 nf = nf_t[px];
-    if (h) X[KH - 1] = nf.y;  // k = 2 KH - 1: the nearfield phase
-    const floatx16 th = phase_block<KH>(S, X);
-    accumulate<true>(th, nf.x, er, ei);
+    for (int g = 0; g < G; ++g)
+      X[g] = pixtab[((t * G + g) * 2 + h) * kTile + pix];
+    nf = nf_t[t * kTile + pix];
+    ot = offtab[(t * 2 + h) * N + kc];
+  };
+  auto block = [&](u32x4* X, const u32x4& nf, const u32x4& ot) {
+    S[G - 1] = s_last | ot;
+    if (!h) {  // p 4..7 of the last group: the nearfield phase and 1
+      X[G - 1][2] = nf[1];
+      X[G - 1][3] = nf[2];
+    }
+    const floatx16 th = phase_block<G>(S, X);
+    accumulate<true, kReduce>(th, __uint_as_float(nf[0]), er, ei);
+  };
+  for (long b = b0; b < b1; ++b) {
+    u32x4 X[G], nf, ot;
+    load(b, X, nf, ot);
+    block(X, nf, ot);
   }
   bfly_reduce(er, ei, q);
   const int ko = mb * 32 + mfma_row(bfly_index(q), h);
   if ((q & 1) == 0 && ko < N)
-    partial[(long)g * N + ko] = make_float2(er[0], ei[0]);
+    partial[(long)gi * N + ko] = make_float2(er[0], ei[0]);
 }
 
-template <int KH>
-static hipError_t fwd_kh(int n_mb, int groups, hipStream_t s, int N,
-                         long n_blk, const float* pixtab, const float* field_t,
-                         const float* spotrec, const float* offtab,
-                         float* partial) {
-  const int waves_per_block = kBlock / kWave;
-  dim3 grid(groups, (n_mb + waves_per_block - 1) / waves_per_block);
-  hipLaunchKernelGGL(k_forward<KH>, grid, dim3(kBlock), 0, s, N, n_blk,
-                     groups, pixtab, reinterpret_cast<const float2*>(field_t),
-                     spotrec, reinterpret_cast<const float4*>(offtab),
+template <int G>
+static hipError_t fwd_g(bool reduce, int n_mb, int groups, hipStream_t s,
+                        int N, long n_blk, const unsigned short* pixtab,
+                        const unsigned* nf_t, const unsigned short* spotrec,
+                        const unsigned* offtab, float* partial) {
+  // groups is a multiple of kXcds (plan_forward); waves per XCD:
+  const long per_xcd = (long)(groups / kXcds) * n_mb;
+  const long blocks_per_xcd = (per_xcd + kBlock / kWave - 1) / (kBlock / kWave);
+  auto* const kern = reduce ? k_forward<G, true> : k_forward<G, false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(blocks_per_xcd * kXcds)),
+                     dim3(kBlock), 0, s, N, n_blk, groups,
+                     reinterpret_cast<const u32x4*>(pixtab),
+                     reinterpret_cast<const u32x4*>(nf_t),
+                     reinterpret_cast<const u32x4*>(spotrec),
+                     reinterpret_cast<const u32x4*>(offtab),
                      reinterpret_cast<float2*>(partial));
   return hipGetLastError();
 }
 
-template <int KH>
+template <int G>
 static int fwd_blocks_per_cu() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_forward<KH>, kBlock,
-                                                   0) != hipSuccess) {
+  // both variants: the plan must fit the larger register footprint
+  int n2 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_forward<G, true>,
+                                                   kBlock, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n2, k_forward<G, false>,
+                                                   kBlock, 0) != hipSuccess) {
     (void)hipGetLastError();
     return 1;
   }
+  n = n < n2 ? n : n2;
   return n > 0 ? n : 1;
 }
 
-#define ASH_KH_CASES(X) \
-  X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) \
-  X(15) X(16)
+#define ASH_G_CASES(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
 
-int forward_blocks_per_cu(int kh) {
-  switch (kh) {
+int forward_blocks_per_cu(int groups) {
+  switch (groups) {
 #define X(n) \
   case n:    \
     return fwd_blocks_per_cu<n>();
-    ASH_KH_CASES(X)
+    ASH_G_CASES(X)
 #undef X
     default:
       return 1;
   }
 }
 
-hipError_t launch_forward(const Basis& b, int N, const FwdPlan& p,
-                          const float* pixtab, const float* field_t,
-                          const float* spotrec, const float* offtab,
-                          float* partial, hipStream_t s) {
+hipError_t launch_forward(const Geom& b, int N, const FwdPlan& p,
+                          const unsigned short* pixtab, const unsigned* nf_t,
+                          const unsigned short* spotrec,
+                          const unsigned* offtab, float* partial,
+                          hipStream_t s) {
   const int n_mb = (N + 31) / 32;
-  const long n_blk = (long)b.n_tiles * (kTile / 32);
-  switch (b.kh) {
-#define X(n)                                                                \
-  case n:                                                                   \
-    return fwd_kh<n>(n_mb, p.groups, s, N, n_blk, pixtab, field_t, spotrec, \
-                     offtab, partial);
-    ASH_KH_CASES(X)
+  const long n_blk = (long)b.n_tiles * kBlkPerTile;
+  switch (b.groups) {
+#define X(n)                                                            \
+  case n:                                                               \
+    return fwd_g<n>(b.reduce != 0, n_mb, p.groups, s, N, n_blk, pixtab, \
+                    nf_t, spotrec, offtab, partial);
+    ASH_G_CASES(X)
 #undef X
     default:
       return hipErrorInvalidValue;
@@ -577,7 +775,7 @@ struct OpMin {
 __global__ __launch_bounds__(kUpd) void k_wgs_update(
     int N, int slices, const float2* __restrict__ red,
     const float* __restrict__ t, float t_norm, float* __restrict__ W,
-    float power, float eff_denom, float2* __restrict__ y,
+    float power, float eff_denom, u32x4* __restrict__ ypol,
     float2* __restrict__ Ebuf, float2* __restrict__ E_extra,
     float* __restrict__ stats) {
   __shared__ float sh[kUpd];
@@ -619,13 +817,13 @@ __global__ __launch_bounds__(kUpd) void k_wgs_update(
   }
   const float var = block_reduce(s_v, sh, OpSum()) / (float)N;
   const float mean_w = block_reduce(s_w, sh, OpSum()) / (float)N;
-  // pass 3: normalise weights, farfield projection y = W t E / |E|
+  // pass 3: normalise weights, farfield projection y = W t E / |E|,
+  // stored in polar form (W t, arg E / 2 pi in pieces); arg 0 = 0
   for (int k = tid; k < N; k += kUpd) {
     const float wk = W[k] / mean_w;
     W[k] = wk;
     const float2 e = Ebuf[k];
-    // y = W t E/|E| in polar form (W t, arg E / 2 pi); arg 0 = 0
-    y[k] = make_float2(wk * t[k], atan2f(e.y, e.x) * kInv2Pi);
+    ypol[k] = polar_record(wk * t[k], atan2f(e.y, e.x) * kInv2Pi, 0u);
   }
   if (stats && tid == 0) {
     stats[0] = eff_denom > 0.0f ? sum_a2 / eff_denom : 0.0f;
@@ -638,59 +836,67 @@ __global__ __launch_bounds__(kUpd) void k_wgs_update(
 
 hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
                              const float* target, float t_norm, float* W,
-                             float power, float eff_denom, float* y,
+                             float power, float eff_denom, unsigned* ypol,
                              float* Ebuf, float* E_extra, float* stats_row,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_wgs_update, dim3(1), dim3(kUpd), 0, s, N, p.slices,
                      reinterpret_cast<const float2*>(red), target, t_norm, W,
-                     power, eff_denom, reinterpret_cast<float2*>(y),
+                     power, eff_denom, reinterpret_cast<u32x4*>(ypol),
                      reinterpret_cast<float2*>(Ebuf),
                      reinterpret_cast<float2*>(E_extra), stats_row);
   return hipGetLastError();
 }
 
-// Adjoint: wave = 32 pixels of one tile x all spots.
+// ---------------------------------------------------------------------------
+// Adjoint: wave = 32 pixels (one tile row) x all spots.
 // g(x) = sum_k |y_k| exp(2 pi i (tau_k(x) + psi_k)); the epilogue writes g,
-// arg g and/or the next nearfield (A, arg g / 2 pi) in tile order.
-constexpr int kAdjWavesPerTile = kTile / 32;  // 32
-
-template <int KH>
+// arg g and/or the next nearfield record in tile order.
+// ---------------------------------------------------------------------------
+template <int G, bool kReduce>
 __global__ __launch_bounds__(kBlock) void k_adjoint(
-    int N, int nx, int ny, int tiles_x, const float* __restrict__ pixtab,
-    const float* __restrict__ spotrec, const float4* __restrict__ offtab,
-    const float2* __restrict__ ypol, const float* __restrict__ amp_t,
+    int N, int nx, int ny, int tiles_x, const u32x4* __restrict__ pixtab,
+    const u32x4* __restrict__ spotrec, const u32x4* __restrict__ offtab,
+    const u32x4* __restrict__ ypol, const float* __restrict__ amp_t,
     int outs, float2* __restrict__ g, float* __restrict__ phase,
-    float2* __restrict__ nf_t) {
-  constexpr int R2 = 2 * KH;
+    u32x4* __restrict__ nf_t) {
   const int lane = threadIdx.x & (kWave - 1);
   const int h = lane >> 5, q = lane & 31;
   const int wv = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
-  const int tile = wv / kAdjWavesPerTile;
-  const int p0 = (wv % kAdjWavesPerTile) * 32;  // first pixel of the block
-  float X[KH];
-  const float* __restrict__ xr =
-      pixtab + ((long)tile * kTile + p0 + q) * R2 + h * KH;
+  const int tile = wv / kBlkPerTile;
+  const int p0 = (wv % kBlkPerTile) * 32;  // first pixel of the block
+  u32x4 X[G];
 #pragma unroll
-  for (int j = 0; j < KH; ++j) X[j] = xr[j];
-  const float4* __restrict__ orow = offtab + (long)tile * N;
+  for (int gg = 0; gg < G; ++gg)
+    X[gg] = pixtab[(((long)tile * G + gg) * 2 + h) * kTile + p0 + q];
+  const u32x4* __restrict__ orow = offtab + ((long)tile * 2 + h) * N;
   float gr[16], gi[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) gr[i] = gi[i] = 0.0f;
-  for (int n0 = 0; n0 < N; n0 += 32) {
-    const int n = n0 + q;
-    const bool live = n < N;
-    const int nc = live ? n : N - 1;
-    float S[KH];
-    const float* __restrict__ sr = spotrec + (long)nc * R2 + h * KH;
+  // records of spot block nb for this lane's spot: pieces, tile slots,
+  // spot field
+  auto load = [&](int nb, u32x4* S, u32x4& ot, u32x4& yp) {
+    const int nc = min(nb * 32 + q, N - 1);
 #pragma unroll
-    for (int j = 0; j < KH; ++j) S[j] = sr[j];
-    const float4 ot = orow[nc];
-    const float2 yp = ypol[nc];
-    S[0] = h ? ot.y : ot.x;
-    if (!h) S[1] = ot.z;
-    if (h) S[KH - 1] = yp.y;  // k = 2 KH - 1: the spot-field phase
-    const floatx16 th = phase_block<KH>(X, S);
-    accumulate<false>(th, live ? yp.x : 0.0f, gr, gi);
+    for (int gg = 0; gg < G; ++gg)
+      S[gg] = spotrec[(((long)nb * G + gg) * 2 + h) * 32 + q];
+    ot = orow[nc];
+    yp = ypol[nc];
+  };
+  auto block = [&](int nb, u32x4* S, const u32x4& ot, const u32x4& yp) {
+    S[G - 1] |= ot;
+    if (!h) {  // p 4..6 of the last group: the spot-field phase
+      S[G - 1][2] = yp[1];
+      S[G - 1][3] = (S[G - 1][3] & 0xFFFF0000u) | yp[2];
+    }
+    const floatx16 th = phase_block<G>(X, S);
+    const bool live = nb * 32 + q < N;
+    accumulate<false, kReduce>(th, live ? __uint_as_float(yp[0]) : 0.0f, gr, gi);
+  };
+  const int NB = (N + 31) / 32;
+  for (int nb = 0; nb < NB; ++nb) {
+    u32x4 S[G], ot, yp;
+    load(nb, S, ot, yp);
+    block(nb, S, ot, yp);
   }
   bfly_reduce(gr, gi, q);
   if (q & 1) return;  // the pair partner holds the same result
@@ -700,8 +906,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
   const float vr = gr[0], vi = gi[0];
   const float ang = atan2f(vi, vr);  // atan2(0, 0) = 0
   if (outs & kOutField)
-    nf_t[(long)tile * kTile + pix] =
-        make_float2(amp_t[(long)tile * kTile + pix], ang * kInv2Pi);
+    nf_t[(long)tile * kTile + pix] = polar_record(
+        amp_t[(long)tile * kTile + pix], ang * kInv2Pi, kBf16One);
   if (i < nx && j < ny) {
     const long p = (long)j * nx + i;
     if (outs & kOutG) g[p] = make_float2(vr, vi);
@@ -709,33 +915,35 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
   }
 }
 
-template <int KH>
-static hipError_t adj_kh(const Basis& b, int N, const float* pixtab,
-                         const float* spotrec, const float* offtab,
-                         const float* ypol, const float* amp_t, int outs,
-                         float* g, float* phase, float* field_t,
-                         hipStream_t s) {
-  const int blocks = b.n_tiles * kAdjWavesPerTile / (kBlock / kWave);
-  hipLaunchKernelGGL(k_adjoint<KH>, dim3(blocks), dim3(kBlock), 0, s, N, b.nx,
-                     b.ny, b.tiles_x, pixtab, spotrec,
-                     reinterpret_cast<const float4*>(offtab),
-                     reinterpret_cast<const float2*>(ypol), amp_t, outs,
+template <int G>
+static hipError_t adj_g(const Geom& b, int N, const unsigned short* pixtab,
+                        const unsigned short* spotrec, const unsigned* offtab,
+                        const unsigned* ypol, const float* amp_t, int outs,
+                        float* g, float* phase, unsigned* nf_t,
+                        hipStream_t s) {
+  const int blocks = b.n_tiles * kBlkPerTile / (kBlock / kWave);
+  auto* const kern = b.reduce ? k_adjoint<G, true> : k_adjoint<G, false>;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, N, b.nx,
+                     b.ny, b.tiles_x, reinterpret_cast<const u32x4*>(pixtab),
+                     reinterpret_cast<const u32x4*>(spotrec),
+                     reinterpret_cast<const u32x4*>(offtab),
+                     reinterpret_cast<const u32x4*>(ypol), amp_t, outs,
                      reinterpret_cast<float2*>(g), phase,
-                     reinterpret_cast<float2*>(field_t));
+                     reinterpret_cast<u32x4*>(nf_t));
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const Basis& b, int N, const float* pixtab,
-                          const float* spotrec, const float* offtab,
-                          const float* ypol, const float* amp_t, int outs,
-                          float* g, float* phase, float* field_t,
-                          hipStream_t s) {
-  switch (b.kh) {
-#define X(n)                                                              \
-  case n:                                                                 \
-    return adj_kh<n>(b, N, pixtab, spotrec, offtab, ypol, amp_t, outs, g, \
-                     phase, field_t, s);
-    ASH_KH_CASES(X)
+hipError_t launch_adjoint(const Geom& b, int N, const unsigned short* pixtab,
+                          const unsigned short* spotrec,
+                          const unsigned* offtab, const unsigned* ypol,
+                          const float* amp_t, int outs, float* g,
+                          float* phase, unsigned* nf_t, hipStream_t s) {
+  switch (b.groups) {
+#define X(n)                                                             \
+  case n:                                                                \
+    return adj_g<n>(b, N, pixtab, spotrec, offtab, ypol, amp_t, outs, g, \
+                    phase, nf_t, s);
+    ASH_G_CASES(X)
 #undef X
     default:
       return hipErrorInvalidValue;
@@ -745,12 +953,13 @@ hipError_t launch_adjoint(const Basis& b, int N, const float* pixtab,
 FwdPlan plan_forward(int n_tiles, int N, int blocks_per_cu, int n_cu) {
   FwdPlan p;
   const int n_mb = (N + 31) / 32;
-  const long n_blk = (long)n_tiles * (kTile / 32);
+  const long n_blk = (long)n_tiles * kBlkPerTile;
   // one full round of resident waves, each wave a range of pixel blocks
   const long waves = (long)blocks_per_cu * (kBlock / kWave) * n_cu;
   long want = waves / n_mb;
-  if (want < 1) want = 1;
   if (want > n_blk) want = n_blk;
+  want = want / kXcds * kXcds;     // whole rounds over the XCDs
+  if (want < kXcds) want = kXcds;  // (empty ranges give zeros)
   p.groups = (int)want;
   p.rows_per_slice = 32;
   p.slices = (p.groups + p.rows_per_slice - 1) / p.rows_per_slice;

@@ -65,13 +65,15 @@ CASES = [
     (200, 120, 130, list(range(15)), 0.8, 100.0),                # 15 modes, 3 waves
     (33, 1, 5, [2, 3, 5], 1.0, 16.5),                            # single row
     (1, 40, 3, [1, 4], 1.0, 20.0),                               # single column
-    (130, 70, 200, list(range(21)), 0.5, 65.0),                  # radial order 5: padded kernel
+    (130, 70, 200, list(range(21)), 0.5, 65.0),                  # radial order 5: 8 groups
+    (512, 512, 300, [1, 2, 3, 4, 5, 6, 7, 8, 9, 12], 0.5, None), # small remainders: 2 pieces
 ]
 
 
+@pytest.mark.parametrize("full", [False, True], ids=["auto", "full"])
 @pytest.mark.parametrize("nx,ny,N,modes,sigma,R", CASES)
-def test_forward_adjoint_parity(A, nx, ny, N, modes, sigma, R):
-    _say("case", nx, ny, N, modes, sigma, R)
+def test_forward_adjoint_parity(A, nx, ny, N, modes, sigma, R, full):
+    _say("case", nx, ny, N, modes, sigma, R, "full" if full else "auto")
     rng = np.random.default_rng(nx * 1000 + ny)
     geom = oracle.Geometry(nx, ny, R=R)
     basis = oracle.ZernikeBasis(modes)
@@ -79,7 +81,18 @@ def test_forward_adjoint_parity(A, nx, ny, N, modes, sigma, R):
     amp = rng.uniform(0.2, 1.0, size=(ny, nx))
     phi = rng.uniform(-np.pi, np.pi, size=(ny, nx))
     y = rng.normal(size=N) + 1j * rng.normal(size=N)
-    c = _ctx(A, nx, ny, modes, w, amp=amp, R=geom.R)
+    c = A.Context(0)
+    c.set_precision(full)
+    c.set_basis(nx, ny, modes=modes, R=geom.R,
+                amp=torch.tensor(amp, dtype=torch.float32, device="cuda"))
+    c.set_spots(w)
+    info = c.info()
+    _say("  info", info)
+    if full:
+        assert info["pieces"] == 3
+    else:
+        assert info["pieces"] == (2 if info["rm_bound"] <= 0.5 else 3)
+    assert info["range_reduce"] == (1 if info["theta_bound"] > 64 else 0)
     amp32 = amp.astype(np.float32).astype(np.float64)
     phi32 = phi.astype(np.float32).astype(np.float64)
     E = c.forward(phase=_cuda(phi32, torch.float32)).cpu().numpy()
@@ -96,6 +109,35 @@ def test_forward_adjoint_parity(A, nx, ny, N, modes, sigma, R):
     f = _cuda((amp32 * np.exp(1j * phi32)).astype(np.complex64), torch.complex64)
     E2 = c.forward(field=f).cpu().numpy()
     assert_fields(E2, Eref, what="forward(field)")
+    c.close()
+
+
+def test_large_phases_take_range_reduction(A):
+    # tilts far beyond the Nyquist field (aliased but a well-defined sum):
+    # phase slopes of several turns per pixel push the phase bound past the
+    # hardware sine's unreduced domain, so the kernels reduce explicitly
+    nx, ny, N, modes = 96, 80, 45, [1, 2, 4, 7]
+    rng = np.random.default_rng(96)
+    geom = oracle.Geometry(nx, ny)
+    basis = oracle.ZernikeBasis(modes)
+    w = _spots(rng, nx, ny, N, modes, 0.7, geom.R)
+    w[:, :2] *= 9.0
+    amp = rng.uniform(0.2, 1.0, size=(ny, nx))
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx)).astype(np.float32)
+    c = _ctx(A, nx, ny, modes, w, amp=amp)
+    info = c.info()
+    _say("  info", info)
+    assert info["range_reduce"] == 1 and info["theta_bound"] > 64
+    amp32 = amp.astype(np.float32).astype(np.float64)
+    E = c.forward(phase=_cuda(phi, torch.float32)).cpu().numpy()
+    Eref = oracle.forward(amp32 * np.exp(1j * phi.astype(np.float64)), w, basis, geom)
+    _say("  forward", field_errors(E, Eref))
+    assert_fields(E, Eref, what="forward")
+    y = (rng.normal(size=N) + 1j * rng.normal(size=N)).astype(np.complex64)
+    g = c.adjoint(_cuda(y, torch.complex64)).cpu().numpy()
+    gref = oracle.adjoint(y.astype(np.complex128), w, basis, geom)
+    _say("  adjoint", field_errors(g, gref))
+    assert_fields(g, gref, what="adjoint")
     c.close()
 
 
