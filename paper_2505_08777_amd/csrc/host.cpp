@@ -540,7 +540,7 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
   if (rc) return rc;
   c->has_spots = false;
   Buffers& B = c->buf;
-  const size_t n_blk32 = ((size_t)N + 31) / 32;
+  const size_t n_blk32 = ((size_t)N + 31) / 32, n_pad = n_blk32 * 32;
   if ((size_t)N > B.cap_spots) {  // per-spot buffers share one capacity
     dfree(B.target);
     dfree(B.y);
@@ -548,7 +548,7 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
     dfree(B.spot64);
     B.cap_spots = 0;
     if ((rc = dalloc(c, &B.target, (size_t)N, "targets")) ||
-        (rc = dalloc(c, &B.y, 4 * (size_t)N, "spot fields")) ||
+        (rc = dalloc(c, &B.y, 8 * n_pad, "spot fields")) ||
         (rc = dalloc(c, &B.Ebuf, 2 * (size_t)N, "spot fields")) ||
         (rc = dalloc(c, &B.spot64, 3 * (size_t)N, "spot offsets")))
       goto fail_alloc;
@@ -556,7 +556,7 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
   }
   if (!B.bound && (rc = dalloc(c, &B.bound, 2, "bound"))) goto fail_alloc;
   if ((rc = grow(c, &B.w64, &B.cap_w, nw, "coefficients")) ||
-      (rc = grow(c, &B.offtab, &B.cap_off, (size_t)g.n_tiles * 2 * N * 4,
+      (rc = grow(c, &B.offtab, &B.cap_off, (size_t)g.n_tiles * 2 * n_pad * 4,
                  "tile offsets")) ||
       (rc = grow(c, &B.spotrec, &B.cap_spotrec,
                  n_blk32 * kMaxGroups * 2 * 32 * 8, "spot records")))
@@ -568,6 +568,9 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
       e = hipMemcpyAsync(B.target, t.data(), N * sizeof(float),
                          hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(B.bound, 0, 8, c->stream);
+    // spot-field records: the padding past N stays zero
+    if (e == hipSuccess)
+      e = hipMemsetAsync(B.y, 0, 8 * n_pad * sizeof(unsigned), c->stream);
     if (e == hipSuccess)
       e = launch_prep_spots(g, N, B.w64, B.aff_dev, B.nlmode_dev, B.tilez,
                             B.rmax, B.spotrec, B.spot64, B.offtab, B.bound,

@@ -68,11 +68,11 @@ struct Buffers {
   int32_t* d_pow = nullptr;          // [n_mono][2]
   double* d_nlcoef = nullptr;        // [nl][n_mono]
   size_t cap_pixtab = 0;             // in unsigned shorts
-  // spots
+  // spots (NP: N padded to whole 32-spot blocks, padding zero)
   unsigned short* spotrec = nullptr;  // [N/32][group][half][32][8] bf16
-  unsigned* offtab = nullptr;         // [n_tiles][half][N][4] per-tile slots
+  unsigned* offtab = nullptr;         // [n_tiles][half][NP][4] per-tile slots
   float* target = nullptr;            // [N]
-  unsigned* y = nullptr;              // [N][4] spot-field records
+  unsigned* y = nullptr;              // [half][NP][4] spot-field records
   float* Ebuf = nullptr;              // [N][2] fields of the last forward
   double* w64 = nullptr;              // [N][D] coefficients (radians)
   double* spot64 = nullptr;           // [N][3] constant, alpha, beta (turns)

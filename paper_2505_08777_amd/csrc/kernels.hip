@@ -110,6 +110,23 @@ __device__ inline u32x4 polar_record(float mag, float turns, unsigned tail) {
   return r;
 }
 
+// Spot-field records of spot k in the two halves of the adjoint's last
+// 16-slot group, [half][NP]: word 0 the magnitude, words 2..3 of half 0
+// the phase pieces at p 4..6, zero elsewhere (OR-ed into the spot record).
+__device__ inline void put_spot_field(u32x4* ypol, int NP, int k, float mag,
+                                      float turns) {
+  unsigned p[3];
+  split3f(turns, p);
+  u32x4 r;
+  r[0] = __float_as_uint(mag);
+  r[1] = 0u;
+  r[2] = p[0] | (p[1] << 16);
+  r[3] = p[2];
+  ypol[k] = r;
+  r[2] = r[3] = 0u;
+  ypol[NP + k] = r;
+}
+
 // Slot f of a record of 16-slot groups: group f / 16, lane half (f % 16)/8,
 // entry f % 8.
 __device__ inline void put_slot(unsigned short* rec, int f, unsigned v) {
@@ -342,7 +359,8 @@ __global__ void k_spot_records(Geom b, int N, const double* __restrict__ w,
   spot64[3 * (long)k + 2] = bb * kInv2PiD / b.R;
 }
 
-// One thread per (tile, spot).  Output [tile][half][spot][8 bf16]: the last
+// One thread per (tile, spot).  Output [tile][half][NP][8 bf16] (spots
+// padded with zero records to NP, a whole number of 32-spot blocks): the last
 // 16-slot group's per-tile slots (p 7 in half 0, p 8..15 in half 1), zero
 // elsewhere, to be OR-ed into the static spot record.  Also the largest
 // bound sum_s |c_s| max|Rm_s| (turns) of the in-tile remainder phase.
@@ -356,7 +374,14 @@ __global__ void k_spot_offsets(Geom b, int N, long total,
                                unsigned* __restrict__ bound_bits) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= total) return;
-  const int tile = (int)(gid / N), k = (int)(gid % N);
+  const int NP = (N + 31) / 32 * 32;  // spots padded to whole blocks
+  const int tile = (int)(gid / NP), k = (int)(gid % NP);
+  if (k >= N) {
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    offtab[((long)tile * 2 + 0) * NP + k] = z;
+    offtab[((long)tile * 2 + 1) * NP + k] = z;
+    return;
+  }
   const int nl = b.nl;
   const double i0 = (double)((tile % b.tiles_x) * kTileW + kAnchorI) - b.cx;
   const double j0 = (double)((tile / b.tiles_x) * kTileH + kAnchorJ) - b.cy;
@@ -386,8 +411,8 @@ __global__ void k_spot_offsets(Geom b, int N, long total,
   h1[1] = pa[0] | (pa[1] << 16);  // p 10, 11
   h1[2] = pa[2] | (pb[0] << 16);  // p 12, 13
   h1[3] = pb[1] | (pb[2] << 16);  // p 14, 15
-  offtab[((long)tile * 2 + 0) * N + k] = h0;
-  offtab[((long)tile * 2 + 1) * N + k] = h1;
+  offtab[((long)tile * 2 + 0) * NP + k] = h0;
+  offtab[((long)tile * 2 + 1) * NP + k] = h1;
   // non-negative floats order like their bit patterns
   atomicMax(bound_bits, __float_as_uint((float)bound));
   atomicMax(bound_bits + 1, __float_as_uint((float)mag));
@@ -404,7 +429,7 @@ hipError_t launch_prep_spots(const Geom& b, int N, const double* d_w,
                      s, b, N, d_w, d_aff, d_nlmode, spotrec, spot64);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const long total = (long)b.n_tiles * N;
+  const long total = (long)b.n_tiles * n_pad;
   hipLaunchKernelGGL(k_spot_offsets, dim3((unsigned)((total + 255) / 256)),
                      dim3(256), 0, s, b, N, total, spot64, d_w, d_nlmode,
                      tilez, rmax, reinterpret_cast<u32x4*>(offtab),
@@ -458,7 +483,8 @@ __global__ void k_to_polar(int N, const float2* __restrict__ y,
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
   const float2 v = y[k];
-  ypol[k] = polar_record(hypotf(v.x, v.y), atan2f(v.y, v.x) * kInv2Pi, 0u);
+  put_spot_field(ypol, (N + 31) / 32 * 32, k, hypotf(v.x, v.y),
+                 atan2f(v.y, v.x) * kInv2Pi);
 }
 
 hipError_t launch_to_polar(int N, const float* y, unsigned* ypol,
@@ -574,12 +600,14 @@ __global__ __launch_bounds__(kBlock) void k_forward(
   const int h = lane >> 5, q = lane & 31;
   const int n_mb = (N + 31) / 32;
   const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
-  const long v = (long)slot * (kBlock / kWave) + threadIdx.x / kWave;
+  // the wave index is uniform over the wave; say so, so that the range
+  // bounds and record addresses live in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const long v = (long)slot * (kBlock / kWave) + wave;
   if (v >= (long)(groups / kXcds) * n_mb) return;  // wave-uniform exit
   const int gi = (int)(v / n_mb) * kXcds + xcd;  // pixel range
   const int mb = (int)(v % n_mb);                // spot block
-  const int k = mb * 32 + q;
-  const int kc = k < N ? k : N - 1;
+  const int NP = n_mb * 32;  // spot stride of the per-tile slot table
   u32x4 S[G];
 #pragma unroll
   for (int g = 0; g < G; ++g)
@@ -590,29 +618,28 @@ __global__ __launch_bounds__(kBlock) void k_forward(
   float er[16], ei[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) er[i] = ei[i] = 0.0f;
-  // records of pixel block b: pixel pieces, nearfield, tile slots of spot k
-  auto load = [&](long b, u32x4* X, u32x4& nf, u32x4& ot) {
+  const u32x4* __restrict__ ot_k = offtab + (long)h * NP + mb * 32 + q;
+  // tiles of the range; the tile slots of the lane's spot once per tile
+  for (long b = b0; b < b1;) {
     const long t = b / kBlkPerTile;
-    const int pix = (int)(b % kBlkPerTile) * 32 + q;
+    const int r0 = (int)(b - t * kBlkPerTile);
+    const int r1 = (int)min((long)kBlkPerTile, r0 + (b1 - b));
+    S[G - 1] = s_last | ot_k[t * 2 * NP];
+    const u32x4* __restrict__ px = pixtab + (t * G * 2 + h) * kTile + q;
+    const u32x4* __restrict__ pn = nf_t + t * kTile + q;
+    for (int r = r0; r < r1; ++r) {
+      u32x4 X[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g)
-      X[g] = pixtab[((t * G + g) * 2 + h) * kTile + pix];
-    nf = nf_t[t * kTile + pix];
-    ot = offtab[(t * 2 + h) * N + kc];
-  };
-  auto block = [&](u32x4* X, const u32x4& nf, const u32x4& ot) {
-    S[G - 1] = s_last | ot;
-    if (!h) {  // p 4..7 of the last group: the nearfield phase and 1
-      X[G - 1][2] = nf[1];
-      X[G - 1][3] = nf[2];
+      for (int g = 0; g < G; ++g) X[g] = px[g * 2 * kTile + r * 32];
+      const u32x4 nf = pn[r * 32];
+      if (!h) {  // p 4..7 of the last group: the nearfield phase and 1
+        X[G - 1][2] = nf[1];
+        X[G - 1][3] = nf[2];
+      }
+      const floatx16 th = phase_block<G>(S, X);
+      accumulate<true, kReduce>(th, __uint_as_float(nf[0]), er, ei);
     }
-    const floatx16 th = phase_block<G>(S, X);
-    accumulate<true, kReduce>(th, __uint_as_float(nf[0]), er, ei);
-  };
-  for (long b = b0; b < b1; ++b) {
-    u32x4 X[G], nf, ot;
-    load(b, X, nf, ot);
-    block(X, nf, ot);
+    b += r1 - r0;
   }
   bfly_reduce(er, ei, q);
   const int ko = mb * 32 + mfma_row(bfly_index(q), h);
@@ -823,7 +850,8 @@ __global__ __launch_bounds__(kUpd) void k_wgs_update(
     const float wk = W[k] / mean_w;
     W[k] = wk;
     const float2 e = Ebuf[k];
-    ypol[k] = polar_record(wk * t[k], atan2f(e.y, e.x) * kInv2Pi, 0u);
+    put_spot_field(ypol, (N + 31) / 32 * 32, k, wk * t[k],
+                   atan2f(e.y, e.x) * kInv2Pi);
   }
   if (stats && tid == 0) {
     stats[0] = eff_denom > 0.0f ? sum_a2 / eff_denom : 0.0f;
@@ -861,42 +889,36 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
     u32x4* __restrict__ nf_t) {
   const int lane = threadIdx.x & (kWave - 1);
   const int h = lane >> 5, q = lane & 31;
-  const int wv = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+  const int wv = blockIdx.x * (kBlock / kWave) +
+                 __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int tile = wv / kBlkPerTile;
   const int p0 = (wv % kBlkPerTile) * 32;  // first pixel of the block
   u32x4 X[G];
 #pragma unroll
   for (int gg = 0; gg < G; ++gg)
     X[gg] = pixtab[(((long)tile * G + gg) * 2 + h) * kTile + p0 + q];
-  const u32x4* __restrict__ orow = offtab + ((long)tile * 2 + h) * N;
+  const int NB = (N + 31) / 32, NP = NB * 32;
+  // per spot block: the lane's spot record, tile slots and spot field;
+  // spot tables are padded to whole blocks with zero records
+  const u32x4* __restrict__ sp = spotrec + h * 32 + q;
+  const u32x4* __restrict__ ot_t = offtab + ((long)tile * 2 + h) * NP + q;
+  const u32x4* __restrict__ yq = ypol + (long)h * NP + q;
   float gr[16], gi[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) gr[i] = gi[i] = 0.0f;
-  // records of spot block nb for this lane's spot: pieces, tile slots,
-  // spot field
-  auto load = [&](int nb, u32x4* S, u32x4& ot, u32x4& yp) {
-    const int nc = min(nb * 32 + q, N - 1);
-#pragma unroll
-    for (int gg = 0; gg < G; ++gg)
-      S[gg] = spotrec[(((long)nb * G + gg) * 2 + h) * 32 + q];
-    ot = orow[nc];
-    yp = ypol[nc];
-  };
-  auto block = [&](int nb, u32x4* S, const u32x4& ot, const u32x4& yp) {
-    S[G - 1] |= ot;
-    if (!h) {  // p 4..6 of the last group: the spot-field phase
-      S[G - 1][2] = yp[1];
-      S[G - 1][3] = (S[G - 1][3] & 0xFFFF0000u) | yp[2];
-    }
-    const floatx16 th = phase_block<G>(X, S);
-    const bool live = nb * 32 + q < N;
-    accumulate<false, kReduce>(th, live ? __uint_as_float(yp[0]) : 0.0f, gr, gi);
-  };
-  const int NB = (N + 31) / 32;
   for (int nb = 0; nb < NB; ++nb) {
-    u32x4 S[G], ot, yp;
-    load(nb, S, ot, yp);
-    block(nb, S, ot, yp);
+    u32x4 S[G];
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) S[gg] = sp[((long)nb * G + gg) * 64];
+    const u32x4 ot = ot_t[nb * 32], yp = yq[nb * 32];
+    // last group: tile slots, and the spot-field phase at p 4..6 (half 0;
+    // these replace the static forward entries there)
+    S[G - 1][0] |= ot[0];
+    S[G - 1][1] |= ot[1];
+    S[G - 1][2] = ot[2] | yp[2];
+    S[G - 1][3] = ot[3] | yp[3];
+    const floatx16 th = phase_block<G>(X, S);
+    accumulate<false, kReduce>(th, __uint_as_float(yp[0]), gr, gi);
   }
   bfly_reduce(gr, gi, q);
   if (q & 1) return;  // the pair partner holds the same result
