@@ -16,6 +16,7 @@ the same workload on the host cores (with the GPU's error against it).
 """
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -64,6 +65,27 @@ def calibrate_copy(mib):
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}),
           flush=True)
+
+
+def profiled_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
+    of this workload (FETCH_SIZE and WRITE_SIZE, scaled by what they read
+    for a plain copy), or None when the summary was taken on other kernel
+    source than the one built here."""
+    path = os.path.join(ROOT, "profiles", "wgs_kernels_%s.txt" % workload)
+    src = os.path.join(ROOT, "paper_2505_08777_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None, None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    rec, val = None, None
+    for line in open(path):
+        if line.startswith("kernels_hip_sha256:"):
+            rec = line.split(":", 1)[1].strip()
+        if line.startswith("traffic_bytes_per_launch[%s]:" % kernel):
+            val = float(line.split(":", 1)[1].split()[0])
+    if rec != sha or val is None:
+        return None, os.path.relpath(path, ROOT)
+    return val, os.path.relpath(path, ROOT)
 
 
 def cpu_baseline(ctx, d, pix_sample):
@@ -175,10 +197,14 @@ def main():
     dom = max(("forward", "adjoint"), key=lambda k: prof[k][0])
     ms_avg = prof[dom][0] / max(prof[dom][1], 1)
     achieved = N * P * F / (ms_avg * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_%s" % dom,
+    kname = "k_%s<%d, %s>" % (dom, info["groups"],
+                              "true" if info["range_reduce"] else "false")
+    traffic, traffic_src = profiled_traffic(args.workload, kname)
+    roofline = {"bound": "alu", "kernel": kname,
                 "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                "traffic": None,
+                "traffic": traffic, "traffic_unit": "bytes/launch",
+                "traffic_source": traffic_src,
                 "avg_launch_ms": ms_avg, "launches": prof[dom][1],
                 "flops_per_eval": F, "evals_per_launch": N * P}
     kernels = {k: {"total_ms": v[0], "launches": v[1],

@@ -876,7 +876,8 @@ hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint: wave = 32 pixels (one tile row) x all spots.
+// Adjoint: wave = 32 pixels (one tile row) x all spots; the four waves of a
+// block are four rows of one tile.
 // g(x) = sum_k |y_k| exp(2 pi i (tau_k(x) + psi_k)); the epilogue writes g,
 // arg g and/or the next nearfield record in tile order.
 // ---------------------------------------------------------------------------
@@ -889,7 +890,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
     u32x4* __restrict__ nf_t) {
   const int lane = threadIdx.x & (kWave - 1);
   const int h = lane >> 5, q = lane & 31;
-  const int wv = blockIdx.x * (kBlock / kWave) +
+  // blocks reach the XCDs round-robin; give each XCD a contiguous run of
+  // blocks in tile order so that the blocks of one tile share its L2
+  const int nblk = gridDim.x, per = nblk / kXcds, extra = nblk % kXcds;
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const int lin = xcd * per + min(xcd, extra) + slot;
+  const int wv = lin * (kBlock / kWave) +
                  __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int tile = wv / kBlkPerTile;
   const int p0 = (wv % kBlkPerTile) * 32;  // first pixel of the block
