@@ -17,8 +17,9 @@ transform  compressed forward and adjoint transforms F_c, F_c^{-1} with
 wgs        one weighted Gerchberg-Saxton step ("A Full-Field 2D Tweezer
            Array", the WGS paragraph; the weighting is a stated reading).
 grad       spot-amplitude loss with phase-gradient TV, its analytic phase
-           gradient and central finite differences (Methods, "Computational
-           Scaling", gradient-descent paragraph).
+           gradient, central finite differences and the Adam update of the
+           phase (Methods, "Computational Scaling", gradient-descent
+           paragraph; Adam as published by Kingma and Ba).
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_pins.py`` except the multi-step WGS trajectory, whose
@@ -30,11 +31,11 @@ from .zernike import (ansi_to_nm, nm_to_ansi, noll_to_nm, noll_to_ansi,
 from .transform import Geometry, kernel_phase, forward, adjoint
 from .wgs import wgs_step, wgs_run, wgs_stats
 from .grad import (spot_norm, spot_loss, tv_loss, total_loss, loss_grad,
-                   fd_grad)
+                   fd_grad, adam_step, adam_run)
 
 __all__ = [
     "ansi_to_nm", "nm_to_ansi", "noll_to_nm", "noll_to_ansi", "zernike_nm",
     "ZernikeBasis", "MonomialBasis", "Geometry", "kernel_phase", "forward",
     "adjoint", "wgs_step", "wgs_run", "wgs_stats", "spot_norm", "spot_loss",
-    "tv_loss", "total_loss", "loss_grad", "fd_grad",
+    "tv_loss", "total_loss", "loss_grad", "fd_grad", "adam_step", "adam_run",
 ]

@@ -147,3 +147,40 @@ def fd_grad(phi, pixels, amp, t, w, basis, geom, h=1e-4, lam=1e-3,
         (lp, dtp), (lm, dtm) = vals
         out[q] = ((lp - lm) + lam * (dtp - dtm) / P) / (2 * h)
     return out
+
+
+def adam_step(phi, grad, m, v, step, lr=0.05, beta1=0.9, beta2=0.999,
+              eps=1e-8):
+    """One Adam update (Kingma and Ba, 2015) of the phase.
+
+    ``step`` is the 1-based index of this update.  The moment estimates are
+    exponential averages of the gradient and of its square; each is divided
+    by one minus its decay rate to the power ``step`` to remove the bias of
+    the zero start, and the phase moves by lr * m_hat / (sqrt(v_hat) + eps).
+    Returns (phi, m, v), new arrays.
+    """
+    g = np.asarray(grad, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    phi = np.asarray(phi, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return phi, m, v
+
+
+def adam_run(phi, amp, t, w, basis, geom, n_steps, lr=0.05, betas=(0.9, 0.999),
+             eps=1e-8, lam=1e-3, tv_eps=1e-3, workers=None):
+    """n_steps Adam updates of L from phi with zero moments.
+
+    Returns (phi, m, v, losses) with losses[s] = L at the phase before
+    update s + 1."""
+    phi = np.asarray(phi, dtype=np.float64)
+    m = np.zeros_like(phi)
+    v = np.zeros_like(phi)
+    losses = []
+    for s in range(1, n_steps + 1):
+        g, L, _ = loss_grad(phi, amp, t, w, basis, geom, lam=lam, eps=tv_eps,
+                            workers=workers)
+        losses.append(L)
+        phi, m, v = adam_step(phi, g, m, v, s, lr, betas[0], betas[1], eps)
+    return phi, m, v, np.array(losses)
