@@ -44,7 +44,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="field1024",
-                    choices=["plain256", "field1024", "volume1920"])
+                    choices=["plain256", "field1024", "volume1920",
+                             "grad1024"],
+                    help="grad1024 times the differentiable form: Adam steps "
+                         "of the spot-amplitude loss with TV")
     ap.add_argument("--iters", type=int, default=None,
                     help="WGS iterations per step (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -134,6 +137,86 @@ def cpu_baseline(ctx, d, pix_sample):
     return obj, parity
 
 
+def bench_adam(args, d):
+    """Adam descent of the 1024 x 1024, 1000-spot loss: a step is the
+    workload's Adam updates (forward, loss, adjoint with the phase gradient
+    and TV, update), timed like the WGS loop."""
+    import numpy as np
+    import torch
+    import paper_2505_08777_amd as A
+
+    n_steps = args.iters or d["n_iter"]
+    nx, ny = d["nx"], d["ny"]
+    N, D = d["w"].shape
+    P = nx * ny
+    dev = torch.device("cuda:0")
+    ctx = A.Context(0)
+    ctx.set_basis(nx, ny, modes=d["modes"],
+                  amp=torch.tensor(d["amp"], dtype=torch.float32, device=dev))
+    ctx.set_spots(d["w"], d["t"])
+    info = ctx.info()
+    phi0 = torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
+    kw = dict(lr=d["lr"], betas=d["betas"], eps=d["adam_eps"],
+              tv_weight=d["lam"], tv_eps=d["tv_eps"])
+
+    def run():
+        ph = phi0.clone()
+        return ctx.adam(ph, n_steps, **kw)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, _, loss, _ = run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    T = t1 - t0
+    F = flops_per_eval(D)
+    value = 2.0 * N * P * n_steps * args.steps / T
+    dom = max(("forward", "adjoint"), key=lambda k: prof[k][0])
+    ms_avg = prof[dom][0] / max(prof[dom][1], 1)
+    achieved = N * P * F / (ms_avg * 1e-3) / 1e12
+    kname = "k_%s<%d, %s>" % (dom, info["groups"],
+                              "true" if info["range_reduce"] else "false")
+    traffic, traffic_src = profiled_traffic(args.workload, kname)
+    L = loss.cpu().numpy()
+    out = {
+        "metric": METRIC, "value": value, "unit": "evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "grad1024", "slm": "%dx%d" % (nx, ny),
+                   "spots": N, "modes": D, "adam_steps_per_step": n_steps},
+        "adam_steps_per_s": n_steps * args.steps / T,
+        "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic, "traffic_unit": "bytes/launch",
+                     "traffic_source": traffic_src, "avg_launch_ms": ms_avg,
+                     "launches": prof[dom][1], "flops_per_eval": F,
+                     "evals_per_launch": N * P},
+        "kernels": {k: {"total_ms": v[0], "launches": v[1],
+                        "avg_ms": v[0] / v[1] if v[1] else None}
+                    for k, v in prof.items()},
+        "loss_first_last": [float(L[0]), float(L[-1])],
+        "layout": info,
+    }
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(12345)
+        pix = np.sort(rng.choice(P, size=min(P, 16384), replace=False))
+        out["cpu_baseline"], out["parity"] = cpu_baseline(ctx, d, pix)
+        out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy_mib:
@@ -150,6 +233,8 @@ def main():
     import paper_2505_08777_amd as A
 
     d = workloads.make(args.workload)
+    if args.workload == "grad1024":
+        return bench_adam(args, d)
     n_iter = args.iters or d["n_iter"]
     nx, ny = d["nx"], d["ny"]
     N, D = d["w"].shape

@@ -193,6 +193,58 @@ int ash_wgs_iterate(ash_ctx* ctx, float* phase_dev, float* weights_dev,
                     int n_iter, const ash_wgs_params* params, float* E_dev,
                     float* stats_dev);
 
+/* Phase gradient of a real loss of the spot fields (the backward of
+ * ash_forward with respect to the phase):
+ *   grad(x) = Im( conj(f(x)) * sum_n G_n exp(+i theta_n(x)) ),
+ *   f = A exp(i phase), G_n = dL/dRe E_n + i dL/dIm E_n.
+ *   phase_dev  device [ny][nx] float32 phase at which E was taken.
+ *   G_dev      device [N][2] float32 field gradient (torch's gradient of a
+ *              real loss with respect to a complex tensor has this form).
+ *   grad_dev   device [ny][nx] float32 output.
+ * Paper: Methods, "Computational Scaling" (gradient descent through the
+ * transforms for precision targets); the derivative of the compressed
+ * forward sum by the phase, evaluated with the adjoint kernels.
+ * Errors: ASH_EINVAL, ASH_ENOTREADY, ASH_EHIP. */
+int ash_phase_grad(ash_ctx* ctx, const float* phase_dev, const float* G_dev,
+                   float* grad_dev);
+
+/* Adam descent of the spot-amplitude loss with a phase-gradient TV term
+ *   L = sum_n (|E_n/s|^2 - t_n)^2 + tv_weight * TV(phase),
+ *   s = sqrt(P sum_x A^2 / N),  t the targets of ash_set_spots,
+ *   TV = (1/P) sum_x sqrt(dx^2 + dy^2 + tv_eps^2), dx, dy the forward
+ *   differences of the phase wrapped into (-pi, pi], 0 at the last
+ *   column / row.
+ * Adam (Kingma and Ba): m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
+ * phase -= lr (m/(1-b1^k)) / (sqrt(v/(1-b2^k)) + eps) at update k. */
+typedef struct ash_adam_params {
+  float lr;         /* 0.05 */
+  float beta1;      /* 0.9 */
+  float beta2;      /* 0.999 */
+  float eps;        /* 1e-8 */
+  float tv_weight;  /* 1e-3 */
+  float tv_eps;     /* 1e-3 rad */
+} ash_adam_params;
+
+/* n_steps Adam updates on the device, each a forward transform, the loss
+ * and its field gradient, the adjoint with the phase gradient and TV term
+ * in its epilogue, and the update.
+ *   phase_dev   device [ny][nx] float32, in: start, out: after n_steps.
+ *   m_dev, v_dev device [ny][nx] float32 Adam moments, in/out (zero at
+ *               the start of a descent).
+ *   step0       updates already made with these moments (0 at the start).
+ *   params      NULL for the defaults above.
+ *   loss_dev    device [n_steps] float32: L at the phase before each
+ *               update, or NULL.
+ *   E_dev       device [N][2] float32: fields of the last forward, or NULL.
+ * Paper: Methods, "Computational Scaling"; the loss, TV term and Adam are
+ * stated readings (the paper names gradient descent only).
+ * Errors: ASH_EINVAL (null arrays, n_steps or step0 < 0, parameters out of
+ * range, zero source amplitude), ASH_ENOTREADY, ASH_ENOMEM, ASH_EHIP. */
+int ash_adam_iterate(ash_ctx* ctx, float* phase_dev, float* m_dev,
+                     float* v_dev, int step0, int n_steps,
+                     const ash_adam_params* params, float* loss_dev,
+                     float* E_dev);
+
 /* Precision of the in-tile remainder terms.  The phase is a sum of
  * products of bf16 pieces.  ASH_PRECISION_AUTO (default) carries the basis
  * remainders and their coefficients in 2 pieces (relative error below

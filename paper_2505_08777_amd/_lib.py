@@ -43,6 +43,12 @@ class Info(ctypes.Structure):
                 ("range_reduce", ctypes.c_int32)]
 
 
+class AdamParams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("tv_weight", ctypes.c_float), ("tv_eps", ctypes.c_float)]
+
+
 PRECISION_AUTO = 0
 PRECISION_FULL = 1
 
@@ -74,6 +80,9 @@ def _load():
         "ash_get_info": (I, [P, ctypes.POINTER(Info)]),
         "ash_profile_enable": (I, [P, I]),
         "ash_profile_read": (I, [P, P, P]),
+        "ash_phase_grad": (I, [P, P, P, P]),
+        "ash_adam_iterate": (I, [P, P, P, P, I, I, ctypes.POINTER(AdamParams),
+                                 P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -12,7 +12,8 @@ import math
 import numpy as np
 import torch
 
-from ._lib import lib, check, AshError, WgsParams, Info, PRECISION_AUTO, PRECISION_FULL
+from ._lib import (lib, check, AshError, WgsParams, AdamParams, Info,
+                   PRECISION_AUTO, PRECISION_FULL)
 from .basis import zernike_table
 
 
@@ -193,3 +194,72 @@ class Context:
         if st is not None:
             st = st[:n_iter]
         return phase, weights, E, st
+
+    # -- differentiable form ----------------------------------------------
+    def phase_grad(self, phase, G, out=None):
+        """Im(conj(f) sum_n G_n exp(+i theta_n)), f = A exp(i phase): the
+        phase gradient of a real loss whose field gradient is G."""
+        P = (self.ny, self.nx)
+        _dev(phase, torch.float32, P, "phase", self.device)
+        _dev(G, torch.complex64, (self.N,), "G", self.device)
+        if out is None:
+            out = torch.empty(P, dtype=torch.float32,
+                              device="cuda:%d" % self.device)
+        _dev(out, torch.float32, P, "out", self.device)
+        self._stream()
+        check(lib.ash_phase_grad(self._h, _ptr(phase), _ptr(G), _ptr(out)),
+              "ash_phase_grad", self._h)
+        return out
+
+    def adam(self, phase, n_steps, m=None, v=None, step0=0, lr=0.05,
+             betas=(0.9, 0.999), eps=1e-8, tv_weight=1e-3, tv_eps=1e-3,
+             want_loss=True, want_E=False):
+        """n_steps Adam updates of the spot-amplitude loss with TV; phase,
+        m and v are updated in place.  Returns (phase, m, v, losses, E)."""
+        P = (self.ny, self.nx)
+        dev = "cuda:%d" % self.device
+        _dev(phase, torch.float32, P, "phase", self.device)
+        if m is None:
+            m = torch.zeros(P, dtype=torch.float32, device=dev)
+        if v is None:
+            v = torch.zeros(P, dtype=torch.float32, device=dev)
+        _dev(m, torch.float32, P, "m", self.device)
+        _dev(v, torch.float32, P, "v", self.device)
+        loss = torch.empty(max(n_steps, 1), dtype=torch.float32,
+                           device=dev) if want_loss else None
+        E = torch.empty(self.N, dtype=torch.complex64, device=dev) \
+            if want_E else None
+        prm = AdamParams(lr, betas[0], betas[1], eps, tv_weight, tv_eps)
+        self._stream()
+        check(lib.ash_adam_iterate(self._h, _ptr(phase), _ptr(m), _ptr(v),
+                                   int(step0), int(n_steps),
+                                   ctypes.byref(prm), _ptr(loss), _ptr(E)),
+              "ash_adam_iterate", self._h)
+        if loss is not None:
+            loss = loss[:n_steps]
+        return phase, m, v, loss, E
+
+
+class Propagate(torch.autograd.Function):
+    """E = forward transform of A exp(i phase), differentiable in phase.
+
+    The backward is the library's adjoint with the phase-gradient epilogue:
+    grad_phase = Im(conj(f) sum_n G_n exp(+i theta_n)), where G is torch's
+    gradient of the loss with respect to the complex E."""
+
+    @staticmethod
+    def forward(ctx, phase, context):
+        ctx.context = context
+        ctx.save_for_backward(phase)
+        return context.forward(phase=phase.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_E):
+        (phase,) = ctx.saved_tensors
+        G = grad_E.to(torch.complex64).contiguous()
+        return ctx.context.phase_grad(phase.contiguous(), G), None
+
+
+def propagate(phase, context):
+    """Differentiable spot fields of the phase (see Propagate)."""
+    return Propagate.apply(phase, context)

@@ -146,7 +146,10 @@ void free_basis(ash_ctx* c) {
   dfree(b.rmax);
   dfree(b.d_pow);
   dfree(b.d_nlcoef);
-  b.cap_pixtab = 0;
+  dfree(b.grad);
+  dfree(b.tvp);
+  dfree(b.lossbuf);
+  b.cap_pixtab = b.cap_grad = b.cap_tvp = 0;
   c->has_basis = false;
   c->basis = Basis();
 }
@@ -676,9 +679,12 @@ int ash_adjoint(ash_ctx* c, const float* y_dev, float* g_dev,
            return launch_to_polar(c->spots.N, y_dev, B.y, c->stream);
          }), "to_polar");
   HIPCHK(c, timed(c, ASH_PROF_ADJOINT, [&] {
+           AdjOut o;
+           o.outs = outs;
+           o.g = g_dev;
+           o.phase = phase_out_dev;
            return launch_adjoint(c->basis.g, c->spots.N, B.pixtab, B.spotrec,
-                                 B.offtab, B.y, B.amp_t, outs, g_dev,
-                                 phase_out_dev, nullptr, c->stream);
+                                 B.offtab, B.y, B.amp_t, o, c->stream);
          }), "adjoint");
   return ASH_OK;
 }
@@ -722,11 +728,131 @@ int ash_wgs_iterate(ash_ctx* c, float* phase_dev, float* weights_dev,
                  stats_dev ? stats_dev + 4 * (size_t)it : nullptr, c->stream);
            }), "wgs_update");
     HIPCHK(c, timed(c, ASH_PROF_ADJOINT, [&] {
+             AdjOut o;
+             o.outs = last ? kOutPhase : kOutField;
+             o.phase = last ? phase_dev : nullptr;
+             o.nf_t = last ? nullptr : B.field_t;
              return launch_adjoint(g, N, B.pixtab, B.spotrec, B.offtab, B.y,
-                                   B.amp_t, last ? kOutPhase : kOutField,
-                                   nullptr, last ? phase_dev : nullptr,
-                                   last ? nullptr : B.field_t, c->stream);
+                                   B.amp_t, o, c->stream);
            }), "adjoint");
+  }
+  return ASH_OK;
+}
+
+namespace {
+
+// Buffers of the differentiable form (sized by the basis).
+int grad_buffers(ash_ctx* c) {
+  Buffers& B = c->buf;
+  const Geom& g = c->basis.g;
+  int rc;
+  if ((rc = grow(c, &B.grad, &B.cap_grad, (size_t)g.nx * g.ny, "gradient")) ||
+      (rc = grow(c, &B.tvp, &B.cap_tvp, (size_t)g.n_tiles * kBlkPerTile,
+                 "TV sums")))
+    return rc;
+  if (!B.lossbuf && (rc = dalloc(c, &B.lossbuf, 1, "loss"))) return rc;
+  return ASH_OK;
+}
+
+}  // namespace
+
+int ash_phase_grad(ash_ctx* c, const float* phase_dev, const float* G_dev,
+                   float* grad_dev) {
+  if (!c) return ASH_EINVAL;
+  c->err.clear();
+  if (!c->has_basis || !c->has_spots)
+    return fail(c, ASH_ENOTREADY, "basis and spots must be set");
+  if (!phase_dev || !G_dev || !grad_dev)
+    return fail(c, ASH_EINVAL, "phase, G and grad required");
+  int rc = use_device(c);
+  if (rc) return rc;
+  Buffers& B = c->buf;
+  HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+           return launch_to_polar(c->spots.N, G_dev, B.y, c->stream);
+         }), "to_polar");
+  HIPCHK(c, timed(c, ASH_PROF_ADJOINT, [&] {
+           AdjOut o;
+           o.outs = kOutGrad;
+           o.phase_in = phase_dev;
+           o.grad = grad_dev;
+           return launch_adjoint(c->basis.g, c->spots.N, B.pixtab, B.spotrec,
+                                 B.offtab, B.y, B.amp_t, o, c->stream);
+         }), "adjoint");
+  return ASH_OK;
+}
+
+int ash_adam_iterate(ash_ctx* c, float* phase_dev, float* m_dev, float* v_dev,
+                     int step0, int n_steps, const ash_adam_params* params,
+                     float* loss_dev, float* E_dev) {
+  if (!c) return ASH_EINVAL;
+  c->err.clear();
+  if (!c->has_basis || !c->has_spots)
+    return fail(c, ASH_ENOTREADY, "basis and spots must be set");
+  if (!phase_dev || !m_dev || !v_dev || n_steps < 0 || step0 < 0)
+    return fail(c, ASH_EINVAL,
+                "phase, m, v required; n_steps and step0 must be >= 0");
+  ash_adam_params pr = {0.05f, 0.9f, 0.999f, 1e-8f, 1e-3f, 1e-3f};
+  if (params) pr = *params;
+  if (!isfinite(pr.lr) || !(pr.beta1 >= 0.0f && pr.beta1 < 1.0f) ||
+      !(pr.beta2 >= 0.0f && pr.beta2 < 1.0f) || !(pr.eps > 0.0f) ||
+      !isfinite(pr.eps) || !isfinite(pr.tv_weight) || pr.tv_weight < 0.0f ||
+      !(pr.tv_eps > 0.0f) || !isfinite(pr.tv_eps))
+    return fail(c, ASH_EINVAL, "Adam parameters out of range");
+  if (n_steps == 0) return ASH_OK;
+  int rc = use_device(c);
+  if (rc) return rc;
+  if ((rc = grad_buffers(c))) return rc;
+  const Geom& g = c->basis.g;
+  Buffers& B = c->buf;
+  const int N = c->spots.N;
+  const double P = (double)g.nx * g.ny;
+  if (!(c->basis.amp_sum2 > 0.0))
+    return fail(c, ASH_EINVAL, "the source amplitude is zero everywhere");
+  const float inv_s = (float)(1.0 / sqrt(P * c->basis.amp_sum2 / N));
+  const int n_tvp = g.n_tiles * kBlkPerTile;
+  HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
+           return launch_make_field(g, phase_dev, nullptr, B.amp_t,
+                                    B.field_t, c->stream);
+         }), "make_field");
+  for (int it = 0; it < n_steps; ++it) {
+    const int step = step0 + it + 1;
+    const bool last = it == n_steps - 1;
+    HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
+             return launch_forward(g, N, c->plan, B.pixtab, B.field_t,
+                                   B.spotrec, B.offtab, B.partial, c->stream);
+           }), "forward");
+    HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+             return launch_reduce(N, c->plan, B.partial, B.red, c->stream);
+           }), "reduce");
+    HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+             return launch_spot_loss(N, c->plan, B.red, B.target, inv_s, B.y,
+                                     last ? E_dev : nullptr, B.lossbuf,
+                                     c->stream);
+           }), "spot_loss");
+    HIPCHK(c, timed(c, ASH_PROF_ADJOINT, [&] {
+             AdjOut o;
+             o.outs = kOutGrad;
+             o.phase_in = phase_dev;
+             o.grad = B.grad;
+             o.tv_scale = (float)(pr.tv_weight / P);
+             o.tv_eps = pr.tv_eps;
+             o.tvp = loss_dev ? B.tvp : nullptr;
+             return launch_adjoint(g, N, B.pixtab, B.spotrec, B.offtab, B.y,
+                                   B.amp_t, o, c->stream);
+           }), "adjoint");
+    if (loss_dev)
+      HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+               return launch_loss_finish(n_tvp, B.tvp,
+                                         (float)(pr.tv_weight / P), B.lossbuf,
+                                         loss_dev + it, c->stream);
+             }), "loss");
+    const float bc1 = (float)(1.0 - pow((double)pr.beta1, step));
+    const float bc2 = (float)(1.0 - pow((double)pr.beta2, step));
+    HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
+             return launch_adam(g, phase_dev, m_dev, v_dev, B.grad, pr.lr,
+                                pr.beta1, pr.beta2, pr.eps, bc1, bc2, B.amp_t,
+                                B.field_t, c->stream);
+           }), "adam");
   }
   return ASH_OK;
 }

@@ -79,6 +79,11 @@ struct Buffers {
   unsigned* bound = nullptr;          // [2] float bits: remainder, |phase|
   float* partial = nullptr;           // [groups][N][2]
   float* red = nullptr;               // [slices][N][2]
+  // differentiable form
+  float* grad = nullptr;              // [P] phase gradient
+  float* tvp = nullptr;               // [n_tiles * kBlkPerTile] TV sums
+  float* lossbuf = nullptr;           // [1] spot term of the loss
+  size_t cap_grad = 0, cap_tvp = 0;
   size_t cap_spots = 0, cap_spotrec = 0, cap_w = 0, cap_off = 0,
          cap_partial = 0, cap_red = 0;
 };
@@ -126,12 +131,33 @@ hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
                              float power, float eff_denom, unsigned* ypol,
                              float* Ebuf, float* E_extra, float* stats_row,
                              hipStream_t s);
-enum AdjOut { kOutG = 1, kOutPhase = 2, kOutField = 4 };
+enum AdjOutFlags { kOutG = 1, kOutPhase = 2, kOutField = 4, kOutGrad = 8 };
+// What the adjoint's epilogue writes for its pixel x, with h = g(x):
+struct AdjOut {
+  int outs = 0;
+  float* g = nullptr;            // kOutG: [P][2] h
+  float* phase = nullptr;        // kOutPhase: [P] arg h
+  unsigned* nf_t = nullptr;      // kOutField: next nearfield A exp(i arg h)
+  const float* phase_in = nullptr;  // kOutGrad: [P] phase of f = A e^{i phi}
+  float* grad = nullptr;         // kOutGrad: [P] Im(conj(f) h) + TV term
+  float tv_scale = 0.0f;         // lambda / P; 0 leaves out the TV term
+  float tv_eps = 0.0f;
+  float* tvp = nullptr;          // [n_tiles * kBlkPerTile] per-wave TV sums
+};
 hipError_t launch_adjoint(const Geom& b, int N, const unsigned short* pixtab,
                           const unsigned short* spotrec,
                           const unsigned* offtab, const unsigned* ypol,
-                          const float* amp_t, int outs, float* g,
-                          float* phase, unsigned* nf_t, hipStream_t s);
+                          const float* amp_t, const AdjOut& o, hipStream_t s);
+hipError_t launch_spot_loss(int N, const FwdPlan& p, const float* red,
+                            const float* target, float inv_s, unsigned* ypol,
+                            float* E_extra, float* lossbuf, hipStream_t s);
+hipError_t launch_loss_finish(int n_tvp, const float* tvp, float tv_sum_scale,
+                              const float* lossbuf, float* loss_out,
+                              hipStream_t s);
+hipError_t launch_adam(const Geom& b, float* phase, float* m, float* v,
+                       const float* grad, float lr, float beta1, float beta2,
+                       float eps, float bc1, float bc2, const float* amp_t,
+                       unsigned* nf_t, hipStream_t s);
 
 }  // namespace ash
 

@@ -52,6 +52,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr float kInv2Pi = 0.15915494309189533577f;
 constexpr double kInv2PiD = 0.15915494309189533577;
+constexpr float kPiF = 3.14159265358979323846f;
+constexpr float k2PiF = 6.28318530717958647692f;
 
 // Anchor of a tile: offsets di in [-16, 15], dj in [-8, 7].
 constexpr int kAnchorI = kTileW / 2;
@@ -876,6 +878,142 @@ hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
 }
 
 // ---------------------------------------------------------------------------
+// Differentiable form: spot-amplitude loss and its field gradient (one
+// block).  With Eh = E / s, d_k = |Eh_k|^2 - t_k:
+//   L_spot = sum_k d_k^2,   G_k = dL/dRe E_k + i dL/dIm E_k = 4 d_k Eh_k / s,
+// stored as spot-field records (|G_k|, arg G_k) for the adjoint.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kUpd) void k_spot_loss(
+    int N, int slices, const float2* __restrict__ red,
+    const float* __restrict__ t, float inv_s, u32x4* __restrict__ ypol,
+    float2* __restrict__ E_extra, float* __restrict__ lossbuf) {
+  __shared__ float sh[kUpd];
+  const int tid = threadIdx.x;
+  float acc = 0.0f, comp = 0.0f;
+  for (int k = tid; k < N; k += kUpd) {
+    const float2 e = sum_slices(red, slices, N, k);
+    if (E_extra) E_extra[k] = e;
+    const float hr = e.x * inv_s, hi = e.y * inv_s;
+    const float d = hr * hr + hi * hi - t[k];
+    kahan_add(acc, comp, d * d);
+    const float c = 4.0f * d * inv_s;
+    put_spot_field(ypol, (N + 31) / 32 * 32, k, fabsf(c) * hypotf(hr, hi),
+                   atan2f(c * hi, c * hr) * kInv2Pi);
+  }
+  const float L = block_reduce(acc, sh, OpSum());
+  if (tid == 0) lossbuf[0] = L;
+}
+
+hipError_t launch_spot_loss(int N, const FwdPlan& p, const float* red,
+                            const float* target, float inv_s, unsigned* ypol,
+                            float* E_extra, float* lossbuf, hipStream_t s) {
+  hipLaunchKernelGGL(k_spot_loss, dim3(1), dim3(kUpd), 0, s, N, p.slices,
+                     reinterpret_cast<const float2*>(red), target, inv_s,
+                     reinterpret_cast<u32x4*>(ypol),
+                     reinterpret_cast<float2*>(E_extra), lossbuf);
+  return hipGetLastError();
+}
+
+// loss = L_spot + tv_sum_scale * (sum of the per-wave TV sums, fixed order)
+__global__ __launch_bounds__(kUpd) void k_loss_finish(
+    int n, const float* __restrict__ tvp, float tv_sum_scale,
+    const float* __restrict__ lossbuf, float* __restrict__ loss_out) {
+  __shared__ float sh[kUpd];
+  float acc = 0.0f, comp = 0.0f;
+  for (int k = threadIdx.x; k < n; k += kUpd) kahan_add(acc, comp, tvp[k]);
+  const float tv = block_reduce(acc, sh, OpSum());
+  if (threadIdx.x == 0) loss_out[0] = lossbuf[0] + tv_sum_scale * tv;
+}
+
+hipError_t launch_loss_finish(int n_tvp, const float* tvp, float tv_sum_scale,
+                              const float* lossbuf, float* loss_out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(kUpd), 0, s, n_tvp, tvp,
+                     tv_sum_scale, lossbuf, loss_out);
+  return hipGetLastError();
+}
+
+// One Adam update per pixel (tile order), and the pixel's next nearfield
+// record.  bc1 = 1 - beta1^step, bc2 = 1 - beta2^step.
+__global__ void k_adam(Geom b, long total, float* __restrict__ phase,
+                       float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ grad, float lr, float beta1,
+                       float beta2, float eps, float bc1, float bc2,
+                       const float* __restrict__ amp_t,
+                       u32x4* __restrict__ nf_t) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const int tile = (int)(gid / kTile), pix = (int)(gid % kTile);
+  int i, j;
+  if (!pixel_ij(b, tile, pix, &i, &j)) return;  // padding stays zero
+  const long p = (long)j * b.nx + i;
+  const float g = grad[p];
+  const float mk = beta1 * m[p] + (1.0f - beta1) * g;
+  const float vk = beta2 * v[p] + (1.0f - beta2) * g * g;
+  m[p] = mk;
+  v[p] = vk;
+  const float ph = phase[p] - lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
+  phase[p] = ph;
+  float turns = ph * kInv2Pi;
+  turns -= rintf(turns);
+  nf_t[gid] = polar_record(amp_t[gid], turns, kBf16One);
+}
+
+hipError_t launch_adam(const Geom& b, float* phase, float* m, float* v,
+                       const float* grad, float lr, float beta1, float beta2,
+                       float eps, float bc1, float bc2, const float* amp_t,
+                       unsigned* nf_t, hipStream_t s) {
+  const long total = (long)b.n_tiles * kTile;
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((total + 255) / 256)), dim3(256),
+                     0, s, b, total, phase, m, v, grad, lr, beta1, beta2, eps,
+                     bc1, bc2, amp_t, reinterpret_cast<u32x4*>(nf_t));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Phase-gradient total variation.  With forward differences of the wrapped
+// phase, dx(j, i) = wrap(phi[j][i+1] - phi[j][i]) (0 in the last column),
+// dy(j, i) likewise along j (0 in the last row), wrap into (-pi, pi], the
+// term of pixel (i, j) is q(j, i) = sqrt(dx^2 + dy^2 + eps^2).  Returns the
+// derivative of sum q over the whole SLM by phi[j][i] (each root through
+// the differences it contains; wrap has unit slope) and sets *term to
+// q(j, i).
+// ---------------------------------------------------------------------------
+__device__ inline float wrap_pi(float d) {
+  const float r = (kPiF - d) - k2PiF * floorf((kPiF - d) * kInv2Pi);
+  return kPiF - r;
+}
+
+__device__ inline void tv_diffs(const float* __restrict__ ph, int nx, int ny,
+                                int i, int j, float* dx, float* dy) {
+  const float c = ph[(long)j * nx + i];
+  *dx = i + 1 < nx ? wrap_pi(ph[(long)j * nx + i + 1] - c) : 0.0f;
+  *dy = j + 1 < ny ? wrap_pi(ph[(long)(j + 1) * nx + i] - c) : 0.0f;
+}
+
+__device__ inline float tv_grad_at(const float* __restrict__ ph, int nx,
+                                   int ny, int i, int j, float eps,
+                                   float* term) {
+  const float e2 = eps * eps;
+  float dx, dy;
+  tv_diffs(ph, nx, ny, i, j, &dx, &dy);
+  const float q = sqrtf(dx * dx + dy * dy + e2);
+  *term = q;
+  float g = -(dx + dy) / q;
+  if (i > 0) {  // the root of (i - 1, j) holds dx(j, i - 1)
+    float ex, ey;
+    tv_diffs(ph, nx, ny, i - 1, j, &ex, &ey);
+    g += ex / sqrtf(ex * ex + ey * ey + e2);
+  }
+  if (j > 0) {  // the root of (i, j - 1) holds dy(j - 1, i)
+    float ex, ey;
+    tv_diffs(ph, nx, ny, i, j - 1, &ex, &ey);
+    g += ey / sqrtf(ex * ex + ey * ey + e2);
+  }
+  return g;
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint: wave = 32 pixels (one tile row) x all spots; the four waves of a
 // block are four rows of one tile.
 // g(x) = sum_k |y_k| exp(2 pi i (tau_k(x) + psi_k)); the epilogue writes g,
@@ -886,8 +1024,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
     int N, int nx, int ny, int tiles_x, const u32x4* __restrict__ pixtab,
     const u32x4* __restrict__ spotrec, const u32x4* __restrict__ offtab,
     const u32x4* __restrict__ ypol, const float* __restrict__ amp_t,
-    int outs, float2* __restrict__ g, float* __restrict__ phase,
-    u32x4* __restrict__ nf_t) {
+    AdjOut o) {
   const int lane = threadIdx.x & (kWave - 1);
   const int h = lane >> 5, q = lane & 31;
   // blocks reach the XCDs round-robin; give each XCD a contiguous run of
@@ -927,50 +1064,66 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
     accumulate<false, kReduce>(th, __uint_as_float(yp[0]), gr, gi);
   }
   bfly_reduce(gr, gi, q);
-  if (q & 1) return;  // the pair partner holds the same result
+  // one result per lane pair; the odd lane of a pair idles in the epilogue
+  const bool lead = (q & 1) == 0;
   const int pix = p0 + mfma_row(bfly_index(q), h);
   const int i = (tile % tiles_x) * kTileW + pix % kTileW;
   const int j = (tile / tiles_x) * kTileH + pix / kTileW;
+  const bool inside = lead && i < nx && j < ny;
+  const long p = (long)j * nx + i;
   const float vr = gr[0], vi = gi[0];
-  const float ang = atan2f(vi, vr);  // atan2(0, 0) = 0
-  if (outs & kOutField)
-    nf_t[(long)tile * kTile + pix] = polar_record(
-        amp_t[(long)tile * kTile + pix], ang * kInv2Pi, kBf16One);
-  if (i < nx && j < ny) {
-    const long p = (long)j * nx + i;
-    if (outs & kOutG) g[p] = make_float2(vr, vi);
-    if (outs & kOutPhase) phase[p] = ang;
+  if (lead && (o.outs & (kOutField | kOutPhase))) {
+    const float ang = atan2f(vi, vr);  // atan2(0, 0) = 0
+    if (o.outs & kOutField)
+      reinterpret_cast<u32x4*>(o.nf_t)[(long)tile * kTile + pix] =
+          polar_record(amp_t[(long)tile * kTile + pix], ang * kInv2Pi,
+                       kBf16One);
+    if (inside && (o.outs & kOutPhase)) o.phase[p] = ang;
+  }
+  if (inside && (o.outs & kOutG))
+    reinterpret_cast<float2*>(o.g)[p] = make_float2(vr, vi);
+  if (o.outs & kOutGrad) {
+    float term = 0.0f;
+    if (inside) {
+      // Im(conj(f) h) with f = A exp(i phi)
+      float sn, cs;
+      sincosf(o.phase_in[p], &sn, &cs);
+      float gv = amp_t[(long)tile * kTile + pix] * (cs * vi - sn * vr);
+      if (o.tv_scale != 0.0f)
+        gv += o.tv_scale * tv_grad_at(o.phase_in, nx, ny, i, j, o.tv_eps, &term);
+      o.grad[p] = gv;
+    }
+    if (o.tvp) {  // this wave's TV terms, in a fixed order
+#pragma unroll
+      for (int w = 32; w >= 1; w >>= 1) term += __shfl_xor(term, w, kWave);
+      if (lane == 0) o.tvp[wv] = term;
+    }
   }
 }
 
 template <int G>
 static hipError_t adj_g(const Geom& b, int N, const unsigned short* pixtab,
                         const unsigned short* spotrec, const unsigned* offtab,
-                        const unsigned* ypol, const float* amp_t, int outs,
-                        float* g, float* phase, unsigned* nf_t,
-                        hipStream_t s) {
+                        const unsigned* ypol, const float* amp_t,
+                        const AdjOut& o, hipStream_t s) {
   const int blocks = b.n_tiles * kBlkPerTile / (kBlock / kWave);
   auto* const kern = b.reduce ? k_adjoint<G, true> : k_adjoint<G, false>;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, N, b.nx,
                      b.ny, b.tiles_x, reinterpret_cast<const u32x4*>(pixtab),
                      reinterpret_cast<const u32x4*>(spotrec),
                      reinterpret_cast<const u32x4*>(offtab),
-                     reinterpret_cast<const u32x4*>(ypol), amp_t, outs,
-                     reinterpret_cast<float2*>(g), phase,
-                     reinterpret_cast<u32x4*>(nf_t));
+                     reinterpret_cast<const u32x4*>(ypol), amp_t, o);
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const Geom& b, int N, const unsigned short* pixtab,
                           const unsigned short* spotrec,
                           const unsigned* offtab, const unsigned* ypol,
-                          const float* amp_t, int outs, float* g,
-                          float* phase, unsigned* nf_t, hipStream_t s) {
+                          const float* amp_t, const AdjOut& o, hipStream_t s) {
   switch (b.groups) {
-#define X(n)                                                             \
-  case n:                                                                \
-    return adj_g<n>(b, N, pixtab, spotrec, offtab, ypol, amp_t, outs, g, \
-                    phase, nf_t, s);
+#define X(n)      \
+  case n:         \
+    return adj_g<n>(b, N, pixtab, spotrec, offtab, ypol, amp_t, o, s);
     ASH_G_CASES(X)
 #undef X
     default:
