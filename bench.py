@@ -166,7 +166,7 @@ def bench_adam(args, d):
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
-    ctx.profile(True)
+    ctx.profile(True, categories=("forward", "adjoint"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -252,8 +252,8 @@ def main():
         ctx.wgs(phase, n_iter, weights=weights, want_E=False, want_stats=False)
     torch.cuda.synchronize()
 
-    # timed region: K steps, every kernel bracketed by HIP events
-    ctx.profile(True)
+    # timed region: K steps, the transform kernels bracketed by HIP events
+    ctx.profile(True, categories=("forward", "adjoint"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):

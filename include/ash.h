@@ -270,21 +270,24 @@ typedef struct ash_info {
 } ash_info;
 int ash_get_info(const ash_ctx* ctx, ash_info* out);
 
-/* Kernel timing, for measurement.  While enabled, every kernel the context
- * enqueues is bracketed by HIP events on the context's stream.  Categories:
+/* Kernel timing, for measurement.  Kernels of the categories selected by
+ * `mask` (bit 1 << category) are bracketed by HIP events on the context's
+ * stream.  Categories:
  *   ASH_PROF_FORWARD   forward transform kernel
  *   ASH_PROF_ADJOINT   adjoint transform kernel (with its epilogue)
- *   ASH_PROF_REDUCE    partial-sum reductions and the weighted-GS update
- *   ASH_PROF_FIELD     nearfield preparation A exp(i phase)
- * ash_profile_read synchronises the stream, writes the summed milliseconds
- * and the launch count of each category into ms_out[4] / launches_out[4]
- * (either may be NULL) and clears the record.  Enabling allocates events;
- * disabled (the default), nothing is recorded. */
+ *   ASH_PROF_REDUCE    partial-sum reductions, weighted-GS update, loss
+ *   ASH_PROF_FIELD     nearfield preparation A exp(i phase), Adam update
+ * ASH_PROF_ALL selects all; 0 (the default) records nothing.  Each event
+ * pair costs a few microseconds of stream time, so select only what is
+ * measured.  ash_profile_read synchronises the stream, writes the summed
+ * milliseconds and the launch count of each category into ms_out[4] /
+ * launches_out[4] (either may be NULL) and clears the record. */
 #define ASH_PROF_FORWARD 0
 #define ASH_PROF_ADJOINT 1
 #define ASH_PROF_REDUCE 2
 #define ASH_PROF_FIELD 3
-int ash_profile_enable(ash_ctx* ctx, int enable);
+#define ASH_PROF_ALL 0xF
+int ash_profile_enable(ash_ctx* ctx, int mask);
 int ash_profile_read(ash_ctx* ctx, double* ms_out, int64_t* launches_out);
 
 #ifdef __cplusplus

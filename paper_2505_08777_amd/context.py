@@ -68,10 +68,18 @@ class Context:
         s = torch.cuda.current_stream(self.device).cuda_stream
         check(lib.ash_set_stream(self._h, ctypes.c_void_p(s)), "ash_set_stream")
 
-    def profile(self, enable=True):
-        """Bracket every enqueued kernel with HIP events (see profile_read)."""
-        check(lib.ash_profile_enable(self._h, 1 if enable else 0),
-              "ash_profile_enable", self._h)
+    PROFILE_CATEGORIES = ("forward", "adjoint", "reduce", "field")
+
+    def profile(self, enable=True, categories=None):
+        """Bracket the kernels of the given categories (default all) with
+        HIP events; see profile_read."""
+        mask = 0
+        if enable:
+            cats = self.PROFILE_CATEGORIES if categories is None else categories
+            for k in cats:
+                mask |= 1 << self.PROFILE_CATEGORIES.index(k)
+        check(lib.ash_profile_enable(self._h, mask), "ash_profile_enable",
+              self._h)
 
     def profile_read(self):
         """{category: (total ms, launches)} since the last read; syncs."""
@@ -79,8 +87,8 @@ class Context:
         n = np.zeros(4, dtype=np.int64)
         check(lib.ash_profile_read(self._h, ms.ctypes.data, n.ctypes.data),
               "ash_profile_read", self._h)
-        names = ("forward", "adjoint", "reduce", "field")
-        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(names)}
+        return {k: (float(ms[i]), int(n[i]))
+                for i, k in enumerate(self.PROFILE_CATEGORIES)}
 
     def set_precision(self, full=False):
         """3 bf16 pieces for every remainder term (full) or the automatic

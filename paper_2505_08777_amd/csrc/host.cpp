@@ -74,7 +74,7 @@ hipEvent_t prof_event(ash_ctx* c) {
 // Enqueue `launch` bracketed by events of category `cat` when profiling.
 template <typename F>
 hipError_t timed(ash_ctx* c, int cat, F&& launch) {
-  if (!c->prof_on) return launch();
+  if (!(c->prof_mask & (1 << cat))) return launch();
   hipEvent_t a = prof_event(c), b = prof_event(c);
   if (a) (void)hipEventRecord(a, c->stream);
   hipError_t e = launch();
@@ -857,9 +857,10 @@ int ash_adam_iterate(ash_ctx* c, float* phase_dev, float* m_dev, float* v_dev,
   return ASH_OK;
 }
 
-int ash_profile_enable(ash_ctx* c, int enable) {
+int ash_profile_enable(ash_ctx* c, int mask) {
   if (!c) return ASH_EINVAL;
-  c->prof_on = enable != 0;
+  if (mask & ~ASH_PROF_ALL) return fail(c, ASH_EINVAL, "unknown category bits");
+  c->prof_mask = mask;
   return ASH_OK;
 }
 

@@ -170,7 +170,7 @@ struct ash_ctx {
   int device = 0;
   int n_cu = 0;
   int precision = ASH_PRECISION_AUTO;
-  bool prof_on = false;
+  int prof_mask = 0;  // categories timed with events (bit 1 << category)
   std::vector<ash_prof_rec> prof;     // recorded pairs (in use)
   std::vector<hipEvent_t> prof_pool;  // free events
   hipStream_t stream = nullptr;
