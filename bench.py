@@ -45,9 +45,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="field1024",
                     choices=["plain256", "field1024", "volume1920",
-                             "grad1024"],
-                    help="grad1024 times the differentiable form: Adam steps "
-                         "of the spot-amplitude loss with TV")
+                             "grad1024", "batch64"],
+                    help="grad1024 times the differentiable form (Adam steps "
+                         "of the spot-amplitude loss with TV); batch64 the "
+                         "batched form (64 holograms' WGS loops together)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch64: skip the autotuner (default range length)")
     ap.add_argument("--iters", type=int, default=None,
                     help="WGS iterations per step (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -217,6 +220,85 @@ def bench_adam(args, d):
     print(json.dumps(out), flush=True)
 
 
+def bench_batch(args, holos):
+    """64 holograms (sides 512..2048, N log-uniform in [10, 5000], 12
+    modes): a step is the workload's 50 WGS iterations of every hologram
+    in the batched persistent launches, continuing from the last phases."""
+    import numpy as np
+    import torch
+    import paper_2505_08777_amd as A
+
+    n_iter = args.iters or holos[0]["n_iter"]
+    dev = torch.device("cuda:0")
+    ctxs = []
+    for d in holos:
+        c = A.Context(0)
+        c.set_basis(d["nx"], d["ny"], modes=d["modes"],
+                    amp=torch.tensor(d["amp"], dtype=torch.float32, device=dev))
+        c.set_spots(d["w"], d["t"])
+        ctxs.append(c)
+    b = A.Batch(ctxs)
+    phases = [torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
+              for d in holos]
+    weights = [torch.ones(d["w"].shape[0], dtype=torch.float32, device=dev)
+               for d in holos]
+    tune_s = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        b.tune(phases)
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - t0
+    info = b.info()
+    for _ in range(args.warmup):
+        b.wgs(phases, n_iter, weights=weights)
+    torch.cuda.synchronize()
+    b.profile(True, categories=("forward", "adjoint"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.wgs(phases, n_iter, weights=weights)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = b.profile_read()
+    b.profile(False)
+    T = t1 - t0
+    D = holos[0]["w"].shape[1]
+    F = flops_per_eval(D)
+    evals = info["evals_per_transform"]
+    value = 2.0 * evals * n_iter * args.steps / T
+    dom = max(("forward", "adjoint"), key=lambda k: prof[k][0])
+    # every launch of a phase covers all holograms of its record shape;
+    # the achieved rate is over all launches of the dominant phase
+    achieved = evals * n_iter * args.steps * F / (prof[dom][0] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batch64", "holograms": len(holos),
+                   "sum_N_P": evals, "modes": D,
+                   "wgs_iters_per_step": n_iter},
+        "wgs_iters_per_s_per_hologram": n_iter * args.steps / T,
+        "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
+        "roofline": {"bound": "alu", "kernel": "k_batch_%s" % dom,
+                     "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": None, "traffic_unit": "bytes/launch",
+                     "avg_launch_ms": prof[dom][0] / max(prof[dom][1], 1),
+                     "launches": prof[dom][1], "flops_per_eval": F},
+        "kernels": {k: {"total_ms": v[0], "launches": v[1],
+                        "avg_ms": v[0] / v[1] if v[1] else None}
+                    for k, v in prof.items()},
+        "layout": info, "tune_s": tune_s,
+    }
+    b.close()
+    for c in ctxs:
+        c.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy_mib:
@@ -235,6 +317,8 @@ def main():
     d = workloads.make(args.workload)
     if args.workload == "grad1024":
         return bench_adam(args, d)
+    if args.workload == "batch64":
+        return bench_batch(args, d)
     n_iter = args.iters or d["n_iter"]
     nx, ny = d["nx"], d["ny"]
     N, D = d["w"].shape

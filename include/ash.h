@@ -270,6 +270,76 @@ typedef struct ash_info {
 } ash_info;
 int ash_get_info(const ash_ctx* ctx, ash_info* out);
 
+/* ---- Batched form ----------------------------------------------------
+ * Many holograms' weighted-GS loops run together.  Each phase of an
+ * iteration is one persistent launch over the work items of all holograms
+ * (one launch per record shape present): the forward over (hologram, pixel
+ * range, 32-spot block) items, a fixed-order reduction and the weight
+ * updates of all holograms, and the adjoint over (hologram, tile row)
+ * items.  Items sit in eight per-XCD queues (longest first, balanced by
+ * work); resident waves take them with an atomic counter and move to the
+ * other queues when theirs runs dry.  The forward range length (pixel
+ * blocks per item) is the tuned parameter.
+ * Paper: Methods, "Computational Scaling" (many holograms); the batched
+ * persistent form is this library's. */
+typedef struct ash_batch ash_batch;
+
+/* A batch of H holograms, each a context with its basis and spots set, all
+ * on one device.  The members stay owned by the caller and must outlive the
+ * batch; the batch computes in their buffers, so a member must not be used
+ * on another stream while a batch call runs.  Changing a member's basis or
+ * spots invalidates the batch: its calls then fail with ASH_ENOTREADY.
+ *   stream  HIP stream of the batch's launches (NULL: the default stream).
+ * Errors: ASH_EINVAL (H < 1, null or unready members, members on different
+ * devices), ASH_ENOMEM, ASH_EUNSUPPORTED (more than 2^31 work items),
+ * ASH_EHIP. */
+int ash_batch_create(ash_batch** out, int H, ash_ctx* const* members,
+                     void* stream);
+int ash_batch_destroy(ash_batch* batch);
+const char* ash_batch_last_error(const ash_batch* batch);
+int ash_batch_set_stream(ash_batch* batch, void* stream);
+
+/* n_iter weighted-GS iterations of every hologram.
+ *   phase_dev    host array of H device pointers, hologram h's
+ *                [ny_h][nx_h] float32 phase, in: start, out: final.
+ *   weights_dev  host array of H device pointers, [N_h] float32 weights,
+ *                in/out (start with 1).
+ *   params       as for ash_wgs_iterate (NULL = power 1).
+ * Each hologram's results equal its own ash_wgs_iterate up to the FP32
+ * summation order of the forward partial sums.  The call synchronises the
+ * stream once at its start (descriptor upload).
+ * Errors: ASH_EINVAL, ASH_ENOTREADY, ASH_ENOMEM, ASH_EHIP. */
+int ash_batch_wgs(ash_batch* batch, float* const* phase_dev,
+                  float* const* weights_dev, int n_iter,
+                  const ash_wgs_params* params);
+
+/* Autotuner: for each record shape, times the forward plus its reduction on
+ * the batch at the given phases for range lengths of 16, 32, 64, 128, 256
+ * and 512 pixel blocks, keeps the fastest, and writes the table
+ * "groups range_reduce range_blocks ms" to table_out (if not NULL).
+ * Errors: ASH_EINVAL (null phases, unwritable file), ASH_ENOTREADY,
+ * ASH_ENOMEM, ASH_EHIP. */
+int ash_batch_tune(ash_batch* batch, float* const* phase_dev,
+                   const char* table_out);
+/* Apply a table written by ash_batch_tune (lines for absent record shapes
+ * are ignored).  Errors: ASH_EINVAL (unreadable file), ASH_ENOMEM. */
+int ash_batch_load_tuning(ash_batch* batch, const char* table_in);
+
+typedef struct ash_batch_info {
+  int32_t holograms;
+  int32_t shapes;           /* record shapes (one launch each per phase)   */
+  int32_t groups[4];        /* matrix-core groups of the first 4 shapes    */
+  int32_t range_blocks[4];  /* their forward range lengths                 */
+  int64_t items;            /* forward + adjoint work items                */
+  double evals_per_transform;  /* sum over holograms of N * P              */
+} ash_batch_info;
+int ash_batch_get_info(const ash_batch* batch, ash_batch_info* out);
+
+/* Event timing of the batch's launches, as ash_profile_enable/read. */
+int ash_batch_profile_enable(ash_batch* batch, int mask);
+int ash_batch_profile_read(ash_batch* batch, double* ms_out,
+                           int64_t* launches_out);
+
 /* Kernel timing, for measurement.  Kernels of the categories selected by
  * `mask` (bit 1 << category) are bracketed by HIP events on the context's
  * stream.  Categories:

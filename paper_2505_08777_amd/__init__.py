@@ -8,7 +8,7 @@ Gerchberg-Saxton loop, as hand-written HIP kernels behind a C ABI
 
 from ._lib import AshError, LIB_PATH, lib
 from .basis import zernike_monomials, zernike_table
-from .context import Context, Propagate, propagate
+from .context import Batch, Context, Propagate, propagate
 
-__all__ = ["AshError", "Context", "LIB_PATH", "Propagate", "lib", "propagate",
-           "zernike_monomials", "zernike_table"]
+__all__ = ["AshError", "Batch", "Context", "LIB_PATH", "Propagate", "lib",
+           "propagate", "zernike_monomials", "zernike_table"]

@@ -49,6 +49,14 @@ class AdamParams(ctypes.Structure):
                 ("tv_weight", ctypes.c_float), ("tv_eps", ctypes.c_float)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("holograms", ctypes.c_int32), ("shapes", ctypes.c_int32),
+                ("groups", ctypes.c_int32 * 4),
+                ("range_blocks", ctypes.c_int32 * 4),
+                ("items", ctypes.c_int64),
+                ("evals_per_transform", ctypes.c_double)]
+
+
 PRECISION_AUTO = 0
 PRECISION_FULL = 1
 
@@ -83,6 +91,16 @@ def _load():
         "ash_phase_grad": (I, [P, P, P, P]),
         "ash_adam_iterate": (I, [P, P, P, P, I, I, ctypes.POINTER(AdamParams),
                                  P, P]),
+        "ash_batch_create": (I, [ctypes.POINTER(P), I, P, P]),
+        "ash_batch_destroy": (I, [P]),
+        "ash_batch_last_error": (ctypes.c_char_p, [P]),
+        "ash_batch_set_stream": (I, [P, P]),
+        "ash_batch_wgs": (I, [P, P, P, I, ctypes.POINTER(WgsParams)]),
+        "ash_batch_tune": (I, [P, P, ctypes.c_char_p]),
+        "ash_batch_load_tuning": (I, [P, ctypes.c_char_p]),
+        "ash_batch_get_info": (I, [P, ctypes.POINTER(BatchInfo)]),
+        "ash_batch_profile_enable": (I, [P, I]),
+        "ash_batch_profile_read": (I, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from ._lib import (lib, check, AshError, WgsParams, AdamParams, Info,
-                   PRECISION_AUTO, PRECISION_FULL)
+                   BatchInfo, PRECISION_AUTO, PRECISION_FULL)
 from .basis import zernike_table
 
 
@@ -271,3 +271,111 @@ class Propagate(torch.autograd.Function):
 def propagate(phase, context):
     """Differentiable spot fields of the phase (see Propagate)."""
     return Propagate.apply(phase, context)
+
+
+class Batch:
+    """Several holograms (contexts with basis and spots set) whose WGS loops
+    run together in persistent launches; see ash_batch_create."""
+
+    def __init__(self, contexts):
+        self.members = list(contexts)   # the batch computes in their buffers
+        if not self.members:
+            raise ValueError("at least one context")
+        self.device = self.members[0].device
+        H = len(self.members)
+        arr = (ctypes.c_void_p * H)(*[c._h.value for c in self.members])
+        self._h = ctypes.c_void_p()
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        rc = lib.ash_batch_create(ctypes.byref(self._h), H, arr,
+                                  ctypes.c_void_p(s))
+        if rc != 0:
+            raise AshError(rc, "ash_batch_create", "")
+
+    def close(self):
+        if self._h:
+            lib.ash_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, where):
+        if rc != 0:
+            raise AshError(rc, where, lib.ash_batch_last_error(self._h).decode())
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self._check(lib.ash_batch_set_stream(self._h, ctypes.c_void_p(s)),
+                    "ash_batch_set_stream")
+
+    def _ptrs(self, tensors, dtype, shapes, name):
+        if len(tensors) != len(self.members):
+            raise ValueError("one %s per hologram" % name)
+        for t, shp in zip(tensors, shapes):
+            _dev(t, dtype, shp, name, self.device)
+        return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+
+    def _phases(self, phases):
+        return self._ptrs(phases, torch.float32,
+                          [(c.ny, c.nx) for c in self.members], "phase")
+
+    def wgs(self, phases, n_iter, weights=None, power=1.0):
+        """n_iter WGS iterations of every hologram; phases and weights are
+        updated in place.  Returns (phases, weights)."""
+        if weights is None:
+            weights = [torch.ones(c.N, dtype=torch.float32,
+                                  device="cuda:%d" % self.device)
+                       for c in self.members]
+        ph = self._phases(phases)
+        w = self._ptrs(weights, torch.float32, [(c.N,) for c in self.members],
+                       "weights")
+        params = WgsParams(float(power), 0)
+        self._stream()
+        self._check(lib.ash_batch_wgs(self._h, ph, w, int(n_iter),
+                                      ctypes.byref(params)), "ash_batch_wgs")
+        return phases, weights
+
+    def tune(self, phases, table_out=None):
+        """Pick the forward range length per record shape by timing."""
+        ph = self._phases(phases)
+        self._stream()
+        self._check(lib.ash_batch_tune(
+            self._h, ph, table_out.encode() if table_out else None),
+            "ash_batch_tune")
+        return self.info()
+
+    def load_tuning(self, table_in):
+        self._check(lib.ash_batch_load_tuning(self._h, table_in.encode()),
+                    "ash_batch_load_tuning")
+
+    def info(self):
+        out = BatchInfo()
+        self._check(lib.ash_batch_get_info(self._h, ctypes.byref(out)),
+                    "ash_batch_get_info")
+        n = out.shapes
+        return {"holograms": out.holograms, "shapes": n,
+                "groups": list(out.groups)[:min(n, 4)],
+                "range_blocks": list(out.range_blocks)[:min(n, 4)],
+                "items": out.items,
+                "evals_per_transform": out.evals_per_transform}
+
+    def profile(self, enable=True, categories=None):
+        mask = 0
+        if enable:
+            cats = Context.PROFILE_CATEGORIES if categories is None else categories
+            for k in cats:
+                mask |= 1 << Context.PROFILE_CATEGORIES.index(k)
+        self._check(lib.ash_batch_profile_enable(self._h, mask),
+                    "ash_batch_profile_enable")
+
+    def profile_read(self):
+        ms = np.zeros(4, dtype=np.float64)
+        n = np.zeros(4, dtype=np.int64)
+        self._check(lib.ash_batch_profile_read(self._h, ms.ctypes.data,
+                                               n.ctypes.data),
+                    "ash_batch_profile_read")
+        return {k: (float(ms[i]), int(n[i]))
+                for i, k in enumerate(Context.PROFILE_CATEGORIES)}

@@ -1,0 +1,657 @@
+// Host side of the batched form: many holograms' WGS loops run together,
+// each phase of an iteration one persistent launch over the work items of
+// all holograms (per record shape), with per-XCD work queues.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "ash.h"
+#include "internal.h"
+
+using namespace ash;
+
+namespace {
+
+constexpr int kDefaultRange = 64;  // pixel blocks per forward item (untuned)
+constexpr int kTuneCandidates[] = {16, 32, 64, 128, 256, 512};
+
+// One record shape (matrix-core groups, range reduction) of the batch.
+struct Cls {
+  int G = 0;
+  int reduce = 0;
+  int L = kDefaultRange;
+  std::vector<int> holos;
+  size_t fwd_off = 0, adj_off = 0;  // first item of each phase
+  int qoff_fwd = 0, qoff_adj = 0;   // index of its 9 queue offsets in qoff
+  int fwd_grid = 0, adj_grid = 0;
+};
+
+struct Snap {  // what the batch's plan depends on, per member
+  int N, n_tiles, groups, reduce;
+  const void *pixtab, *spotrec, *offtab, *y, *field_t;
+};
+
+}  // namespace
+
+struct ash_batch {
+  int device = 0;
+  int n_cu = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<ash_ctx*> m;
+  std::vector<Snap> snap;
+  std::vector<Cls> cls;
+  std::vector<HoloDesc> desc;
+  std::vector<int4> items, rblk;
+  std::vector<int> qoff;
+  double evals_per_transform = 0.0;
+  // device
+  HoloDesc* d_desc = nullptr;
+  float2* d_partial = nullptr;
+  float2* d_red = nullptr;
+  int4* d_items = nullptr;
+  int4* d_rblk = nullptr;
+  int* d_qoff = nullptr;
+  int* d_ctr = nullptr;
+  size_t cap_partial = 0, cap_red = 0, cap_items = 0, cap_rblk = 0,
+         cap_qoff = 0, cap_ctr = 0;
+  // timing
+  int prof_mask = 0;
+  std::vector<ash_prof_rec> prof;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+int bfail(ash_batch* b, int code, const std::string& msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+int bhip(ash_batch* b, hipError_t e, const char* what) {
+  if (b) b->err = std::string(what) + ": " + hipGetErrorString(e);
+  return ASH_EHIP;
+}
+
+#define BCHK(b, expr, what)                           \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return bhip(b, e_, what);   \
+  } while (0)
+
+int buse(ash_batch* b) {
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return bhip(b, e, "hipGetDevice");
+  if (cur != b->device && (e = hipSetDevice(b->device)) != hipSuccess)
+    return bhip(b, e, "hipSetDevice");
+  return ASH_OK;
+}
+
+template <typename T>
+void bfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+template <typename T>
+int bgrow(ash_batch* b, T** p, size_t* cap, size_t need, const char* what) {
+  if (need == 0) need = 1;
+  if (need <= *cap) return ASH_OK;
+  bfree(*p);
+  *cap = 0;
+  if (hipMalloc(reinterpret_cast<void**>(p), need * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return bfail(b, ASH_ENOMEM, std::string("out of device memory for ") + what);
+  }
+  *cap = need;
+  return ASH_OK;
+}
+
+template <typename F>
+hipError_t btimed(ash_batch* b, int cat, F&& launch) {
+  if (!(b->prof_mask & (1 << cat))) return launch();
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (auto& e : ev) {
+    if (!b->pool.empty()) {
+      e = b->pool.back();
+      b->pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      e = nullptr;
+    }
+  }
+  if (ev[0]) (void)hipEventRecord(ev[0], b->stream);
+  hipError_t r = launch();
+  if (ev[0] && ev[1]) {
+    (void)hipEventRecord(ev[1], b->stream);
+    b->prof.push_back({cat, ev[0], ev[1]});
+  } else {
+    for (auto e : ev)
+      if (e) b->pool.push_back(e);
+  }
+  return r;
+}
+
+Snap snapshot(const ash_ctx* c) {
+  const Buffers& B = c->buf;
+  return {c->spots.N, c->basis.g.n_tiles, c->basis.g.groups, c->basis.g.reduce,
+          B.pixtab, B.spotrec, B.offtab, B.y, B.field_t};
+}
+
+bool same(const Snap& a, const Snap& b) {
+  return a.N == b.N && a.n_tiles == b.n_tiles && a.groups == b.groups &&
+         a.reduce == b.reduce && a.pixtab == b.pixtab &&
+         a.spotrec == b.spotrec && a.offtab == b.offtab && a.y == b.y &&
+         a.field_t == b.field_t;
+}
+
+// Assign units of work to the 8 XCD queues, largest first to the least
+// loaded queue (longest-processing-time order), keeping each unit's items
+// together; returns, per queue, the units in assignment order.
+std::vector<std::vector<int>> lpt(const std::vector<double>& work) {
+  std::vector<int> order(work.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return work[a] > work[c]; });
+  std::vector<std::vector<int>> q(kXcds);
+  double load[kXcds] = {0};
+  for (int u : order) {
+    int best = 0;
+    for (int x = 1; x < kXcds; ++x)
+      if (load[x] < load[best]) best = x;
+    q[best].push_back(u);
+    load[best] += work[u];
+  }
+  return q;
+}
+
+// Build descriptors (without the per-call phase and weight pointers),
+// work items, queues and reduction blocks for the current range lengths.
+int plan(ash_batch* b) {
+  // launches of an earlier plan may still read the buffers rewritten here
+  BCHK(b, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  const int H = (int)b->m.size();
+  b->desc.assign(H, HoloDesc());
+  size_t part = 0, red = 0;
+  b->evals_per_transform = 0.0;
+  std::vector<int> L_of(H, kDefaultRange);
+  for (auto& c : b->cls)
+    for (int h : c.holos) L_of[h] = c.L;
+  for (int h = 0; h < H; ++h) {
+    ash_ctx* c = b->m[h];
+    const Geom& g = c->basis.g;
+    Buffers& B = c->buf;
+    HoloDesc& d = b->desc[h];
+    d.pixtab = reinterpret_cast<const u32x4*>(B.pixtab);
+    d.nf_t = reinterpret_cast<u32x4*>(B.field_t);
+    d.spotrec = reinterpret_cast<const u32x4*>(B.spotrec);
+    d.offtab = reinterpret_cast<const u32x4*>(B.offtab);
+    d.ypol = reinterpret_cast<u32x4*>(B.y);
+    d.amp_t = B.amp_t;
+    d.target = B.target;
+    d.Ebuf = reinterpret_cast<float2*>(B.Ebuf);
+    d.n_blk = (long)g.n_tiles * kBlkPerTile;
+    d.N = c->spots.N;
+    d.nx = g.nx;
+    d.ny = g.ny;
+    d.tiles_x = g.tiles_x;
+    d.L = L_of[h];
+    d.n_ranges = (int)((d.n_blk + d.L - 1) / d.L);
+    d.slices = (d.n_ranges + kRowsPerSlice - 1) / kRowsPerSlice;
+    d.t_norm = (float)sqrt(c->spots.t_norm2);
+    d.eff_denom = (float)((double)g.nx * g.ny * c->basis.amp_sum2);
+    d.partial = reinterpret_cast<float2*>(part);  // offsets for now
+    d.red = reinterpret_cast<float2*>(red);
+    part += (size_t)d.n_ranges * d.N;
+    red += (size_t)d.slices * d.N;
+    b->evals_per_transform += (double)d.N * g.nx * g.ny;
+  }
+  int rc;
+  if ((rc = bgrow(b, &b->d_partial, &b->cap_partial, part, "partial sums")) ||
+      (rc = bgrow(b, &b->d_red, &b->cap_red, red, "partial sums")))
+    return rc;
+  for (auto& d : b->desc) {
+    d.partial = b->d_partial + reinterpret_cast<size_t>(d.partial);
+    d.red = b->d_red + reinterpret_cast<size_t>(d.red);
+  }
+  // work items and queues, per record shape
+  b->items.clear();
+  b->qoff.clear();
+  for (auto& c : b->cls) {
+    // forward: unit = (holo, range), items = its spot blocks
+    std::vector<int2> units;
+    std::vector<double> work;
+    for (int h : c.holos) {
+      const HoloDesc& d = b->desc[h];
+      const int n_mb = (d.N + 31) / 32;
+      for (int r = 0; r < d.n_ranges; ++r) {
+        const long len = std::min<long>(d.L, d.n_blk - (long)r * d.L);
+        units.push_back(make_int2(h, r));
+        work.push_back((double)len * n_mb);
+      }
+    }
+    auto q = lpt(work);
+    c.fwd_off = b->items.size();
+    c.qoff_fwd = (int)b->qoff.size();
+    for (int x = 0; x < kXcds; ++x) {
+      b->qoff.push_back((int)(b->items.size() - c.fwd_off));
+      for (int u : q[x]) {
+        const int h = units[u].x, r = units[u].y;
+        const int n_mb = (b->desc[h].N + 31) / 32;
+        for (int mb = 0; mb < n_mb; ++mb)
+          b->items.push_back(make_int4(h, r, mb, 0));
+      }
+    }
+    b->qoff.push_back((int)(b->items.size() - c.fwd_off));
+    // adjoint: unit = (holo, tile), items = runs of its 16 rows, as many
+    // rows per item as keep an item at >= ~8 spot blocks of work (an item
+    // costs one atomic take)
+    units.clear();
+    work.clear();
+    for (int h : c.holos) {
+      const HoloDesc& d = b->desc[h];
+      const int n_tiles = (int)(d.n_blk / kBlkPerTile);
+      for (int t = 0; t < n_tiles; ++t) {
+        units.push_back(make_int2(h, t));
+        work.push_back((double)kBlkPerTile * ((d.N + 31) / 32));
+      }
+    }
+    q = lpt(work);
+    c.adj_off = b->items.size();
+    c.qoff_adj = (int)b->qoff.size();
+    for (int x = 0; x < kXcds; ++x) {
+      b->qoff.push_back((int)(b->items.size() - c.adj_off));
+      for (int u : q[x]) {
+        const int h = units[u].x, n_mb = (b->desc[h].N + 31) / 32;
+        int rows = kBlkPerTile;
+        while (rows > 1 && rows * n_mb > 8) rows >>= 1;
+        for (int r = 0; r < kBlkPerTile; r += rows)
+          b->items.push_back(
+              make_int4(h, units[u].y * kBlkPerTile + r, rows, 0));
+      }
+    }
+    b->qoff.push_back((int)(b->items.size() - c.adj_off));
+    c.fwd_grid = std::max(
+        kXcds, batch_blocks_per_cu(c.G, c.reduce != 0, true) * b->n_cu /
+                   kXcds * kXcds);
+    c.adj_grid = std::max(
+        kXcds, batch_blocks_per_cu(c.G, c.reduce != 0, false) * b->n_cu /
+                   kXcds * kXcds);
+  }
+  if (b->items.size() > (size_t)INT32_MAX)
+    return bfail(b, ASH_EUNSUPPORTED, "too many work items");
+  // reduction blocks: {holo, first spot, slice}
+  b->rblk.clear();
+  for (int h = 0; h < H; ++h) {
+    const HoloDesc& d = b->desc[h];
+    for (int sl = 0; sl < d.slices; ++sl)
+      for (int k0 = 0; k0 < d.N; k0 += 64)
+        b->rblk.push_back(make_int4(h, k0, sl, 0));
+  }
+  if ((rc = bgrow(b, &b->d_items, &b->cap_items, b->items.size(), "items")) ||
+      (rc = bgrow(b, &b->d_rblk, &b->cap_rblk, b->rblk.size(), "items")) ||
+      (rc = bgrow(b, &b->d_qoff, &b->cap_qoff, b->qoff.size(), "queues")))
+    return rc;
+  hipError_t e = hipMemcpy(b->d_items, b->items.data(),
+                           b->items.size() * sizeof(int4),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess && !b->rblk.empty())
+    e = hipMemcpy(b->d_rblk, b->rblk.data(), b->rblk.size() * sizeof(int4),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_qoff, b->qoff.data(), b->qoff.size() * sizeof(int),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bhip(b, e, "uploading the batch plan");
+  return ASH_OK;
+}
+
+// Upload the descriptors with this call's phase and weight pointers.
+int upload_desc(ash_batch* b, float* const* phase, float* const* W) {
+  for (size_t h = 0; h < b->desc.size(); ++h) {
+    b->desc[h].phase = phase ? phase[h] : nullptr;
+    b->desc[h].W = W ? W[h] : nullptr;
+  }
+  // synchronous: the host copy is rewritten by the next call
+  BCHK(b, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  BCHK(b, hipMemcpy(b->d_desc, b->desc.data(),
+                    b->desc.size() * sizeof(HoloDesc), hipMemcpyHostToDevice),
+       "uploading descriptors");
+  return ASH_OK;
+}
+
+int check_members(ash_batch* b) {
+  for (size_t h = 0; h < b->m.size(); ++h)
+    if (!b->m[h]->has_basis || !b->m[h]->has_spots ||
+        !same(b->snap[h], snapshot(b->m[h])))
+      return bfail(b, ASH_ENOTREADY,
+                   "member " + std::to_string(h) +
+                       " changed since the batch was made; make it again");
+  return ASH_OK;
+}
+
+// Enqueue one forward phase (all record shapes) with counters ctr[cls][8].
+int enqueue_forward(ash_batch* b, int* ctr) {
+  for (size_t k = 0; k < b->cls.size(); ++k) {
+    const Cls& c = b->cls[k];
+    BCHK(b, btimed(b, ASH_PROF_FORWARD, [&] {
+           return launch_batch_forward(c.G, c.reduce != 0, c.fwd_grid,
+                                       b->d_desc, b->d_items + c.fwd_off,
+                                       b->d_qoff + c.qoff_fwd, ctr + 8 * k,
+                                       b->stream);
+         }), "batch forward");
+  }
+  return ASH_OK;
+}
+
+int enqueue_reduce_update(ash_batch* b, float power, bool update) {
+  BCHK(b, btimed(b, ASH_PROF_REDUCE, [&] {
+         return launch_batch_reduce(b->d_desc, b->d_rblk, (int)b->rblk.size(),
+                                    b->stream);
+       }), "batch reduce");
+  if (update)
+    BCHK(b, btimed(b, ASH_PROF_REDUCE, [&] {
+           return launch_batch_update((int)b->m.size(), b->d_desc, power,
+                                      b->stream);
+         }), "batch update");
+  return ASH_OK;
+}
+
+int enqueue_adjoint(ash_batch* b, int* ctr, int last) {
+  for (size_t k = 0; k < b->cls.size(); ++k) {
+    const Cls& c = b->cls[k];
+    BCHK(b, btimed(b, ASH_PROF_ADJOINT, [&] {
+           return launch_batch_adjoint(c.G, c.reduce != 0, c.adj_grid,
+                                       b->d_desc, b->d_items + c.adj_off,
+                                       b->d_qoff + c.qoff_adj, ctr + 8 * k,
+                                       last, b->stream);
+         }), "batch adjoint");
+  }
+  return ASH_OK;
+}
+
+int make_fields(ash_batch* b, float* const* phase) {
+  for (size_t h = 0; h < b->m.size(); ++h) {
+    ash_ctx* c = b->m[h];
+    BCHK(b, btimed(b, ASH_PROF_FIELD, [&] {
+           return launch_make_field(c->basis.g, phase[h], nullptr,
+                                    c->buf.amp_t, c->buf.field_t, b->stream);
+         }), "make_field");
+  }
+  return ASH_OK;
+}
+
+// Zeroed take counters for `launches` persistent launches of 8 queues per
+// record shape.
+int counters(ash_batch* b, size_t launches, int** out) {
+  const size_t n = launches * b->cls.size() * kXcds;
+  int rc = bgrow(b, &b->d_ctr, &b->cap_ctr, n, "queue counters");
+  if (rc) return rc;
+  BCHK(b, hipMemsetAsync(b->d_ctr, 0, n * sizeof(int), b->stream),
+       "clearing queue counters");
+  *out = b->d_ctr;
+  return ASH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ash_batch_create(ash_batch** out, int H, ash_ctx* const* members,
+                     void* stream) {
+  if (!out) return ASH_EINVAL;
+  *out = nullptr;
+  if (H < 1 || !members) return ASH_EINVAL;
+  for (int h = 0; h < H; ++h)
+    if (!members[h] || !members[h]->has_basis || !members[h]->has_spots ||
+        members[h]->device != members[0]->device)
+      return ASH_EINVAL;
+  ash_batch* b = new (std::nothrow) ash_batch();
+  if (!b) return ASH_ENOMEM;
+  b->device = members[0]->device;
+  b->n_cu = members[0]->n_cu;
+  b->stream = reinterpret_cast<hipStream_t>(stream);
+  b->m.assign(members, members + H);
+  for (int h = 0; h < H; ++h) {
+    b->snap.push_back(snapshot(members[h]));
+    const Geom& g = members[h]->basis.g;
+    auto it = std::find_if(b->cls.begin(), b->cls.end(), [&](const Cls& c) {
+      return c.G == g.groups && c.reduce == g.reduce;
+    });
+    if (it == b->cls.end()) {
+      Cls c;
+      c.G = g.groups;
+      c.reduce = g.reduce;
+      b->cls.push_back(c);
+      it = b->cls.end() - 1;
+    }
+    it->holos.push_back(h);
+  }
+  int rc = buse(b);
+  if (!rc) {
+    if (hipMalloc(reinterpret_cast<void**>(&b->d_desc),
+                  H * sizeof(HoloDesc)) != hipSuccess) {
+      (void)hipGetLastError();
+      b->d_desc = nullptr;
+      rc = ASH_ENOMEM;
+    }
+  }
+  if (!rc) rc = plan(b);
+  if (rc) {
+    ash_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return ASH_OK;
+}
+
+int ash_batch_destroy(ash_batch* b) {
+  if (!b) return ASH_EINVAL;
+  (void)buse(b);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  bfree(b->d_desc);
+  bfree(b->d_partial);
+  bfree(b->d_red);
+  bfree(b->d_items);
+  bfree(b->d_rblk);
+  bfree(b->d_qoff);
+  bfree(b->d_ctr);
+  for (auto& r : b->prof) {
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  for (auto e : b->pool) (void)hipEventDestroy(e);
+  delete b;
+  return ASH_OK;
+}
+
+const char* ash_batch_last_error(const ash_batch* b) {
+  return b ? b->err.c_str() : "";
+}
+
+int ash_batch_set_stream(ash_batch* b, void* stream) {
+  if (!b) return ASH_EINVAL;
+  b->stream = reinterpret_cast<hipStream_t>(stream);
+  return ASH_OK;
+}
+
+int ash_batch_wgs(ash_batch* b, float* const* phase_dev,
+                  float* const* weights_dev, int n_iter,
+                  const ash_wgs_params* params) {
+  if (!b) return ASH_EINVAL;
+  b->err.clear();
+  if (!phase_dev || !weights_dev || n_iter < 0)
+    return bfail(b, ASH_EINVAL, "phases, weights and n_iter >= 0 required");
+  for (size_t h = 0; h < b->m.size(); ++h)
+    if (!phase_dev[h] || !weights_dev[h])
+      return bfail(b, ASH_EINVAL, "null phase or weights");
+  const float power = params ? params->power : 1.0f;
+  if (!isfinite(power)) return bfail(b, ASH_EINVAL, "power must be finite");
+  if (n_iter == 0) return ASH_OK;
+  int rc;
+  if ((rc = buse(b)) || (rc = check_members(b)) ||
+      (rc = upload_desc(b, phase_dev, weights_dev)))
+    return rc;
+  int* ctr = nullptr;
+  if ((rc = counters(b, 2 * (size_t)n_iter, &ctr))) return rc;
+  const size_t per = b->cls.size() * kXcds;
+  if ((rc = make_fields(b, phase_dev))) return rc;
+  for (int it = 0; it < n_iter; ++it) {
+    if ((rc = enqueue_forward(b, ctr + (2 * it) * per)) ||
+        (rc = enqueue_reduce_update(b, power, true)) ||
+        (rc = enqueue_adjoint(b, ctr + (2 * it + 1) * per, it == n_iter - 1)))
+      return rc;
+  }
+  return ASH_OK;
+}
+
+int ash_batch_tune(ash_batch* b, float* const* phase_dev,
+                   const char* table_out) {
+  if (!b) return ASH_EINVAL;
+  b->err.clear();
+  if (!phase_dev) return bfail(b, ASH_EINVAL, "phases required");
+  int rc;
+  if ((rc = buse(b)) || (rc = check_members(b))) return rc;
+  if ((rc = upload_desc(b, phase_dev, nullptr)) ||
+      (rc = make_fields(b, phase_dev)))
+    return rc;
+  const int n_cand = (int)(sizeof(kTuneCandidates) / sizeof(int));
+  constexpr int kWarm = 1, kTimed = 3;
+  std::vector<float> best_ms(b->cls.size(), 0.0f);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BCHK(b, hipEventCreate(&e0), "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return bfail(b, ASH_EHIP, "hipEventCreate");
+  }
+  const int saved_mask = b->prof_mask;
+  b->prof_mask = 0;
+  for (size_t k = 0; k < b->cls.size() && !rc; ++k) {
+    int best = b->cls[k].L;
+    float best_t = -1.0f;
+    for (int ci = 0; ci < n_cand && !rc; ++ci) {
+      b->cls[k].L = kTuneCandidates[ci];
+      if ((rc = plan(b)) || (rc = upload_desc(b, phase_dev, nullptr))) break;
+      int* ctr = nullptr;
+      if ((rc = counters(b, kWarm + kTimed, &ctr))) break;
+      float ms = 0.0f;
+      for (int r = 0; r < kWarm + kTimed && !rc; ++r) {
+        if (r == kWarm && hipEventRecord(e0, b->stream) != hipSuccess)
+          rc = bfail(b, ASH_EHIP, "hipEventRecord");
+        const Cls& c = b->cls[k];
+        hipError_t e = launch_batch_forward(
+            c.G, c.reduce != 0, c.fwd_grid, b->d_desc,
+            b->d_items + c.fwd_off, b->d_qoff + c.qoff_fwd,
+            ctr + (size_t)r * b->cls.size() * kXcds + 8 * k, b->stream);
+        if (e != hipSuccess) rc = bhip(b, e, "tuning forward");
+        if (!rc && (rc = enqueue_reduce_update(b, 1.0f, false))) break;
+      }
+      if (!rc && (hipEventRecord(e1, b->stream) != hipSuccess ||
+                  hipEventSynchronize(e1) != hipSuccess ||
+                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = bfail(b, ASH_EHIP, "timing");
+      if (!rc && (best_t < 0.0f || ms < best_t)) {
+        best_t = ms;
+        best = kTuneCandidates[ci];
+      }
+    }
+    b->cls[k].L = best;
+    best_ms[k] = best_t / kTimed;
+  }
+  b->prof_mask = saved_mask;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!rc) rc = plan(b);
+  if (rc) return rc;
+  if (table_out) {
+    FILE* f = fopen(table_out, "w");
+    if (!f) return bfail(b, ASH_EINVAL, std::string("cannot write ") + table_out);
+    fprintf(f, "# groups range_reduce range_blocks forward_plus_reduce_ms\n");
+    for (size_t k = 0; k < b->cls.size(); ++k)
+      fprintf(f, "%d %d %d %.4f\n", b->cls[k].G, b->cls[k].reduce,
+              b->cls[k].L, best_ms[k]);
+    fclose(f);
+  }
+  return ASH_OK;
+}
+
+int ash_batch_load_tuning(ash_batch* b, const char* table_in) {
+  if (!b || !table_in) return ASH_EINVAL;
+  b->err.clear();
+  FILE* f = fopen(table_in, "r");
+  if (!f) return bfail(b, ASH_EINVAL, std::string("cannot read ") + table_in);
+  char line[256];
+  int n_set = 0;
+  while (fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    int G = 0, red = 0, L = 0;
+    if (sscanf(line, "%d %d %d", &G, &red, &L) != 3) continue;
+    if (L < 1 || L > (1 << 20)) continue;
+    for (auto& c : b->cls)
+      if (c.G == G && c.reduce == red) {
+        c.L = L;
+        ++n_set;
+      }
+  }
+  fclose(f);
+  int rc = buse(b);
+  if (!rc) rc = plan(b);
+  return rc ? rc : ASH_OK;
+}
+
+int ash_batch_get_info(const ash_batch* b, ash_batch_info* out) {
+  if (!b || !out) return ASH_EINVAL;
+  memset(out, 0, sizeof *out);
+  out->holograms = (int32_t)b->m.size();
+  out->shapes = (int32_t)b->cls.size();
+  for (size_t k = 0; k < b->cls.size() && k < 4; ++k) {
+    out->groups[k] = b->cls[k].G;
+    out->range_blocks[k] = b->cls[k].L;
+  }
+  out->items = (int64_t)b->items.size();
+  out->evals_per_transform = b->evals_per_transform;
+  return ASH_OK;
+}
+
+int ash_batch_profile_enable(ash_batch* b, int mask) {
+  if (!b) return ASH_EINVAL;
+  if (mask & ~ASH_PROF_ALL) return bfail(b, ASH_EINVAL, "unknown category bits");
+  b->prof_mask = mask;
+  return ASH_OK;
+}
+
+int ash_batch_profile_read(ash_batch* b, double* ms_out,
+                           int64_t* launches_out) {
+  if (!b) return ASH_EINVAL;
+  int rc = buse(b);
+  if (rc) return rc;
+  double ms[4] = {0, 0, 0, 0};
+  int64_t n[4] = {0, 0, 0, 0};
+  hipError_t e = hipStreamSynchronize(b->stream);
+  for (auto& r : b->prof) {
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.start, r.stop);
+    ms[r.cat] += t;
+    n[r.cat] += 1;
+    b->pool.push_back(r.start);
+    b->pool.push_back(r.stop);
+  }
+  b->prof.clear();
+  if (e != hipSuccess) return bhip(b, e, "reading kernel timings");
+  for (int k = 0; k < 4; ++k) {
+    if (ms_out) ms_out[k] = ms[k];
+    if (launches_out) launches_out[k] = n[k];
+  }
+  return ASH_OK;
+}
+
+}  // extern "C"

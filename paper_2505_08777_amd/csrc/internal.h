@@ -159,6 +159,50 @@ hipError_t launch_adam(const Geom& b, float* phase, float* m, float* v,
                        float eps, float bc1, float bc2, const float* amp_t,
                        unsigned* nf_t, hipStream_t s);
 
+// ---- batched form ----
+constexpr int kRowsPerSlice = 32;  // forward partial rows per reduce slice
+
+// One hologram of a batch as the batched kernels see it (device copy).
+struct HoloDesc {
+  const u32x4* pixtab;
+  u32x4* nf_t;
+  const u32x4* spotrec;
+  const u32x4* offtab;
+  u32x4* ypol;
+  const float* amp_t;
+  float2* partial;  // [n_ranges][N]
+  float2* red;      // [slices][N]
+  const float* target;
+  float* W;      // spot weights (caller's)
+  float* phase;  // phase (caller's): written by the last adjoint
+  float2* Ebuf;
+  long n_blk;
+  int N, nx, ny, tiles_x;
+  int L;         // pixel blocks per forward range
+  int n_ranges;  // ceil(n_blk / L)
+  int slices;    // ceil(n_ranges / kRowsPerSlice)
+  float t_norm, eff_denom;
+};
+
+// Work items: forward {holo, range, spot block, 0}; adjoint {holo, first
+// wave (tile * kBlkPerTile + row), rows, 0}; reduce {holo, first spot,
+// slice, 0}.
+// The items of a persistent launch sit in 8 per-XCD queues:
+// items[qoff[x] .. qoff[x+1]) with take counters ctr[x].
+hipError_t launch_batch_forward(int G, bool reduce, int grid,
+                                const HoloDesc* d, const int4* items,
+                                const int* qoff, int* ctr, hipStream_t s);
+hipError_t launch_batch_adjoint(int G, bool reduce, int grid,
+                                const HoloDesc* d, const int4* items,
+                                const int* qoff, int* ctr, int last,
+                                hipStream_t s);
+hipError_t launch_batch_reduce(const HoloDesc* d, const int4* blocks,
+                               int n_blocks, hipStream_t s);
+hipError_t launch_batch_update(int H, const HoloDesc* d, float power,
+                               hipStream_t s);
+// Resident blocks per CU of the persistent kernels.
+int batch_blocks_per_cu(int G, bool reduce, bool forward);
+
 }  // namespace ash
 
 struct ash_prof_rec {

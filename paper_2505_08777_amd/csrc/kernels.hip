@@ -62,6 +62,16 @@ constexpr int kAnchorJ = kTileH / 2;
 constexpr unsigned kBf16One = 0x3F80u;
 constexpr unsigned kBf16MinusOne = 0xBF80u;
 
+// Global-memory pointers.  The transforms take their tables through
+// pointers in the global address space, so that the compiler emits global
+// loads with scalar base addresses; pointers read from memory (the batch's
+// descriptors) are generic and are converted with as_global.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T* as_global(T* p) {
+  return (GLOBAL T*)p;
+}
+
 __host__ __device__ int slots_per_mode(int pieces) {
   return pieces == 2 ? 3 : 6;
 }
@@ -586,49 +596,38 @@ __device__ __forceinline__ void accumulate(const floatx16& th, float m,
   }
 }
 
-// Forward: wave = 32 spots x a contiguous range of 32-pixel blocks (tile
-// rows, tile order); the ranges split the pixel blocks of the SLM evenly.
-// Blocks are handed to the XCDs round-robin by linear id; range r belongs
-// to XCD r % 8, and the waves of one XCD enumerate (range, spot block)
-// pairs with the spot block fastest, so all spot blocks of a range run on
-// one XCD at neighbouring slots and its L2 serves the range's records to
-// all of them.  E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))).
+// Forward sum of one wave: the 32 spots of spot block mb over the pixel
+// blocks [b0, b1) (tile rows, tile order).  Operand A is the spot record,
+// B the pixel record of a block; each lane keeps 16 spot rows, and a
+// butterfly over the 32 lanes of each half-wave finishes the pixel sums,
+// written to row[k] for the block's spots k < N.
+// E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))).
 template <int G, bool kReduce>
-__global__ __launch_bounds__(kBlock) void k_forward(
-    int N, long n_blk, int groups, const u32x4* __restrict__ pixtab,
-    const u32x4* __restrict__ nf_t, const u32x4* __restrict__ spotrec,
-    const u32x4* __restrict__ offtab, float2* __restrict__ partial) {
+__device__ __forceinline__ void forward_range(
+    int N, int mb, long b0, long b1, const GLOBAL u32x4* __restrict__ pixtab,
+    const GLOBAL u32x4* __restrict__ nf_t,
+    const GLOBAL u32x4* __restrict__ spotrec,
+    const GLOBAL u32x4* __restrict__ offtab, float2* __restrict__ row) {
   const int lane = threadIdx.x & (kWave - 1);
   const int h = lane >> 5, q = lane & 31;
-  const int n_mb = (N + 31) / 32;
-  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
-  // the wave index is uniform over the wave; say so, so that the range
-  // bounds and record addresses live in scalar registers
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const long v = (long)slot * (kBlock / kWave) + wave;
-  if (v >= (long)(groups / kXcds) * n_mb) return;  // wave-uniform exit
-  const int gi = (int)(v / n_mb) * kXcds + xcd;  // pixel range
-  const int mb = (int)(v % n_mb);                // spot block
-  const int NP = n_mb * 32;  // spot stride of the per-tile slot table
+  const int NP = (N + 31) / 32 * 32;  // spot stride of the per-tile slots
   u32x4 S[G];
 #pragma unroll
   for (int g = 0; g < G; ++g)
     S[g] = spotrec[(((long)mb * G + g) * 2 + h) * 32 + q];
   const u32x4 s_last = S[G - 1];
-  const long b0 = n_blk * gi / groups;
-  const long b1 = n_blk * (gi + 1) / groups;
   float er[16], ei[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) er[i] = ei[i] = 0.0f;
-  const u32x4* __restrict__ ot_k = offtab + (long)h * NP + mb * 32 + q;
+  const GLOBAL u32x4* __restrict__ ot_k = offtab + (long)h * NP + mb * 32 + q;
   // tiles of the range; the tile slots of the lane's spot once per tile
   for (long b = b0; b < b1;) {
     const long t = b / kBlkPerTile;
     const int r0 = (int)(b - t * kBlkPerTile);
     const int r1 = (int)min((long)kBlkPerTile, r0 + (b1 - b));
     S[G - 1] = s_last | ot_k[t * 2 * NP];
-    const u32x4* __restrict__ px = pixtab + (t * G * 2 + h) * kTile + q;
-    const u32x4* __restrict__ pn = nf_t + t * kTile + q;
+    const GLOBAL u32x4* __restrict__ px = pixtab + (t * G * 2 + h) * kTile + q;
+    const GLOBAL u32x4* __restrict__ pn = nf_t + t * kTile + q;
     for (int r = r0; r < r1; ++r) {
       u32x4 X[G];
 #pragma unroll
@@ -645,8 +644,33 @@ __global__ __launch_bounds__(kBlock) void k_forward(
   }
   bfly_reduce(er, ei, q);
   const int ko = mb * 32 + mfma_row(bfly_index(q), h);
-  if ((q & 1) == 0 && ko < N)
-    partial[(long)gi * N + ko] = make_float2(er[0], ei[0]);
+  if ((q & 1) == 0 && ko < N) row[ko] = make_float2(er[0], ei[0]);
+}
+
+// Forward of one hologram: wave = 32 spots x a contiguous range of pixel
+// blocks; the ranges split the pixel blocks of the SLM evenly.  Blocks are
+// handed to the XCDs round-robin by linear id; range r belongs to XCD r % 8,
+// and the waves of one XCD enumerate (range, spot block) pairs with the
+// spot block fastest, so all spot blocks of a range run on one XCD at
+// neighbouring slots and its L2 serves the range's records to all of them.
+template <int G, bool kReduce>
+__global__ __launch_bounds__(kBlock) void k_forward(
+    int N, long n_blk, int groups, const u32x4* __restrict__ pixtab,
+    const u32x4* __restrict__ nf_t, const u32x4* __restrict__ spotrec,
+    const u32x4* __restrict__ offtab, float2* __restrict__ partial) {
+  const int n_mb = (N + 31) / 32;
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  // the wave index is uniform over the wave; say so, so that the range
+  // bounds and record addresses live in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const long v = (long)slot * (kBlock / kWave) + wave;
+  if (v >= (long)(groups / kXcds) * n_mb) return;  // wave-uniform exit
+  const int gi = (int)(v / n_mb) * kXcds + xcd;  // pixel range
+  const int mb = (int)(v % n_mb);                // spot block
+  forward_range<G, kReduce>(N, mb, n_blk * gi / groups,
+                            n_blk * (gi + 1) / groups, as_global(pixtab),
+                            as_global(nf_t), as_global(spotrec),
+                            as_global(offtab), partial + (long)gi * N);
 }
 
 template <int G>
@@ -801,13 +825,14 @@ struct OpMin {
   __device__ float operator()(float a, float b) const { return fminf(a, b); }
 };
 
-__global__ __launch_bounds__(kUpd) void k_wgs_update(
+// The weighted-GS farfield update of one hologram by one kUpd-thread block
+// (sh: kUpd floats of LDS).
+__device__ void wgs_update_block(
     int N, int slices, const float2* __restrict__ red,
     const float* __restrict__ t, float t_norm, float* __restrict__ W,
     float power, float eff_denom, u32x4* __restrict__ ypol,
     float2* __restrict__ Ebuf, float2* __restrict__ E_extra,
-    float* __restrict__ stats) {
-  __shared__ float sh[kUpd];
+    float* __restrict__ stats, float* sh) {
   const int tid = threadIdx.x;
   // pass 1: fields, |E|^2 and normalised intensities I = |E|^2 / t^2
   float s_a2 = 0.0f, s_I = 0.0f, mx = 0.0f, mn = INFINITY;
@@ -862,6 +887,17 @@ __global__ __launch_bounds__(kUpd) void k_wgs_update(
     stats[2] = meanI > 0.0f ? sqrtf(var) / meanI : 0.0f;
     stats[3] = sum_a2;
   }
+}
+
+__global__ __launch_bounds__(kUpd) void k_wgs_update(
+    int N, int slices, const float2* __restrict__ red,
+    const float* __restrict__ t, float t_norm, float* __restrict__ W,
+    float power, float eff_denom, u32x4* __restrict__ ypol,
+    float2* __restrict__ Ebuf, float2* __restrict__ E_extra,
+    float* __restrict__ stats) {
+  __shared__ float sh[kUpd];
+  wgs_update_block(N, slices, red, t, t_norm, W, power, eff_denom, ypol, Ebuf,
+                   E_extra, stats, sh);
 }
 
 hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
@@ -1014,28 +1050,22 @@ __device__ inline float tv_grad_at(const float* __restrict__ ph, int nx,
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint: wave = 32 pixels (one tile row) x all spots; the four waves of a
-// block are four rows of one tile.
-// g(x) = sum_k |y_k| exp(2 pi i (tau_k(x) + psi_k)); the epilogue writes g,
-// arg g and/or the next nearfield record in tile order.
+// Adjoint of one wave: the 32 pixels of one tile row (first pixel p0 of
+// tile `tile`) over all spots.  g(x) = sum_k |y_k| exp(2 pi i (tau_k(x) +
+// psi_k)); the epilogue writes g, arg g, the next nearfield record in tile
+// order, or the phase gradient (see AdjOut).  `wv` indexes the per-wave TV
+// sums.
 // ---------------------------------------------------------------------------
 template <int G, bool kReduce>
-__global__ __launch_bounds__(kBlock) void k_adjoint(
-    int N, int nx, int ny, int tiles_x, const u32x4* __restrict__ pixtab,
-    const u32x4* __restrict__ spotrec, const u32x4* __restrict__ offtab,
-    const u32x4* __restrict__ ypol, const float* __restrict__ amp_t,
-    AdjOut o) {
+__device__ __forceinline__ void adjoint_row(
+    int N, int nx, int ny, int tiles_x, int tile, int p0, long wv,
+    const GLOBAL u32x4* __restrict__ pixtab,
+    const GLOBAL u32x4* __restrict__ spotrec,
+    const GLOBAL u32x4* __restrict__ offtab,
+    const GLOBAL u32x4* __restrict__ ypol,
+    const GLOBAL float* __restrict__ amp_t, const AdjOut& o) {
   const int lane = threadIdx.x & (kWave - 1);
   const int h = lane >> 5, q = lane & 31;
-  // blocks reach the XCDs round-robin; give each XCD a contiguous run of
-  // blocks in tile order so that the blocks of one tile share its L2
-  const int nblk = gridDim.x, per = nblk / kXcds, extra = nblk % kXcds;
-  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
-  const int lin = xcd * per + min(xcd, extra) + slot;
-  const int wv = lin * (kBlock / kWave) +
-                 __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int tile = wv / kBlkPerTile;
-  const int p0 = (wv % kBlkPerTile) * 32;  // first pixel of the block
   u32x4 X[G];
 #pragma unroll
   for (int gg = 0; gg < G; ++gg)
@@ -1043,9 +1073,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
   const int NB = (N + 31) / 32, NP = NB * 32;
   // per spot block: the lane's spot record, tile slots and spot field;
   // spot tables are padded to whole blocks with zero records
-  const u32x4* __restrict__ sp = spotrec + h * 32 + q;
-  const u32x4* __restrict__ ot_t = offtab + ((long)tile * 2 + h) * NP + q;
-  const u32x4* __restrict__ yq = ypol + (long)h * NP + q;
+  const GLOBAL u32x4* __restrict__ sp = spotrec + h * 32 + q;
+  const GLOBAL u32x4* __restrict__ ot_t = offtab + ((long)tile * 2 + h) * NP + q;
+  const GLOBAL u32x4* __restrict__ yq = ypol + (long)h * NP + q;
   float gr[16], gi[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) gr[i] = gi[i] = 0.0f;
@@ -1101,6 +1131,27 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
   }
 }
 
+
+// Adjoint of one hologram: the four waves of a block are four rows of one
+// tile; blocks reach the XCDs round-robin, so each XCD gets a contiguous run
+// of blocks in tile order and the blocks of one tile share its L2.
+template <int G, bool kReduce>
+__global__ __launch_bounds__(kBlock) void k_adjoint(
+    int N, int nx, int ny, int tiles_x, const u32x4* __restrict__ pixtab,
+    const u32x4* __restrict__ spotrec, const u32x4* __restrict__ offtab,
+    const u32x4* __restrict__ ypol, const float* __restrict__ amp_t,
+    AdjOut o) {
+  const int nblk = gridDim.x, per = nblk / kXcds, extra = nblk % kXcds;
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const int lin = xcd * per + min(xcd, extra) + slot;
+  const int wv = lin * (kBlock / kWave) +
+                 __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  adjoint_row<G, kReduce>(N, nx, ny, tiles_x, wv / kBlkPerTile,
+                          (wv % kBlkPerTile) * 32, wv, as_global(pixtab),
+                          as_global(spotrec), as_global(offtab),
+                          as_global(ypol), as_global(amp_t), o);
+}
+
 template <int G>
 static hipError_t adj_g(const Geom& b, int N, const unsigned short* pixtab,
                         const unsigned short* spotrec, const unsigned* offtab,
@@ -1128,6 +1179,190 @@ hipError_t launch_adjoint(const Geom& b, int N, const unsigned short* pixtab,
 #undef X
     default:
       return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched form: persistent launches over the work items of many holograms.
+// Each wave takes items from its XCD's queue (block id mod 8, as blocks
+// reach the XCDs round-robin), then from the other queues in turn; it asks
+// for the next item before computing the current one so that the atomic's
+// latency is hidden.  Every wave stops after the eighth queue runs dry.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_take(int* ctr) {
+  int v = 0;
+  if ((threadIdx.x & (kWave - 1)) == 0) v = atomicAdd(ctr, 1);
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int4 uniform_item(const int4* items, long i) {
+  const int4 it = items[i];
+  return make_int4(__builtin_amdgcn_readfirstlane(it.x),
+                   __builtin_amdgcn_readfirstlane(it.y),
+                   __builtin_amdgcn_readfirstlane(it.z), 0);
+}
+
+template <typename F>
+__device__ __forceinline__ void drain_queues(const int4* __restrict__ items,
+                                             const int* __restrict__ qoff,
+                                             int* __restrict__ ctr, F&& work) {
+  const int home = blockIdx.x % kXcds;
+  for (int qi = 0; qi < kXcds; ++qi) {
+    const int x = (home + qi) % kXcds;
+    const int base = qoff[x], cnt = qoff[x + 1] - base;
+    int idx = wave_take(ctr + x);
+    while (idx < cnt) {
+      const int4 it = uniform_item(items, (long)base + idx);
+      const int nxt = wave_take(ctr + x);
+      work(it);
+      idx = nxt;
+    }
+  }
+}
+
+template <int G, bool kReduce>
+__global__ __launch_bounds__(kBlock) void k_batch_forward(
+    const HoloDesc* __restrict__ hd, const int4* __restrict__ items,
+    const int* __restrict__ qoff, int* __restrict__ ctr) {
+  drain_queues(items, qoff, ctr, [&](const int4& it) {
+    const HoloDesc& d = hd[it.x];
+    const long b0 = (long)it.y * d.L;
+    const long b1 = min(b0 + d.L, d.n_blk);
+    forward_range<G, kReduce>(d.N, it.z, b0, b1, as_global(d.pixtab),
+                              as_global(d.nf_t), as_global(d.spotrec),
+                              as_global(d.offtab), d.partial + (long)it.y * d.N);
+  });
+}
+
+template <int G, bool kReduce>
+__global__ __launch_bounds__(kBlock) void k_batch_adjoint(
+    const HoloDesc* __restrict__ hd, const int4* __restrict__ items,
+    const int* __restrict__ qoff, int* __restrict__ ctr, int last) {
+  drain_queues(items, qoff, ctr, [&](const int4& it) {
+    const HoloDesc& d = hd[it.x];
+    AdjOut o;
+    o.outs = last ? kOutPhase : kOutField;
+    o.phase = d.phase;
+    o.nf_t = reinterpret_cast<unsigned*>(d.nf_t);
+    for (int wv = it.y; wv < it.y + it.z; ++wv)  // it.z tile rows
+      adjoint_row<G, kReduce>(d.N, d.nx, d.ny, d.tiles_x, wv / kBlkPerTile,
+                              (wv % kBlkPerTile) * 32, wv,
+                              as_global(d.pixtab), as_global(d.spotrec),
+                              as_global(d.offtab), as_global(d.ypol),
+                              as_global(d.amp_t), o);
+  });
+}
+
+// one block per {holo, 64 spots, slice of kRowsPerSlice forward ranges}
+__global__ __launch_bounds__(64) void k_batch_reduce(
+    const HoloDesc* __restrict__ hd, const int4* __restrict__ blocks) {
+  const int4 bl = blocks[blockIdx.x];
+  const HoloDesc& d = hd[bl.x];
+  const int k = bl.y + threadIdx.x;
+  if (k >= d.N) return;
+  const int r0 = bl.z * kRowsPerSlice;
+  const int r1 = min(r0 + kRowsPerSlice, d.n_ranges);
+  float sr = 0.0f, si = 0.0f, cr = 0.0f, ci = 0.0f;
+  for (int r = r0; r < r1; ++r) {
+    const float2 v = d.partial[(long)r * d.N + k];
+    kahan_add(sr, cr, v.x);
+    kahan_add(si, ci, v.y);
+  }
+  d.red[(long)bl.z * d.N + k] = make_float2(sr, si);
+}
+
+__global__ __launch_bounds__(kUpd) void k_batch_update(
+    const HoloDesc* __restrict__ hd, float power) {
+  __shared__ float sh[kUpd];
+  const HoloDesc& d = hd[blockIdx.x];
+  wgs_update_block(d.N, d.slices, d.red, d.target, d.t_norm, d.W, power,
+                   d.eff_denom, d.ypol, d.Ebuf, nullptr, nullptr, sh);
+}
+
+template <int G, bool kReduce>
+static hipError_t bfwd_g(int grid, const HoloDesc* d, const int4* items,
+                         const int* qoff, int* ctr, hipStream_t s) {
+  hipLaunchKernelGGL((k_batch_forward<G, kReduce>), dim3(grid), dim3(kBlock),
+                     0, s, d, items, qoff, ctr);
+  return hipGetLastError();
+}
+
+template <int G, bool kReduce>
+static hipError_t badj_g(int grid, const HoloDesc* d, const int4* items,
+                         const int* qoff, int* ctr, int last, hipStream_t s) {
+  hipLaunchKernelGGL((k_batch_adjoint<G, kReduce>), dim3(grid), dim3(kBlock),
+                     0, s, d, items, qoff, ctr, last);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_forward(int G, bool reduce, int grid,
+                                const HoloDesc* d, const int4* items,
+                                const int* qoff, int* ctr, hipStream_t s) {
+  switch (G) {
+#define X(n)                                                       \
+  case n:                                                          \
+    return reduce ? bfwd_g<n, true>(grid, d, items, qoff, ctr, s)  \
+                  : bfwd_g<n, false>(grid, d, items, qoff, ctr, s);
+    ASH_G_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_batch_adjoint(int G, bool reduce, int grid,
+                                const HoloDesc* d, const int4* items,
+                                const int* qoff, int* ctr, int last,
+                                hipStream_t s) {
+  switch (G) {
+#define X(n)                                                             \
+  case n:                                                                \
+    return reduce ? badj_g<n, true>(grid, d, items, qoff, ctr, last, s)  \
+                  : badj_g<n, false>(grid, d, items, qoff, ctr, last, s);
+    ASH_G_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_batch_reduce(const HoloDesc* d, const int4* blocks,
+                               int n_blocks, hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_reduce, dim3(n_blocks), dim3(64), 0, s, d,
+                     blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_update(int H, const HoloDesc* d, float power,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_update, dim3(H), dim3(kUpd), 0, s, d, power);
+  return hipGetLastError();
+}
+
+template <typename K>
+static int occupancy(K kern) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kBlock, 0) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n > 0 ? n : 1;
+}
+
+int batch_blocks_per_cu(int G, bool reduce, bool forward) {
+  switch (G) {
+#define X(n)                                                          \
+  case n:                                                             \
+    return forward ? (reduce ? occupancy(k_batch_forward<n, true>)    \
+                             : occupancy(k_batch_forward<n, false>))  \
+                   : (reduce ? occupancy(k_batch_adjoint<n, true>)    \
+                             : occupancy(k_batch_adjoint<n, false>));
+    ASH_G_CASES(X)
+#undef X
+    default:
+      return 1;
   }
 }
 

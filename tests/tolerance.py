@@ -69,19 +69,3 @@ def assert_phase(got, ref_phase, ref_field, bar=PHASE_RAD, what="phase",
 GRAD_REL = 1e-4
 GRAD_FD_REL = 1e-3
 
-
-def near_tv_wrap(phi, pixels, nx, ny, h=1e-3):
-    """Flat pixels whose phase enters a TV difference within h of an odd
-    multiple of pi (a central difference there crosses the wrap)."""
-    phi = np.asarray(phi, dtype=np.float64).reshape(ny, nx)
-    out = []
-    for p in pixels:
-        j, i = divmod(int(p), nx)
-        ds = []
-        if i + 1 < nx: ds.append(phi[j, i + 1] - phi[j, i])
-        if j + 1 < ny: ds.append(phi[j + 1, i] - phi[j, i])
-        if i > 0: ds.append(phi[j, i] - phi[j, i - 1])
-        if j > 0: ds.append(phi[j, i] - phi[j - 1, i])
-        r = [abs(np.mod(d - np.pi, 2 * np.pi)) for d in ds]
-        out.append(any(min(x, 2 * np.pi - x) < h for x in r))
-    return np.array(out, dtype=bool)
