@@ -193,10 +193,10 @@ int plan(ash_batch* b) {
     Buffers& B = c->buf;
     HoloDesc& d = b->desc[h];
     d.pixtab = reinterpret_cast<const u32x4*>(B.pixtab);
-    d.nf_t = reinterpret_cast<u32x4*>(B.field_t);
+    d.nf_t = B.field_t;
     d.spotrec = reinterpret_cast<const u32x4*>(B.spotrec);
-    d.offtab = reinterpret_cast<const u32x4*>(B.offtab);
-    d.ypol = reinterpret_cast<u32x4*>(B.y);
+    d.offtab = B.offtab;
+    d.ypol = B.y;
     d.amp_t = B.amp_t;
     d.target = B.target;
     d.Ebuf = reinterpret_cast<float2*>(B.Ebuf);
@@ -384,7 +384,8 @@ int make_fields(ash_batch* b, float* const* phase) {
     ash_ctx* c = b->m[h];
     BCHK(b, btimed(b, ASH_PROF_FIELD, [&] {
            return launch_make_field(c->basis.g, phase[h], nullptr,
-                                    c->buf.amp_t, c->buf.field_t, b->stream);
+                                    c->buf.amp_t, c->buf.pixtab,
+                                    c->buf.field_t, b->stream);
          }), "make_field");
   }
   return ASH_OK;

@@ -452,7 +452,7 @@ int ash_set_basis(ash_ctx* c, int nx, int ny, double cx, double cy, double R,
   const size_t npix = (size_t)g.n_tiles * kTile;
   const size_t nl1 = (size_t)std::max(g.nl, 1);
   if ((rc = dalloc(c, &B.amp_t, npix, "amplitude")) ||
-      (rc = dalloc(c, &B.field_t, 4 * npix, "nearfield")) ||
+      (rc = dalloc(c, &B.field_t, 5 * npix, "nearfield")) ||
       (rc = dalloc(c, &B.aff_dev, 3 * (size_t)D, "basis affine terms")) ||
       (rc = dalloc(c, &B.nlmode_dev, nl1, "modes")) ||
       (rc = dalloc(c, &B.tilez, 3 * (size_t)g.n_tiles * nl1, "tile basis")) ||
@@ -648,7 +648,7 @@ int ash_forward(ash_ctx* c, const float* phase_dev, const float* field_dev,
   const int N = c->spots.N;
   HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
            return launch_make_field(g, phase_dev, field_dev, B.amp_t,
-                                    B.field_t, c->stream);
+                                    B.pixtab, B.field_t, c->stream);
          }), "make_field");
   HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
            return launch_forward(g, N, c->plan, B.pixtab, B.field_t,
@@ -710,7 +710,7 @@ int ash_wgs_iterate(ash_ctx* c, float* phase_dev, float* weights_dev,
   const float eff_denom = (float)((double)g.nx * g.ny * c->basis.amp_sum2);
   HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
            return launch_make_field(g, phase_dev, nullptr, B.amp_t,
-                                    B.field_t, c->stream);
+                                    B.pixtab, B.field_t, c->stream);
          }), "make_field");
   for (int it = 0; it < n_iter; ++it) {
     const bool last = it == n_iter - 1;
@@ -812,7 +812,7 @@ int ash_adam_iterate(ash_ctx* c, float* phase_dev, float* m_dev, float* v_dev,
   const int n_tvp = g.n_tiles * kBlkPerTile;
   HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
            return launch_make_field(g, phase_dev, nullptr, B.amp_t,
-                                    B.field_t, c->stream);
+                                    B.pixtab, B.field_t, c->stream);
          }), "make_field");
   for (int it = 0; it < n_steps; ++it) {
     const int step = step0 + it + 1;
@@ -850,7 +850,7 @@ int ash_adam_iterate(ash_ctx* c, float* phase_dev, float* m_dev, float* v_dev,
     const float bc2 = (float)(1.0 - pow((double)pr.beta2, step));
     HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
              return launch_adam(g, phase_dev, m_dev, v_dev, B.grad, pr.lr,
-                                pr.beta1, pr.beta2, pr.eps, bc1, bc2, B.amp_t,
+                                pr.beta1, pr.beta2, pr.eps, bc1, bc2, B.pixtab,
                                 B.field_t, c->stream);
            }), "adam");
   }

@@ -12,6 +12,7 @@
 namespace ash {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // Pixel tile: 32 columns x 16 rows.  Tiles are stored tile-major, pixels
 // row-major inside a tile, ragged tiles padded with zero-amplitude pixels.
@@ -60,7 +61,7 @@ struct Buffers {
   // basis
   unsigned short* pixtab = nullptr;  // [tile][group][half][kTile][8] bf16
   float* amp_t = nullptr;            // [n_tiles][kTile]
-  unsigned* field_t = nullptr;       // [n_tiles][kTile][4] nearfield records
+  unsigned* field_t = nullptr;  // nearfield: [n_pix] u32x4 records, [n_pix] f32
   double* aff_dev = nullptr;         // [D][3]
   int* nlmode_dev = nullptr;         // [nl]
   double* tilez = nullptr;           // [n_tiles][nl][3] Z^nl, d/di, d/dj
@@ -70,9 +71,9 @@ struct Buffers {
   size_t cap_pixtab = 0;             // in unsigned shorts
   // spots (NP: N padded to whole 32-spot blocks, padding zero)
   unsigned short* spotrec = nullptr;  // [N/32][group][half][32][8] bf16
-  unsigned* offtab = nullptr;         // [n_tiles][half][NP][4] per-tile slots
+  unsigned* offtab = nullptr;   // [n_tiles][half][NP] u32x4 last-group slots
   float* target = nullptr;            // [N]
-  unsigned* y = nullptr;              // [half][NP][4] spot-field records
+  unsigned* y = nullptr;        // spot fields: [NP] 2 x u32 phase, [NP] f32
   float* Ebuf = nullptr;              // [N][2] fields of the last forward
   double* w64 = nullptr;              // [N][D] coefficients (radians)
   double* spot64 = nullptr;           // [N][3] constant, alpha, beta (turns)
@@ -114,7 +115,8 @@ hipError_t launch_prep_spots(const Geom& b, int N, const double* d_w,
                              hipStream_t s);
 hipError_t launch_make_field(const Geom& b, const float* phase,
                              const float* field, const float* amp_t,
-                             unsigned* nf_t, hipStream_t s);
+                             const unsigned short* pixtab, unsigned* nf_t,
+                             hipStream_t s);
 hipError_t launch_to_polar(int N, const float* y, unsigned* ypol,
                            hipStream_t s);
 hipError_t launch_forward(const Geom& b, int N, const FwdPlan& p,
@@ -156,8 +158,9 @@ hipError_t launch_loss_finish(int n_tvp, const float* tvp, float tv_sum_scale,
                               hipStream_t s);
 hipError_t launch_adam(const Geom& b, float* phase, float* m, float* v,
                        const float* grad, float lr, float beta1, float beta2,
-                       float eps, float bc1, float bc2, const float* amp_t,
-                       unsigned* nf_t, hipStream_t s);
+                       float eps, float bc1, float bc2,
+                       const unsigned short* pixtab, unsigned* nf_t,
+                       hipStream_t s);
 
 // ---- batched form ----
 constexpr int kRowsPerSlice = 32;  // forward partial rows per reduce slice
@@ -165,10 +168,10 @@ constexpr int kRowsPerSlice = 32;  // forward partial rows per reduce slice
 // One hologram of a batch as the batched kernels see it (device copy).
 struct HoloDesc {
   const u32x4* pixtab;
-  u32x4* nf_t;
+  unsigned* nf_t;    // nearfield planes (phase words, magnitudes)
   const u32x4* spotrec;
-  const u32x4* offtab;
-  u32x4* ypol;
+  unsigned* offtab;  // per-tile slot planes
+  unsigned* ypol;    // spot-field planes
   const float* amp_t;
   float2* partial;  // [n_ranges][N]
   float2* red;      // [slices][N]

@@ -109,34 +109,52 @@ __device__ inline void split3f(float v, unsigned* p) {
   p[2] = bf16_bits(r2);
 }
 
-// Polar value with its phase in pieces, as one 16-byte record:
-// {magnitude bits, phase_h | phase_m << 16, phase_l | tail << 16, 0}
-__device__ inline u32x4 polar_record(float mag, float turns, unsigned tail) {
+// Dynamic per-pixel and per-spot data are kept as planes, so that each
+// lane half of a matrix-core operand loads only the words it uses.
+//
+// Nearfield of the tile-ordered pixels: records [n_pix] (u32x4: the words
+// of half 0 of the pixel record's last group, i.e. its nonlinear slots
+// p 0..3 and the phase pieces with a 1 at p 4..7), then the magnitudes
+// [n_pix].
+struct NearField {
+  u32x4* rec;
+  float* mag;
+};
+__host__ __device__ inline NearField near_field(unsigned* f, long n_pix) {
+  return {reinterpret_cast<u32x4*>(f),
+          reinterpret_cast<float*>(f + 4 * n_pix)};
+}
+// Record of a pixel from its table nonlinear words and phase (turns).
+__device__ inline u32x4 nearfield_record(u32x2 nl, float turns) {
   unsigned p[3];
   split3f(turns, p);
-  u32x4 r;
-  r[0] = __float_as_uint(mag);
-  r[1] = p[0] | (p[1] << 16);
-  r[2] = p[2] | (tail << 16);
-  r[3] = 0u;
-  return r;
+  return u32x4{nl.x, nl.y, p[0] | (p[1] << 16), p[2] | (kBf16One << 16)};
+}
+// The nonlinear words (p 0..3 of the last group, half 0) of pixel `pix` of
+// `tile` in the pixel table.
+__device__ inline u32x2 pixel_nl_words(const u32x4* pixtab, int G, long tile,
+                                       int pix) {
+  return *reinterpret_cast<const u32x2*>(
+      pixtab + ((tile * G + G - 1) * 2) * kTile + pix);
 }
 
-// Spot-field records of spot k in the two halves of the adjoint's last
-// 16-slot group, [half][NP]: word 0 the magnitude, words 2..3 of half 0
-// the phase pieces at p 4..6, zero elsewhere (OR-ed into the spot record).
-__device__ inline void put_spot_field(u32x4* ypol, int NP, int k, float mag,
+// Spot fields of the adjoint: phase words [NP] (2 x u32: the phase pieces
+// at p 4..6 of the spot record's last group, words 2..3 of half 0), then
+// the magnitudes [NP].  Entries past N stay zero.
+struct SpotField {
+  u32x2* ph;
+  float* mag;
+};
+__host__ __device__ inline SpotField spot_field(unsigned* y, int NP) {
+  return {reinterpret_cast<u32x2*>(y),
+          reinterpret_cast<float*>(y + 2 * (size_t)NP)};
+}
+__device__ inline void put_spot_field(SpotField f, int k, float mag,
                                       float turns) {
   unsigned p[3];
   split3f(turns, p);
-  u32x4 r;
-  r[0] = __float_as_uint(mag);
-  r[1] = 0u;
-  r[2] = p[0] | (p[1] << 16);
-  r[3] = p[2];
-  ypol[k] = r;
-  r[2] = r[3] = 0u;
-  ypol[NP + k] = r;
+  f.ph[k] = u32x2{p[0] | (p[1] << 16), p[2]};
+  f.mag[k] = mag;
 }
 
 // Slot f of a record of 16-slot groups: group f / 16, lane half (f % 16)/8,
@@ -371,27 +389,30 @@ __global__ void k_spot_records(Geom b, int N, const double* __restrict__ w,
   spot64[3 * (long)k + 2] = bb * kInv2PiD / b.R;
 }
 
-// One thread per (tile, spot).  Output [tile][half][NP][8 bf16] (spots
-// padded with zero records to NP, a whole number of 32-spot blocks): the last
-// 16-slot group's per-tile slots (p 7 in half 0, p 8..15 in half 1), zero
-// elsewhere, to be OR-ed into the static spot record.  Also the largest
-// bound sum_s |c_s| max|Rm_s| (turns) of the in-tile remainder phase.
+// One thread per (tile, spot).  Output [tile][half][NP] u32x4: the last
+// 16-slot group of the spot record with its per-tile slots (half 0: the
+// record's nonlinear slots p 0..3 and p 7; half 1: p 8..15), spots padded
+// with zero records to NP, a whole number of 32-spot blocks.  Also the
+// largest bound sum_s |c_s| max|Rm_s| (turns) of the in-tile remainder
+// phase, and a bound on |theta|.
 __global__ void k_spot_offsets(Geom b, int N, long total,
                                const double* __restrict__ spot64,
                                const double* __restrict__ w,
                                const int* __restrict__ nlmode,
                                const double* __restrict__ tilez,
                                const float* __restrict__ rmax,
-                               u32x4* __restrict__ offtab,
+                               const u32x4* __restrict__ spotrec,
+                               unsigned* __restrict__ offtab,
                                unsigned* __restrict__ bound_bits) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= total) return;
   const int NP = (N + 31) / 32 * 32;  // spots padded to whole blocks
   const int tile = (int)(gid / NP), k = (int)(gid % NP);
+  u32x4* __restrict__ ot = reinterpret_cast<u32x4*>(offtab);
   if (k >= N) {
     const u32x4 z = {0u, 0u, 0u, 0u};
-    offtab[((long)tile * 2 + 0) * NP + k] = z;
-    offtab[((long)tile * 2 + 1) * NP + k] = z;
+    ot[((long)tile * 2 + 0) * NP + k] = z;
+    ot[((long)tile * 2 + 1) * NP + k] = z;
     return;
   }
   const int nl = b.nl;
@@ -416,15 +437,21 @@ __global__ void k_spot_offsets(Geom b, int N, long total,
   split3(t, po);
   split3(a, pa);
   split3(bs, pb);
+  // half 0: the spot record's nonlinear slots p 0..3 (so that the adjoint
+  // need not read the record's last group), and p 7
+  const u32x2 nlw = *reinterpret_cast<const u32x2*>(
+      spotrec + ((((long)k / 32) * b.groups + b.groups - 1) * 2) * 32 + k % 32);
   u32x4 h0, h1;
-  h0[0] = h0[1] = h0[2] = 0u;
+  h0[0] = nlw.x;
+  h0[1] = nlw.y;
+  h0[2] = 0u;
   h0[3] = po[0] << 16;            // p 7
   h1[0] = po[1] | (po[2] << 16);  // p 8, 9
   h1[1] = pa[0] | (pa[1] << 16);  // p 10, 11
   h1[2] = pa[2] | (pb[0] << 16);  // p 12, 13
   h1[3] = pb[1] | (pb[2] << 16);  // p 14, 15
-  offtab[((long)tile * 2 + 0) * NP + k] = h0;
-  offtab[((long)tile * 2 + 1) * NP + k] = h1;
+  ot[((long)tile * 2 + 0) * NP + k] = h0;
+  ot[((long)tile * 2 + 1) * NP + k] = h1;
   // non-negative floats order like their bit patterns
   atomicMax(bound_bits, __float_as_uint((float)bound));
   atomicMax(bound_bits + 1, __float_as_uint((float)mag));
@@ -444,8 +471,8 @@ hipError_t launch_prep_spots(const Geom& b, int N, const double* d_w,
   const long total = (long)b.n_tiles * n_pad;
   hipLaunchKernelGGL(k_spot_offsets, dim3((unsigned)((total + 255) / 256)),
                      dim3(256), 0, s, b, N, total, spot64, d_w, d_nlmode,
-                     tilez, rmax, reinterpret_cast<u32x4*>(offtab),
-                     bound_bits);
+                     tilez, rmax, reinterpret_cast<const u32x4*>(spotrec),
+                     offtab, bound_bits);
   return hipGetLastError();
 }
 
@@ -458,7 +485,7 @@ __global__ void k_make_field(Geom b, long total,
                              const float* __restrict__ phase,
                              const float2* __restrict__ field,
                              const float* __restrict__ amp_t,
-                             u32x4* __restrict__ nf_t) {
+                             const u32x4* __restrict__ pixtab, NearField nf) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= total) return;
   const int tile = (int)(gid / kTile), pix = (int)(gid % kTile);
@@ -476,34 +503,37 @@ __global__ void k_make_field(Geom b, long total,
       turns = atan2f(f.y, f.x) * kInv2Pi;
     }
   }
-  nf_t[gid] = polar_record(mag, turns, kBf16One);
+  nf.rec[gid] = nearfield_record(pixel_nl_words(pixtab, b.groups, tile, pix),
+                                 turns);
+  nf.mag[gid] = mag;
 }
 
 hipError_t launch_make_field(const Geom& b, const float* phase,
                              const float* field, const float* amp_t,
-                             unsigned* nf_t, hipStream_t s) {
+                             const unsigned short* pixtab, unsigned* nf_t,
+                             hipStream_t s) {
   const long total = (long)b.n_tiles * kTile;
   hipLaunchKernelGGL(k_make_field, dim3((unsigned)((total + 255) / 256)),
                      dim3(256), 0, s, b, total, phase,
                      reinterpret_cast<const float2*>(field), amp_t,
-                     reinterpret_cast<u32x4*>(nf_t));
+                     reinterpret_cast<const u32x4*>(pixtab),
+                     near_field(nf_t, total));
   return hipGetLastError();
 }
 
 __global__ void k_to_polar(int N, const float2* __restrict__ y,
-                           u32x4* __restrict__ ypol) {
+                           unsigned* __restrict__ ypol) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
   const float2 v = y[k];
-  put_spot_field(ypol, (N + 31) / 32 * 32, k, hypotf(v.x, v.y),
+  put_spot_field(spot_field(ypol, (N + 31) / 32 * 32), k, hypotf(v.x, v.y),
                  atan2f(v.y, v.x) * kInv2Pi);
 }
 
 hipError_t launch_to_polar(int N, const float* y, unsigned* ypol,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_to_polar, dim3((N + 255) / 256), dim3(256), 0, s, N,
-                     reinterpret_cast<const float2*>(y),
-                     reinterpret_cast<u32x4*>(ypol));
+                     reinterpret_cast<const float2*>(y), ypol);
   return hipGetLastError();
 }
 
@@ -600,45 +630,62 @@ __device__ __forceinline__ void accumulate(const floatx16& th, float m,
 // blocks [b0, b1) (tile rows, tile order).  Operand A is the spot record,
 // B the pixel record of a block; each lane keeps 16 spot rows, and a
 // butterfly over the 32 lanes of each half-wave finishes the pixel sums,
-// written to row[k] for the block's spots k < N.
+// written to row[k] for the block's spots k < N.  The last group of the
+// pixel record comes per half: half 0 from the nearfield record (the
+// table's nonlinear slots, the phase pieces and 1), half 1 (p 8..15: 1, 1,
+// di x 3, dj x 3) built in registers, so it is not read at all.
 // E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))).
 template <int G, bool kReduce>
 __device__ __forceinline__ void forward_range(
     int N, int mb, long b0, long b1, const GLOBAL u32x4* __restrict__ pixtab,
-    const GLOBAL u32x4* __restrict__ nf_t,
+    const GLOBAL u32x4* __restrict__ nf_rec,
+    const GLOBAL float* __restrict__ nf_mag,
     const GLOBAL u32x4* __restrict__ spotrec,
     const GLOBAL u32x4* __restrict__ offtab, float2* __restrict__ row) {
   const int lane = threadIdx.x & (kWave - 1);
   const int h = lane >> 5, q = lane & 31;
   const int NP = (N + 31) / 32 * 32;  // spot stride of the per-tile slots
+  // the record's last group is the per-tile slots (which carry its
+  // nonlinear slots p 0..3) with -1 at p 4..6 against the nearfield phase
+  // addresses: a wave-uniform base plus a 32-bit lane offset, so that
+  // loads take the scalar-base form
+  const unsigned lane_pix = h * kTile + q, lane_spot = h * 32 + q;
   u32x4 S[G];
+  const GLOBAL u32x4* __restrict__ sb = spotrec + (long)mb * G * 64;
 #pragma unroll
-  for (int g = 0; g < G; ++g)
-    S[g] = spotrec[(((long)mb * G + g) * 2 + h) * 32 + q];
-  const u32x4 s_last = S[G - 1];
+  for (int g = 0; g < G - 1; ++g) S[g] = sb[lane_spot + g * 64];
+  const unsigned m2 = h ? 0u : (kBf16MinusOne | (kBf16MinusOne << 16));
+  const unsigned m3 = h ? 0u : kBf16MinusOne;
   float er[16], ei[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) er[i] = ei[i] = 0.0f;
-  const GLOBAL u32x4* __restrict__ ot_k = offtab + (long)h * NP + mb * 32 + q;
+  const unsigned lane_ot = h * NP + q;
+  const GLOBAL u32x4* __restrict__ ot_k = offtab + (long)mb * 32;
+  const unsigned bdi = bf16_bits((float)(q - kAnchorI));
+  const unsigned one2 = kBf16One | (kBf16One << 16);
   // tiles of the range; the tile slots of the lane's spot once per tile
   for (long b = b0; b < b1;) {
     const long t = b / kBlkPerTile;
     const int r0 = (int)(b - t * kBlkPerTile);
     const int r1 = (int)min((long)kBlkPerTile, r0 + (b1 - b));
-    S[G - 1] = s_last | ot_k[t * 2 * NP];
-    const GLOBAL u32x4* __restrict__ px = pixtab + (t * G * 2 + h) * kTile + q;
-    const GLOBAL u32x4* __restrict__ pn = nf_t + t * kTile + q;
+    S[G - 1] = (ot_k + t * 2 * NP)[lane_ot];
+    S[G - 1][2] |= m2;
+    S[G - 1][3] |= m3;
+    const GLOBAL u32x4* __restrict__ px = pixtab + t * G * 2 * kTile;
+    const GLOBAL u32x4* __restrict__ pn = nf_rec + t * kTile;
+    const GLOBAL float* __restrict__ pm = nf_mag + t * kTile;
     for (int r = r0; r < r1; ++r) {
       u32x4 X[G];
 #pragma unroll
-      for (int g = 0; g < G; ++g) X[g] = px[g * 2 * kTile + r * 32];
-      const u32x4 nf = pn[r * 32];
-      if (!h) {  // p 4..7 of the last group: the nearfield phase and 1
-        X[G - 1][2] = nf[1];
-        X[G - 1][3] = nf[2];
-      }
+      for (int g = 0; g < G - 1; ++g)
+        X[g] = (px + g * 2 * kTile + r * 32)[lane_pix];
+      const unsigned bdj = bf16_bits((float)(r - kAnchorJ));
+      u32x4 last =
+          u32x4{one2, bdi | (bdi << 16), bdi | (bdj << 16), bdj | (bdj << 16)};
+      if (!h) last = (pn + r * 32)[q];
+      X[G - 1] = last;
       const floatx16 th = phase_block<G>(S, X);
-      accumulate<true, kReduce>(th, __uint_as_float(nf[0]), er, ei);
+      accumulate<true, kReduce>(th, (pm + r * 32)[q], er, ei);
     }
     b += r1 - r0;
   }
@@ -654,10 +701,11 @@ __device__ __forceinline__ void forward_range(
 // spot block fastest, so all spot blocks of a range run on one XCD at
 // neighbouring slots and its L2 serves the range's records to all of them.
 template <int G, bool kReduce>
-__global__ __launch_bounds__(kBlock) void k_forward(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(G <= 3 ? 5 : 1))) void k_forward(
     int N, long n_blk, int groups, const u32x4* __restrict__ pixtab,
-    const u32x4* __restrict__ nf_t, const u32x4* __restrict__ spotrec,
-    const u32x4* __restrict__ offtab, float2* __restrict__ partial) {
+    const unsigned* __restrict__ nf_t, const u32x4* __restrict__ spotrec,
+    const unsigned* __restrict__ offtab, float2* __restrict__ partial) {
   const int n_mb = (N + 31) / 32;
   const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
   // the wave index is uniform over the wave; say so, so that the range
@@ -667,10 +715,13 @@ __global__ __launch_bounds__(kBlock) void k_forward(
   if (v >= (long)(groups / kXcds) * n_mb) return;  // wave-uniform exit
   const int gi = (int)(v / n_mb) * kXcds + xcd;  // pixel range
   const int mb = (int)(v % n_mb);                // spot block
+  const NearField nf = near_field(const_cast<unsigned*>(nf_t), n_blk * 32);
   forward_range<G, kReduce>(N, mb, n_blk * gi / groups,
                             n_blk * (gi + 1) / groups, as_global(pixtab),
-                            as_global(nf_t), as_global(spotrec),
-                            as_global(offtab), partial + (long)gi * N);
+                            as_global(nf.rec), as_global(nf.mag),
+                            as_global(spotrec),
+                            as_global(reinterpret_cast<const u32x4*>(offtab)),
+                            partial + (long)gi * N);
 }
 
 template <int G>
@@ -684,10 +735,8 @@ static hipError_t fwd_g(bool reduce, int n_mb, int groups, hipStream_t s,
   auto* const kern = reduce ? k_forward<G, true> : k_forward<G, false>;
   hipLaunchKernelGGL(kern, dim3((unsigned)(blocks_per_xcd * kXcds)),
                      dim3(kBlock), 0, s, N, n_blk, groups,
-                     reinterpret_cast<const u32x4*>(pixtab),
-                     reinterpret_cast<const u32x4*>(nf_t),
-                     reinterpret_cast<const u32x4*>(spotrec),
-                     reinterpret_cast<const u32x4*>(offtab),
+                     reinterpret_cast<const u32x4*>(pixtab), nf_t,
+                     reinterpret_cast<const u32x4*>(spotrec), offtab,
                      reinterpret_cast<float2*>(partial));
   return hipGetLastError();
 }
@@ -830,7 +879,7 @@ struct OpMin {
 __device__ void wgs_update_block(
     int N, int slices, const float2* __restrict__ red,
     const float* __restrict__ t, float t_norm, float* __restrict__ W,
-    float power, float eff_denom, u32x4* __restrict__ ypol,
+    float power, float eff_denom, unsigned* __restrict__ ypol,
     float2* __restrict__ Ebuf, float2* __restrict__ E_extra,
     float* __restrict__ stats, float* sh) {
   const int tid = threadIdx.x;
@@ -877,7 +926,7 @@ __device__ void wgs_update_block(
     const float wk = W[k] / mean_w;
     W[k] = wk;
     const float2 e = Ebuf[k];
-    put_spot_field(ypol, (N + 31) / 32 * 32, k, wk * t[k],
+    put_spot_field(spot_field(ypol, (N + 31) / 32 * 32), k, wk * t[k],
                    atan2f(e.y, e.x) * kInv2Pi);
   }
   if (stats && tid == 0) {
@@ -892,7 +941,7 @@ __device__ void wgs_update_block(
 __global__ __launch_bounds__(kUpd) void k_wgs_update(
     int N, int slices, const float2* __restrict__ red,
     const float* __restrict__ t, float t_norm, float* __restrict__ W,
-    float power, float eff_denom, u32x4* __restrict__ ypol,
+    float power, float eff_denom, unsigned* __restrict__ ypol,
     float2* __restrict__ Ebuf, float2* __restrict__ E_extra,
     float* __restrict__ stats) {
   __shared__ float sh[kUpd];
@@ -907,7 +956,7 @@ hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_wgs_update, dim3(1), dim3(kUpd), 0, s, N, p.slices,
                      reinterpret_cast<const float2*>(red), target, t_norm, W,
-                     power, eff_denom, reinterpret_cast<u32x4*>(ypol),
+                     power, eff_denom, ypol,
                      reinterpret_cast<float2*>(Ebuf),
                      reinterpret_cast<float2*>(E_extra), stats_row);
   return hipGetLastError();
@@ -921,7 +970,7 @@ hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kUpd) void k_spot_loss(
     int N, int slices, const float2* __restrict__ red,
-    const float* __restrict__ t, float inv_s, u32x4* __restrict__ ypol,
+    const float* __restrict__ t, float inv_s, unsigned* __restrict__ ypol,
     float2* __restrict__ E_extra, float* __restrict__ lossbuf) {
   __shared__ float sh[kUpd];
   const int tid = threadIdx.x;
@@ -933,8 +982,8 @@ __global__ __launch_bounds__(kUpd) void k_spot_loss(
     const float d = hr * hr + hi * hi - t[k];
     kahan_add(acc, comp, d * d);
     const float c = 4.0f * d * inv_s;
-    put_spot_field(ypol, (N + 31) / 32 * 32, k, fabsf(c) * hypotf(hr, hi),
-                   atan2f(c * hi, c * hr) * kInv2Pi);
+    put_spot_field(spot_field(ypol, (N + 31) / 32 * 32), k,
+                   fabsf(c) * hypotf(hr, hi), atan2f(c * hi, c * hr) * kInv2Pi);
   }
   const float L = block_reduce(acc, sh, OpSum());
   if (tid == 0) lossbuf[0] = L;
@@ -945,7 +994,7 @@ hipError_t launch_spot_loss(int N, const FwdPlan& p, const float* red,
                             float* E_extra, float* lossbuf, hipStream_t s) {
   hipLaunchKernelGGL(k_spot_loss, dim3(1), dim3(kUpd), 0, s, N, p.slices,
                      reinterpret_cast<const float2*>(red), target, inv_s,
-                     reinterpret_cast<u32x4*>(ypol),
+                     ypol,
                      reinterpret_cast<float2*>(E_extra), lossbuf);
   return hipGetLastError();
 }
@@ -975,8 +1024,8 @@ __global__ void k_adam(Geom b, long total, float* __restrict__ phase,
                        float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ grad, float lr, float beta1,
                        float beta2, float eps, float bc1, float bc2,
-                       const float* __restrict__ amp_t,
-                       u32x4* __restrict__ nf_t) {
+                       const u32x4* __restrict__ pixtab,
+                       u32x4* __restrict__ nf_rec) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= total) return;
   const int tile = (int)(gid / kTile), pix = (int)(gid % kTile);
@@ -992,17 +1041,21 @@ __global__ void k_adam(Geom b, long total, float* __restrict__ phase,
   phase[p] = ph;
   float turns = ph * kInv2Pi;
   turns -= rintf(turns);
-  nf_t[gid] = polar_record(amp_t[gid], turns, kBf16One);
+  // next nearfield record; the magnitudes stay
+  nf_rec[gid] = nearfield_record(pixel_nl_words(pixtab, b.groups, tile, pix),
+                                 turns);
 }
 
 hipError_t launch_adam(const Geom& b, float* phase, float* m, float* v,
                        const float* grad, float lr, float beta1, float beta2,
-                       float eps, float bc1, float bc2, const float* amp_t,
-                       unsigned* nf_t, hipStream_t s) {
+                       float eps, float bc1, float bc2,
+                       const unsigned short* pixtab, unsigned* nf_t,
+                       hipStream_t s) {
   const long total = (long)b.n_tiles * kTile;
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((total + 255) / 256)), dim3(256),
                      0, s, b, total, phase, m, v, grad, lr, beta1, beta2, eps,
-                     bc1, bc2, amp_t, reinterpret_cast<u32x4*>(nf_t));
+                     bc1, bc2, reinterpret_cast<const u32x4*>(pixtab),
+                     near_field(nf_t, total).rec);
   return hipGetLastError();
 }
 
@@ -1062,36 +1115,39 @@ __device__ __forceinline__ void adjoint_row(
     const GLOBAL u32x4* __restrict__ pixtab,
     const GLOBAL u32x4* __restrict__ spotrec,
     const GLOBAL u32x4* __restrict__ offtab,
-    const GLOBAL u32x4* __restrict__ ypol,
+    const GLOBAL u32x2* __restrict__ y_ph,
+    const GLOBAL float* __restrict__ y_mag,
     const GLOBAL float* __restrict__ amp_t, const AdjOut& o) {
   const int lane = threadIdx.x & (kWave - 1);
   const int h = lane >> 5, q = lane & 31;
   u32x4 X[G];
+  const unsigned lane_spot = h * 32 + q;
 #pragma unroll
   for (int gg = 0; gg < G; ++gg)
-    X[gg] = pixtab[(((long)tile * G + gg) * 2 + h) * kTile + p0 + q];
+    X[gg] = (pixtab + (((long)tile * G + gg) * 2 + h) * kTile + p0)[q];
   const int NB = (N + 31) / 32, NP = NB * 32;
-  // per spot block: the lane's spot record, tile slots and spot field;
-  // spot tables are padded to whole blocks with zero records
-  const GLOBAL u32x4* __restrict__ sp = spotrec + h * 32 + q;
-  const GLOBAL u32x4* __restrict__ ot_t = offtab + ((long)tile * 2 + h) * NP + q;
-  const GLOBAL u32x4* __restrict__ yq = ypol + (long)h * NP + q;
+  const unsigned lane_ot = h * NP + q;
+  // per spot block: the lane's spot record, groups 0..G-2 from the record
+  // and the last group from the per-tile slots, with the spot-field phase
+  // (p 4..6, half 0) OR-ed in; and the spot's magnitude.  Spot tables are
+  // padded to whole blocks with zero records.
+  const GLOBAL u32x4* __restrict__ ot_t = offtab + (long)tile * 2 * NP;
   float gr[16], gi[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) gr[i] = gi[i] = 0.0f;
   for (int nb = 0; nb < NB; ++nb) {
     u32x4 S[G];
+    const GLOBAL u32x4* __restrict__ sb = spotrec + (long)nb * G * 64;
 #pragma unroll
-    for (int gg = 0; gg < G; ++gg) S[gg] = sp[((long)nb * G + gg) * 64];
-    const u32x4 ot = ot_t[nb * 32], yp = yq[nb * 32];
-    // last group: tile slots, and the spot-field phase at p 4..6 (half 0;
-    // these replace the static forward entries there)
-    S[G - 1][0] |= ot[0];
-    S[G - 1][1] |= ot[1];
-    S[G - 1][2] = ot[2] | yp[2];
-    S[G - 1][3] = ot[3] | yp[3];
+    for (int gg = 0; gg < G - 1; ++gg) S[gg] = sb[lane_spot + gg * 64];
+    u32x4 last = (ot_t + nb * 32)[lane_ot];
+    u32x2 yp = u32x2{0u, 0u};
+    if (!h) yp = (y_ph + nb * 32)[q];
+    last[2] |= yp.x;
+    last[3] |= yp.y;
+    S[G - 1] = last;
     const floatx16 th = phase_block<G>(X, S);
-    accumulate<false, kReduce>(th, __uint_as_float(yp[0]), gr, gi);
+    accumulate<false, kReduce>(th, (y_mag + nb * 32)[q], gr, gi);
   }
   bfly_reduce(gr, gi, q);
   // one result per lane pair; the odd lane of a pair idles in the epilogue
@@ -1104,10 +1160,11 @@ __device__ __forceinline__ void adjoint_row(
   const float vr = gr[0], vi = gi[0];
   if (lead && (o.outs & (kOutField | kOutPhase))) {
     const float ang = atan2f(vi, vr);  // atan2(0, 0) = 0
-    if (o.outs & kOutField)
+    if (o.outs & kOutField)  // next nearfield: the magnitudes stay
       reinterpret_cast<u32x4*>(o.nf_t)[(long)tile * kTile + pix] =
-          polar_record(amp_t[(long)tile * kTile + pix], ang * kInv2Pi,
-                       kBf16One);
+          nearfield_record(
+              pixel_nl_words((const u32x4*)pixtab, G, tile, pix),
+              ang * kInv2Pi);
     if (inside && (o.outs & kOutPhase)) o.phase[p] = ang;
   }
   if (inside && (o.outs & kOutG))
@@ -1138,18 +1195,22 @@ __device__ __forceinline__ void adjoint_row(
 template <int G, bool kReduce>
 __global__ __launch_bounds__(kBlock) void k_adjoint(
     int N, int nx, int ny, int tiles_x, const u32x4* __restrict__ pixtab,
-    const u32x4* __restrict__ spotrec, const u32x4* __restrict__ offtab,
-    const u32x4* __restrict__ ypol, const float* __restrict__ amp_t,
+    const u32x4* __restrict__ spotrec, const unsigned* __restrict__ offtab,
+    const unsigned* __restrict__ ypol, const float* __restrict__ amp_t,
     AdjOut o) {
   const int nblk = gridDim.x, per = nblk / kXcds, extra = nblk % kXcds;
   const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
   const int lin = xcd * per + min(xcd, extra) + slot;
   const int wv = lin * (kBlock / kWave) +
                  __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const SpotField y = spot_field(const_cast<unsigned*>(ypol),
+                                 (N + 31) / 32 * 32);
   adjoint_row<G, kReduce>(N, nx, ny, tiles_x, wv / kBlkPerTile,
                           (wv % kBlkPerTile) * 32, wv, as_global(pixtab),
-                          as_global(spotrec), as_global(offtab),
-                          as_global(ypol), as_global(amp_t), o);
+                          as_global(spotrec),
+                          as_global(reinterpret_cast<const u32x4*>(offtab)),
+                          as_global(y.ph), as_global(y.mag), as_global(amp_t),
+                          o);
 }
 
 template <int G>
@@ -1161,9 +1222,8 @@ static hipError_t adj_g(const Geom& b, int N, const unsigned short* pixtab,
   auto* const kern = b.reduce ? k_adjoint<G, true> : k_adjoint<G, false>;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, N, b.nx,
                      b.ny, b.tiles_x, reinterpret_cast<const u32x4*>(pixtab),
-                     reinterpret_cast<const u32x4*>(spotrec),
-                     reinterpret_cast<const u32x4*>(offtab),
-                     reinterpret_cast<const u32x4*>(ypol), amp_t, o);
+                     reinterpret_cast<const u32x4*>(spotrec), offtab, ypol,
+                     amp_t, o);
   return hipGetLastError();
 }
 
@@ -1228,9 +1288,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(
     const HoloDesc& d = hd[it.x];
     const long b0 = (long)it.y * d.L;
     const long b1 = min(b0 + d.L, d.n_blk);
-    forward_range<G, kReduce>(d.N, it.z, b0, b1, as_global(d.pixtab),
-                              as_global(d.nf_t), as_global(d.spotrec),
-                              as_global(d.offtab), d.partial + (long)it.y * d.N);
+    const NearField nf = near_field(d.nf_t, d.n_blk * 32);
+    forward_range<G, kReduce>(
+        d.N, it.z, b0, b1, as_global(d.pixtab), as_global(nf.rec),
+        as_global(nf.mag), as_global(d.spotrec),
+        as_global(reinterpret_cast<const u32x4*>(d.offtab)),
+        d.partial + (long)it.y * d.N);
   });
 }
 
@@ -1243,13 +1306,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_adjoint(
     AdjOut o;
     o.outs = last ? kOutPhase : kOutField;
     o.phase = d.phase;
-    o.nf_t = reinterpret_cast<unsigned*>(d.nf_t);
+    o.nf_t = d.nf_t;
+    const SpotField y = spot_field(d.ypol, (d.N + 31) / 32 * 32);
     for (int wv = it.y; wv < it.y + it.z; ++wv)  // it.z tile rows
-      adjoint_row<G, kReduce>(d.N, d.nx, d.ny, d.tiles_x, wv / kBlkPerTile,
-                              (wv % kBlkPerTile) * 32, wv,
-                              as_global(d.pixtab), as_global(d.spotrec),
-                              as_global(d.offtab), as_global(d.ypol),
-                              as_global(d.amp_t), o);
+      adjoint_row<G, kReduce>(
+          d.N, d.nx, d.ny, d.tiles_x, wv / kBlkPerTile,
+          (wv % kBlkPerTile) * 32, wv, as_global(d.pixtab),
+          as_global(d.spotrec),
+          as_global(reinterpret_cast<const u32x4*>(d.offtab)),
+          as_global(y.ph), as_global(y.mag), as_global(d.amp_t), o);
   });
 }
 
