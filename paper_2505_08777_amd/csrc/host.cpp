@@ -452,7 +452,7 @@ int ash_set_basis(ash_ctx* c, int nx, int ny, double cx, double cy, double R,
   const size_t npix = (size_t)g.n_tiles * kTile;
   const size_t nl1 = (size_t)std::max(g.nl, 1);
   if ((rc = dalloc(c, &B.amp_t, npix, "amplitude")) ||
-      (rc = dalloc(c, &B.field_t, 5 * npix, "nearfield")) ||
+      (rc = dalloc(c, &B.field_t, 8 * npix, "nearfield")) ||
       (rc = dalloc(c, &B.aff_dev, 3 * (size_t)D, "basis affine terms")) ||
       (rc = dalloc(c, &B.nlmode_dev, nl1, "modes")) ||
       (rc = dalloc(c, &B.tilez, 3 * (size_t)g.n_tiles * nl1, "tile basis")) ||

@@ -61,7 +61,7 @@ struct Buffers {
   // basis
   unsigned short* pixtab = nullptr;  // [tile][group][half][kTile][8] bf16
   float* amp_t = nullptr;            // [n_tiles][kTile]
-  unsigned* field_t = nullptr;  // nearfield: [n_pix] u32x4 records, [n_pix] f32
+  unsigned* field_t = nullptr;  // nearfield [n_tiles * 16][half][32] u32x4
   double* aff_dev = nullptr;         // [D][3]
   int* nlmode_dev = nullptr;         // [nl]
   double* tilez = nullptr;           // [n_tiles][nl][3] Z^nl, d/di, d/dj
@@ -73,7 +73,7 @@ struct Buffers {
   unsigned short* spotrec = nullptr;  // [N/32][group][half][32][8] bf16
   unsigned* offtab = nullptr;   // [n_tiles][half][NP] u32x4 last-group slots
   float* target = nullptr;            // [N]
-  unsigned* y = nullptr;        // spot fields: [NP] 2 x u32 phase, [NP] f32
+  unsigned* y = nullptr;        // spot fields [NP] u32x4 (phase words, |y|)
   float* Ebuf = nullptr;              // [N][2] fields of the last forward
   double* w64 = nullptr;              // [N][D] coefficients (radians)
   double* spot64 = nullptr;           // [N][3] constant, alpha, beta (turns)
@@ -168,10 +168,10 @@ constexpr int kRowsPerSlice = 32;  // forward partial rows per reduce slice
 // One hologram of a batch as the batched kernels see it (device copy).
 struct HoloDesc {
   const u32x4* pixtab;
-  unsigned* nf_t;    // nearfield planes (phase words, magnitudes)
+  unsigned* nf_t;    // nearfield records
   const u32x4* spotrec;
   unsigned* offtab;  // per-tile slot planes
-  unsigned* ypol;    // spot-field planes
+  unsigned* ypol;    // spot-field records
   const float* amp_t;
   float2* partial;  // [n_ranges][N]
   float2* red;      // [slices][N]

@@ -109,20 +109,17 @@ __device__ inline void split3f(float v, unsigned* p) {
   p[2] = bf16_bits(r2);
 }
 
-// Dynamic per-pixel and per-spot data are kept as planes, so that each
-// lane half of a matrix-core operand loads only the words it uses.
+// The dynamic per-pixel and per-spot data are laid out so that a wave
+// fetches what both lane halves of a matrix-core operand need in one load:
+// the vector-memory data path, not the arithmetic, is what these loads
+// contend for.
 //
-// Nearfield of the tile-ordered pixels: records [n_pix] (u32x4: the words
-// of half 0 of the pixel record's last group, i.e. its nonlinear slots
-// p 0..3 and the phase pieces with a 1 at p 4..7), then the magnitudes
-// [n_pix].
-struct NearField {
-  u32x4* rec;
-  float* mag;
-};
-__host__ __device__ inline NearField near_field(unsigned* f, long n_pix) {
-  return {reinterpret_cast<u32x4*>(f),
-          reinterpret_cast<float*>(f + 4 * n_pix)};
+// Nearfield of the tile-ordered pixels, per 32-pixel block (tile row)
+// [tile * kBlkPerTile + row][half][32] u32x4.  Half 0: the words of half 0
+// of the pixel record's last group (its nonlinear slots p 0..3, the phase
+// pieces and a 1 at p 4..7).  Half 1: {magnitude bits, 0, 0, 0}.
+__host__ __device__ inline long nf_index(long tile, int pix, int half) {
+  return ((tile * kBlkPerTile + pix / 32) * 2 + half) * 32 + pix % 32;
 }
 // Record of a pixel from its table nonlinear words and phase (turns).
 __device__ inline u32x4 nearfield_record(u32x2 nl, float turns) {
@@ -138,23 +135,15 @@ __device__ inline u32x2 pixel_nl_words(const u32x4* pixtab, int G, long tile,
       pixtab + ((tile * G + G - 1) * 2) * kTile + pix);
 }
 
-// Spot fields of the adjoint: phase words [NP] (2 x u32: the phase pieces
-// at p 4..6 of the spot record's last group, words 2..3 of half 0), then
-// the magnitudes [NP].  Entries past N stay zero.
-struct SpotField {
-  u32x2* ph;
-  float* mag;
-};
-__host__ __device__ inline SpotField spot_field(unsigned* y, int NP) {
-  return {reinterpret_cast<u32x2*>(y),
-          reinterpret_cast<float*>(y + 2 * (size_t)NP)};
-}
-__device__ inline void put_spot_field(SpotField f, int k, float mag,
+// Spot fields of the adjoint, [NP] u32x4: {the phase pieces at p 4..6 of
+// the spot record's last group (words 2..3 of half 0), magnitude bits, 0}.
+// Entries past N stay zero.
+__device__ inline void put_spot_field(unsigned* y, int k, float mag,
                                       float turns) {
   unsigned p[3];
   split3f(turns, p);
-  f.ph[k] = u32x2{p[0] | (p[1] << 16), p[2]};
-  f.mag[k] = mag;
+  reinterpret_cast<u32x4*>(y)[k] =
+      u32x4{p[0] | (p[1] << 16), p[2], __float_as_uint(mag), 0u};
 }
 
 // Slot f of a record of 16-slot groups: group f / 16, lane half (f % 16)/8,
@@ -485,7 +474,8 @@ __global__ void k_make_field(Geom b, long total,
                              const float* __restrict__ phase,
                              const float2* __restrict__ field,
                              const float* __restrict__ amp_t,
-                             const u32x4* __restrict__ pixtab, NearField nf) {
+                             const u32x4* __restrict__ pixtab,
+                             u32x4* __restrict__ nf) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= total) return;
   const int tile = (int)(gid / kTile), pix = (int)(gid % kTile);
@@ -503,9 +493,9 @@ __global__ void k_make_field(Geom b, long total,
       turns = atan2f(f.y, f.x) * kInv2Pi;
     }
   }
-  nf.rec[gid] = nearfield_record(pixel_nl_words(pixtab, b.groups, tile, pix),
-                                 turns);
-  nf.mag[gid] = mag;
+  nf[nf_index(tile, pix, 0)] = nearfield_record(
+      pixel_nl_words(pixtab, b.groups, tile, pix), turns);
+  nf[nf_index(tile, pix, 1)] = u32x4{__float_as_uint(mag), 0u, 0u, 0u};
 }
 
 hipError_t launch_make_field(const Geom& b, const float* phase,
@@ -517,7 +507,7 @@ hipError_t launch_make_field(const Geom& b, const float* phase,
                      dim3(256), 0, s, b, total, phase,
                      reinterpret_cast<const float2*>(field), amp_t,
                      reinterpret_cast<const u32x4*>(pixtab),
-                     near_field(nf_t, total));
+                     reinterpret_cast<u32x4*>(nf_t));
   return hipGetLastError();
 }
 
@@ -526,8 +516,7 @@ __global__ void k_to_polar(int N, const float2* __restrict__ y,
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
   const float2 v = y[k];
-  put_spot_field(spot_field(ypol, (N + 31) / 32 * 32), k, hypotf(v.x, v.y),
-                 atan2f(v.y, v.x) * kInv2Pi);
+  put_spot_field(ypol, k, hypotf(v.x, v.y), atan2f(v.y, v.x) * kInv2Pi);
 }
 
 hipError_t launch_to_polar(int N, const float* y, unsigned* ypol,
@@ -630,16 +619,16 @@ __device__ __forceinline__ void accumulate(const floatx16& th, float m,
 // blocks [b0, b1) (tile rows, tile order).  Operand A is the spot record,
 // B the pixel record of a block; each lane keeps 16 spot rows, and a
 // butterfly over the 32 lanes of each half-wave finishes the pixel sums,
-// written to row[k] for the block's spots k < N.  The last group of the
-// pixel record comes per half: half 0 from the nearfield record (the
-// table's nonlinear slots, the phase pieces and 1), half 1 (p 8..15: 1, 1,
-// di x 3, dj x 3) built in registers, so it is not read at all.
+// written to row[k] for the block's spots k < N.  One load brings half 0
+// its nearfield record (the last group's nonlinear slots, the phase pieces
+// and 1) and half 1 the pixel's magnitude; half 1's last group (p 8..15:
+// 1, 1, di x 3, dj x 3) is formed in registers and the magnitude crosses
+// to half 0 with a lane-half swap.
 // E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))).
 template <int G, bool kReduce>
 __device__ __forceinline__ void forward_range(
     int N, int mb, long b0, long b1, const GLOBAL u32x4* __restrict__ pixtab,
-    const GLOBAL u32x4* __restrict__ nf_rec,
-    const GLOBAL float* __restrict__ nf_mag,
+    const GLOBAL u32x4* __restrict__ nf,
     const GLOBAL u32x4* __restrict__ spotrec,
     const GLOBAL u32x4* __restrict__ offtab, float2* __restrict__ row) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -672,20 +661,22 @@ __device__ __forceinline__ void forward_range(
     S[G - 1][2] |= m2;
     S[G - 1][3] |= m3;
     const GLOBAL u32x4* __restrict__ px = pixtab + t * G * 2 * kTile;
-    const GLOBAL u32x4* __restrict__ pn = nf_rec + t * kTile;
-    const GLOBAL float* __restrict__ pm = nf_mag + t * kTile;
+    const GLOBAL u32x4* __restrict__ pn = nf + t * kBlkPerTile * 64;
     for (int r = r0; r < r1; ++r) {
       u32x4 X[G];
 #pragma unroll
       for (int g = 0; g < G - 1; ++g)
         X[g] = (px + g * 2 * kTile + r * 32)[lane_pix];
+      const u32x4 rec = (pn + r * 64)[lane_spot];
       const unsigned bdj = bf16_bits((float)(r - kAnchorJ));
-      u32x4 last =
-          u32x4{one2, bdi | (bdi << 16), bdi | (bdj << 16), bdj | (bdj << 16)};
-      if (!h) last = (pn + r * 32)[q];
-      X[G - 1] = last;
+      X[G - 1] = h ? u32x4{one2, bdi | (bdi << 16), bdi | (bdj << 16),
+                           bdj | (bdj << 16)}
+                   : rec;
+      // the magnitude sits in half 1's record; give half 0 its copy
+      const float m = __uint_as_float(
+          __builtin_amdgcn_permlane32_swap(rec.x, rec.x, false, false)[1]);
       const floatx16 th = phase_block<G>(S, X);
-      accumulate<true, kReduce>(th, (pm + r * 32)[q], er, ei);
+      accumulate<true, kReduce>(th, m, er, ei);
     }
     b += r1 - r0;
   }
@@ -701,8 +692,7 @@ __device__ __forceinline__ void forward_range(
 // spot block fastest, so all spot blocks of a range run on one XCD at
 // neighbouring slots and its L2 serves the range's records to all of them.
 template <int G, bool kReduce>
-__global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(G <= 3 ? 5 : 1))) void k_forward(
+__global__ __launch_bounds__(kBlock) void k_forward(
     int N, long n_blk, int groups, const u32x4* __restrict__ pixtab,
     const unsigned* __restrict__ nf_t, const u32x4* __restrict__ spotrec,
     const unsigned* __restrict__ offtab, float2* __restrict__ partial) {
@@ -715,10 +705,9 @@ __attribute__((amdgpu_waves_per_eu(G <= 3 ? 5 : 1))) void k_forward(
   if (v >= (long)(groups / kXcds) * n_mb) return;  // wave-uniform exit
   const int gi = (int)(v / n_mb) * kXcds + xcd;  // pixel range
   const int mb = (int)(v % n_mb);                // spot block
-  const NearField nf = near_field(const_cast<unsigned*>(nf_t), n_blk * 32);
   forward_range<G, kReduce>(N, mb, n_blk * gi / groups,
                             n_blk * (gi + 1) / groups, as_global(pixtab),
-                            as_global(nf.rec), as_global(nf.mag),
+                            as_global(reinterpret_cast<const u32x4*>(nf_t)),
                             as_global(spotrec),
                             as_global(reinterpret_cast<const u32x4*>(offtab)),
                             partial + (long)gi * N);
@@ -926,8 +915,7 @@ __device__ void wgs_update_block(
     const float wk = W[k] / mean_w;
     W[k] = wk;
     const float2 e = Ebuf[k];
-    put_spot_field(spot_field(ypol, (N + 31) / 32 * 32), k, wk * t[k],
-                   atan2f(e.y, e.x) * kInv2Pi);
+    put_spot_field(ypol, k, wk * t[k], atan2f(e.y, e.x) * kInv2Pi);
   }
   if (stats && tid == 0) {
     stats[0] = eff_denom > 0.0f ? sum_a2 / eff_denom : 0.0f;
@@ -982,8 +970,8 @@ __global__ __launch_bounds__(kUpd) void k_spot_loss(
     const float d = hr * hr + hi * hi - t[k];
     kahan_add(acc, comp, d * d);
     const float c = 4.0f * d * inv_s;
-    put_spot_field(spot_field(ypol, (N + 31) / 32 * 32), k,
-                   fabsf(c) * hypotf(hr, hi), atan2f(c * hi, c * hr) * kInv2Pi);
+    put_spot_field(ypol, k, fabsf(c) * hypotf(hr, hi),
+                   atan2f(c * hi, c * hr) * kInv2Pi);
   }
   const float L = block_reduce(acc, sh, OpSum());
   if (tid == 0) lossbuf[0] = L;
@@ -1042,8 +1030,8 @@ __global__ void k_adam(Geom b, long total, float* __restrict__ phase,
   float turns = ph * kInv2Pi;
   turns -= rintf(turns);
   // next nearfield record; the magnitudes stay
-  nf_rec[gid] = nearfield_record(pixel_nl_words(pixtab, b.groups, tile, pix),
-                                 turns);
+  nf_rec[nf_index(tile, pix, 0)] = nearfield_record(
+      pixel_nl_words(pixtab, b.groups, tile, pix), turns);
 }
 
 hipError_t launch_adam(const Geom& b, float* phase, float* m, float* v,
@@ -1055,7 +1043,7 @@ hipError_t launch_adam(const Geom& b, float* phase, float* m, float* v,
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((total + 255) / 256)), dim3(256),
                      0, s, b, total, phase, m, v, grad, lr, beta1, beta2, eps,
                      bc1, bc2, reinterpret_cast<const u32x4*>(pixtab),
-                     near_field(nf_t, total).rec);
+                     reinterpret_cast<u32x4*>(nf_t));
   return hipGetLastError();
 }
 
@@ -1115,8 +1103,7 @@ __device__ __forceinline__ void adjoint_row(
     const GLOBAL u32x4* __restrict__ pixtab,
     const GLOBAL u32x4* __restrict__ spotrec,
     const GLOBAL u32x4* __restrict__ offtab,
-    const GLOBAL u32x2* __restrict__ y_ph,
-    const GLOBAL float* __restrict__ y_mag,
+    const GLOBAL u32x4* __restrict__ yrec,
     const GLOBAL float* __restrict__ amp_t, const AdjOut& o) {
   const int lane = threadIdx.x & (kWave - 1);
   const int h = lane >> 5, q = lane & 31;
@@ -1129,8 +1116,9 @@ __device__ __forceinline__ void adjoint_row(
   const unsigned lane_ot = h * NP + q;
   // per spot block: the lane's spot record, groups 0..G-2 from the record
   // and the last group from the per-tile slots, with the spot-field phase
-  // (p 4..6, half 0) OR-ed in; and the spot's magnitude.  Spot tables are
-  // padded to whole blocks with zero records.
+  // (p 4..6) OR-ed in by half 0, which also loads the spot's magnitude and
+  // passes it to half 1 with a lane-half swap.  Spot tables are padded to
+  // whole blocks with zero records.
   const GLOBAL u32x4* __restrict__ ot_t = offtab + (long)tile * 2 * NP;
   float gr[16], gi[16];
 #pragma unroll
@@ -1141,13 +1129,15 @@ __device__ __forceinline__ void adjoint_row(
 #pragma unroll
     for (int gg = 0; gg < G - 1; ++gg) S[gg] = sb[lane_spot + gg * 64];
     u32x4 last = (ot_t + nb * 32)[lane_ot];
-    u32x2 yp = u32x2{0u, 0u};
-    if (!h) yp = (y_ph + nb * 32)[q];
-    last[2] |= yp.x;
-    last[3] |= yp.y;
+    u32x4 yv = u32x4{0u, 0u, 0u, 0u};
+    if (!h) yv = (yrec + nb * 32)[q];
+    last[2] |= yv[0];
+    last[3] |= yv[1];
     S[G - 1] = last;
+    const float m = __uint_as_float(
+        __builtin_amdgcn_permlane32_swap(yv[2], yv[2], false, false)[0]);
     const floatx16 th = phase_block<G>(X, S);
-    accumulate<false, kReduce>(th, (y_mag + nb * 32)[q], gr, gi);
+    accumulate<false, kReduce>(th, m, gr, gi);
   }
   bfly_reduce(gr, gi, q);
   // one result per lane pair; the odd lane of a pair idles in the epilogue
@@ -1161,7 +1151,7 @@ __device__ __forceinline__ void adjoint_row(
   if (lead && (o.outs & (kOutField | kOutPhase))) {
     const float ang = atan2f(vi, vr);  // atan2(0, 0) = 0
     if (o.outs & kOutField)  // next nearfield: the magnitudes stay
-      reinterpret_cast<u32x4*>(o.nf_t)[(long)tile * kTile + pix] =
+      reinterpret_cast<u32x4*>(o.nf_t)[nf_index(tile, pix, 0)] =
           nearfield_record(
               pixel_nl_words((const u32x4*)pixtab, G, tile, pix),
               ang * kInv2Pi);
@@ -1203,14 +1193,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
   const int lin = xcd * per + min(xcd, extra) + slot;
   const int wv = lin * (kBlock / kWave) +
                  __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const SpotField y = spot_field(const_cast<unsigned*>(ypol),
-                                 (N + 31) / 32 * 32);
   adjoint_row<G, kReduce>(N, nx, ny, tiles_x, wv / kBlkPerTile,
                           (wv % kBlkPerTile) * 32, wv, as_global(pixtab),
                           as_global(spotrec),
                           as_global(reinterpret_cast<const u32x4*>(offtab)),
-                          as_global(y.ph), as_global(y.mag), as_global(amp_t),
-                          o);
+                          as_global(reinterpret_cast<const u32x4*>(ypol)),
+                          as_global(amp_t), o);
 }
 
 template <int G>
@@ -1288,10 +1276,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(
     const HoloDesc& d = hd[it.x];
     const long b0 = (long)it.y * d.L;
     const long b1 = min(b0 + d.L, d.n_blk);
-    const NearField nf = near_field(d.nf_t, d.n_blk * 32);
     forward_range<G, kReduce>(
-        d.N, it.z, b0, b1, as_global(d.pixtab), as_global(nf.rec),
-        as_global(nf.mag), as_global(d.spotrec),
+        d.N, it.z, b0, b1, as_global(d.pixtab),
+        as_global(reinterpret_cast<const u32x4*>(d.nf_t)), as_global(d.spotrec),
         as_global(reinterpret_cast<const u32x4*>(d.offtab)),
         d.partial + (long)it.y * d.N);
   });
@@ -1307,14 +1294,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_adjoint(
     o.outs = last ? kOutPhase : kOutField;
     o.phase = d.phase;
     o.nf_t = d.nf_t;
-    const SpotField y = spot_field(d.ypol, (d.N + 31) / 32 * 32);
     for (int wv = it.y; wv < it.y + it.z; ++wv)  // it.z tile rows
       adjoint_row<G, kReduce>(
           d.N, d.nx, d.ny, d.tiles_x, wv / kBlkPerTile,
           (wv % kBlkPerTile) * 32, wv, as_global(d.pixtab),
           as_global(d.spotrec),
           as_global(reinterpret_cast<const u32x4*>(d.offtab)),
-          as_global(y.ph), as_global(y.mag), as_global(d.amp_t), o);
+          as_global(reinterpret_cast<const u32x4*>(d.ypol)),
+          as_global(d.amp_t), o);
   });
 }
 
