@@ -839,16 +839,18 @@ hipError_t launch_finish_E(int N, const FwdPlan& p, const float* red, float* E,
 // ---------------------------------------------------------------------------
 constexpr int kUpd = 1024;
 
+// Reduction over the block (any multiple of 64 threads, sh: one float per
+// wave): a butterfly within each wave, then the waves' results in wave
+// order; every thread returns the same value.
 template <typename Op>
 __device__ float block_reduce(float v, float* sh, Op op) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) v = op(v, __shfl_xor(v, w, kWave));
+  const int nw = blockDim.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = v;
   __syncthreads();
-  for (int w = kUpd / 2; w > 0; w >>= 1) {
-    if (tid < w) sh[tid] = op(sh[tid], sh[tid + w]);
-    __syncthreads();
-  }
-  const float r = sh[0];
+  float r = sh[0];
+  for (int i = 1; i < nw; ++i) r = op(r, sh[i]);
   __syncthreads();
   return r;
 }
@@ -863,8 +865,8 @@ struct OpMin {
   __device__ float operator()(float a, float b) const { return fminf(a, b); }
 };
 
-// The weighted-GS farfield update of one hologram by one kUpd-thread block
-// (sh: kUpd floats of LDS).
+// The weighted-GS farfield update of one hologram by one block (sh: one
+// float of LDS per wave).
 __device__ void wgs_update_block(
     int N, int slices, const float2* __restrict__ red,
     const float* __restrict__ t, float t_norm, float* __restrict__ W,
@@ -874,7 +876,7 @@ __device__ void wgs_update_block(
   const int tid = threadIdx.x;
   // pass 1: fields, |E|^2 and normalised intensities I = |E|^2 / t^2
   float s_a2 = 0.0f, s_I = 0.0f, mx = 0.0f, mn = INFINITY;
-  for (int k = tid; k < N; k += kUpd) {
+  for (int k = tid; k < N; k += blockDim.x) {
     const float2 e = sum_slices(red, slices, N, k);
     Ebuf[k] = e;
     if (E_extra) E_extra[k] = e;
@@ -893,7 +895,7 @@ __device__ void wgs_update_block(
   const float meanI = sum_I / (float)N;
   // pass 2: spread of I, unnormalised weight update
   float s_v = 0.0f, s_w = 0.0f;
-  for (int k = tid; k < N; k += kUpd) {
+  for (int k = tid; k < N; k += blockDim.x) {
     const float2 e = Ebuf[k];
     const float a2 = e.x * e.x + e.y * e.y;
     const float dI = a2 / (t[k] * t[k]) - meanI;
@@ -911,7 +913,7 @@ __device__ void wgs_update_block(
   const float mean_w = block_reduce(s_w, sh, OpSum()) / (float)N;
   // pass 3: normalise weights, farfield projection y = W t E / |E|,
   // stored in polar form (W t, arg E / 2 pi in pieces); arg 0 = 0
-  for (int k = tid; k < N; k += kUpd) {
+  for (int k = tid; k < N; k += blockDim.x) {
     const float wk = W[k] / mean_w;
     W[k] = wk;
     const float2 e = Ebuf[k];
@@ -932,7 +934,7 @@ __global__ __launch_bounds__(kUpd) void k_wgs_update(
     float power, float eff_denom, unsigned* __restrict__ ypol,
     float2* __restrict__ Ebuf, float2* __restrict__ E_extra,
     float* __restrict__ stats) {
-  __shared__ float sh[kUpd];
+  __shared__ float sh[kUpd / kWave];
   wgs_update_block(N, slices, red, t, t_norm, W, power, eff_denom, ypol, Ebuf,
                    E_extra, stats, sh);
 }
@@ -956,14 +958,15 @@ hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
 //   L_spot = sum_k d_k^2,   G_k = dL/dRe E_k + i dL/dIm E_k = 4 d_k Eh_k / s,
 // stored as spot-field records (|G_k|, arg G_k) for the adjoint.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kUpd) void k_spot_loss(
-    int N, int slices, const float2* __restrict__ red,
-    const float* __restrict__ t, float inv_s, unsigned* __restrict__ ypol,
-    float2* __restrict__ E_extra, float* __restrict__ lossbuf) {
-  __shared__ float sh[kUpd];
+__device__ void spot_loss_block(int N, int slices,
+                                const float2* __restrict__ red,
+                                const float* __restrict__ t, float inv_s,
+                                unsigned* __restrict__ ypol,
+                                float2* __restrict__ E_extra,
+                                float* __restrict__ lossbuf, float* sh) {
   const int tid = threadIdx.x;
   float acc = 0.0f, comp = 0.0f;
-  for (int k = tid; k < N; k += kUpd) {
+  for (int k = tid; k < N; k += blockDim.x) {
     const float2 e = sum_slices(red, slices, N, k);
     if (E_extra) E_extra[k] = e;
     const float hr = e.x * inv_s, hi = e.y * inv_s;
@@ -975,6 +978,14 @@ __global__ __launch_bounds__(kUpd) void k_spot_loss(
   }
   const float L = block_reduce(acc, sh, OpSum());
   if (tid == 0) lossbuf[0] = L;
+}
+
+__global__ __launch_bounds__(kUpd) void k_spot_loss(
+    int N, int slices, const float2* __restrict__ red,
+    const float* __restrict__ t, float inv_s, unsigned* __restrict__ ypol,
+    float2* __restrict__ E_extra, float* __restrict__ lossbuf) {
+  __shared__ float sh[kUpd / kWave];
+  spot_loss_block(N, slices, red, t, inv_s, ypol, E_extra, lossbuf, sh);
 }
 
 hipError_t launch_spot_loss(int N, const FwdPlan& p, const float* red,
@@ -991,7 +1002,7 @@ hipError_t launch_spot_loss(int N, const FwdPlan& p, const float* red,
 __global__ __launch_bounds__(kUpd) void k_loss_finish(
     int n, const float* __restrict__ tvp, float tv_sum_scale,
     const float* __restrict__ lossbuf, float* __restrict__ loss_out) {
-  __shared__ float sh[kUpd];
+  __shared__ float sh[kUpd / kWave];
   float acc = 0.0f, comp = 0.0f;
   for (int k = threadIdx.x; k < n; k += kUpd) kahan_add(acc, comp, tvp[k]);
   const float tv = block_reduce(acc, sh, OpSum());
@@ -1325,7 +1336,7 @@ __global__ __launch_bounds__(64) void k_batch_reduce(
 
 __global__ __launch_bounds__(kUpd) void k_batch_update(
     const HoloDesc* __restrict__ hd, float power) {
-  __shared__ float sh[kUpd];
+  __shared__ float sh[kUpd / kWave];
   const HoloDesc& d = hd[blockIdx.x];
   wgs_update_block(d.N, d.slices, d.red, d.target, d.t_norm, d.W, power,
                    d.eff_denom, d.ypol, d.Ebuf, nullptr, nullptr, sh);
