@@ -38,6 +38,29 @@ def flops_per_eval(D):
     return 2 * D + 11
 
 
+# Issue costs on gfx950 in cycles per wave64 instruction per SIMD at the
+# nominal 2.4 GHz, from microbenchmarks: FP32 FMA, hardware sine or cosine,
+# and one 32x32x16 bf16 matrix-core product (vector and matrix-core issue
+# do not overlap).  A 32 x 32 block of evaluations needs 32 sines and
+# cosines, 32 FMAs and `groups` matrix-core products at the least.
+ISSUE_CYCLES = {"fma": 2.68, "trans": 9.03, "mfma": 36.0}
+SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
+
+
+def issue_ceiling(groups):
+    """Evaluations/s if every SIMD issued only the irreducible work."""
+    c = (32 * ISSUE_CYCLES["trans"] + 32 * ISSUE_CYCLES["fma"]
+         + groups * ISSUE_CYCLES["mfma"])
+    return SIMDS * CLOCK_HZ * 1024 / c
+
+
+def issue_model(evals_per_s, groups):
+    ceil = issue_ceiling(groups)
+    return {"ceiling_evals_per_s": ceil, "achieved_evals_per_s": evals_per_s,
+            "frac": evals_per_s / ceil, "groups": groups,
+            "cycles": ISSUE_CYCLES}
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +231,7 @@ def bench_adam(args, d):
         "kernels": {k: {"total_ms": v[0], "launches": v[1],
                         "avg_ms": v[0] / v[1] if v[1] else None}
                     for k, v in prof.items()},
+        "issue_model": issue_model(N * P / (ms_avg * 1e-3), info["groups"]),
         "loss_first_last": [float(L[0]), float(L[-1])],
         "layout": info,
     }
@@ -291,6 +315,9 @@ def bench_batch(args, holos):
         "kernels": {k: {"total_ms": v[0], "launches": v[1],
                         "avg_ms": v[0] / v[1] if v[1] else None}
                     for k, v in prof.items()},
+        "issue_model": issue_model(
+            evals * n_iter * args.steps / (prof[dom][0] * 1e-3),
+            info["groups"][0] if info["groups"] else 0),
         "layout": info, "tune_s": tune_s,
     }
     b.close()
@@ -391,7 +418,9 @@ def main():
         "wgs_iters_per_s": n_iter * args.steps / T,
         "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
         "ms_per_step_without_events": 1e3 * (t3 - t2) / args.steps,
-        "roofline": roofline, "kernels": kernels, "layout": info,
+        "roofline": roofline,
+        "issue_model": issue_model(N * P / (ms_avg * 1e-3), info["groups"]),
+        "kernels": kernels, "layout": info,
     }
 
     if not args.no_cpu_baseline:

@@ -30,7 +30,7 @@ struct Cls {
   int L = kDefaultRange;
   std::vector<int> holos;
   size_t fwd_off = 0, adj_off = 0;  // first item of each phase
-  int qoff_fwd = 0, qoff_adj = 0;   // index of its 9 queue offsets in qoff
+  int qoff_fwd = 0;                 // index of its 9 queue offsets in qoff
   int fwd_grid = 0, adj_grid = 0;
 };
 
@@ -253,9 +253,10 @@ int plan(ash_batch* b) {
       }
     }
     b->qoff.push_back((int)(b->items.size() - c.fwd_off));
-    // adjoint: unit = (holo, tile), items = runs of its 16 rows, as many
-    // rows per item as keep an item at >= ~8 spot blocks of work (an item
-    // costs one atomic take)
+    // adjoint: unit = (holo, tile), one block per quarter tile (four rows,
+    // one per wave).  Blocks reach the XCDs round-robin, so block j * 8 + x
+    // takes the j-th block of XCD x's list (longest first); shorter lists
+    // are padded with idle blocks.
     units.clear();
     work.clear();
     for (int h : c.holos) {
@@ -267,26 +268,23 @@ int plan(ash_batch* b) {
       }
     }
     q = lpt(work);
+    constexpr int kQuarters = kBlkPerTile / (kBlock / kWave);
+    size_t longest = 0;
+    for (int x = 0; x < kXcds; ++x)
+      longest = std::max(longest, q[x].size() * kQuarters);
     c.adj_off = b->items.size();
-    c.qoff_adj = (int)b->qoff.size();
+    b->items.resize(c.adj_off + longest * kXcds, make_int4(-1, 0, 0, 0));
     for (int x = 0; x < kXcds; ++x) {
-      b->qoff.push_back((int)(b->items.size() - c.adj_off));
-      for (int u : q[x]) {
-        const int h = units[u].x, n_mb = (b->desc[h].N + 31) / 32;
-        int rows = kBlkPerTile;
-        while (rows > 1 && rows * n_mb > 8) rows >>= 1;
-        for (int r = 0; r < kBlkPerTile; r += rows)
-          b->items.push_back(
-              make_int4(h, units[u].y * kBlkPerTile + r, rows, 0));
-      }
+      size_t j = 0;
+      for (int u : q[x])
+        for (int qt = 0; qt < kQuarters; ++qt, ++j)
+          b->items[c.adj_off + j * kXcds + x] =
+              make_int4(units[u].x, units[u].y * kQuarters + qt, 0, 0);
     }
-    b->qoff.push_back((int)(b->items.size() - c.adj_off));
     c.fwd_grid = std::max(
         kXcds, batch_blocks_per_cu(c.G, c.reduce != 0, true) * b->n_cu /
                    kXcds * kXcds);
-    c.adj_grid = std::max(
-        kXcds, batch_blocks_per_cu(c.G, c.reduce != 0, false) * b->n_cu /
-                   kXcds * kXcds);
+    c.adj_grid = (int)(longest * kXcds);
   }
   if (b->items.size() > (size_t)INT32_MAX)
     return bfail(b, ASH_EUNSUPPORTED, "too many work items");
@@ -366,13 +364,12 @@ int enqueue_reduce_update(ash_batch* b, float power, bool update) {
   return ASH_OK;
 }
 
-int enqueue_adjoint(ash_batch* b, int* ctr, int last) {
+int enqueue_adjoint(ash_batch* b, int last) {
   for (size_t k = 0; k < b->cls.size(); ++k) {
     const Cls& c = b->cls[k];
     BCHK(b, btimed(b, ASH_PROF_ADJOINT, [&] {
            return launch_batch_adjoint(c.G, c.reduce != 0, c.adj_grid,
                                        b->d_desc, b->d_items + c.adj_off,
-                                       b->d_qoff + c.qoff_adj, ctr + 8 * k,
                                        last, b->stream);
          }), "batch adjoint");
   }
@@ -503,13 +500,13 @@ int ash_batch_wgs(ash_batch* b, float* const* phase_dev,
       (rc = upload_desc(b, phase_dev, weights_dev)))
     return rc;
   int* ctr = nullptr;
-  if ((rc = counters(b, 2 * (size_t)n_iter, &ctr))) return rc;
+  if ((rc = counters(b, (size_t)n_iter, &ctr))) return rc;
   const size_t per = b->cls.size() * kXcds;
   if ((rc = make_fields(b, phase_dev))) return rc;
   for (int it = 0; it < n_iter; ++it) {
-    if ((rc = enqueue_forward(b, ctr + (2 * it) * per)) ||
+    if ((rc = enqueue_forward(b, ctr + it * per)) ||
         (rc = enqueue_reduce_update(b, power, true)) ||
-        (rc = enqueue_adjoint(b, ctr + (2 * it + 1) * per, it == n_iter - 1)))
+        (rc = enqueue_adjoint(b, it == n_iter - 1)))
       return rc;
   }
   return ASH_OK;

@@ -187,18 +187,16 @@ struct HoloDesc {
   float t_norm, eff_denom;
 };
 
-// Work items: forward {holo, range, spot block, 0}; adjoint {holo, first
-// wave (tile * kBlkPerTile + row), rows, 0}; reduce {holo, first spot,
-// slice, 0}.
-// The items of a persistent launch sit in 8 per-XCD queues:
-// items[qoff[x] .. qoff[x+1]) with take counters ctr[x].
+// Work items: forward {holo, range, spot block, 0} in 8 per-XCD queues
+// items[qoff[x] .. qoff[x+1]) of a persistent launch, with take counters
+// ctr[x]; adjoint blocks {holo, tile * 4 + quarter, 0, 0} (holo < 0: idle);
+// reduce blocks {holo, first spot, slice, 0}.
 hipError_t launch_batch_forward(int G, bool reduce, int grid,
                                 const HoloDesc* d, const int4* items,
                                 const int* qoff, int* ctr, hipStream_t s);
 hipError_t launch_batch_adjoint(int G, bool reduce, int grid,
                                 const HoloDesc* d, const int4* items,
-                                const int* qoff, int* ctr, int last,
-                                hipStream_t s);
+                                int last, hipStream_t s);
 hipError_t launch_batch_reduce(const HoloDesc* d, const int4* blocks,
                                int n_blocks, hipStream_t s);
 hipError_t launch_batch_update(int H, const HoloDesc* d, float power,

@@ -1295,25 +1295,28 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(
   });
 }
 
+// Adjoint of a batch: one block per quarter tile {holo, tile * 4 +
+// quarter} of the item list (negative holo: idle padding), four rows, one
+// per wave; the hardware hands the blocks out as slots free up.
 template <int G, bool kReduce>
 __global__ __launch_bounds__(kBlock) void k_batch_adjoint(
     const HoloDesc* __restrict__ hd, const int4* __restrict__ items,
-    const int* __restrict__ qoff, int* __restrict__ ctr, int last) {
-  drain_queues(items, qoff, ctr, [&](const int4& it) {
-    const HoloDesc& d = hd[it.x];
-    AdjOut o;
-    o.outs = last ? kOutPhase : kOutField;
-    o.phase = d.phase;
-    o.nf_t = d.nf_t;
-    for (int wv = it.y; wv < it.y + it.z; ++wv)  // it.z tile rows
-      adjoint_row<G, kReduce>(
-          d.N, d.nx, d.ny, d.tiles_x, wv / kBlkPerTile,
-          (wv % kBlkPerTile) * 32, wv, as_global(d.pixtab),
-          as_global(d.spotrec),
-          as_global(reinterpret_cast<const u32x4*>(d.offtab)),
-          as_global(reinterpret_cast<const u32x4*>(d.ypol)),
-          as_global(d.amp_t), o);
-  });
+    int last) {
+  const int4 it = uniform_item(items, blockIdx.x);
+  if (it.x < 0) return;
+  const HoloDesc& d = hd[it.x];
+  AdjOut o;
+  o.outs = last ? kOutPhase : kOutField;
+  o.phase = d.phase;
+  o.nf_t = d.nf_t;
+  const int wv = it.y * (kBlock / kWave) +
+                 __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  adjoint_row<G, kReduce>(d.N, d.nx, d.ny, d.tiles_x, wv / kBlkPerTile,
+                          (wv % kBlkPerTile) * 32, wv, as_global(d.pixtab),
+                          as_global(d.spotrec),
+                          as_global(reinterpret_cast<const u32x4*>(d.offtab)),
+                          as_global(reinterpret_cast<const u32x4*>(d.ypol)),
+                          as_global(d.amp_t), o);
 }
 
 // one block per {holo, 64 spots, slice of kRowsPerSlice forward ranges}
@@ -1352,9 +1355,9 @@ static hipError_t bfwd_g(int grid, const HoloDesc* d, const int4* items,
 
 template <int G, bool kReduce>
 static hipError_t badj_g(int grid, const HoloDesc* d, const int4* items,
-                         const int* qoff, int* ctr, int last, hipStream_t s) {
+                         int last, hipStream_t s) {
   hipLaunchKernelGGL((k_batch_adjoint<G, kReduce>), dim3(grid), dim3(kBlock),
-                     0, s, d, items, qoff, ctr, last);
+                     0, s, d, items, last);
   return hipGetLastError();
 }
 
@@ -1375,13 +1378,13 @@ hipError_t launch_batch_forward(int G, bool reduce, int grid,
 
 hipError_t launch_batch_adjoint(int G, bool reduce, int grid,
                                 const HoloDesc* d, const int4* items,
-                                const int* qoff, int* ctr, int last,
-                                hipStream_t s) {
+                                int last, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
   switch (G) {
-#define X(n)                                                             \
-  case n:                                                                \
-    return reduce ? badj_g<n, true>(grid, d, items, qoff, ctr, last, s)  \
-                  : badj_g<n, false>(grid, d, items, qoff, ctr, last, s);
+#define X(n)                                                        \
+  case n:                                                           \
+    return reduce ? badj_g<n, true>(grid, d, items, last, s)        \
+                  : badj_g<n, false>(grid, d, items, last, s);
     ASH_G_CASES(X)
 #undef X
     default:
