@@ -117,7 +117,9 @@ __device__ inline void split3f(float v, unsigned* p) {
 // Nearfield of the tile-ordered pixels, per 32-pixel block (tile row)
 // [tile * kBlkPerTile + row][half][32] u32x4.  Half 0: the words of half 0
 // of the pixel record's last group (its nonlinear slots p 0..3, the phase
-// pieces and a 1 at p 4..7).  Half 1: {magnitude bits, 0, 0, 0}.
+// pieces and a 1 at p 4..7).  Half 1: {magnitude bits, then words 1..3
+// of half 1 of the last group (di, di | di, dj | dj, dj as bf16)}; word 0
+// of half 1 (p 8, 9: 1, 1) is a constant.
 __host__ __device__ inline long nf_index(long tile, int pix, int half) {
   return ((tile * kBlkPerTile + pix / 32) * 2 + half) * 32 + pix % 32;
 }
@@ -495,7 +497,11 @@ __global__ void k_make_field(Geom b, long total,
   }
   nf[nf_index(tile, pix, 0)] = nearfield_record(
       pixel_nl_words(pixtab, b.groups, tile, pix), turns);
-  nf[nf_index(tile, pix, 1)] = u32x4{__float_as_uint(mag), 0u, 0u, 0u};
+  const unsigned bdi = bf16_bits((float)(pix % kTileW - kAnchorI));
+  const unsigned bdj = bf16_bits((float)(pix / kTileW - kAnchorJ));
+  nf[nf_index(tile, pix, 1)] =
+      u32x4{__float_as_uint(mag), bdi | (bdi << 16), bdi | (bdj << 16),
+            bdj | (bdj << 16)};
 }
 
 hipError_t launch_make_field(const Geom& b, const float* phase,
@@ -621,9 +627,9 @@ __device__ __forceinline__ void accumulate(const floatx16& th, float m,
 // butterfly over the 32 lanes of each half-wave finishes the pixel sums,
 // written to row[k] for the block's spots k < N.  One load brings half 0
 // its nearfield record (the last group's nonlinear slots, the phase pieces
-// and 1) and half 1 the pixel's magnitude; half 1's last group (p 8..15:
-// 1, 1, di x 3, dj x 3) is formed in registers and the magnitude crosses
-// to half 0 with a lane-half swap.
+// and 1) and half 1 the pixel's magnitude with its last-group words 1..3
+// (di, dj); half 1's word 0 (1, 1) is a constant, and the magnitude
+// crosses to half 0 with a lane-half swap.
 // E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))).
 template <int G, bool kReduce>
 __device__ __forceinline__ void forward_range(
@@ -650,7 +656,6 @@ __device__ __forceinline__ void forward_range(
   for (int i = 0; i < 16; ++i) er[i] = ei[i] = 0.0f;
   const unsigned lane_ot = h * NP + q;
   const GLOBAL u32x4* __restrict__ ot_k = offtab + (long)mb * 32;
-  const unsigned bdi = bf16_bits((float)(q - kAnchorI));
   const unsigned one2 = kBf16One | (kBf16One << 16);
   // tiles of the range; the tile slots of the lane's spot once per tile
   for (long b = b0; b < b1;) {
@@ -668,10 +673,8 @@ __device__ __forceinline__ void forward_range(
       for (int g = 0; g < G - 1; ++g)
         X[g] = (px + g * 2 * kTile + r * 32)[lane_pix];
       const u32x4 rec = (pn + r * 64)[lane_spot];
-      const unsigned bdj = bf16_bits((float)(r - kAnchorJ));
-      X[G - 1] = h ? u32x4{one2, bdi | (bdi << 16), bdi | (bdj << 16),
-                           bdj | (bdj << 16)}
-                   : rec;
+      X[G - 1] = rec;
+      if (h) X[G - 1][0] = one2;
       // the magnitude sits in half 1's record; give half 0 its copy
       const float m = __uint_as_float(
           __builtin_amdgcn_permlane32_swap(rec.x, rec.x, false, false)[1]);
