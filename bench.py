@@ -54,6 +54,30 @@ def issue_ceiling(groups):
     return SIMDS * CLOCK_HZ * 1024 / c
 
 
+def alu_roofline(kernel, evals_per_launch, ms_avg, launches, D, groups,
+                 traffic=None, traffic_src=None):
+    """Roofline of a transform kernel in algorithmic FP32 flops.
+
+    The peak is the issue ceiling (irreducible sines, cosines, FMAs and
+    matrix-core products per 32 x 32 block on 1024 SIMDs at 2.4 GHz)
+    expressed in the same algorithmic flops per evaluation; the FP32
+    vector peak is given beside it.  Part of each evaluation runs on the
+    matrix cores, so the fraction of the vector peak alone can pass 1.
+    """
+    F = flops_per_eval(D)
+    achieved = evals_per_launch * F / (ms_avg * 1e-3) / 1e12
+    peak = F * issue_ceiling(groups) / 1e12
+    return {"bound": "alu", "kernel": kernel, "achieved": achieved,
+            "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": traffic, "traffic_unit": "bytes/launch",
+            "traffic_source": traffic_src, "avg_launch_ms": ms_avg,
+            "launches": launches, "flops_per_eval": F,
+            "evals_per_launch": evals_per_launch,
+            "peak_basis": "issue ceiling, %d matrix-core groups" % groups,
+            "fp32_vector_peak": FP32_VECTOR_PEAK_TFLOPS,
+            "frac_of_fp32_vector_peak": achieved / FP32_VECTOR_PEAK_TFLOPS}
+
+
 def issue_model(evals_per_s, groups):
     ceil = issue_ceiling(groups)
     return {"ceiling_evals_per_s": ceil, "achieved_evals_per_s": evals_per_s,
@@ -206,7 +230,6 @@ def bench_adam(args, d):
     value = 2.0 * N * P * n_steps * args.steps / T
     dom = max(("forward", "adjoint"), key=lambda k: prof[k][0])
     ms_avg = prof[dom][0] / max(prof[dom][1], 1)
-    achieved = N * P * F / (ms_avg * 1e-3) / 1e12
     kname = "k_%s<%d, %s>" % (dom, info["groups"],
                               "true" if info["range_reduce"] else "false")
     traffic, traffic_src = profiled_traffic(args.workload, kname)
@@ -221,13 +244,8 @@ def bench_adam(args, d):
                    "spots": N, "modes": D, "adam_steps_per_step": n_steps},
         "adam_steps_per_s": n_steps * args.steps / T,
         "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
-        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved,
-                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic, "traffic_unit": "bytes/launch",
-                     "traffic_source": traffic_src, "avg_launch_ms": ms_avg,
-                     "launches": prof[dom][1], "flops_per_eval": F,
-                     "evals_per_launch": N * P},
+        "roofline": alu_roofline(kname, N * P, ms_avg, prof[dom][1], D,
+                                 info["groups"], traffic, traffic_src),
         "kernels": {k: {"total_ms": v[0], "launches": v[1],
                         "avg_ms": v[0] / v[1] if v[1] else None}
                     for k, v in prof.items()},
@@ -291,9 +309,9 @@ def bench_batch(args, holos):
     evals = info["evals_per_transform"]
     value = 2.0 * evals * n_iter * args.steps / T
     dom = max(("forward", "adjoint"), key=lambda k: prof[k][0])
-    # every launch of a phase covers all holograms of its record shape;
-    # the achieved rate is over all launches of the dominant phase
-    achieved = evals * n_iter * args.steps * F / (prof[dom][0] * 1e-3) / 1e12
+    # every launch of a phase covers all holograms of its record shape
+    ms_avg = prof[dom][0] / max(prof[dom][1], 1)
+    groups = info["groups"][0] if info["groups"] else 0
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -305,19 +323,12 @@ def bench_batch(args, holos):
                    "wgs_iters_per_step": n_iter},
         "wgs_iters_per_s_per_hologram": n_iter * args.steps / T,
         "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
-        "roofline": {"bound": "alu", "kernel": "k_batch_%s" % dom,
-                     "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": None, "traffic_unit": "bytes/launch",
-                     "avg_launch_ms": prof[dom][0] / max(prof[dom][1], 1),
-                     "launches": prof[dom][1], "flops_per_eval": F},
+        "roofline": alu_roofline("k_batch_%s" % dom, evals, ms_avg,
+                                 prof[dom][1], D, groups),
         "kernels": {k: {"total_ms": v[0], "launches": v[1],
                         "avg_ms": v[0] / v[1] if v[1] else None}
                     for k, v in prof.items()},
-        "issue_model": issue_model(
-            evals * n_iter * args.steps / (prof[dom][0] * 1e-3),
-            info["groups"][0] if info["groups"] else 0),
+        "issue_model": issue_model(evals / (ms_avg * 1e-3), groups),
         "layout": info, "tune_s": tune_s,
     }
     b.close()
@@ -392,17 +403,11 @@ def main():
     # dominant kernel: the transform with the larger total time
     dom = max(("forward", "adjoint"), key=lambda k: prof[k][0])
     ms_avg = prof[dom][0] / max(prof[dom][1], 1)
-    achieved = N * P * F / (ms_avg * 1e-3) / 1e12
     kname = "k_%s<%d, %s>" % (dom, info["groups"],
                               "true" if info["range_reduce"] else "false")
     traffic, traffic_src = profiled_traffic(args.workload, kname)
-    roofline = {"bound": "alu", "kernel": kname,
-                "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                "traffic": traffic, "traffic_unit": "bytes/launch",
-                "traffic_source": traffic_src,
-                "avg_launch_ms": ms_avg, "launches": prof[dom][1],
-                "flops_per_eval": F, "evals_per_launch": N * P}
+    roofline = alu_roofline(kname, N * P, ms_avg, prof[dom][1], D,
+                            info["groups"], traffic, traffic_src)
     kernels = {k: {"total_ms": v[0], "launches": v[1],
                    "avg_ms": v[0] / v[1] if v[1] else None}
                for k, v in prof.items()}

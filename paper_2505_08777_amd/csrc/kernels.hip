@@ -167,6 +167,28 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
   s = t;
 }
 
+// Compensated sum of the n complex values p[0], p[stride], ... in index
+// order.  The loads go out eight at a time, so their latencies overlap; the
+// additions keep the serial order, so the result does not depend on it.
+__device__ __forceinline__ float2 kahan_sum_strided(
+    const float2* __restrict__ p, long stride, int n) {
+  float sr = 0.0f, si = 0.0f, cr = 0.0f, ci = 0.0f;
+  for (int q = 0; q < n; q += 8) {
+    float2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      v[u] = q + u < n ? p[(long)(q + u) * stride] : make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (q + u < n) {
+        kahan_add(sr, cr, v[u].x);
+        kahan_add(si, ci, v[u].y);
+      }
+    }
+  }
+  return make_float2(sr, si);
+}
+
 // ---------------------------------------------------------------------------
 // Basis table (FP64, rounded once into bf16 pieces).
 // ---------------------------------------------------------------------------
@@ -793,13 +815,8 @@ __global__ __launch_bounds__(64) void k_reduce(int N, int groups, int rows,
   if (k >= N) return;
   const int g0 = blockIdx.y * rows;
   const int g1 = min(g0 + rows, groups);
-  float sr = 0.0f, si = 0.0f, cr = 0.0f, ci = 0.0f;
-  for (int g = g0; g < g1; ++g) {
-    const float2 v = part[(long)g * N + k];
-    kahan_add(sr, cr, v.x);
-    kahan_add(si, ci, v.y);
-  }
-  red[(long)blockIdx.y * N + k] = make_float2(sr, si);
+  red[(long)blockIdx.y * N + k] =
+      kahan_sum_strided(part + (long)g0 * N + k, N, g1 - g0);
 }
 
 hipError_t launch_reduce(int N, const FwdPlan& p, const float* partial,
@@ -814,13 +831,7 @@ hipError_t launch_reduce(int N, const FwdPlan& p, const float* partial,
 
 __device__ __forceinline__ float2 sum_slices(const float2* __restrict__ red,
                                              int slices, int N, int k) {
-  float sr = 0.0f, si = 0.0f, cr = 0.0f, ci = 0.0f;
-  for (int q = 0; q < slices; ++q) {
-    const float2 v = red[(long)q * N + k];
-    kahan_add(sr, cr, v.x);
-    kahan_add(si, ci, v.y);
-  }
-  return make_float2(sr, si);
+  return kahan_sum_strided(red + k, N, slices);
 }
 
 __global__ void k_finish_E(int N, int slices, const float2* __restrict__ red,
@@ -870,7 +881,7 @@ struct OpMin {
 
 // The weighted-GS farfield update of one hologram by one block (sh: one
 // float of LDS per wave).
-__device__ void wgs_update_block(
+__device__ __forceinline__ void wgs_update_block(
     int N, int slices, const float2* __restrict__ red,
     const float* __restrict__ t, float t_norm, float* __restrict__ W,
     float power, float eff_denom, unsigned* __restrict__ ypol,
@@ -961,7 +972,7 @@ hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
 //   L_spot = sum_k d_k^2,   G_k = dL/dRe E_k + i dL/dIm E_k = 4 d_k Eh_k / s,
 // stored as spot-field records (|G_k|, arg G_k) for the adjoint.
 // ---------------------------------------------------------------------------
-__device__ void spot_loss_block(int N, int slices,
+__device__ __forceinline__ void spot_loss_block(int N, int slices,
                                 const float2* __restrict__ red,
                                 const float* __restrict__ t, float inv_s,
                                 unsigned* __restrict__ ypol,
@@ -1331,13 +1342,8 @@ __global__ __launch_bounds__(64) void k_batch_reduce(
   if (k >= d.N) return;
   const int r0 = bl.z * kRowsPerSlice;
   const int r1 = min(r0 + kRowsPerSlice, d.n_ranges);
-  float sr = 0.0f, si = 0.0f, cr = 0.0f, ci = 0.0f;
-  for (int r = r0; r < r1; ++r) {
-    const float2 v = d.partial[(long)r * d.N + k];
-    kahan_add(sr, cr, v.x);
-    kahan_add(si, ci, v.y);
-  }
-  d.red[(long)bl.z * d.N + k] = make_float2(sr, si);
+  d.red[(long)bl.z * d.N + k] =
+      kahan_sum_strided(d.partial + (long)r0 * d.N + k, d.N, r1 - r0);
 }
 
 __global__ __launch_bounds__(kUpd) void k_batch_update(
