@@ -20,6 +20,9 @@ grad       spot-amplitude loss with phase-gradient TV, its analytic phase
            gradient, central finite differences and the Adam update of the
            phase (Methods, "Computational Scaling", gradient-descent
            paragraph; Adam as published by Kingma and Ba).
+principal  principal isoplanatic modes: the SVD rotation of the non-linear
+           modes and its rank-K truncation (Methods, "Anisoplanatic
+           Singular Value Decomposition").
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_pins.py`` except the multi-step WGS trajectory, whose
@@ -29,13 +32,15 @@ FP32-vs-FP64 drift makes it "parity unpinned" beyond one step.
 from .zernike import (ansi_to_nm, nm_to_ansi, noll_to_nm, noll_to_ansi,
                       zernike_nm, ZernikeBasis, MonomialBasis)
 from .transform import Geometry, kernel_phase, forward, adjoint
-from .wgs import wgs_step, wgs_run, wgs_stats
+from .wgs import wgs_farfield, wgs_step, wgs_run, wgs_stats
 from .grad import (spot_norm, spot_loss, tv_loss, total_loss, loss_grad,
                    fd_grad, adam_step, adam_run)
+from .principal import linear_modes, RotatedBasis, principal_modes
 
 __all__ = [
     "ansi_to_nm", "nm_to_ansi", "noll_to_nm", "noll_to_ansi", "zernike_nm",
     "ZernikeBasis", "MonomialBasis", "Geometry", "kernel_phase", "forward",
-    "adjoint", "wgs_step", "wgs_run", "wgs_stats", "spot_norm", "spot_loss",
+    "adjoint", "wgs_farfield", "wgs_step", "wgs_run", "wgs_stats", "spot_norm", "spot_loss",
     "tv_loss", "total_loss", "loss_grad", "fd_grad", "adam_step", "adam_run",
+    "linear_modes", "RotatedBasis", "principal_modes",
 ]

@@ -44,15 +44,14 @@ def wgs_stats(E, t, amp):
     return np.array([eta, unif, spread, np.sum(a2)])
 
 
-def wgs_step(phi, weights, t, amp, w, basis, geom, power=1.0, workers=None):
-    """One WGS iteration. Returns (phi_new, weights_new, E, stats)."""
-    phi = np.asarray(phi, dtype=np.float64)
-    amp = np.asarray(amp, dtype=np.float64)
+def wgs_farfield(E, weights, t, power=1.0):
+    """Steps 2-5: the weight update and the farfield projection y of fields E.
+
+    Returns (y, weights_new).
+    """
+    E = np.asarray(E, dtype=np.complex128)
     t = np.asarray(t, dtype=np.float64)
     W = np.asarray(weights, dtype=np.float64).copy()
-
-    f = amp * np.exp(1j * phi)
-    E = forward(f, w, basis, geom, workers=workers)
     a = np.abs(E)
     na = np.sqrt(np.sum(a ** 2))
     nt = np.sqrt(np.sum(t ** 2))
@@ -65,6 +64,18 @@ def wgs_step(phi, weights, t, amp, w, basis, geom, power=1.0, workers=None):
 
     y = W * t + 0j
     y[lit] = W[lit] * t[lit] * E[lit] / a[lit]
+    return y, W
+
+
+def wgs_step(phi, weights, t, amp, w, basis, geom, power=1.0, workers=None):
+    """One WGS iteration. Returns (phi_new, weights_new, E, stats)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    amp = np.asarray(amp, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+
+    f = amp * np.exp(1j * phi)
+    E = forward(f, w, basis, geom, workers=workers)
+    y, W = wgs_farfield(E, weights, t, power)
     g = adjoint(y, w, basis, geom, workers=workers)
     phi_new = np.arctan2(g.imag, g.real)
     return phi_new, W, E, wgs_stats(E, t, amp)
