@@ -92,9 +92,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="field1024",
                     choices=["plain256", "field1024", "volume1920",
-                             "grad1024", "batch64"],
+                             "grad1024", "batch64", "principal1024"],
                     help="grad1024 times the differentiable form (Adam steps "
-                         "of the spot-amplitude loss with TV); batch64 the "
+                         "of the spot-amplitude loss with TV); principal1024 "
+                         "the WGS loop on 8 principal isoplanatic modes of a "
+                         "27-mode calibration; batch64 the "
                          "batched form (64 holograms' WGS loops together)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batch64: skip the autotuner (default range length)")
@@ -141,7 +143,7 @@ def profiled_traffic(workload, kernel):
     return val, os.path.relpath(path, ROOT)
 
 
-def cpu_baseline(ctx, d, pix_sample):
+def cpu_baseline(ctx, d, pix_sample, w=None, basis=None):
     """The FP64 oracle on a bounded sample of the same workload.
 
     Sample: one full forward transform (all spots, all pixels) at the
@@ -155,17 +157,20 @@ def cpu_baseline(ctx, d, pix_sample):
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from tolerance import field_errors
     geom = oracle.Geometry(d["nx"], d["ny"])
-    basis = oracle.ZernikeBasis(d["modes"])
+    if basis is None:
+        basis = oracle.ZernikeBasis(d["modes"])
+    if w is None:
+        w = d["w"]
     cores = len(os.sched_getaffinity(0))
     amp32 = d["amp"].astype(np.float32).astype(np.float64)
     phi32 = d["phi0"].astype(np.float32)
-    N, P = d["w"].shape[0], geom.P
+    N, P = w.shape[0], geom.P
     t0 = time.perf_counter()
     Eref = oracle.forward(amp32 * np.exp(1j * phi32.astype(np.float64)),
-                          d["w"], basis, geom, workers=cores)
+                          w, basis, geom, workers=cores)
     t1 = time.perf_counter()
     y = (d["t"] * Eref / np.abs(Eref)).astype(np.complex64)
-    gref = oracle.adjoint(y.astype(np.complex128), d["w"], basis, geom,
+    gref = oracle.adjoint(y.astype(np.complex128), w, basis, geom,
                           pixels=pix_sample, workers=cores)
     t2 = time.perf_counter()
     evals = N * P + N * len(pix_sample)
@@ -362,10 +367,30 @@ def main():
     N, D = d["w"].shape
     P = nx * ny
     dev = torch.device("cuda:0")
+    amp_t = torch.tensor(d["amp"], dtype=torch.float32, device=dev)
     ctx = A.Context(0)
-    ctx.set_basis(nx, ny, modes=d["modes"],
-                  amp=torch.tensor(d["amp"], dtype=torch.float32, device=dev))
-    ctx.set_spots(d["w"], d["t"])
+    principal = None
+    if args.workload == "principal1024":
+        # the WGS loop on the K leading principal modes; the full-basis loop
+        # is timed beside it
+        pw, cf = A.zernike_table(d["modes"])
+        cfK, wK, sigma = A.principal_modes(pw, cf, d["w"], d["K"])
+        ctx.set_basis(nx, ny, mono_pow=pw, mono_coef=cfK, amp=amp_t)
+        ctx.set_spots(wK, d["t"])
+        n_keep = wK.shape[1] - d["K"]
+        rot = d["w"][:, n_keep:]
+        # the Zernike modes are orthonormal over the pupil, so the norm of
+        # the dropped coefficients is the rms phase change over the pupil
+        drop = np.sqrt(np.maximum(0.0, np.sum(rot ** 2, axis=1)
+                                  - np.sum(wK[:, n_keep:] ** 2, axis=1)))
+        principal = {"K": d["K"], "modes_in": D, "modes_evaluated": wK.shape[1],
+                     "sigma": [float(x) for x in sigma],
+                     "rms_phase_change_rad": {"mean": float(drop.mean()),
+                                              "max": float(drop.max())}}
+        D = wK.shape[1]
+    else:
+        ctx.set_basis(nx, ny, modes=d["modes"], amp=amp_t)
+        ctx.set_spots(d["w"], d["t"])
     info = ctx.info()
     phase = torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
     weights = torch.ones(N, dtype=torch.float32, device=dev)
@@ -427,11 +452,43 @@ def main():
         "issue_model": issue_model(N * P / (ms_avg * 1e-3), info["groups"]),
         "kernels": kernels, "layout": info,
     }
+    if principal is not None:
+        out["config"].update(modes=principal["modes_in"],
+                             principal_modes=principal["K"],
+                             modes_evaluated=principal["modes_evaluated"])
+        full = A.Context(0)
+        full.set_basis(nx, ny, modes=d["modes"], amp=amp_t)
+        full.set_spots(d["w"], d["t"])
+        ph_f = torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
+        w_f = torch.ones(N, dtype=torch.float32, device=dev)
+        full.wgs(ph_f, 2, weights=w_f, want_E=False, want_stats=False)
+        torch.cuda.synchronize()
+        n_ref = min(n_iter, 20)
+        t4 = time.perf_counter()
+        full.wgs(ph_f, n_ref, weights=w_f, want_E=False, want_stats=False)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        ms_full = 1e3 * (t5 - t4) / n_ref
+        ms_princ = 1e3 * (t3 - t2) / args.steps / n_iter
+        principal["full_basis"] = {"groups": full.info()["groups"],
+                                   "ms_per_iter": ms_full,
+                                   "evals_per_s": 2.0 * N * P / (ms_full * 1e-3)}
+        principal["ms_per_iter"] = ms_princ
+        principal["loop_speedup"] = ms_full / ms_princ
+        full.close()
+        out["principal"] = principal
 
     if not args.no_cpu_baseline:
         rng = np.random.default_rng(12345)
         pix = np.sort(rng.choice(P, size=min(P, 65536), replace=False))
-        out["cpu_baseline"], out["parity"] = cpu_baseline(ctx, d, pix)
+        if principal is not None:
+            import oracle
+            wr, br, _ = oracle.principal_modes(
+                d["w"], oracle.ZernikeBasis(d["modes"]), d["K"])
+            out["cpu_baseline"], out["parity"] = cpu_baseline(
+                ctx, d, pix, w=wr, basis=br)
+        else:
+            out["cpu_baseline"], out["parity"] = cpu_baseline(ctx, d, pix)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -123,6 +123,37 @@ int ash_sync(ash_ctx* ctx);
 int ash_zernike_monomials(int ansi, int cap, int32_t* pow_out,
                           double* coef_out);
 
+/* Principal isoplanatic modes (paper: Methods, "Anisoplanatic Singular
+ * Value Decomposition"; the modal-expansion paragraph of "Computational
+ * Scaling" notes that such a basis lowers D).  Host-only: touches no
+ * context or device memory.
+ *   N, D, n_mono, mono_pow, mono_coef  a basis as for ash_set_basis and
+ *              w (host [N][D] float64) the spots' coefficients on it.
+ *   K          principal modes to keep, 0 .. n_rot, where the n_rot rotated
+ *              modes are those with a non-zero term of total degree >= 2;
+ *              the others (piston, tilts: constant and position of each
+ *              spot) are kept unchanged and come first, in their order.
+ * With W_R = U S V^T the SVD of the rotated modes' coefficients (singular
+ * values descending; each singular vector's largest entry positive), the
+ * new basis is [kept modes, B_1 .. B_K], B_j = sum_i V[i][j] Z_rot[i], and
+ * the new coefficients are [w_kept, W_R V_K]: the kernel phases change by
+ * replacing W_R with its best rank-K approximation W_R V_K V_K^T.
+ * Outputs (host, caller-allocated):
+ *   D_out      number of output modes, n_keep + K.
+ *   sigma      [n_rot] singular values of W_R, descending (n_rot <= D).
+ *   mono_out   [D_out][n_mono] monomial coefficients of the new basis
+ *              (same mono_pow), contiguous with row stride n_mono.
+ *   w_out      [N][D_out] new coefficients, contiguous with row stride
+ *              D_out (a [N][D] buffer is large enough).
+ * Pass mono_out / w_out to ash_set_basis / ash_set_spots.  Errors:
+ * ASH_EINVAL (sizes < 1, null pointers, non-finite values, negative
+ * exponents, K outside 0 .. n_rot), ASH_EUNSUPPORTED (D, n_mono or N above
+ * the limits). */
+int ash_principal_modes(int N, int D, int n_mono, const int32_t* mono_pow,
+                        const double* mono_coef, const double* w, int K,
+                        int* D_out, double* sigma, double* mono_out,
+                        double* w_out);
+
 /* Define the SLM and the basis.
  *   nx, ny     SLM size in pixels (1 .. ASH_MAX_SIDE).
  *   cx, cy, R  pupil centre (pixels) and unit radius (pixels, > 0).

@@ -7,8 +7,9 @@ Gerchberg-Saxton loop, as hand-written HIP kernels behind a C ABI
 """
 
 from ._lib import AshError, LIB_PATH, lib
-from .basis import zernike_monomials, zernike_table
+from .basis import principal_modes, zernike_monomials, zernike_table
 from .context import Batch, Context, Propagate, propagate
 
 __all__ = ["AshError", "Batch", "Context", "LIB_PATH", "Propagate", "lib",
-           "propagate", "zernike_monomials", "zernike_table"]
+           "principal_modes", "propagate", "zernike_monomials",
+           "zernike_table"]

@@ -79,6 +79,8 @@ def _load():
         "ash_set_stream": (I, [P, P]),
         "ash_sync": (I, [P]),
         "ash_zernike_monomials": (I, [I, I, P, P]),
+        "ash_principal_modes": (I, [I, I, I, P, P, P, I,
+                                    ctypes.POINTER(ctypes.c_int), P, P, P]),
         "ash_set_basis": (I, [P, I, I, D, D, D, I, I, P, P, P]),
         "ash_set_spots": (I, [P, I, P, P]),
         "ash_forward": (I, [P, P, P, P]),

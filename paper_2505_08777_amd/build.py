@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libash.so")
 
-SOURCES = ["host.cpp", "batch.cpp", "kernels.hip"]
+SOURCES = ["host.cpp", "batch.cpp", "principal.cpp", "kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for all device code: hipcc -O3 would

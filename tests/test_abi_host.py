@@ -95,3 +95,66 @@ def test_create_without_gpu_reports_hip_error():
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
     assert _lib.lib.ash_create(ctypes.byref(h), 0, None) == _lib.EHIP
+
+
+# -- principal isoplanatic modes (host-only entry point) ---------------------
+PM_MODES = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 13]
+
+
+def _pm_case(seed, N, rank=None):
+    rng = np.random.default_rng(seed)
+    nr = len(PM_MODES) - 3
+    if rank is None:
+        WR = rng.normal(0, 1.0, size=(N, nr)) * np.linspace(2.0, 0.1, nr)
+    else:
+        WR = rng.normal(size=(N, rank)) @ rng.normal(size=(rank, nr))
+    w = np.concatenate([rng.normal(size=(N, 1)), rng.uniform(-40, 40, size=(N, 2)), WR], axis=1)
+    return w
+
+
+@pytest.mark.parametrize("N,K", [(40, 3), (7, 9), (200, 1), (5, 0), (30, 9)])
+def test_principal_modes_match_oracle(N, K):
+    """Singular values and the truncated kernel phases against the oracle
+    (numpy's SVD); the phases do not depend on singular-vector signs."""
+    w = _pm_case(N * 10 + K, N)
+    pw, cf = A.zernike_table(PM_MODES)
+    cfK, wK, sigma = A.principal_modes(pw, cf, w, K)
+    basis = oracle.ZernikeBasis(PM_MODES)
+    wr, br, sr = oracle.principal_modes(w, basis, K)
+    np.testing.assert_allclose(sigma, sr, rtol=1e-10, atol=1e-12 * sr[0])
+    assert cfK.shape == (3 + K, pw.shape[0]) and wK.shape == (N, 3 + K)
+    geom = oracle.Geometry(40, 30)
+    idx = np.arange(geom.P)
+    th = oracle.kernel_phase(wK, oracle.MonomialBasis(pw, cfK), geom, idx)
+    th_ref = oracle.kernel_phase(wr, br, geom, idx)
+    assert np.max(np.abs(th - th_ref)) < 1e-9 * max(1.0, np.max(np.abs(th_ref)))
+    # kept modes first and unchanged
+    np.testing.assert_array_equal(wK[:, :3], w[:, :3])
+    np.testing.assert_array_equal(cfK[:3], cf[:3])
+
+
+def test_principal_modes_rank_k_exact():
+    w = _pm_case(3, 60, rank=4)
+    pw, cf = A.zernike_table(PM_MODES)
+    cfK, wK, sigma = A.principal_modes(pw, cf, w, 4)
+    assert np.all(sigma[4:] < 1e-12 * sigma[0])
+    geom = oracle.Geometry(24, 24)
+    idx = np.arange(geom.P)
+    th = oracle.kernel_phase(w, oracle.ZernikeBasis(PM_MODES), geom, idx)
+    thK = oracle.kernel_phase(wK, oracle.MonomialBasis(pw, cfK), geom, idx)
+    assert np.max(np.abs(thK - th)) < 1e-10
+
+
+def test_principal_modes_errors():
+    pw, cf = A.zernike_table(PM_MODES)
+    w = _pm_case(1, 10)
+    with pytest.raises(A.AshError):
+        A.principal_modes(pw, cf, w, 10)          # only 9 modes rotate
+    with pytest.raises(A.AshError):
+        A.principal_modes(pw, cf, w, -1)
+    w2 = w.copy()
+    w2[3, 5] = np.nan
+    with pytest.raises(A.AshError):
+        A.principal_modes(pw, cf, w2, 2)
+    assert _lib.lib.ash_principal_modes(0, 1, 1, None, None, None, 0, None,
+                                        None, None, None) == _lib.EINVAL

@@ -1,0 +1,155 @@
+"""GPU parity of transforms on principal isoplanatic modes.
+
+The library rotates the basis (ash_principal_modes, host FP64 Jacobi SVD)
+and the HIP transforms run on the rotated tables; the oracle rotates with
+numpy's SVD and evaluates the rotated Zernike basis by the radial formula.
+The transforms do not depend on singular-vector signs, so they are compared
+directly, to the field bar.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tolerance import assert_fields, assert_phase, field_errors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_08777_amd as A
+    return A
+
+
+def _order(ansi):
+    n = 0
+    while (n + 1) * (n + 2) // 2 <= ansi:
+        n += 1
+    return n
+
+
+def _smooth_w(rng, nx, ny, N, modes, rank=None, noise=0.05):
+    """Positions uniform over the Nyquist field; the aberration block is a
+    smooth function of position plus noise (or of a given rank), scaled by
+    1.2/(n-1) for radial order n so that the phase stays sampled within a
+    pixel tile."""
+    u = rng.uniform(-nx / 2, nx / 2, N)
+    v = rng.uniform(-ny / 2, ny / 2, N)
+    lin = [d for d in modes if d <= 2]
+    nr = len(modes) - len(lin)
+    if rank is None:
+        F = np.stack([np.ones(N), u / nx, v / ny, (u / nx) ** 2, u * v / (nx * ny)], 1)
+        WR = F @ rng.normal(0, 1.0, size=(F.shape[1], nr)) + rng.normal(0, noise, (N, nr))
+    else:
+        WR = rng.normal(size=(N, rank)) @ rng.normal(0, 0.7, size=(rank, nr))
+    w = np.zeros((N, len(modes)))
+    R = min(nx, ny) / 2
+    for k, d in enumerate(lin):
+        w[:, k] = {0: rng.normal(size=N), 1: np.pi * v * R / ny, 2: np.pi * u * R / nx}[d]
+    w[:, len(lin):] = WR * np.array([1.2 / (_order(d) - 1) for d in modes
+                                     if d > 2])
+    return w
+
+
+def _run(A, nx, ny, modes, w, K, amp, phi, y, full=False):
+    pw, cf = A.zernike_table(modes)
+    cfK, wK, sigma = A.principal_modes(pw, cf, w, K)
+    c = A.Context(0)
+    c.set_precision(full)
+    c.set_basis(nx, ny, mono_pow=pw, mono_coef=cfK,
+                amp=torch.tensor(amp, dtype=torch.float32, device="cuda"))
+    c.set_spots(wK)
+    _say("  info", c.info())
+    E = c.forward(phase=torch.tensor(phi, dtype=torch.float32, device="cuda")).cpu().numpy()
+    g, ph = c.adjoint(torch.tensor(y, dtype=torch.complex64, device="cuda"),
+                      field=True, phase=True)
+    c.close()
+    return E, g.cpu().numpy(), ph.cpu().numpy(), sigma
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["auto", "full"])
+@pytest.mark.parametrize("nx,ny,N,modes,K", [
+    (256, 200, 90, list(range(15)), 5),
+    (256, 192, 300, [1, 2] + list(range(3, 28)), 8),
+    (64, 48, 20, [1, 2, 4, 12], 1),
+])
+def test_principal_transforms_match_oracle(A, nx, ny, N, modes, K, full):
+    _say("case", nx, ny, N, len(modes), K, full)
+    rng = np.random.default_rng(nx + ny + N)
+    w = _smooth_w(rng, nx, ny, N, modes)
+    amp = rng.uniform(0.2, 1.0, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    y = (rng.normal(size=N) + 1j * rng.normal(size=N)).astype(np.complex64)
+    E, g, ph, sigma = _run(A, nx, ny, modes, w, K, amp, phi, y, full)
+    geom = oracle.Geometry(nx, ny)
+    wr, br, sr = oracle.principal_modes(w, oracle.ZernikeBasis(modes), K)
+    np.testing.assert_allclose(sigma, sr, rtol=1e-9, atol=1e-12 * sr[0])
+    Eref = oracle.forward(amp * np.exp(1j * phi), wr, br, geom)
+    _say("  forward", field_errors(E, Eref))
+    assert_fields(E, Eref, what="principal forward")
+    gref = oracle.adjoint(y.astype(np.complex128), wr, br, geom)
+    _say("  adjoint", field_errors(g, gref))
+    assert_fields(g, gref, what="principal adjoint")
+    assert_phase(ph, np.angle(gref), gref, what="principal adjoint phase")
+
+
+def test_rank_k_principal_equals_full_basis(A):
+    """A calibration of rank 3 loses nothing on 3 principal modes: the GPU
+    transforms on them match the oracle on the full 15-mode basis."""
+    nx, ny, N, modes = 160, 96, 64, list(range(15))
+    rng = np.random.default_rng(3)
+    w = _smooth_w(rng, nx, ny, N, modes, rank=3)
+    amp = rng.uniform(0.2, 1.0, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    y = (rng.normal(size=N) + 1j * rng.normal(size=N)).astype(np.complex64)
+    E, g, _, sigma = _run(A, nx, ny, modes, w, 3, amp, phi, y)
+    assert np.all(sigma[3:] < 1e-12 * sigma[0])
+    geom = oracle.Geometry(nx, ny)
+    basis = oracle.ZernikeBasis(modes)
+    assert_fields(E, oracle.forward(amp * np.exp(1j * phi), w, basis, geom),
+                  what="rank-3 forward")
+    assert_fields(g, oracle.adjoint(y.astype(np.complex128), w, basis, geom),
+                  what="rank-3 adjoint")
+
+
+def test_principal1024_sampled(A):
+    """The benchmarked workload (1024 x 1024, 400 spots, 27 modes onto 8
+    principal modes): 64 spots and 4096 pixels against the oracle."""
+    d = workloads.make("principal1024")
+    nx, ny, N = d["nx"], d["ny"], d["w"].shape[0]
+    pw, cf = A.zernike_table(d["modes"])
+    cfK, wK, _ = A.principal_modes(pw, cf, d["w"], d["K"])
+    c = A.Context(0)
+    c.set_basis(nx, ny, mono_pow=pw, mono_coef=cfK,
+                amp=torch.tensor(d["amp"], dtype=torch.float32, device="cuda"))
+    c.set_spots(wK, d["t"])
+    _say("  info", c.info())
+    geom = oracle.Geometry(nx, ny)
+    wr, br, _ = oracle.principal_modes(d["w"], oracle.ZernikeBasis(d["modes"]), d["K"])
+    amp = d["amp"].astype(np.float32).astype(np.float64)
+    phi = d["phi0"].astype(np.float32).astype(np.float64)
+    E = c.forward(phase=torch.tensor(phi, dtype=torch.float32, device="cuda")).cpu().numpy()
+    rng = np.random.default_rng(8)
+    sel = np.sort(rng.choice(N, size=64, replace=False))
+    Eref = oracle.forward(amp * np.exp(1j * phi), wr, br, geom, spots=sel)
+    _say("  forward", field_errors(E[sel], Eref))
+    assert_fields(E[sel], Eref, what="principal1024 forward")
+    y = (np.exp(1j * rng.uniform(-np.pi, np.pi, N))).astype(np.complex64)
+    g = c.adjoint(torch.tensor(y, device="cuda")).cpu().numpy().reshape(-1)
+    pix = np.sort(rng.choice(geom.P, size=4096, replace=False))
+    gref = oracle.adjoint(y.astype(np.complex128), wr, br, geom, pixels=pix)
+    _say("  adjoint", field_errors(g[pix], gref))
+    assert_fields(g[pix], gref, what="principal1024 adjoint")
+    c.close()

@@ -25,6 +25,18 @@ paper's experiments:
   batch64     64 holograms, SLM side from {512, 1024, 1536, 2048}, spot
               counts log-uniform in [10, 5000], ANSI tilt + Noll 4-13,
               aberration ~ N(0, 0.7)
+  principal1024
+              field1024's SLM and 20x20 spot grid with a higher-order
+              calibration: 50 patches (10x5) over ANSI 3-27 (radial orders
+              2-6) whose coefficients vary smoothly over the field (each a
+              random quadratic in the normalised field position, terms of
+              std 1.2/(n-1) rad for radial order n), bilinearly interpolated
+              to the spots, plus independent calibration noise N(0, 0.05)
+              per spot and mode; to be compressed onto K = 8 principal
+              isoplanatic modes
+              (stand-in for the 44th-order calibration projected onto 8
+              principal modes, "A Full-Field 2D Tweezer Array" and Methods,
+              "Anisoplanatic Singular Value Decomposition")
 
 Conventions shared with the consumers (and stated on the C ABI):
   pixel (i, j), i the column index (fastest); pupil centre (nx/2, ny/2);
@@ -46,7 +58,8 @@ BASE_SEED = 2505
 NOLL4_11_ANSI = [3, 4, 5, 6, 7, 8, 9, 12]
 NOLL4_13_ANSI = [3, 4, 5, 6, 7, 8, 9, 12, 13, 11]
 
-WORKLOADS = ("plain256", "field1024", "volume1920", "grad1024", "batch64")
+WORKLOADS = ("plain256", "field1024", "volume1920", "grad1024", "batch64",
+             "principal1024")
 
 
 def geometry(nx, ny):
@@ -177,6 +190,37 @@ def grad1024(seed=None, n=1024, N=1000):
     return d
 
 
+def _radial_order(ansi):
+    n = 0
+    while (n + 1) * (n + 2) // 2 <= ansi:
+        n += 1
+    return n
+
+
+def principal1024(seed=None, n=1024, K=8):
+    seed = BASE_SEED + 7 if seed is None else seed
+    rng = np.random.default_rng(seed)
+    aber = list(range(3, 28))
+    std = np.array([1.2 / (_radial_order(d) - 1) for d in aber])
+    px = -n / 2 + (np.arange(10) + 0.5) * n / 10
+    py = -n / 2 + (np.arange(5) + 0.5) * n / 5
+    fy, fx = np.meshgrid(py / (n / 2), px / (n / 2), indexing="ij")
+    field = np.stack([np.ones_like(fx), fx, fy, fx * fx, fx * fy, fy * fy])
+    coef = rng.normal(0.0, 1.0, size=(6, len(aber))) * std
+    patches = np.tensordot(field, coef, axes=(0, 0))      # [y, x, mode]
+    c = -n / 2 + (np.arange(20) + 0.5) * n / 20
+    v, u = np.meshgrid(c, c, indexing="ij")
+    u, v = u.ravel(), v.ravel()
+    N = u.size
+    modes = [1, 2] + aber
+    w = np.zeros((N, len(modes)))
+    w[:, 0], w[:, 1] = tilt_coefs(u, v, n, n)
+    w[:, 2:] = _bilinear(px, py, patches, u, v) \
+        + rng.normal(0.0, 0.05, size=(N, len(aber)))
+    return _pack("principal1024", seed, n, n, modes, w, np.ones(N), rng, 100,
+                 u=u, v=v, K=K)
+
+
 BATCH_SIDES = (512, 1024, 1536, 2048)
 
 
@@ -208,4 +252,5 @@ def make(name, seed=None):
     if name == "batch64":
         return [batch_hologram(s) for s in batch64_specs(seed)]
     return {"plain256": plain256, "field1024": field1024,
-            "volume1920": volume1920, "grad1024": grad1024}[name](seed)
+            "volume1920": volume1920, "grad1024": grad1024,
+            "principal1024": principal1024}[name](seed)
