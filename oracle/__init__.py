@@ -19,7 +19,9 @@ wgs        one weighted Gerchberg-Saxton step ("A Full-Field 2D Tweezer
 grad       spot-amplitude loss with phase-gradient TV, its analytic phase
            gradient, central finite differences and the Adam update of the
            phase (Methods, "Computational Scaling", gradient-descent
-           paragraph; Adam as published by Kingma and Ba).
+           paragraph; Adam as published by Kingma and Ba); the basis
+           moments of the forward and the gradient with respect to the
+           kernel coefficients w.
 principal  principal isoplanatic modes: the SVD rotation of the non-linear
            modes and its rank-K truncation (Methods, "Anisoplanatic
            Singular Value Decomposition").
@@ -34,7 +36,7 @@ from .zernike import (ansi_to_nm, nm_to_ansi, noll_to_nm, noll_to_ansi,
 from .transform import Geometry, kernel_phase, forward, adjoint
 from .wgs import wgs_farfield, wgs_step, wgs_run, wgs_stats
 from .grad import (spot_norm, spot_loss, tv_loss, total_loss, loss_grad,
-                   fd_grad, adam_step, adam_run)
+                   fd_grad, adam_step, adam_run, forward_moments, coef_grad)
 from .principal import linear_modes, RotatedBasis, principal_modes
 
 __all__ = [
@@ -42,5 +44,6 @@ __all__ = [
     "ZernikeBasis", "MonomialBasis", "Geometry", "kernel_phase", "forward",
     "adjoint", "wgs_farfield", "wgs_step", "wgs_run", "wgs_stats", "spot_norm", "spot_loss",
     "tv_loss", "total_loss", "loss_grad", "fd_grad", "adam_step", "adam_run",
-    "linear_modes", "RotatedBasis", "principal_modes",
+    "linear_modes", "RotatedBasis", "principal_modes", "forward_moments",
+    "coef_grad",
 ]

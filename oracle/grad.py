@@ -184,3 +184,35 @@ def adam_run(phi, amp, t, w, basis, geom, n_steps, lr=0.05, betas=(0.9, 0.999),
         losses.append(L)
         phi, m, v = adam_step(phi, g, m, v, s, lr, betas[0], betas[1], eps)
     return phi, m, v, np.array(losses)
+
+
+# ---------------------------------------------------------------------------
+# Gradients with respect to the kernel coefficients w[k, d]
+# ---------------------------------------------------------------------------
+# The paper moves spots in aberration space by changing w (Methods,
+# "Computational Scaling": agile updates of the N x D matrix) and fits
+# aberrations in situ; differentiating the spot fields by w gives
+#
+#   dE_k/dw[k, d] = -i M[k, d],   M[k, d] = sum_x Z_d(x) f(x) exp(-i theta_k(x))
+#
+# (each E_k depends on its own row w[k] only), so for a real loss with
+# G_k = dL/dRe E_k + i dL/dIm E_k
+#
+#   dL/dw[k, d] = Re(conj(G_k) dE_k/dw[k, d]) = Im(conj(G_k) M[k, d]).
+
+def forward_moments(f, w, basis, geom, workers=None):
+    """M[k, d] = sum_x Z_d(x) f(x) exp(-i theta_k(x)), complex128 [N, D]."""
+    f = np.asarray(f, dtype=np.complex128).reshape(-1)
+    w = np.asarray(w, dtype=np.float64)
+    xh, yh = geom.coords(np.arange(geom.P))
+    Z = basis.evaluate(xh, yh)                             # [D, P]
+    cols = [forward(Z[d] * f, w, basis, geom, workers=workers)
+            for d in range(Z.shape[0])]
+    return np.stack(cols, axis=1)
+
+
+def coef_grad(f, w, basis, geom, G, workers=None):
+    """dL/dw[k, d] = Im(conj(G_k) M[k, d]) for the field gradient G."""
+    M = forward_moments(f, w, basis, geom, workers)
+    G = np.asarray(G, dtype=np.complex128).reshape(-1)
+    return np.imag(np.conj(G)[:, None] * M)

@@ -486,3 +486,71 @@ def test_adam_run_descends_and_uses_loss_grad():
         g, _, _ = oracle.loss_grad(q, amp, t, w, basis, geom)
         q, mm, vv = oracle.adam_step(q, g, mm, vv, s, lr=0.02)
     np.testing.assert_allclose(phi1, q, rtol=0, atol=1e-14)
+
+
+# -- gradients with respect to the kernel coefficients ----------------------
+def _coef_case(seed=21, nx=14, ny=10, N=6):
+    rng = np.random.default_rng(seed)
+    geom = oracle.Geometry(nx, ny)
+    modes = [0, 1, 2, 3, 4, 7, 12]
+    basis = oracle.ZernikeBasis(modes)
+    w = rng.normal(0, 0.8, size=(N, len(modes)))
+    w[:, 1:3] *= 4.0
+    f = rng.uniform(0.3, 1, size=(ny, nx)) * np.exp(1j * rng.uniform(-np.pi, np.pi, (ny, nx)))
+    return geom, basis, w, f, rng
+
+
+def test_moments_are_central_differences_of_the_fields():
+    """-i M[k, d] is the derivative of E_k along w[k, d] (FP64 central
+    differences, truncation ~h^2)."""
+    geom, basis, w, f, _ = _coef_case()
+    M = oracle.forward_moments(f, w, basis, geom)
+
+    def central(k, d, h):
+        wp = w.copy(); wp[k, d] += h
+        wm = w.copy(); wm[k, d] -= h
+        return (oracle.forward(f, wp, basis, geom, spots=[k])
+                - oracle.forward(f, wm, basis, geom, spots=[k]))[0] / (2 * h)
+    h = 1e-4
+    for k in range(w.shape[0]):
+        for d in range(w.shape[1]):
+            # Richardson: cancels the h^2 term of the central difference
+            dE = (4.0 * central(k, d, h / 2) - central(k, d, h)) / 3.0
+            assert abs(dE - (-1j) * M[k, d]) < 1e-8 * max(1.0, abs(M[k, d]))
+
+
+def test_piston_moment_is_the_field_and_tilt_moment_closed_form():
+    """Z_0 = 1 gives M[:, 0] = E; with f = 1 and w = 0 the x-tilt moment is
+    the plain sum of Z_2 = 2 xh over the grid."""
+    geom, basis, w, f, _ = _coef_case()
+    M = oracle.forward_moments(f, w, basis, geom)
+    E = oracle.forward(f, w, basis, geom)
+    np.testing.assert_allclose(M[:, 0], E, rtol=1e-13, atol=1e-12)
+    # f = 1, w = 0 on the 8 x 8 SLM: M = sum_x 2 (i - nx/2) / R
+    nx = ny = 8
+    g = oracle.Geometry(nx, ny)
+    b = oracle.ZernikeBasis([2])
+    Mx = oracle.forward_moments(np.ones((ny, nx)), np.zeros((1, 1)), b, g)
+    # sum_x 2 (i - nx/2)/R over the grid: ny * 2/R * sum_i (i - nx/2) = ny * 2/R * (-nx/2)
+    np.testing.assert_allclose(Mx[0, 0], ny * 2.0 / g.R * (-nx / 2.0), rtol=1e-14)
+
+
+def test_coef_grad_matches_torch_autograd_dense_kernel():
+    torch = pytest.importorskip("torch")
+    geom, basis, w, f, rng = _coef_case(seed=22)
+    N = w.shape[0]
+    t = rng.uniform(0.5, 1.0, N)
+    s = 3.0
+    E = oracle.forward(f, w, basis, geom)
+    Eh = E / s
+    G = 4.0 * (np.abs(Eh) ** 2 - t) * Eh / s
+    g = oracle.coef_grad(f, w, basis, geom, G)
+    # independent route: dense kernel built from w in torch, autograd on w
+    xh, yh = geom.coords(np.arange(geom.P))
+    Z = torch.tensor(basis.evaluate(xh, yh))
+    wt = torch.tensor(w, requires_grad=True)
+    th = wt @ Z
+    Et = torch.exp(-1j * th) @ torch.tensor(f.reshape(-1))
+    L = torch.sum((torch.abs(Et / s) ** 2 - torch.tensor(t)) ** 2)
+    L.backward()
+    np.testing.assert_allclose(g, wt.grad.numpy(), rtol=1e-10, atol=1e-12 * np.abs(g).max())
