@@ -92,11 +92,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="field1024",
                     choices=["plain256", "field1024", "volume1920",
-                             "grad1024", "batch64", "principal1024"],
+                             "grad1024", "batch64", "principal1024",
+                             "coefgrad1024"],
                     help="grad1024 times the differentiable form (Adam steps "
                          "of the spot-amplitude loss with TV); principal1024 "
                          "the WGS loop on 8 principal isoplanatic modes of a "
-                         "27-mode calibration; batch64 the "
+                         "27-mode calibration; coefgrad1024 the gradient in "
+                         "the kernel coefficients (moment transform) on the "
+                         "grad1024 inputs; batch64 the "
                          "batched form (64 holograms' WGS loops together)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batch64: skip the autotuner (default range length)")
@@ -190,6 +193,117 @@ def cpu_baseline(ctx, d, pix_sample, w=None, basis=None):
               "adjoint_max_rel": ge[0], "adjoint_norm_rel": ge[1],
               "bar": 1e-4}
     return obj, parity
+
+
+def coef_issue_ceiling(groups):
+    """Evaluations/s of the moment transform if every SIMD issued only its
+    sines, cosines and matrix-core products (G for the phase, 8 for the two
+    bf16 pieces of the cosines and sines against the moment table, over two
+    16-pixel K blocks) per 32 x 32 block."""
+    c = 32 * ISSUE_CYCLES["trans"] + (groups + 8) * ISSUE_CYCLES["mfma"]
+    return SIMDS * CLOCK_HZ * 1024 / c
+
+
+def bench_coef(args, d):
+    """Gradient in the kernel coefficients on the 1024 x 1024, 1000-spot
+    inputs: a step is `iters` calls of ash_coef_grad (moment transform and
+    the gradient finish) for a fixed field gradient G."""
+    import numpy as np
+    import torch
+    import paper_2505_08777_amd as A
+
+    n_calls = args.iters or 20
+    nx, ny = d["nx"], d["ny"]
+    N, D = d["w"].shape
+    P = nx * ny
+    dev = torch.device("cuda:0")
+    ctx = A.Context(0)
+    ctx.set_basis(nx, ny, modes=d["modes"],
+                  amp=torch.tensor(d["amp"], dtype=torch.float32, device=dev))
+    ctx.set_spots(d["w"], d["t"])
+    info = ctx.info()
+    phase = torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(1024)
+    G = torch.tensor((rng.normal(size=N) + 1j * rng.normal(size=N))
+                     .astype(np.complex64), device=dev)
+    grad = torch.empty((N, D), dtype=torch.float32, device=dev)
+
+    def run():
+        for _ in range(n_calls):
+            ctx.coef_grad(phase, G, out=grad)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    ctx.profile(True, categories=("forward",))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    T = t1 - t0
+    value = N * P * n_calls * args.steps / T
+    ms_avg = prof["forward"][0] / max(prof["forward"][1], 1)
+    groups = info["groups"]
+    kname = "k_moments<%d, %d>" % (groups, 2 if 2 * D > 32 else 1)
+    F = 6 * D + 3       # phase 2D, reduction 1, sin + cos, 4D moment flops
+    achieved = N * P * F / (ms_avg * 1e-3) / 1e12
+    ceil = coef_issue_ceiling(groups)
+    peak = F * ceil / 1e12
+    out = {
+        "metric": "spot·pixel moment evals/s (gradient in the kernel "
+                  "coefficients)", "value": value, "unit": "evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "coefgrad1024", "slm": "%dx%d" % (nx, ny),
+                   "spots": N, "modes": D, "calls_per_step": n_calls},
+        "coef_grads_per_s": n_calls * args.steps / T,
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None, "avg_launch_ms": ms_avg,
+                     "launches": prof["forward"][1], "flops_per_eval": F,
+                     "evals_per_launch": N * P,
+                     "peak_basis": "issue ceiling: 32 sines and cosines, "
+                                   "%d + 8 matrix-core products per block"
+                                   % groups},
+        "kernels": {k: {"total_ms": v[0], "launches": v[1],
+                        "avg_ms": v[0] / v[1] if v[1] else None}
+                    for k, v in prof.items()},
+        "layout": info,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from tolerance import field_errors
+        geom = oracle.Geometry(nx, ny)
+        basis = oracle.ZernikeBasis(d["modes"])
+        cores = len(os.sched_getaffinity(0))
+        sel = np.sort(rng.choice(N, size=8, replace=False))
+        amp = d["amp"].astype(np.float32).astype(np.float64)
+        phi = d["phi0"].astype(np.float32).astype(np.float64)
+        Gh = G.cpu().numpy().astype(np.complex128)
+        t2 = time.perf_counter()
+        gref = oracle.coef_grad(amp * np.exp(1j * phi), d["w"], basis, geom,
+                                Gh[sel], spots=sel, workers=cores)
+        t3 = time.perf_counter()
+        ctx.coef_grad(phase, G, out=grad)
+        ge = field_errors(grad.cpu().numpy()[sel], gref)
+        out["cpu_baseline"] = {
+            "value": len(sel) * P / (t3 - t2), "unit": "evals/s",
+            "cores": cores, "kind": "oracle",
+            "sample": "coefficient gradient of %d spots over all %d pixels "
+                      "and %d modes (%.2f s), FP64 numpy on %d threads"
+                      % (len(sel), P, D, t3 - t2, cores)}
+        out["parity"] = {"coef_grad_max_rel": ge[0],
+                         "coef_grad_norm_rel": ge[1], "bar": 1e-4}
+        out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 def bench_adam(args, d):
@@ -357,6 +471,8 @@ def main():
     import workloads
     import paper_2505_08777_amd as A
 
+    if args.workload == "coefgrad1024":
+        return bench_coef(args, workloads.grad1024())
     d = workloads.make(args.workload)
     if args.workload == "grad1024":
         return bench_adam(args, d)

@@ -247,6 +247,28 @@ int ash_phase_grad(ash_ctx* ctx, const float* phase_dev, const float* G_dev,
  *   column / row.
  * Adam (Kingma and Ba): m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
  * phase -= lr (m/(1-b1^k)) / (sqrt(v/(1-b2^k)) + eps) at update k. */
+/* Basis moments of the forward transform,
+ *   M[k][d] = sum_x Z_d(x) f(x) exp(-i theta_k(x)),   f = A exp(i phase),
+ * so that dE_k/dw[k][d] = -i M[k][d]: the derivative of every spot field
+ * along its own kernel coefficients (paper: Methods, "Computational
+ * Scaling": spots move in aberration space through w; the same sums give
+ * the gradients for fitting w).
+ *   phase_dev  device [ny][nx] float32 phase (A is the context's amplitude).
+ *   M_dev      device [N][D] complex64 output (row k: spot k).
+ * Evaluated like the forward (same phases and precision; the products with
+ * A Z_d are matrix-core sums of bf16 pieces, relative error ~2^-16 per
+ * term).  Errors: ASH_EINVAL, ASH_ENOTREADY, ASH_EHIP. */
+int ash_forward_moments(ash_ctx* ctx, const float* phase_dev, float* M_dev);
+
+/* Gradient of a real loss L(E) with respect to the kernel coefficients:
+ *   dL/dw[k][d] = Im(conj(G_k) M[k][d]),   G_k = dL/dRe E_k + i dL/dIm E_k.
+ *   phase_dev  device [ny][nx] float32 phase (A is the context's amplitude).
+ *   G_dev      device [N] complex64 field gradient.
+ *   grad_dev   device [N][D] float32 output.
+ * Errors: ASH_EINVAL, ASH_ENOTREADY, ASH_EHIP. */
+int ash_coef_grad(ash_ctx* ctx, const float* phase_dev, const float* G_dev,
+                  float* grad_dev);
+
 typedef struct ash_adam_params {
   float lr;         /* 0.05 */
   float beta1;      /* 0.9 */
@@ -374,7 +396,7 @@ int ash_batch_profile_read(ash_batch* batch, double* ms_out,
 /* Kernel timing, for measurement.  Kernels of the categories selected by
  * `mask` (bit 1 << category) are bracketed by HIP events on the context's
  * stream.  Categories:
- *   ASH_PROF_FORWARD   forward transform kernel
+ *   ASH_PROF_FORWARD   forward transform kernel (and the moment kernel)
  *   ASH_PROF_ADJOINT   adjoint transform kernel (with its epilogue)
  *   ASH_PROF_REDUCE    partial-sum reductions, weighted-GS update, loss
  *   ASH_PROF_FIELD     nearfield preparation A exp(i phase), Adam update

@@ -200,19 +200,21 @@ def adam_run(phi, amp, t, w, basis, geom, n_steps, lr=0.05, betas=(0.9, 0.999),
 #
 #   dL/dw[k, d] = Re(conj(G_k) dE_k/dw[k, d]) = Im(conj(G_k) M[k, d]).
 
-def forward_moments(f, w, basis, geom, workers=None):
-    """M[k, d] = sum_x Z_d(x) f(x) exp(-i theta_k(x)), complex128 [N, D]."""
+def forward_moments(f, w, basis, geom, spots=None, workers=None):
+    """M[k, d] = sum_x Z_d(x) f(x) exp(-i theta_k(x)), complex128 [N, D]
+    (rows of the `spots` subset only, if given)."""
     f = np.asarray(f, dtype=np.complex128).reshape(-1)
     w = np.asarray(w, dtype=np.float64)
     xh, yh = geom.coords(np.arange(geom.P))
     Z = basis.evaluate(xh, yh)                             # [D, P]
-    cols = [forward(Z[d] * f, w, basis, geom, workers=workers)
+    cols = [forward(Z[d] * f, w, basis, geom, spots=spots, workers=workers)
             for d in range(Z.shape[0])]
     return np.stack(cols, axis=1)
 
 
-def coef_grad(f, w, basis, geom, G, workers=None):
-    """dL/dw[k, d] = Im(conj(G_k) M[k, d]) for the field gradient G."""
-    M = forward_moments(f, w, basis, geom, workers)
+def coef_grad(f, w, basis, geom, G, spots=None, workers=None):
+    """dL/dw[k, d] = Im(conj(G_k) M[k, d]) for the field gradient G
+    (G indexed like the rows returned)."""
+    M = forward_moments(f, w, basis, geom, spots, workers)
     G = np.asarray(G, dtype=np.complex128).reshape(-1)
     return np.imag(np.conj(G)[:, None] * M)

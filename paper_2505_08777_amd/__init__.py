@@ -8,8 +8,9 @@ Gerchberg-Saxton loop, as hand-written HIP kernels behind a C ABI
 
 from ._lib import AshError, LIB_PATH, lib
 from .basis import principal_modes, zernike_monomials, zernike_table
-from .context import Batch, Context, Propagate, propagate
+from .context import Batch, Context, Propagate, PropagateSpots, propagate
 
-__all__ = ["AshError", "Batch", "Context", "LIB_PATH", "Propagate", "lib",
+__all__ = ["AshError", "Batch", "Context", "LIB_PATH", "Propagate",
+           "PropagateSpots", "lib",
            "principal_modes", "propagate", "zernike_monomials",
            "zernike_table"]

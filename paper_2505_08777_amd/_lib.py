@@ -91,6 +91,8 @@ def _load():
         "ash_profile_enable": (I, [P, I]),
         "ash_profile_read": (I, [P, P, P]),
         "ash_phase_grad": (I, [P, P, P, P]),
+        "ash_forward_moments": (I, [P, P, P]),
+        "ash_coef_grad": (I, [P, P, P, P]),
         "ash_adam_iterate": (I, [P, P, P, P, I, I, ctypes.POINTER(AdamParams),
                                  P, P]),
         "ash_batch_create": (I, [ctypes.POINTER(P), I, P, P]),

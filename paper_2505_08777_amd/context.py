@@ -45,6 +45,7 @@ class Context:
             raise AshError(rc, "ash_create", lib.ash_last_error(None).decode())
         self.nx = self.ny = self.N = self.D = None
         self.modes = None
+        self.target = None
 
     # -- lifetime ---------------------------------------------------------
     def close(self):
@@ -128,6 +129,7 @@ class Context:
               "ash_set_basis", self._h)
         self.nx, self.ny, self.D = int(nx), int(ny), mono_coef.shape[0]
         self.N = None
+        self.target = None
 
     def set_spots(self, w, target=None):
         w = np.ascontiguousarray(w, dtype=np.float64)
@@ -143,6 +145,7 @@ class Context:
                                 t.ctypes.data if t is not None else None),
               "ash_set_spots", self._h)
         self.N = w.shape[0]
+        self.target = t
 
     # -- transforms ---------------------------------------------------------
     def forward(self, phase=None, field=None, out=None):
@@ -219,6 +222,32 @@ class Context:
               "ash_phase_grad", self._h)
         return out
 
+    def forward_moments(self, phase, out=None):
+        """M[k, d] = sum_x Z_d(x) f(x) exp(-i theta_k(x)), f = A exp(i phase):
+        dE_k/dw[k, d] = -i M[k, d]."""
+        _dev(phase, torch.float32, (self.ny, self.nx), "phase", self.device)
+        if out is None:
+            out = torch.empty((self.N, self.D), dtype=torch.complex64,
+                              device="cuda:%d" % self.device)
+        _dev(out, torch.complex64, (self.N, self.D), "out", self.device)
+        self._stream()
+        check(lib.ash_forward_moments(self._h, _ptr(phase), _ptr(out)),
+              "ash_forward_moments", self._h)
+        return out
+
+    def coef_grad(self, phase, G, out=None):
+        """dL/dw[k, d] = Im(conj(G_k) M[k, d]) for the field gradient G."""
+        _dev(phase, torch.float32, (self.ny, self.nx), "phase", self.device)
+        _dev(G, torch.complex64, (self.N,), "G", self.device)
+        if out is None:
+            out = torch.empty((self.N, self.D), dtype=torch.float32,
+                              device="cuda:%d" % self.device)
+        _dev(out, torch.float32, (self.N, self.D), "out", self.device)
+        self._stream()
+        check(lib.ash_coef_grad(self._h, _ptr(phase), _ptr(G), _ptr(out)),
+              "ash_coef_grad", self._h)
+        return out
+
     def adam(self, phase, n_steps, m=None, v=None, step0=0, lr=0.05,
              betas=(0.9, 0.999), eps=1e-8, tv_weight=1e-3, tv_eps=1e-3,
              want_loss=True, want_E=False):
@@ -268,9 +297,42 @@ class Propagate(torch.autograd.Function):
         return ctx.context.phase_grad(phase.contiguous(), G), None
 
 
-def propagate(phase, context):
-    """Differentiable spot fields of the phase (see Propagate)."""
-    return Propagate.apply(phase, context)
+class PropagateSpots(torch.autograd.Function):
+    """E = forward transform of A exp(i phase) with kernel coefficients w,
+    differentiable in phase and in w.
+
+    The forward sets the context's spots to w (keeping its targets); the
+    backward returns the phase gradient of Propagate and
+    dL/dw[k, d] = Im(conj(G_k) M[k, d]) from the library's moment
+    transform (ash_coef_grad)."""
+
+    @staticmethod
+    def forward(ctx, phase, w, context):
+        context.set_spots(w.detach().to("cpu", torch.float64).numpy(),
+                          context.target)
+        ctx.context = context
+        ctx.save_for_backward(phase, w)
+        return context.forward(phase=phase.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_E):
+        phase, w = ctx.saved_tensors
+        G = grad_E.to(torch.complex64).contiguous()
+        gp = gw = None
+        if ctx.needs_input_grad[0]:
+            gp = ctx.context.phase_grad(phase.contiguous(), G)
+        if ctx.needs_input_grad[1]:
+            gw = ctx.context.coef_grad(phase.contiguous(), G).to(w.device,
+                                                                 w.dtype)
+        return gp, gw, None
+
+
+def propagate(phase, context, w=None):
+    """Differentiable spot fields of the phase (see Propagate); with w, also
+    differentiable in the kernel coefficients (see PropagateSpots)."""
+    if w is None:
+        return Propagate.apply(phase, context)
+    return PropagateSpots.apply(phase, w, context)
 
 
 class Batch:

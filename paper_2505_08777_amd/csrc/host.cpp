@@ -128,8 +128,9 @@ void free_spots(ash_ctx* c) {
   dfree(b.bound);
   dfree(b.partial);
   dfree(b.red);
+  dfree(b.mom_partial);
   b.cap_spots = b.cap_spotrec = b.cap_w = b.cap_off = b.cap_partial =
-      b.cap_red = 0;
+      b.cap_red = b.cap_mom = 0;
   c->has_spots = false;
   c->spots = Spots();
 }
@@ -146,6 +147,8 @@ void free_basis(ash_ctx* c) {
   dfree(b.rmax);
   dfree(b.d_pow);
   dfree(b.d_nlcoef);
+  dfree(b.d_coef);
+  dfree(b.momtab);
   dfree(b.grad);
   dfree(b.tvp);
   dfree(b.lossbuf);
@@ -459,7 +462,9 @@ int ash_set_basis(ash_ctx* c, int nx, int ny, double cx, double cy, double R,
       (rc = dalloc(c, &B.rmax, (size_t)g.n_tiles * nl1, "tile bounds")) ||
       (rc = dalloc(c, &B.d_pow, 2 * (size_t)n_mono, "monomials")) ||
       (rc = dalloc(c, &B.d_nlcoef, std::max(nlcoef.size(), (size_t)1),
-                   "monomial coefficients"))) {
+                   "monomial coefficients")) ||
+      (rc = dalloc(c, &B.d_coef, (size_t)D * n_mono, "basis coefficients")) ||
+      (rc = dalloc(c, &B.momtab, npix * 2 * (size_t)D, "moment table"))) {
     free_basis(c);
     return rc;
   }
@@ -473,6 +478,9 @@ int ash_set_basis(ash_ctx* c, int nx, int ny, double cx, double cy, double R,
   if (e == hipSuccess)
     e = hipMemcpyAsync(B.aff_dev, b.aff.data(), 3 * D * sizeof(double),
                        hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(B.d_coef, mono_coef, (size_t)D * n_mono * sizeof(double),
+                       hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && g.nl > 0)
     e = hipMemcpyAsync(B.nlmode_dev, b.nl_mode.data(), g.nl * sizeof(int),
                        hipMemcpyHostToDevice, c->stream);
@@ -485,7 +493,9 @@ int ash_set_basis(ash_ctx* c, int nx, int ny, double cx, double cy, double R,
   }
   rc = build_pixtab(c, amp_dev, true);
   if (rc == ASH_OK) {
-    e = hipStreamSynchronize(c->stream);
+    e = launch_build_momtab(g, B.d_pow, B.d_coef, n_mono, B.amp_t, B.momtab,
+                            c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) rc = hip_fail(c, e, "building basis table");
   }
   if (rc) {
@@ -614,13 +624,17 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
     c->spots.theta_bound = theta_bound;
   }
   {
-    const FwdPlan plan = plan_forward(g.n_tiles, N,
-                                      forward_blocks_per_cu(g.groups),
-                                      c->n_cu);
+    FwdPlan plan = plan_forward(g.n_tiles, N, forward_blocks_per_cu(g.groups),
+                                c->n_cu);
+    plan.mom_groups = plan_moment_ranges(
+        g.n_tiles, N, moments_blocks_per_cu(g.groups, g.D), c->n_cu);
     if ((rc = grow(c, &B.partial, &B.cap_partial,
                    (size_t)plan.groups * N * 2, "partial sums")) ||
         (rc = grow(c, &B.red, &B.cap_red, (size_t)plan.slices * N * 2,
-                   "partial sums")))
+                   "partial sums")) ||
+        (rc = grow(c, &B.mom_partial, &B.cap_mom,
+                   (size_t)plan.mom_groups * 2 * g.D * n_pad * 2,
+                   "moment sums")))
       goto fail_alloc;
     c->plan = plan;
   }
@@ -661,6 +675,52 @@ int ash_forward(ash_ctx* c, const float* phase_dev, const float* field_dev,
            return launch_finish_E(N, c->plan, B.red, E_dev, c->stream);
          }), "finish");
   return ASH_OK;
+}
+
+// Basis moments of the forward, and with G the coefficient gradient; both
+// take the phase with the context's amplitude.
+static int moments(ash_ctx* c, const float* phase_dev, const float* G_dev,
+                   float* M_dev, float* grad_dev) {
+  int rc = use_device(c);
+  if (rc) return rc;
+  const Geom& g = c->basis.g;
+  Buffers& B = c->buf;
+  const int N = c->spots.N;
+  HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
+           return launch_make_field(g, phase_dev, nullptr, B.amp_t, B.pixtab,
+                                    B.field_t, c->stream);
+         }), "make_field");
+  HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
+           return launch_moments(g, N, c->plan.mom_groups, B.pixtab,
+                                 B.field_t, B.spotrec, B.offtab, B.momtab,
+                                 B.mom_partial, c->stream);
+         }), "moments");
+  HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+           return launch_moments_finish(N, g.D, c->plan.mom_groups,
+                                        B.mom_partial, G_dev, M_dev, grad_dev,
+                                        c->stream);
+         }), "moments finish");
+  return ASH_OK;
+}
+
+int ash_forward_moments(ash_ctx* c, const float* phase_dev, float* M_dev) {
+  if (!c) return ASH_EINVAL;
+  c->err.clear();
+  if (!c->has_basis || !c->has_spots)
+    return fail(c, ASH_ENOTREADY, "basis and spots must be set");
+  if (!phase_dev || !M_dev) return fail(c, ASH_EINVAL, "phase and M required");
+  return moments(c, phase_dev, nullptr, M_dev, nullptr);
+}
+
+int ash_coef_grad(ash_ctx* c, const float* phase_dev, const float* G_dev,
+                  float* grad_dev) {
+  if (!c) return ASH_EINVAL;
+  c->err.clear();
+  if (!c->has_basis || !c->has_spots)
+    return fail(c, ASH_ENOTREADY, "basis and spots must be set");
+  if (!phase_dev || !G_dev || !grad_dev)
+    return fail(c, ASH_EINVAL, "phase, G and grad required");
+  return moments(c, phase_dev, G_dev, nullptr, grad_dev);
 }
 
 int ash_adjoint(ash_ctx* c, const float* y_dev, float* g_dev,

@@ -68,6 +68,8 @@ struct Buffers {
   float* rmax = nullptr;             // [n_tiles][nl] max |Rm_s| in a tile
   int32_t* d_pow = nullptr;          // [n_mono][2]
   double* d_nlcoef = nullptr;        // [nl][n_mono]
+  double* d_coef = nullptr;          // [D][n_mono] whole basis
+  unsigned short* momtab = nullptr;  // [block][kb][h][2D][8] bf16 A Z_d
   size_t cap_pixtab = 0;             // in unsigned shorts
   // spots (NP: N padded to whole 32-spot blocks, padding zero)
   unsigned short* spotrec = nullptr;  // [N/32][group][half][32][8] bf16
@@ -85,14 +87,16 @@ struct Buffers {
   float* tvp = nullptr;               // [n_tiles * kBlkPerTile] TV sums
   float* lossbuf = nullptr;           // [1] spot term of the loss
   size_t cap_grad = 0, cap_tvp = 0;
+  float* mom_partial = nullptr;  // [ranges][2D][NP] moment range sums
   size_t cap_spots = 0, cap_spotrec = 0, cap_w = 0, cap_off = 0,
-         cap_partial = 0, cap_red = 0;
+         cap_partial = 0, cap_red = 0, cap_mom = 0;
 };
 
 struct FwdPlan {
   int groups = 0;  // pixel-block ranges (forward partial rows)
   int slices = 0;  // second-level reduction rows
   int rows_per_slice = 0;
+  int mom_groups = 0;  // pixel-block ranges of the moment transform
 };
 
 // Resident forward blocks per CU for a compiled record length.
@@ -126,6 +130,21 @@ hipError_t launch_forward(const Geom& b, int N, const FwdPlan& p,
                           hipStream_t s);
 hipError_t launch_reduce(int N, const FwdPlan& p, const float* partial,
                          float* red, hipStream_t s);
+hipError_t launch_build_momtab(const Geom& b, const int32_t* d_pow,
+                               const double* d_coef, int n_mono,
+                               const float* amp_t, unsigned short* momtab,
+                               hipStream_t s);
+int moments_blocks_per_cu(int groups, int D);
+int plan_moment_ranges(int n_tiles, int N, int blocks_per_cu, int n_cu);
+hipError_t launch_moments(const Geom& b, int N, int groups,
+                          const unsigned short* pixtab, const unsigned* nf_t,
+                          const unsigned short* spotrec,
+                          const unsigned* offtab,
+                          const unsigned short* momtab, float* partial,
+                          hipStream_t s);
+hipError_t launch_moments_finish(int N, int D, int ranges,
+                                 const float* partial, const float* G,
+                                 float* M, float* grad, hipStream_t s);
 hipError_t launch_finish_E(int N, const FwdPlan& p, const float* red,
                            float* E, hipStream_t s);
 hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,

@@ -806,6 +806,305 @@ hipError_t launch_forward(const Geom& b, int N, const FwdPlan& p,
 }
 
 // ---------------------------------------------------------------------------
+// Basis moments of the forward,
+//   M[k][d] = sum_x Z_d(x) f(x) exp(-i theta_k(x)),  dE_k/dw[k][d] = -i M[k][d].
+// The phases come from the forward's records with the matrix-core operands
+// swapped (rows: 32 pixels, column: the lane's spot), so that every lane holds
+// one spot and 16 pixels.  Their cosines and sines, split into two bf16
+// pieces, are the B operand of a second product whose A operand is the
+// moment table (rows: the hi and lo bf16 pieces of A(x) Z_d(x); K: pixels);
+// the matrix cores then sum over the pixels of the block.
+// ---------------------------------------------------------------------------
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two values as bf16 pieces, packed two per word (x0 in the low half):
+// hi rounds to nearest even, the remainder x - hi is exact, and lo is its
+// rounding, so x = hi + lo + O(2^-17 |x|).
+__device__ __forceinline__ void split2(float x0, float x1, unsigned& hi,
+                                       unsigned& lo) {
+  hi = __builtin_bit_cast(unsigned,
+                          __builtin_convertvector(float2v{x0, x1}, bf16x2));
+  const float r0 = x0 - __uint_as_float(hi << 16);
+  const float r1 = x1 - __uint_as_float(hi & 0xFFFF0000u);
+  lo = __builtin_bit_cast(unsigned,
+                          __builtin_convertvector(float2v{r0, r1}, bf16x2));
+}
+
+// Moment-table slot of pixel p (0..31) of a 32-pixel block: K block kb
+// (16 pixels), lane half h and element e, such that element e of half h in
+// K block kb is the pixel of phase value 8 kb + e of a lane of half h.
+__device__ __forceinline__ void mom_slot(int p, int* kb, int* h, int* e) {
+  *kb = p >> 4;
+  *h = (p >> 2) & 1;
+  *e = ((p >> 3) & 1) * 4 + (p & 3);
+}
+
+// One thread per pixel: A(x) Z_d(x) for every mode in FP64, stored as two
+// bf16 pieces in rows d (hi) and D + d (lo) of [block][kb][h][2D][8].
+__global__ void k_build_momtab(Geom b, long total, int n_mono,
+                               const int32_t* __restrict__ pw,
+                               const double* __restrict__ coef,
+                               const float* __restrict__ amp_t,
+                               unsigned short* __restrict__ momtab) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const int tile = (int)(gid / kTile), pix = (int)(gid % kTile);
+  const int D = b.D, D2 = 2 * b.D;
+  int i, j;
+  const bool valid = pixel_ij(b, tile, pix, &i, &j);
+  const double invR = 1.0 / b.R;
+  const double x = (i - b.cx) * invR, y = (j - b.cy) * invR;
+  const double a = valid ? (double)amp_t[gid] : 0.0;
+  const long blk = gid / 32;
+  int kb, h, e;
+  mom_slot((int)(gid % 32), &kb, &h, &e);
+  unsigned short* dst = momtab + ((blk * 2 + kb) * 2 + h) * D2 * 8 + e;
+  for (int d = 0; d < D; ++d) {
+    double z = 0.0;
+    for (int m = 0; m < n_mono; ++m) {
+      const double c = coef[d * n_mono + m];
+      if (c != 0.0) z += c * ipow(x, pw[2 * m]) * ipow(y, pw[2 * m + 1]);
+    }
+    unsigned pc[3];
+    split3(a * z, pc);
+    dst[d * 8] = (unsigned short)pc[0];
+    dst[(D + d) * 8] = (unsigned short)pc[1];
+  }
+}
+
+hipError_t launch_build_momtab(const Geom& b, const int32_t* d_pow,
+                               const double* d_coef, int n_mono,
+                               const float* amp_t, unsigned short* momtab,
+                               hipStream_t s) {
+  const long total = (long)b.n_tiles * kTile;
+  hipLaunchKernelGGL(k_build_momtab, dim3((unsigned)((total + 255) / 256)),
+                     dim3(256), 0, s, b, total, n_mono, d_pow, d_coef, amp_t,
+                     momtab);
+  return hipGetLastError();
+}
+
+// Moments of one wave: the 32 spots of spot block mb over pixel blocks
+// [b0, b1).  RT tiles of 32 moment rows; out: [2D][NP] (re, -im) sums.
+template <int G, int RT>
+__device__ __forceinline__ void moments_range(
+    int N, int D2, int mb, long b0, long b1, bool reduce,
+    const GLOBAL u32x4* __restrict__ pixtab, const GLOBAL u32x4* __restrict__ nf,
+    const GLOBAL u32x4* __restrict__ spotrec,
+    const GLOBAL u32x4* __restrict__ offtab,
+    const GLOBAL u32x4* __restrict__ momtab, float2* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int h = lane >> 5, q = lane & 31;
+  const int NP = (N + 31) / 32 * 32;
+  const unsigned lane_pix = h * kTile + q, lane_spot = h * 32 + q;
+  u32x4 S[G];
+  const GLOBAL u32x4* __restrict__ sb = spotrec + (long)mb * G * 64;
+#pragma unroll
+  for (int g = 0; g < G - 1; ++g) S[g] = sb[lane_spot + g * 64];
+  const unsigned m2 = h ? 0u : (kBf16MinusOne | (kBf16MinusOne << 16));
+  const unsigned m3 = h ? 0u : kBf16MinusOne;
+  floatx16 are[RT], aim[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) are[rt][i] = aim[rt][i] = 0.0f;
+  const unsigned lane_ot = h * NP + q;
+  const GLOBAL u32x4* __restrict__ ot_k = offtab + (long)mb * 32;
+  const unsigned one2 = kBf16One | (kBf16One << 16);
+  for (long b = b0; b < b1;) {
+    const long t = b / kBlkPerTile;
+    const int r0 = (int)(b - t * kBlkPerTile);
+    const int r1 = (int)min((long)kBlkPerTile, r0 + (b1 - b));
+    S[G - 1] = (ot_k + t * 2 * NP)[lane_ot];
+    S[G - 1][2] |= m2;
+    S[G - 1][3] |= m3;
+    const GLOBAL u32x4* __restrict__ px = pixtab + t * G * 2 * kTile;
+    const GLOBAL u32x4* __restrict__ pn = nf + t * kBlkPerTile * 64;
+    for (int r = r0; r < r1; ++r) {
+      u32x4 X[G];
+#pragma unroll
+      for (int g = 0; g < G - 1; ++g)
+        X[g] = (px + g * 2 * kTile + r * 32)[lane_pix];
+      X[G - 1] = (pn + r * 64)[lane_spot];
+      if (h) X[G - 1][0] = one2;
+      const GLOBAL u32x4* __restrict__ mt =
+          momtab + (t * kBlkPerTile + r) * 4 * D2;
+      u32x4 A[RT][2];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+          const int row = 32 * rt + q;
+          A[rt][kb] = row < D2 ? mt[(kb * 2 + h) * D2 + row]
+                               : u32x4{0u, 0u, 0u, 0u};
+        }
+      const floatx16 th = phase_block<G>(X, S);
+      u32x4 ch[2], cl[2], sh[2], sl[2];
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          float t0 = th[8 * kb + 2 * w], t1 = th[8 * kb + 2 * w + 1];
+          if (reduce) {
+            t0 = __builtin_amdgcn_fractf(t0);
+            t1 = __builtin_amdgcn_fractf(t1);
+          }
+          unsigned a0, a1, b0w, b1w;
+          split2(__builtin_amdgcn_cosf(t0), __builtin_amdgcn_cosf(t1), a0, a1);
+          split2(__builtin_amdgcn_sinf(t0), __builtin_amdgcn_sinf(t1), b0w,
+                 b1w);
+          ch[kb][w] = a0;
+          cl[kb][w] = a1;
+          sh[kb][w] = b0w;
+          sl[kb][w] = b1w;
+        }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+          are[rt] = mfma_bf16(A[rt][kb], ch[kb], are[rt]);
+          are[rt] = mfma_bf16(A[rt][kb], cl[kb], are[rt]);
+          aim[rt] = mfma_bf16(A[rt][kb], sh[kb], aim[rt]);
+          aim[rt] = mfma_bf16(A[rt][kb], sl[kb], aim[rt]);
+        }
+    }
+    b += r1 - r0;
+  }
+  const long k = (long)mb * 32 + q;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = 32 * rt + mfma_row(i, h);
+      if (row < D2) out[(long)row * NP + k] = make_float2(are[rt][i], aim[rt][i]);
+    }
+}
+
+// Waves and ranges are laid out over the XCDs as in k_forward.
+template <int G, int RT>
+__global__ __launch_bounds__(kBlock) void k_moments(
+    int N, int D2, long n_blk, int groups, int reduce,
+    const u32x4* __restrict__ pixtab, const unsigned* __restrict__ nf_t,
+    const u32x4* __restrict__ spotrec, const unsigned* __restrict__ offtab,
+    const u32x4* __restrict__ momtab, float2* __restrict__ partial) {
+  const int n_mb = (N + 31) / 32;
+  const int NP = n_mb * 32;
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const long v = (long)slot * (kBlock / kWave) + wave;
+  if (v >= (long)(groups / kXcds) * n_mb) return;  // wave-uniform exit
+  const int gi = (int)(v / n_mb) * kXcds + xcd;
+  const int mb = (int)(v % n_mb);
+  moments_range<G, RT>(N, D2, mb, n_blk * gi / groups,
+                       n_blk * (gi + 1) / groups, reduce != 0,
+                       as_global(pixtab),
+                       as_global(reinterpret_cast<const u32x4*>(nf_t)),
+                       as_global(spotrec),
+                       as_global(reinterpret_cast<const u32x4*>(offtab)),
+                       as_global(momtab), partial + (long)gi * D2 * NP);
+}
+
+template <int G, int RT>
+static hipError_t mom_g(const Geom& b, int N, int groups, hipStream_t s,
+                        const unsigned short* pixtab, const unsigned* nf_t,
+                        const unsigned short* spotrec, const unsigned* offtab,
+                        const unsigned short* momtab, float* partial) {
+  const int n_mb = (N + 31) / 32;
+  const long n_blk = (long)b.n_tiles * kBlkPerTile;
+  const long per_xcd = (long)(groups / kXcds) * n_mb;
+  const long blocks_per_xcd =
+      (per_xcd + kBlock / kWave - 1) / (kBlock / kWave);
+  hipLaunchKernelGGL((k_moments<G, RT>), dim3((unsigned)(blocks_per_xcd * kXcds)),
+                     dim3(kBlock), 0, s, N, 2 * b.D, n_blk, groups, b.reduce,
+                     reinterpret_cast<const u32x4*>(pixtab), nf_t,
+                     reinterpret_cast<const u32x4*>(spotrec), offtab,
+                     reinterpret_cast<const u32x4*>(momtab),
+                     reinterpret_cast<float2*>(partial));
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const Geom& b, int N, int groups,
+                          const unsigned short* pixtab, const unsigned* nf_t,
+                          const unsigned short* spotrec,
+                          const unsigned* offtab,
+                          const unsigned short* momtab, float* partial,
+                          hipStream_t s) {
+  const bool two = 2 * b.D > 32;
+  switch (b.groups) {
+#define X(n)                                                               \
+  case n:                                                                  \
+    return two ? mom_g<n, 2>(b, N, groups, s, pixtab, nf_t, spotrec,       \
+                             offtab, momtab, partial)                      \
+               : mom_g<n, 1>(b, N, groups, s, pixtab, nf_t, spotrec,       \
+                             offtab, momtab, partial);
+    ASH_G_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <int G, int RT>
+static int mom_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_moments<G, RT>,
+                                                   kBlock, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n > 0 ? n : 1;
+}
+
+int moments_blocks_per_cu(int groups, int D) {
+  const bool two = 2 * D > 32;
+  switch (groups) {
+#define X(n) \
+  case n:    \
+    return two ? mom_blocks_per_cu<n, 2>() : mom_blocks_per_cu<n, 1>();
+    ASH_G_CASES(X)
+#undef X
+    default:
+      return 1;
+  }
+}
+
+// Sum of the range partials of moment rows d (hi pieces) and D + d (lo
+// pieces) in a fixed order; M = (re, -im) and, with G, the coefficient
+// gradient Im(conj(G_k) M[k][d]).  One thread per (d, k), k fastest.
+__global__ void k_moments_finish(int N, int D, int ranges,
+                                 const float2* __restrict__ partial,
+                                 const float2* __restrict__ Gk,
+                                 float2* __restrict__ M,
+                                 float* __restrict__ grad) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)N * D) return;
+  const int d = (int)(t / N), k = (int)(t % N);
+  const int NP = (N + 31) / 32 * 32;
+  const long stride = (long)2 * D * NP;
+  const float2 a = kahan_sum_strided(partial + (long)d * NP + k, stride, ranges);
+  const float2 c =
+      kahan_sum_strided(partial + (long)(D + d) * NP + k, stride, ranges);
+  const float mr = a.x + c.x, mi = -(a.y + c.y);
+  if (M) M[(long)k * D + d] = make_float2(mr, mi);
+  if (grad) {
+    const float2 g = Gk[k];
+    grad[(long)k * D + d] = g.x * mi - g.y * mr;
+  }
+}
+
+hipError_t launch_moments_finish(int N, int D, int ranges,
+                                 const float* partial, const float* G,
+                                 float* M, float* grad, hipStream_t s) {
+  const long total = (long)N * D;
+  hipLaunchKernelGGL(k_moments_finish, dim3((unsigned)((total + 255) / 256)),
+                     dim3(256), 0, s, N, D, ranges,
+                     reinterpret_cast<const float2*>(partial),
+                     reinterpret_cast<const float2*>(G),
+                     reinterpret_cast<float2*>(M), grad);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Reductions of the forward partials (fixed order, compensated).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_reduce(int N, int groups, int rows,
@@ -1459,6 +1758,19 @@ FwdPlan plan_forward(int n_tiles, int N, int blocks_per_cu, int n_cu) {
   p.rows_per_slice = 32;
   p.slices = (p.groups + p.rows_per_slice - 1) / p.rows_per_slice;
   return p;
+}
+
+// Ranges of the moment transform: about two rounds of resident waves (its
+// partial sums carry 2D rows per spot, and the finish sums all ranges).
+int plan_moment_ranges(int n_tiles, int N, int blocks_per_cu, int n_cu) {
+  const int n_mb = (N + 31) / 32;
+  const long n_blk = (long)n_tiles * kBlkPerTile;
+  const long waves = (long)blocks_per_cu * (kBlock / kWave) * n_cu;
+  long want = 2 * waves / n_mb;
+  if (want > n_blk / 32) want = n_blk / 32;
+  want = want / kXcds * kXcds;
+  if (want < kXcds) want = kXcds;
+  return (int)want;
 }
 
 }  // namespace ash
