@@ -382,6 +382,93 @@ def test_wgs_stats_definitions():
     assert st[3] == pytest.approx(30.0)
 
 
+def _bins_case(seed=17, N=9):
+    nx, ny = 32, 24
+    geom = Geometry(nx, ny)
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(nx * ny, size=N, replace=False)
+    v, u = np.divmod(flat, nx)
+    u = u - nx // 2
+    v = v - ny // 2
+    amp = np.exp(-(((np.arange(nx) - nx / 2) / 10.0) ** 2)[None, :]
+                 - (((np.arange(ny) - ny / 2) / 8.0) ** 2)[:, None])
+    return geom, rng, u, v, _tilt_w(u, v, geom), amp
+
+
+def test_feedback_with_model_amplitudes_is_the_plain_step():
+    geom, rng, u, v, w, amp = _bins_case()
+    t = rng.uniform(0.5, 1.0, size=len(u))
+    phi = rng.uniform(-np.pi, np.pi, size=amp.shape)
+    W = rng.uniform(0.5, 2.0, size=len(u))
+    b = ZernikeBasis([1, 2])
+    E = oracle.forward(amp * np.exp(1j * phi), w, b, geom)
+    ref = oracle.wgs_step(phi, W, t, amp, w, b, geom)
+    got = oracle.wgs_step(phi, W, t, amp, w, b, geom, measured=np.abs(E))
+    for a, c in zip(ref, got):
+        np.testing.assert_array_equal(a, c)
+
+
+def test_feedback_weight_update_closed_forms():
+    E = np.array([1.0 + 0j, 1j])
+    # two spots, equal targets, measured 2 : 1 -> W proportional to 1/r,
+    # r = (a/|a|)/(t/|t|) = (2 sqrt2/sqrt5, sqrt2/sqrt5): W = (2/3, 4/3)
+    _, W = oracle.wgs_farfield(E, [1.0, 1.0], [1.0, 1.0], measured=[2.0, 1.0])
+    np.testing.assert_allclose(W, [2.0 / 3.0, 4.0 / 3.0], rtol=1e-15)
+    # measured proportional to the targets: the weights only renormalise
+    t = np.array([0.5, 1.0, 0.8])
+    E3 = np.array([1.0, 2.0, 3.0j])
+    _, W3 = oracle.wgs_farfield(E3, [1.0, 2.0, 3.0], t, measured=3.0 * t)
+    np.testing.assert_allclose(W3, np.array([1.0, 2.0, 3.0]) / 2.0, rtol=1e-15)
+    # dark measurements keep their weight (before renormalisation)
+    _, W4 = oracle.wgs_farfield(E3, [1.0, 2.0, 3.0], t, measured=[0.0, 2.0, 1.6])
+    r1 = (2.0 / math.sqrt(2.0 ** 2 + 1.6 ** 2)) / (1.0 / math.sqrt(0.5 ** 2 + 1.0 + 0.8 ** 2))
+    assert W4[0] / W4[1] == pytest.approx(1.0 / (2.0 / r1), rel=1e-14)
+
+
+def test_phase_fixed_projection_against_fft():
+    """With the farfield phases fixed, a step's new hologram is arg of the
+    inverse DFT of W t exp(i psi) placed at the spot bins."""
+    geom, rng, u, v, w, amp = _bins_case(seed=18)
+    N = len(u)
+    ny, nx = amp.shape
+    t = rng.uniform(0.5, 1.0, size=N)
+    phi = rng.uniform(-np.pi, np.pi, size=amp.shape)
+    psi = rng.uniform(-np.pi, np.pi, size=N)
+    W = rng.uniform(0.5, 2.0, size=N)
+    b = ZernikeBasis([1, 2])
+    phi1, W1, E, _ = oracle.wgs_step(phi, W, t, amp, w, b, geom, fixed_phase=psi)
+    y, W2 = oracle.wgs_farfield(E, W, t, fixed_phase=psi)
+    np.testing.assert_allclose(np.abs(y), W1 * t, rtol=1e-14)
+    np.testing.assert_allclose(np.angle(y * np.exp(-1j * psi)), 0.0, atol=1e-14)
+    sgn = (-1.0) ** (u + v)
+    grid = np.zeros((ny, nx), complex)
+    grid[v % ny, u % nx] = sgn * W1 * t * np.exp(1j * psi)
+    g = nx * ny * np.fft.ifft2(grid)
+    d = np.angle(np.exp(1j * (phi1 - np.angle(g))))
+    assert np.max(np.abs(d)) < 1e-9
+
+
+def test_phase_fixed_run_uses_the_stored_iteration():
+    geom, rng, u, v, w, amp = _bins_case(seed=19)
+    t = rng.uniform(0.5, 1.0, size=len(u))
+    phi0 = rng.uniform(-np.pi, np.pi, size=amp.shape)
+    b = ZernikeBasis([1, 2])
+    phi_r, W_r, E_r, st_r, _ = oracle.wgs_run(phi0, t, amp, w, b, geom, 6,
+                                              fix_phase_after=3)
+    phi, W = phi0, np.ones(len(u))
+    for it in range(6):
+        fixed = psi if it >= 3 else None
+        phi, W, E, _ = oracle.wgs_step(phi, W, t, amp, w, b, geom,
+                                       fixed_phase=fixed)
+        if it == 2:
+            psi = np.angle(E)
+    np.testing.assert_array_equal(phi, phi_r)
+    np.testing.assert_array_equal(W, W_r)
+    # the fixed run differs from the free one after iteration 3
+    phi_f, _, _, _, _ = oracle.wgs_run(phi0, t, amp, w, b, geom, 6)
+    assert np.max(np.abs(np.angle(np.exp(1j * (phi_f - phi_r))))) > 1e-6
+
+
 # --------------------------------------------------------------------------
 # Loss and gradient
 # --------------------------------------------------------------------------
