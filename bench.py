@@ -93,13 +93,15 @@ def parse():
     ap.add_argument("--workload", default="field1024",
                     choices=["plain256", "field1024", "volume1920",
                              "grad1024", "batch64", "principal1024",
-                             "coefgrad1024"],
+                             "coefgrad1024", "feedback1024"],
                     help="grad1024 times the differentiable form (Adam steps "
                          "of the spot-amplitude loss with TV); principal1024 "
                          "the WGS loop on 8 principal isoplanatic modes of a "
                          "27-mode calibration; coefgrad1024 the gradient in "
                          "the kernel coefficients (moment transform) on the "
-                         "grad1024 inputs; batch64 the "
+                         "grad1024 inputs; feedback1024 a closed WGS loop on "
+                         "simulated spot measurements with phase fixing; "
+                         "batch64 the "
                          "batched form (64 holograms' WGS loops together)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batch64: skip the autotuner (default range length)")
@@ -306,6 +308,97 @@ def bench_coef(args, d):
     print(json.dumps(out), flush=True)
 
 
+def bench_feedback(args, d):
+    """Closed-loop weighted GS with experimental feedback on a simulated
+    system (1024 x 1024, 400 spots): each loop iteration measures the spot
+    amplitudes of the current hologram on the 'true' system (a forward
+    transform with perturbed aberrations, times per-spot gains) and runs one
+    ash_wgs_feedback iteration on the model; the farfield phases are fixed
+    after the first iterations.  A step is the workload's loop iterations."""
+    import numpy as np
+    import torch
+    import paper_2505_08777_amd as A
+
+    n_iter = args.iters or d["n_iter"]
+    fix = d["fix_phase_after"]
+    nx, ny = d["nx"], d["ny"]
+    N, D = d["w"].shape
+    P = nx * ny
+    dev = torch.device("cuda:0")
+    amp = torch.tensor(d["amp"], dtype=torch.float32, device=dev)
+    model = A.Context(0)
+    model.set_basis(nx, ny, modes=d["modes"], amp=amp)
+    model.set_spots(d["w"], d["t"])
+    system = A.Context(0)
+    system.set_basis(nx, ny, modes=d["modes"], amp=amp)
+    system.set_spots(d["w_true"], d["t"])
+    gain = torch.tensor(d["gain"], dtype=torch.float32, device=dev)
+    t = torch.tensor(d["t"], dtype=torch.float32, device=dev)
+
+    def uniformity(E):
+        I = (gain * torch.abs(E)) ** 2 / t ** 2
+        return float(1.0 - (I.max() - I.min()) / (I.max() + I.min()))
+
+    def loop(phase, W):
+        for it in range(n_iter):
+            meas = gain * torch.abs(system.forward(phase=phase))
+            mode = 0 if it < fix - 1 else (1 if it == fix - 1 else -1)
+            model.wgs_feedback(phase, meas, weights=W, fix_phase_after=mode,
+                               want_E=False, want_stats=False)
+
+    phase = torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
+    W = torch.ones(N, dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        loop(phase.clone(), W.clone())
+    torch.cuda.synchronize()
+    model.profile(True, categories=("forward", "adjoint"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ph = torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
+        Ws = torch.ones(N, dtype=torch.float32, device=dev)
+        loop(ph, Ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = model.profile_read()
+    model.profile(False)
+    T = t1 - t0
+    value = 3.0 * N * P * n_iter * args.steps / T
+    u_fb = uniformity(system.forward(phase=ph))
+    # the same number of model-only WGS iterations, for comparison
+    ph2 = torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
+    model.wgs(ph2, n_iter, want_E=False, want_stats=False)
+    u_model = uniformity(system.forward(phase=ph2))
+    info = model.info()
+    dom = max(("forward", "adjoint"), key=lambda k: prof[k][0])
+    ms_avg = prof[dom][0] / max(prof[dom][1], 1)
+    kname = "k_%s<%d, %s>" % (dom, info["groups"],
+                              "true" if info["range_reduce"] else "false")
+    out = {
+        "metric": "spot·pixel kernel evals/s of the closed loop (measurement "
+                  "forward + WGS forward + adjoint)",
+        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "feedback1024", "slm": "%dx%d" % (nx, ny),
+                   "spots": N, "modes": D, "loop_iters_per_step": n_iter,
+                   "fix_phase_after": fix},
+        "loop_iters_per_s": n_iter * args.steps / T,
+        "system_uniformity": {"feedback_loop": u_fb,
+                              "model_only_wgs": u_model},
+        "roofline": alu_roofline(kname, N * P, ms_avg, prof[dom][1], D,
+                                 info["groups"]),
+        "kernels": {k: {"total_ms": v[0], "launches": v[1],
+                        "avg_ms": v[0] / v[1] if v[1] else None}
+                    for k, v in prof.items()},
+        "layout": info,
+    }
+    model.close()
+    system.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_adam(args, d):
     """Adam descent of the 1024 x 1024, 1000-spot loss: a step is the
     workload's Adam updates (forward, loss, adjoint with the phase gradient
@@ -473,6 +566,8 @@ def main():
 
     if args.workload == "coefgrad1024":
         return bench_coef(args, workloads.grad1024())
+    if args.workload == "feedback1024":
+        return bench_feedback(args, workloads.feedback1024())
     d = workloads.make(args.workload)
     if args.workload == "grad1024":
         return bench_adam(args, d)

@@ -79,15 +79,23 @@ extern "C" {
 
 typedef struct ash_ctx ash_ctx;
 
-/* Weighted-GS parameters (the paper cites weighted GS without a formula;
- * the reading implemented is, per iteration:
+/* Weighted-GS parameters (the paper cites weighted GS, with its
+ * phase-fixed variant, without a formula; the reading implemented is, per
+ * iteration:
  *   a_k = |E_k|,  r_k = (a_k/||a||) / (t_k/||t||),
  *   W_k <- W_k r_k^(-power) where a_k > 0, then W <- W / mean(W),
- *   y_k = W_k t_k E_k / a_k  (W_k t_k where a_k = 0),
- *   phi <- arg(F_c^{-1} y)   with arg(0) = 0.)                             */
+ *   y_k = W_k t_k exp(i psi_k),  psi_k = arg E_k (0 where E_k = 0),
+ *   phi <- arg(F_c^{-1} y)   with arg(0) = 0.
+ * Phase fixing freezes psi_k at the phases of one iteration; experimental
+ * feedback (ash_wgs_feedback) takes a_k from measurements.)                */
 typedef struct ash_wgs_params {
   float power; /* weight exponent p; 1 = classic WGS, 0 = plain GS         */
-  int32_t reserved;
+  /* 0: psi = arg E every iteration.  n > 0: iterations 0 .. n-1 of the
+   * call are free and the psi of iteration n-1 are stored in the context;
+   * iterations n .. use the stored psi.  n < 0: every iteration uses the
+   * psi stored by an earlier call (ASH_ENOTREADY if none since the last
+   * ash_set_spots).                                                        */
+  int32_t fix_phase_after;
 } ash_wgs_params;
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -223,6 +231,22 @@ int ash_adjoint(ash_ctx* ctx, const float* y_dev, float* g_dev,
 int ash_wgs_iterate(ash_ctx* ctx, float* phase_dev, float* weights_dev,
                     int n_iter, const ash_wgs_params* params, float* E_dev,
                     float* stats_dev);
+
+/* One weighted-GS iteration driven by measured spot amplitudes
+ * (experimental feedback: the paper's software closes the loop on camera
+ * measurements, "A Full-Field 2D Tweezer Array" and Discussion):
+ *   measured_dev  device [N] float32 amplitudes a_k of the spots produced by
+ *                 phase_dev on the system (values <= 0 or NaN count as dark:
+ *                 their weights are kept).
+ * The weights are updated from these a_k instead of |E_k|; the projection
+ * uses psi_k = arg E_k of the model, or the stored phases
+ * (params->fix_phase_after as for ash_wgs_iterate with n_iter = 1).
+ * phase_dev and weights_dev are updated in place; E_dev [N] complex64 and
+ * stats_dev [4] (of the model fields E) are optional.  Errors: ASH_EINVAL,
+ * ASH_ENOTREADY, ASH_EHIP. */
+int ash_wgs_feedback(ash_ctx* ctx, float* phase_dev, float* weights_dev,
+                     const float* measured_dev, const ash_wgs_params* params,
+                     float* E_dev, float* stats_dev);
 
 /* Phase gradient of a real loss of the spot fields (the backward of
  * ash_forward with respect to the phase):

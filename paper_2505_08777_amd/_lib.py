@@ -32,7 +32,7 @@ class AshError(RuntimeError):
 
 
 class WgsParams(ctypes.Structure):
-    _fields_ = [("power", ctypes.c_float), ("reserved", ctypes.c_int32)]
+    _fields_ = [("power", ctypes.c_float), ("fix_phase_after", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -86,6 +86,7 @@ def _load():
         "ash_forward": (I, [P, P, P, P]),
         "ash_adjoint": (I, [P, P, P, P]),
         "ash_wgs_iterate": (I, [P, P, P, I, ctypes.POINTER(WgsParams), P, P]),
+        "ash_wgs_feedback": (I, [P, P, P, P, ctypes.POINTER(WgsParams), P, P]),
         "ash_set_precision": (I, [P, I]),
         "ash_get_info": (I, [P, ctypes.POINTER(Info)]),
         "ash_profile_enable": (I, [P, I]),

@@ -184,8 +184,10 @@ class Context:
         return g if field else ph
 
     def wgs(self, phase, n_iter, weights=None, power=1.0, want_E=True,
-            want_stats=True):
+            want_stats=True, fix_phase_after=0):
         """n_iter weighted-GS iterations; phase is updated in place.
+        fix_phase_after: 0 free farfield phases; n > 0 fixed after the
+        first n iterations; < 0 fixed at the phases stored earlier.
 
         Returns (phase, weights, E_last, stats[n_iter, 4])."""
         _dev(phase, torch.float32, (self.ny, self.nx), "phase", self.device)
@@ -197,13 +199,37 @@ class Context:
             if want_E else None
         st = torch.empty((max(n_iter, 1), 4), dtype=torch.float32,
                          device=dev) if want_stats else None
-        params = WgsParams(float(power), 0)
+        params = WgsParams(float(power), int(fix_phase_after))
         self._stream()
         check(lib.ash_wgs_iterate(self._h, _ptr(phase), _ptr(weights),
                                   int(n_iter), ctypes.byref(params), _ptr(E),
                                   _ptr(st)), "ash_wgs_iterate", self._h)
         if st is not None:
             st = st[:n_iter]
+        return phase, weights, E, st
+
+    def wgs_feedback(self, phase, measured, weights=None, power=1.0,
+                     fix_phase_after=0, want_E=True, want_stats=True):
+        """One weighted-GS iteration whose weights follow the measured spot
+        amplitudes; phase and weights are updated in place.
+
+        Returns (phase, weights, E, stats[4]) (E and stats of the model)."""
+        _dev(phase, torch.float32, (self.ny, self.nx), "phase", self.device)
+        _dev(measured, torch.float32, (self.N,), "measured", self.device)
+        dev = "cuda:%d" % self.device
+        if weights is None:
+            weights = torch.ones(self.N, dtype=torch.float32, device=dev)
+        _dev(weights, torch.float32, (self.N,), "weights", self.device)
+        E = torch.empty(self.N, dtype=torch.complex64, device=dev) \
+            if want_E else None
+        st = torch.empty(4, dtype=torch.float32, device=dev) \
+            if want_stats else None
+        params = WgsParams(float(power), int(fix_phase_after))
+        self._stream()
+        check(lib.ash_wgs_feedback(self._h, _ptr(phase), _ptr(weights),
+                                   _ptr(measured), ctypes.byref(params),
+                                   _ptr(E), _ptr(st)),
+              "ash_wgs_feedback", self._h)
         return phase, weights, E, st
 
     # -- differentiable form ----------------------------------------------

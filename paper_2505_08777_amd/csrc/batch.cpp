@@ -494,6 +494,8 @@ int ash_batch_wgs(ash_batch* b, float* const* phase_dev,
       return bfail(b, ASH_EINVAL, "null phase or weights");
   const float power = params ? params->power : 1.0f;
   if (!isfinite(power)) return bfail(b, ASH_EINVAL, "power must be finite");
+  if (params && params->fix_phase_after != 0)
+    return bfail(b, ASH_EUNSUPPORTED, "phase fixing runs per hologram");
   if (n_iter == 0) return ASH_OK;
   int rc;
   if ((rc = buse(b)) || (rc = check_members(b)) ||

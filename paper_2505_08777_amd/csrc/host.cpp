@@ -129,9 +129,11 @@ void free_spots(ash_ctx* c) {
   dfree(b.partial);
   dfree(b.red);
   dfree(b.mom_partial);
+  dfree(b.fixph);
   b.cap_spots = b.cap_spotrec = b.cap_w = b.cap_off = b.cap_partial =
       b.cap_red = b.cap_mom = 0;
   c->has_spots = false;
+  c->has_fixed = false;
   c->spots = Spots();
 }
 
@@ -562,6 +564,7 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
     B.cap_spots = 0;
     if ((rc = dalloc(c, &B.target, (size_t)N, "targets")) ||
         (rc = dalloc(c, &B.y, 8 * n_pad, "spot fields")) ||
+        (rc = dalloc(c, &B.fixph, n_pad, "fixed phases")) ||
         (rc = dalloc(c, &B.Ebuf, 2 * (size_t)N, "spot fields")) ||
         (rc = dalloc(c, &B.spot64, 3 * (size_t)N, "spot offsets")))
       goto fail_alloc;
@@ -641,6 +644,7 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
   c->spots.N = N;
   c->spots.t_norm2 = tn2;
   c->has_spots = true;
+  c->has_fixed = false;  // stored farfield phases belong to the old spots
   return ASH_OK;
 fail_alloc:
   free_spots(c);
@@ -749,9 +753,11 @@ int ash_adjoint(ash_ctx* c, const float* y_dev, float* g_dev,
   return ASH_OK;
 }
 
-int ash_wgs_iterate(ash_ctx* c, float* phase_dev, float* weights_dev,
+// n_iter weighted-GS iterations; meas (one iteration) replaces |E| in the
+// weight update.
+static int wgs_loop(ash_ctx* c, float* phase_dev, float* weights_dev,
                     int n_iter, const ash_wgs_params* params, float* E_dev,
-                    float* stats_dev) {
+                    float* stats_dev, const float* meas_dev) {
   if (!c) return ASH_EINVAL;
   c->err.clear();
   if (!c->has_basis || !c->has_spots)
@@ -759,7 +765,10 @@ int ash_wgs_iterate(ash_ctx* c, float* phase_dev, float* weights_dev,
   if (!phase_dev || !weights_dev || n_iter < 0)
     return fail(c, ASH_EINVAL, "phase, weights and n_iter >= 0 required");
   const float power = params ? params->power : 1.0f;
+  const int fix_after = params ? params->fix_phase_after : 0;
   if (!isfinite(power)) return fail(c, ASH_EINVAL, "power must be finite");
+  if (fix_after < 0 && !c->has_fixed)
+    return fail(c, ASH_ENOTREADY, "no stored farfield phases to fix");
   if (n_iter == 0) return ASH_OK;
   int rc = use_device(c);
   if (rc) return rc;
@@ -774,6 +783,13 @@ int ash_wgs_iterate(ash_ctx* c, float* phase_dev, float* weights_dev,
          }), "make_field");
   for (int it = 0; it < n_iter; ++it) {
     const bool last = it == n_iter - 1;
+    // fix_phase_after = n > 0: iterations 0 .. n-1 free, n-1 stores its
+    // phases, n .. use them; < 0: every iteration uses stored phases
+    const int mode = fix_after < 0        ? kPhaseFixed
+                     : fix_after == 0     ? kPhaseFree
+                     : it < fix_after - 1 ? kPhaseFree
+                     : it == fix_after - 1 ? kPhaseStore
+                                           : kPhaseFixed;
     HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
              return launch_forward(g, N, c->plan, B.pixtab, B.field_t,
                                    B.spotrec, B.offtab, B.partial, c->stream);
@@ -785,8 +801,10 @@ int ash_wgs_iterate(ash_ctx* c, float* phase_dev, float* weights_dev,
              return launch_wgs_update(
                  N, c->plan, B.red, B.target, t_norm, weights_dev, power,
                  eff_denom, B.y, B.Ebuf, last ? E_dev : nullptr,
-                 stats_dev ? stats_dev + 4 * (size_t)it : nullptr, c->stream);
+                 stats_dev ? stats_dev + 4 * (size_t)it : nullptr, meas_dev,
+                 B.fixph, mode, c->stream);
            }), "wgs_update");
+    if (mode == kPhaseStore) c->has_fixed = true;
     HIPCHK(c, timed(c, ASH_PROF_ADJOINT, [&] {
              AdjOut o;
              o.outs = last ? kOutPhase : kOutField;
@@ -797,6 +815,24 @@ int ash_wgs_iterate(ash_ctx* c, float* phase_dev, float* weights_dev,
            }), "adjoint");
   }
   return ASH_OK;
+}
+
+int ash_wgs_iterate(ash_ctx* c, float* phase_dev, float* weights_dev,
+                    int n_iter, const ash_wgs_params* params, float* E_dev,
+                    float* stats_dev) {
+  return wgs_loop(c, phase_dev, weights_dev, n_iter, params, E_dev, stats_dev,
+                  nullptr);
+}
+
+int ash_wgs_feedback(ash_ctx* c, float* phase_dev, float* weights_dev,
+                     const float* measured_dev, const ash_wgs_params* params,
+                     float* E_dev, float* stats_dev) {
+  if (c && !measured_dev) {
+    c->err.clear();
+    return fail(c, ASH_EINVAL, "measured amplitudes required");
+  }
+  return wgs_loop(c, phase_dev, weights_dev, 1, params, E_dev, stats_dev,
+                  measured_dev);
 }
 
 namespace {

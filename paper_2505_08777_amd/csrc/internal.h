@@ -88,9 +88,14 @@ struct Buffers {
   float* lossbuf = nullptr;           // [1] spot term of the loss
   size_t cap_grad = 0, cap_tvp = 0;
   float* mom_partial = nullptr;  // [ranges][2D][NP] moment range sums
+  float* fixph = nullptr;        // [NP] stored farfield phases (turns)
   size_t cap_spots = 0, cap_spotrec = 0, cap_w = 0, cap_off = 0,
          cap_partial = 0, cap_red = 0, cap_mom = 0;
 };
+
+// Phase of the weighted-GS farfield projection: arg E (free), arg E also
+// stored (store), or the stored phases (fixed).
+enum : int { kPhaseFree = 0, kPhaseStore = 1, kPhaseFixed = 2 };
 
 struct FwdPlan {
   int groups = 0;  // pixel-block ranges (forward partial rows)
@@ -151,6 +156,7 @@ hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
                              const float* target, float t_norm, float* W,
                              float power, float eff_denom, unsigned* ypol,
                              float* Ebuf, float* E_extra, float* stats_row,
+                             const float* meas, float* fixph, int phase_mode,
                              hipStream_t s);
 enum AdjOutFlags { kOutG = 1, kOutPhase = 2, kOutField = 4, kOutGrad = 8 };
 // What the adjoint's epilogue writes for its pixel x, with h = g(x):
@@ -240,6 +246,7 @@ struct ash_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   bool has_basis = false, has_spots = false;
+  bool has_fixed = false;  // farfield phases stored since the last set_spots
   ash::Basis basis;
   ash::Spots spots;
   ash::Buffers buf;

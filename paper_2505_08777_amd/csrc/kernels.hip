@@ -1180,15 +1180,21 @@ struct OpMin {
 
 // The weighted-GS farfield update of one hologram by one block (sh: one
 // float of LDS per wave).
+// meas: amplitudes that replace |E_k| in the weight update (experimental
+// feedback), or null.  phase_mode: kPhaseFree projects onto arg E_k;
+// kPhaseStore also stores arg E_k (turns) in fixph; kPhaseFixed projects
+// onto the stored phases (phase-fixed weighted GS).
 __device__ __forceinline__ void wgs_update_block(
     int N, int slices, const float2* __restrict__ red,
     const float* __restrict__ t, float t_norm, float* __restrict__ W,
     float power, float eff_denom, unsigned* __restrict__ ypol,
     float2* __restrict__ Ebuf, float2* __restrict__ E_extra,
-    float* __restrict__ stats, float* sh) {
+    float* __restrict__ stats, float* sh, const float* __restrict__ meas,
+    float* __restrict__ fixph, int phase_mode) {
   const int tid = threadIdx.x;
-  // pass 1: fields, |E|^2 and normalised intensities I = |E|^2 / t^2
-  float s_a2 = 0.0f, s_I = 0.0f, mx = 0.0f, mn = INFINITY;
+  // pass 1: fields, |E|^2 and normalised intensities I = |E|^2 / t^2, and
+  // the norm of the amplitudes that drive the weights
+  float s_a2 = 0.0f, s_I = 0.0f, mx = 0.0f, mn = INFINITY, s_m2 = 0.0f;
   for (int k = tid; k < N; k += blockDim.x) {
     const float2 e = sum_slices(red, slices, N, k);
     Ebuf[k] = e;
@@ -1199,12 +1205,17 @@ __device__ __forceinline__ void wgs_update_block(
     s_I += I;
     mx = fmaxf(mx, I);
     mn = fminf(mn, I);
+    if (meas) {
+      const float m = fmaxf(meas[k], 0.0f);  // NaN and negatives: dark
+      s_m2 += m * m;
+    }
   }
   const float sum_a2 = block_reduce(s_a2, sh, OpSum());
   const float sum_I = block_reduce(s_I, sh, OpSum());
   const float maxI = block_reduce(mx, sh, OpMax());
   const float minI = block_reduce(mn, sh, OpMin());
-  const float norm_a = sqrtf(sum_a2);
+  const float norm_a =
+      sqrtf(meas ? block_reduce(s_m2, sh, OpSum()) : sum_a2);
   const float meanI = sum_I / (float)N;
   // pass 2: spread of I, unnormalised weight update
   float s_v = 0.0f, s_w = 0.0f;
@@ -1213,7 +1224,7 @@ __device__ __forceinline__ void wgs_update_block(
     const float a2 = e.x * e.x + e.y * e.y;
     const float dI = a2 / (t[k] * t[k]) - meanI;
     s_v += dI * dI;
-    const float a = sqrtf(a2);
+    const float a = meas ? fmaxf(meas[k], 0.0f) : sqrtf(a2);
     float wk = W[k];
     if (a > 0.0f && norm_a > 0.0f) {
       const float r = (a / norm_a) / (t[k] / t_norm);
@@ -1224,13 +1235,21 @@ __device__ __forceinline__ void wgs_update_block(
   }
   const float var = block_reduce(s_v, sh, OpSum()) / (float)N;
   const float mean_w = block_reduce(s_w, sh, OpSum()) / (float)N;
-  // pass 3: normalise weights, farfield projection y = W t E / |E|,
-  // stored in polar form (W t, arg E / 2 pi in pieces); arg 0 = 0
+  // pass 3: normalise weights, farfield projection y = W t exp(i psi) with
+  // psi = arg E (arg 0 = 0) or the stored phase, in polar form (W t,
+  // psi / 2 pi in pieces)
   for (int k = tid; k < N; k += blockDim.x) {
     const float wk = W[k] / mean_w;
     W[k] = wk;
-    const float2 e = Ebuf[k];
-    put_spot_field(ypol, k, wk * t[k], atan2f(e.y, e.x) * kInv2Pi);
+    float turns;
+    if (phase_mode == kPhaseFixed) {
+      turns = fixph[k];
+    } else {
+      const float2 e = Ebuf[k];
+      turns = atan2f(e.y, e.x) * kInv2Pi;
+      if (phase_mode == kPhaseStore) fixph[k] = turns;
+    }
+    put_spot_field(ypol, k, wk * t[k], turns);
   }
   if (stats && tid == 0) {
     stats[0] = eff_denom > 0.0f ? sum_a2 / eff_denom : 0.0f;
@@ -1246,22 +1265,25 @@ __global__ __launch_bounds__(kUpd) void k_wgs_update(
     const float* __restrict__ t, float t_norm, float* __restrict__ W,
     float power, float eff_denom, unsigned* __restrict__ ypol,
     float2* __restrict__ Ebuf, float2* __restrict__ E_extra,
-    float* __restrict__ stats) {
+    float* __restrict__ stats, const float* __restrict__ meas,
+    float* __restrict__ fixph, int phase_mode) {
   __shared__ float sh[kUpd / kWave];
   wgs_update_block(N, slices, red, t, t_norm, W, power, eff_denom, ypol, Ebuf,
-                   E_extra, stats, sh);
+                   E_extra, stats, sh, meas, fixph, phase_mode);
 }
 
 hipError_t launch_wgs_update(int N, const FwdPlan& p, const float* red,
                              const float* target, float t_norm, float* W,
                              float power, float eff_denom, unsigned* ypol,
                              float* Ebuf, float* E_extra, float* stats_row,
+                             const float* meas, float* fixph, int phase_mode,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_wgs_update, dim3(1), dim3(kUpd), 0, s, N, p.slices,
                      reinterpret_cast<const float2*>(red), target, t_norm, W,
                      power, eff_denom, ypol,
                      reinterpret_cast<float2*>(Ebuf),
-                     reinterpret_cast<float2*>(E_extra), stats_row);
+                     reinterpret_cast<float2*>(E_extra), stats_row, meas,
+                     fixph, phase_mode);
   return hipGetLastError();
 }
 
@@ -1650,7 +1672,8 @@ __global__ __launch_bounds__(kUpd) void k_batch_update(
   __shared__ float sh[kUpd / kWave];
   const HoloDesc& d = hd[blockIdx.x];
   wgs_update_block(d.N, d.slices, d.red, d.target, d.t_norm, d.W, power,
-                   d.eff_denom, d.ypol, d.Ebuf, nullptr, nullptr, sh);
+                   d.eff_denom, d.ypol, d.Ebuf, nullptr, nullptr, sh, nullptr,
+                   nullptr, kPhaseFree);
 }
 
 template <int G, bool kReduce>

@@ -1,0 +1,132 @@
+"""GPU parity of the weighted-GS variants: phase-fixed WGS and experimental
+feedback (ash_wgs_iterate's fix_phase_after, ash_wgs_feedback), one step at a
+time from the oracle's state (FP32 and FP64 trajectories drift apart, so
+whole runs are not compared)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tolerance import assert_fields, assert_phase, field_errors, STEP_PHASE_MASK
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_08777_amd as A
+    return A
+
+
+def _setup(A):
+    d = workloads.plain256()
+    geom = oracle.Geometry(d["nx"], d["ny"])
+    basis = oracle.ZernikeBasis(d["modes"])
+    amp = d["amp"].astype(np.float32).astype(np.float64)
+    phi0 = d["phi0"].astype(np.float32).astype(np.float64)
+    c = A.Context(0)
+    c.set_basis(d["nx"], d["ny"], modes=d["modes"],
+                amp=torch.tensor(d["amp"], dtype=torch.float32, device="cuda"))
+    c.set_spots(d["w"], d["t"])
+    return d, geom, basis, amp, phi0, c
+
+
+def _cuda(x):
+    return torch.tensor(np.asarray(x), dtype=torch.float32, device="cuda")
+
+
+def test_phase_fixed_step_matches_oracle(A):
+    d, geom, basis, amp, phi0, c = _setup(A)
+    t = d["t"]
+    # oracle: 3 free iterations, the phases of iteration 2 fixed afterwards
+    _, _, _, _, kept = oracle.wgs_run(phi0, t, amp, d["w"], basis, geom, 5,
+                                      keep=(2, 3, 4), fix_phase_after=3)
+    phi2, W2 = kept[2]
+    _, _, E2, _ = oracle.wgs_step(phi2, W2, t, amp, d["w"], basis, geom)
+    psi = np.angle(E2)
+    for it in (3, 4):
+        phi_i, W_i = kept[it]
+        phi_i = phi_i.astype(np.float32).astype(np.float64)
+        W_i = W_i.astype(np.float32).astype(np.float64)
+        # the GPU stores its own arg E of iteration 2 from the oracle's state
+        ph = _cuda(phi2)
+        _, _, Eg2, _ = c.wgs(ph, 1, weights=_cuda(W2), fix_phase_after=1)
+        _say("  stored fields", field_errors(Eg2.cpu().numpy(), E2))
+        assert_fields(Eg2.cpu().numpy(), E2, what="fields of the stored step")
+        ph = _cuda(phi_i)
+        Wt = _cuda(W_i)
+        _, Wg, Eg, _ = c.wgs(ph, 1, weights=Wt, fix_phase_after=-1)
+        ref_phi, ref_W, ref_E, _ = oracle.wgs_step(phi_i, W_i, t, amp, d["w"],
+                                                   basis, geom, fixed_phase=psi)
+        np.testing.assert_allclose(Wg.cpu().numpy(), ref_W, rtol=2e-4)
+        y, _ = oracle.wgs_farfield(ref_E, W_i, t, fixed_phase=psi)
+        gref = oracle.adjoint(y, d["w"], basis, geom)
+        _say("  phase @%d" % it, assert_phase(ph.cpu().numpy(), ref_phi, gref,
+                                              mask=STEP_PHASE_MASK,
+                                              what="phase-fixed step %d" % it))
+    c.close()
+
+
+def test_storing_step_equals_free_step_and_fixed_needs_store(A):
+    d, geom, basis, amp, phi0, c = _setup(A)
+    W = _cuda(np.ones(d["w"].shape[0]))
+    a = _cuda(phi0)
+    b = _cuda(phi0)
+    Wa, Wb = W.clone(), W.clone()
+    from paper_2505_08777_amd import AshError
+    with pytest.raises(AshError):
+        c.wgs(a.clone(), 1, weights=Wa.clone(), fix_phase_after=-1)
+    c.wgs(a, 2, weights=Wa, fix_phase_after=0)
+    c.wgs(b, 2, weights=Wb, fix_phase_after=2)
+    assert torch.equal(a, b) and torch.equal(Wa, Wb)
+    # set_spots forgets the stored phases
+    c.set_spots(d["w"], d["t"])
+    with pytest.raises(AshError):
+        c.wgs(a, 1, weights=Wa, fix_phase_after=-1)
+    c.close()
+
+
+def test_feedback_step_matches_oracle(A):
+    """Weights driven by 'measured' amplitudes: the model's |E| times fixed
+    per-spot factors (a system whose spots are brighter or dimmer than
+    modelled), from the oracle's state at iterations 0 and 5."""
+    d, geom, basis, amp, phi0, c = _setup(A)
+    t = d["t"]
+    N = d["w"].shape[0]
+    rng = np.random.default_rng(77)
+    gain = rng.uniform(0.7, 1.3, size=N)
+    gain[3] = 0.0                                   # a dark spot
+    _, _, _, _, kept = oracle.wgs_run(phi0, t, amp, d["w"], basis, geom, 6,
+                                      keep=(0, 5))
+    for it in (0, 5):
+        phi_i, W_i = kept[it]
+        phi_i = phi_i.astype(np.float32).astype(np.float64)
+        W_i = W_i.astype(np.float32).astype(np.float64)
+        E_i = oracle.forward(amp * np.exp(1j * phi_i), d["w"], basis, geom)
+        meas = (gain * np.abs(E_i)).astype(np.float32).astype(np.float64)
+        ph = _cuda(phi_i)
+        Wt = _cuda(W_i)
+        _, Wg, Eg, st = c.wgs_feedback(ph, _cuda(meas), weights=Wt)
+        ref_phi, ref_W, ref_E, ref_st = oracle.wgs_step(
+            phi_i, W_i, t, amp, d["w"], basis, geom, measured=meas)
+        _say("  fields @%d" % it, field_errors(Eg.cpu().numpy(), ref_E))
+        assert_fields(Eg.cpu().numpy(), ref_E, what="feedback fields")
+        np.testing.assert_allclose(Wg.cpu().numpy(), ref_W, rtol=2e-4)
+        y, _ = oracle.wgs_farfield(ref_E, W_i, t, measured=meas)
+        gref = oracle.adjoint(y, d["w"], basis, geom)
+        _say("  phase @%d" % it, assert_phase(ph.cpu().numpy(), ref_phi, gref,
+                                              mask=STEP_PHASE_MASK,
+                                              what="feedback step %d" % it))
+        np.testing.assert_allclose(st.cpu().numpy(), ref_st, rtol=1e-3, atol=1e-3)
+    c.close()

@@ -37,6 +37,13 @@ paper's experiments:
               (stand-in for the 44th-order calibration projected onto 8
               principal modes, "A Full-Field 2D Tweezer Array" and Methods,
               "Anisoplanatic Singular Value Decomposition")
+  feedback1024
+              field1024 as the model, and a simulated optical system for
+              the closed loop: the same spots with model errors N(0, 0.1 rad)
+              added to each aberration coefficient and per-spot efficiency
+              gains U(0.8, 1.2) between the fields and the measured spot
+              amplitudes; 30 loop iterations per step, farfield phases fixed
+              after 10
 
 Conventions shared with the consumers (and stated on the C ABI):
   pixel (i, j), i the column index (fastest); pupil centre (nx/2, ny/2);
@@ -59,7 +66,7 @@ NOLL4_11_ANSI = [3, 4, 5, 6, 7, 8, 9, 12]
 NOLL4_13_ANSI = [3, 4, 5, 6, 7, 8, 9, 12, 13, 11]
 
 WORKLOADS = ("plain256", "field1024", "volume1920", "grad1024", "batch64",
-             "principal1024")
+             "principal1024", "feedback1024")
 
 
 def geometry(nx, ny):
@@ -221,6 +228,18 @@ def principal1024(seed=None, n=1024, K=8):
                  u=u, v=v, K=K)
 
 
+def feedback1024(seed=None):
+    d = field1024()
+    d["name"] = "feedback1024"
+    rng = np.random.default_rng(BASE_SEED + 8 if seed is None else seed)
+    N = d["w"].shape[0]
+    w_true = d["w"].copy()
+    w_true[:, 2:] += rng.normal(0.0, 0.1, size=(N, w_true.shape[1] - 2))
+    d.update(w_true=w_true, gain=rng.uniform(0.8, 1.2, size=N), n_iter=30,
+             fix_phase_after=10)
+    return d
+
+
 BATCH_SIDES = (512, 1024, 1536, 2048)
 
 
@@ -253,4 +272,5 @@ def make(name, seed=None):
         return [batch_hologram(s) for s in batch64_specs(seed)]
     return {"plain256": plain256, "field1024": field1024,
             "volume1920": volume1920, "grad1024": grad1024,
-            "principal1024": principal1024}[name](seed)
+            "principal1024": principal1024,
+            "feedback1024": feedback1024}[name](seed)
