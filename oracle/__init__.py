@@ -22,6 +22,8 @@ grad       spot-amplitude loss with phase-gradient TV, its analytic phase
            paragraph; Adam as published by Kingma and Ba); the basis
            moments of the forward and the gradient with respect to the
            kernel coefficients w.
+quality    in-silico spot quality: the windowed Strehl proxy S' (Methods,
+           "Relative Strehl Metrology") of farfield windows around spots.
 principal  principal isoplanatic modes: the SVD rotation of the non-linear
            modes and its rank-K truncation (Methods, "Anisoplanatic
            Singular Value Decomposition").
@@ -38,6 +40,7 @@ from .wgs import wgs_farfield, wgs_step, wgs_run, wgs_stats
 from .grad import (spot_norm, spot_loss, tv_loss, total_loss, loss_grad,
                    fd_grad, adam_step, adam_run, forward_moments, coef_grad)
 from .principal import linear_modes, RotatedBasis, principal_modes
+from .quality import window_coefficients, window_strehl, spot_quality
 
 __all__ = [
     "ansi_to_nm", "nm_to_ansi", "noll_to_nm", "noll_to_ansi", "zernike_nm",
@@ -45,5 +48,5 @@ __all__ = [
     "adjoint", "wgs_farfield", "wgs_step", "wgs_run", "wgs_stats", "spot_norm", "spot_loss",
     "tv_loss", "total_loss", "loss_grad", "fd_grad", "adam_step", "adam_run",
     "linear_modes", "RotatedBasis", "principal_modes", "forward_moments",
-    "coef_grad",
+    "coef_grad", "window_coefficients", "window_strehl", "spot_quality",
 ]

@@ -641,3 +641,55 @@ def test_coef_grad_matches_torch_autograd_dense_kernel():
     L = torch.sum((torch.abs(Et / s) ** 2 - torch.tensor(t)) ** 2)
     L.backward()
     np.testing.assert_allclose(g, wt.grad.numpy(), rtol=1e-10, atol=1e-12 * np.abs(g).max())
+
+
+# -- in-silico spot quality --------------------------------------------------
+def _dirichlet2(delta, n):
+    """|sum_i exp(-2 pi i delta (i - c)/n)|^2 over n pixels (closed form)."""
+    d = np.asarray(delta, dtype=np.float64)
+    out = np.full(d.shape, float(n * n))
+    nz = np.abs(np.sin(np.pi * d / n)) > 1e-15
+    out[nz] = (np.sin(np.pi * d[nz]) / np.sin(np.pi * d[nz] / n)) ** 2
+    return out
+
+
+@pytest.mark.parametrize("step,win", [(1.0, 5), (0.5, 7), (0.25, 9)])
+def test_window_strehl_of_a_perfect_spot_closed_form(step, win):
+    """A = 1 and the hologram of one spot on an integer bin (its own tilt
+    phase, written out here), no aberration: the window samples
+    |D_nx(a step)|^2 |D_ny(b step)|^2 (Dirichlet kernels)."""
+    nx, ny = 24, 16
+    geom = Geometry(nx, ny)
+    u, v = np.array([3]), np.array([-2])
+    w = _tilt_w(u, v, geom)
+    i = np.arange(nx)[None, :]
+    j = np.arange(ny)[:, None]
+    phi = 2 * np.pi * (u[0] * (i - nx / 2) / nx + v[0] * (j - ny / 2) / ny)
+    S = oracle.spot_quality(np.exp(1j * phi), w, ZernikeBasis([1, 2]), geom,
+                            ix=1, iy=0, win=win, step=step)
+    offs = (np.arange(win) - win // 2) * step
+    Ix, Iy = _dirichlet2(offs, nx), _dirichlet2(offs, ny)
+    ref = Ix.max() * Iy.max() / (Ix.sum() * Iy.sum())
+    assert S[0] == pytest.approx(ref, rel=1e-10)
+    if step == 1.0:
+        assert S[0] == pytest.approx(1.0, rel=1e-12)
+
+
+def test_window_strehl_invariances_and_layout():
+    nx, ny = 20, 20
+    geom = Geometry(nx, ny)
+    rng = np.random.default_rng(23)
+    basis = ZernikeBasis([1, 2, 4, 5])
+    w = rng.normal(0, 1.0, size=(3, 4))
+    f = rng.uniform(0.2, 1, (ny, nx)) * np.exp(1j * rng.uniform(-np.pi, np.pi, (ny, nx)))
+    S = oracle.spot_quality(f, w, basis, geom, ix=1, iy=0, win=5, step=0.5)
+    S2 = oracle.spot_quality(3.7 * f, w, basis, geom, ix=1, iy=0, win=5, step=0.5)
+    np.testing.assert_allclose(S, S2, rtol=1e-12)
+    assert np.all((S > 0) & (S <= 1))
+    S1 = oracle.spot_quality(f, w, basis, geom, ix=1, iy=0, win=1, step=0.5)
+    np.testing.assert_allclose(S1, 1.0, rtol=1e-14)
+    ww = oracle.window_coefficients(w, 1, 0, 0.1, 0.2, 3)
+    assert ww.shape == (27, 4)
+    # row (k * 3 + b) * 3 + a: x offset a - 1, y offset b - 1
+    np.testing.assert_allclose(ww[(1 * 3 + 0) * 3 + 2], w[1] + [-0.2, 0.1, 0, 0], rtol=1e-15)
+    np.testing.assert_allclose(ww[(2 * 3 + 1) * 3 + 1], w[2], rtol=1e-15)
