@@ -93,7 +93,7 @@ def parse():
     ap.add_argument("--workload", default="field1024",
                     choices=["plain256", "field1024", "volume1920",
                              "grad1024", "batch64", "principal1024",
-                             "coefgrad1024", "feedback1024"],
+                             "coefgrad1024", "feedback1024", "quality1024"],
                     help="grad1024 times the differentiable form (Adam steps "
                          "of the spot-amplitude loss with TV); principal1024 "
                          "the WGS loop on 8 principal isoplanatic modes of a "
@@ -101,6 +101,8 @@ def parse():
                          "the kernel coefficients (moment transform) on the "
                          "grad1024 inputs; feedback1024 a closed WGS loop on "
                          "simulated spot measurements with phase fixing; "
+                         "quality1024 the windowed Strehl proxy of three "
+                         "corrections; "
                          "batch64 the "
                          "batched form (64 holograms' WGS loops together)")
     ap.add_argument("--no-tune", action="store_true",
@@ -127,12 +129,12 @@ def calibrate_copy(mib):
           flush=True)
 
 
-def profiled_traffic(workload, kernel):
+def profiled_traffic(workload, kernel, summary="wgs_kernels"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
     of this workload (FETCH_SIZE and WRITE_SIZE, scaled by what they read
     for a plain copy), or None when the summary was taken on other kernel
     source than the one built here."""
-    path = os.path.join(ROOT, "profiles", "wgs_kernels_%s.txt" % workload)
+    path = os.path.join(ROOT, "profiles", "%s_%s.txt" % (summary, workload))
     src = os.path.join(ROOT, "paper_2505_08777_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None, None
@@ -255,6 +257,8 @@ def bench_coef(args, d):
     achieved = N * P * F / (ms_avg * 1e-3) / 1e12
     ceil = coef_issue_ceiling(groups)
     peak = F * ceil / 1e12
+    traffic, traffic_src = profiled_traffic("coefgrad1024", kname,
+                                            "coef_grad_kernels")
     out = {
         "metric": "spot·pixel moment evals/s (gradient in the kernel "
                   "coefficients)", "value": value, "unit": "evals/s",
@@ -267,7 +271,8 @@ def bench_coef(args, d):
         "coef_grads_per_s": n_calls * args.steps / T,
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "avg_launch_ms": ms_avg,
+                     "traffic": traffic, "traffic_unit": "bytes/launch",
+                     "traffic_source": traffic_src, "avg_launch_ms": ms_avg,
                      "launches": prof["forward"][1], "flops_per_eval": F,
                      "evals_per_launch": N * P,
                      "peak_basis": "issue ceiling: 32 sines and cosines, "
@@ -396,6 +401,94 @@ def bench_feedback(args, d):
     }
     model.close()
     system.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_quality(args, d):
+    """In-silico spot quality on the 1024 x 1024, 400-spot field: WGS
+    holograms for three corrections of the workload's aberrations
+    (uncorrected: tilts only; isoplanatic: every spot gets the aberration of
+    the spot nearest the centre; anisoplanatic: each its own) are seen
+    through the true system, and S' = max I / sum I is taken over 21 x 21
+    farfield windows sampled every 0.25 bins around every spot.  A step is
+    one quality evaluation of the anisoplanatic hologram (window spots set
+    on the camera context, forward over 400 x 441 kernels, per-window
+    S')."""
+    import numpy as np
+    import torch
+    import paper_2505_08777_amd as A
+
+    win, step_bins = 21, 0.25
+    nx, ny = d["nx"], d["ny"]
+    truth = d["w"]
+    N, D = truth.shape
+    P = nx * ny
+    dev = torch.device("cuda:0")
+    amp = torch.tensor(d["amp"], dtype=torch.float32, device=dev)
+    centre = int(np.argmin(d["u"] ** 2 + d["v"] ** 2))
+    corr = {"uncorrected": truth.copy(), "isoplanatic": truth.copy(),
+            "anisoplanatic": truth}
+    corr["uncorrected"][:, 2:] = 0.0
+    corr["isoplanatic"][:, 2:] = truth[centre, 2:]
+    model = A.Context(0)
+    model.set_basis(nx, ny, modes=d["modes"], amp=amp)
+    holo = {}
+    for name, w in corr.items():
+        model.set_spots(w, d["t"])
+        ph = torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
+        model.wgs(ph, d["n_iter"], want_E=False, want_stats=False)
+        holo[name] = ph
+    model.close()
+    cam = A.Context(0)
+    cam.set_basis(nx, ny, modes=d["modes"], amp=amp)
+
+    def quality(ph):
+        return A.spot_quality(cam, ph, truth, ix=1, iy=0, win=win,
+                              step=step_bins)
+
+    for _ in range(args.warmup):
+        quality(holo["anisoplanatic"])
+    torch.cuda.synchronize()
+    cam.profile(True, categories=("forward",))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S = quality(holo["anisoplanatic"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = cam.profile_read()
+    cam.profile(False)
+    T = t1 - t0
+    S_all = {name: quality(ph).cpu().numpy() for name, ph in holo.items()}
+    top = max(float(v.max()) for v in S_all.values())
+    info = cam.info()
+    n_k = N * win * win
+    ms_avg = prof["forward"][0] / max(prof["forward"][1], 1)
+    kname = "k_forward<%d, %s>" % (info["groups"],
+                                   "true" if info["range_reduce"] else "false")
+    out = {
+        "metric": "spot·pixel kernel evals/s of the windowed quality "
+                  "evaluation (set-up, forward, S')",
+        "value": n_k * P * args.steps / T, "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "quality1024", "slm": "%dx%d" % (nx, ny),
+                   "spots": N, "modes": D, "window": win,
+                   "window_step_bins": step_bins, "wgs_iters": d["n_iter"]},
+        "relative_strehl_mean": {name: float(v.mean()) / top
+                                 for name, v in S_all.items()},
+        "relative_strehl_min": {name: float(v.min()) / top
+                                for name, v in S_all.items()},
+        "roofline": alu_roofline(kname, n_k * P, ms_avg, prof["forward"][1],
+                                 D, info["groups"]),
+        "kernels": {k: {"total_ms": v[0], "launches": v[1],
+                        "avg_ms": v[0] / v[1] if v[1] else None}
+                    for k, v in prof.items()},
+        "layout": info,
+    }
+    cam.close()
     print(json.dumps(out), flush=True)
 
 
@@ -568,6 +661,8 @@ def main():
         return bench_coef(args, workloads.grad1024())
     if args.workload == "feedback1024":
         return bench_feedback(args, workloads.feedback1024())
+    if args.workload == "quality1024":
+        return bench_quality(args, workloads.field1024())
     d = workloads.make(args.workload)
     if args.workload == "grad1024":
         return bench_adam(args, d)

@@ -293,6 +293,29 @@ int ash_forward_moments(ash_ctx* ctx, const float* phase_dev, float* M_dev);
 int ash_coef_grad(ash_ctx* ctx, const float* phase_dev, const float* G_dev,
                   float* grad_dev);
 
+/* In-silico spot quality (paper: Methods, "Relative Strehl Metrology":
+ * S' = max I / sum I over a 21 x 21 camera box around each spot).  The
+ * "image" near a spot is sampled as the spot fields of kernels whose tilt
+ * coefficients are moved by the window offsets.
+ *
+ * ash_window_coefficients (host-only): expand w (host [N][D] float64) into
+ * w_out (host [N*win*win][D]), spot-major with the window's x offset
+ * fastest: row (k*win + b)*win + a is w[k] with w[k][ix] += (a - win/2) dwx
+ * and w[k][iy] += (b - win/2) dwy (radians; dwx = pi s R / nx moves the x
+ * tilt Z_2 = 2 xh by s DFT bins).  win odd; ix != iy the x / y tilt modes.
+ * Errors: ASH_EINVAL, ASH_EUNSUPPORTED (N*win*win > ASH_MAX_SPOTS).
+ *
+ * ash_window_strehl: with the context's spots set to such an expansion
+ * (N = n_windows * win * win), the forward transform of A exp(i phase)
+ * and, per window, S_dev[w] = max |E|^2 / sum |E|^2 over its win*win
+ * fields (0 for a dark window).  phase_dev device [ny][nx] float32; S_dev
+ * device [n_windows] float32.  Errors: ASH_EINVAL, ASH_ENOTREADY,
+ * ASH_ESHAPE (spot count not n_windows*win*win), ASH_EHIP. */
+int ash_window_coefficients(int N, int D, const double* w, int ix, int iy,
+                            double dwx, double dwy, int win, double* w_out);
+int ash_window_strehl(ash_ctx* ctx, const float* phase_dev, int n_windows,
+                      int win, float* S_dev);
+
 typedef struct ash_adam_params {
   float lr;         /* 0.05 */
   float beta1;      /* 0.9 */

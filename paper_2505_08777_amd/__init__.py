@@ -8,9 +8,10 @@ Gerchberg-Saxton loop, as hand-written HIP kernels behind a C ABI
 
 from ._lib import AshError, LIB_PATH, lib
 from .basis import principal_modes, zernike_monomials, zernike_table
-from .context import Batch, Context, Propagate, PropagateSpots, propagate
+from .context import (Batch, Context, Propagate, PropagateSpots, propagate,
+                      spot_quality, window_coefficients)
 
 __all__ = ["AshError", "Batch", "Context", "LIB_PATH", "Propagate",
            "PropagateSpots", "lib",
-           "principal_modes", "propagate", "zernike_monomials",
-           "zernike_table"]
+           "principal_modes", "propagate", "spot_quality",
+           "window_coefficients", "zernike_monomials", "zernike_table"]

@@ -94,6 +94,8 @@ def _load():
         "ash_phase_grad": (I, [P, P, P, P]),
         "ash_forward_moments": (I, [P, P, P]),
         "ash_coef_grad": (I, [P, P, P, P]),
+        "ash_window_coefficients": (I, [I, I, P, I, I, D, D, I, P]),
+        "ash_window_strehl": (I, [P, P, I, I, P]),
         "ash_adam_iterate": (I, [P, P, P, P, I, I, ctypes.POINTER(AdamParams),
                                  P, P]),
         "ash_batch_create": (I, [ctypes.POINTER(P), I, P, P]),

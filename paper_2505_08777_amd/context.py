@@ -44,6 +44,7 @@ class Context:
         if rc != 0:
             raise AshError(rc, "ash_create", lib.ash_last_error(None).decode())
         self.nx = self.ny = self.N = self.D = None
+        self.cx = self.cy = self.R = None
         self.modes = None
         self.target = None
 
@@ -128,6 +129,7 @@ class Context:
                                 mono_coef.ctypes.data, _ptr(amp)),
               "ash_set_basis", self._h)
         self.nx, self.ny, self.D = int(nx), int(ny), mono_coef.shape[0]
+        self.cx, self.cy, self.R = float(cx), float(cy), float(R)
         self.N = None
         self.target = None
 
@@ -274,6 +276,20 @@ class Context:
               "ash_coef_grad", self._h)
         return out
 
+    def window_strehl(self, phase, n_windows, win, out=None):
+        """S' = max |E|^2 / sum |E|^2 per window of win*win consecutive
+        spots (the spots set by spot_quality / window_coefficients)."""
+        _dev(phase, torch.float32, (self.ny, self.nx), "phase", self.device)
+        if out is None:
+            out = torch.empty(n_windows, dtype=torch.float32,
+                              device="cuda:%d" % self.device)
+        _dev(out, torch.float32, (n_windows,), "out", self.device)
+        self._stream()
+        check(lib.ash_window_strehl(self._h, _ptr(phase), int(n_windows),
+                                    int(win), _ptr(out)),
+              "ash_window_strehl", self._h)
+        return out
+
     def adam(self, phase, n_steps, m=None, v=None, step0=0, lr=0.05,
              betas=(0.9, 0.999), eps=1e-8, tv_weight=1e-3, tv_eps=1e-3,
              want_loss=True, want_E=False):
@@ -359,6 +375,30 @@ def propagate(phase, context, w=None):
     if w is None:
         return Propagate.apply(phase, context)
     return PropagateSpots.apply(phase, w, context)
+
+
+def window_coefficients(w, ix, iy, dwx, dwy, win):
+    """Coefficients of the win x win window points of every spot (see
+    ash_window_coefficients): [N * win * win, D] float64."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    N, D = w.shape
+    out = np.empty((N * win * win, D), dtype=np.float64)
+    check(lib.ash_window_coefficients(N, D, w.ctypes.data, int(ix), int(iy),
+                                      float(dwx), float(dwy), int(win),
+                                      out.ctypes.data),
+          "ash_window_coefficients")
+    return out
+
+
+def spot_quality(camera, phase, w, ix, iy, win=21, step=0.25):
+    """S' of win x win farfield windows sampled every `step` DFT bins around
+    the spots w, seen through `camera` (a context holding the system's basis
+    and amplitude; its spots are replaced by the windows)."""
+    dwx = math.pi * step * camera.R / camera.nx
+    dwy = math.pi * step * camera.R / camera.ny
+    ww = window_coefficients(w, ix, iy, dwx, dwy, win)
+    camera.set_spots(ww)
+    return camera.window_strehl(phase, np.asarray(w).shape[0], win)
 
 
 class Batch:

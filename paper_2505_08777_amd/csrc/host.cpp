@@ -727,6 +727,61 @@ int ash_coef_grad(ash_ctx* c, const float* phase_dev, const float* G_dev,
   return moments(c, phase_dev, G_dev, nullptr, grad_dev);
 }
 
+int ash_window_coefficients(int N, int D, const double* w, int ix, int iy,
+                            double dwx, double dwy, int win, double* w_out) {
+  if (N < 1 || D < 1 || !w || !w_out || win < 1 || win % 2 == 0 || ix < 0 ||
+      iy < 0 || ix >= D || iy >= D || ix == iy || !isfinite(dwx) ||
+      !isfinite(dwy))
+    return ASH_EINVAL;
+  if ((long)N * win * win > ASH_MAX_SPOTS) return ASH_EUNSUPPORTED;
+  const int h = win / 2;
+  for (int k = 0; k < N; ++k)
+    for (int b = 0; b < win; ++b)
+      for (int a = 0; a < win; ++a) {
+        double* row = w_out + (((long)k * win + b) * win + a) * D;
+        for (int d = 0; d < D; ++d) row[d] = w[(long)k * D + d];
+        row[ix] += (a - h) * dwx;
+        row[iy] += (b - h) * dwy;
+      }
+  return ASH_OK;
+}
+
+int ash_window_strehl(ash_ctx* c, const float* phase_dev, int n_windows,
+                      int win, float* S_dev) {
+  if (!c) return ASH_EINVAL;
+  c->err.clear();
+  if (!c->has_basis || !c->has_spots)
+    return fail(c, ASH_ENOTREADY, "basis and spots must be set");
+  if (!phase_dev || !S_dev || n_windows < 1 || win < 1)
+    return fail(c, ASH_EINVAL, "phase, S, n_windows >= 1 and win >= 1 required");
+  if ((long)n_windows * win * win != c->spots.N)
+    return fail(c, ASH_ESHAPE, "spots must be n_windows * win * win");
+  int rc = use_device(c);
+  if (rc) return rc;
+  const Geom& g = c->basis.g;
+  Buffers& B = c->buf;
+  const int N = c->spots.N;
+  HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
+           return launch_make_field(g, phase_dev, nullptr, B.amp_t, B.pixtab,
+                                    B.field_t, c->stream);
+         }), "make_field");
+  HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
+           return launch_forward(g, N, c->plan, B.pixtab, B.field_t,
+                                 B.spotrec, B.offtab, B.partial, c->stream);
+         }), "forward");
+  HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+           return launch_reduce(N, c->plan, B.partial, B.red, c->stream);
+         }), "reduce");
+  HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+           return launch_finish_E(N, c->plan, B.red, B.Ebuf, c->stream);
+         }), "finish");
+  HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+           return launch_window_strehl(n_windows, win * win, B.Ebuf, S_dev,
+                                       c->stream);
+         }), "window strehl");
+  return ASH_OK;
+}
+
 int ash_adjoint(ash_ctx* c, const float* y_dev, float* g_dev,
                 float* phase_out_dev) {
   if (!c) return ASH_EINVAL;

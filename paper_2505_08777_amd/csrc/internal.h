@@ -147,6 +147,8 @@ hipError_t launch_moments(const Geom& b, int N, int groups,
                           const unsigned* offtab,
                           const unsigned short* momtab, float* partial,
                           hipStream_t s);
+hipError_t launch_window_strehl(int n_windows, int win2, const float* E,
+                                float* S, hipStream_t s);
 hipError_t launch_moments_finish(int N, int D, int ranges,
                                  const float* partial, const float* G,
                                  float* M, float* grad, hipStream_t s);

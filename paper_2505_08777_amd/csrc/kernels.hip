@@ -418,56 +418,72 @@ __global__ void k_spot_offsets(Geom b, int N, long total,
                                unsigned* __restrict__ offtab,
                                unsigned* __restrict__ bound_bits) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= total) return;
   const int NP = (N + 31) / 32 * 32;  // spots padded to whole blocks
-  const int tile = (int)(gid / NP), k = (int)(gid % NP);
-  u32x4* __restrict__ ot = reinterpret_cast<u32x4*>(offtab);
-  if (k >= N) {
-    const u32x4 z = {0u, 0u, 0u, 0u};
-    ot[((long)tile * 2 + 0) * NP + k] = z;
-    ot[((long)tile * 2 + 1) * NP + k] = z;
-    return;
+  float bnd = 0.0f, mg = 0.0f;  // this thread's bounds (0: none)
+  if (gid < total) {
+    const int tile = (int)(gid / NP), k = (int)(gid % NP);
+    u32x4* __restrict__ ot = reinterpret_cast<u32x4*>(offtab);
+    if (k >= N) {
+      const u32x4 z = {0u, 0u, 0u, 0u};
+      ot[((long)tile * 2 + 0) * NP + k] = z;
+      ot[((long)tile * 2 + 1) * NP + k] = z;
+    } else {
+      const int nl = b.nl;
+      const double i0 =
+          (double)((tile % b.tiles_x) * kTileW + kAnchorI) - b.cx;
+      const double j0 =
+          (double)((tile / b.tiles_x) * kTileH + kAnchorJ) - b.cy;
+      const double al = spot64[3 * (long)k + 1], be = spot64[3 * (long)k + 2];
+      double t = spot64[3 * (long)k] + al * i0 + be * j0;
+      double a = al, bs = be, bound = 0.0;
+      const double* tz = tilez + 3 * (long)tile * nl;
+      for (int s = 0; s < nl; ++s) {
+        const double c = w[(long)k * b.D + nlmode[s]] * kInv2PiD;
+        t += c * tz[3 * s];
+        a += c * tz[3 * s + 1];
+        bs += c * tz[3 * s + 2];
+        bound += fabs(c) * (double)rmax[(long)tile * nl + s];
+      }
+      t -= floor(t);
+      // |theta| over the tile: offset, slopes times the largest distance
+      // from the anchor, remainder, and the two record phases of at most
+      // 1/2 each
+      const double mag = 2.0 + kAnchorI * fabs(a) + kAnchorJ * fabs(bs) + bound;
+      unsigned po[3], pa[3], pb[3];
+      split3(t, po);
+      split3(a, pa);
+      split3(bs, pb);
+      // half 0: the spot record's nonlinear slots p 0..3 (so that the
+      // adjoint need not read the record's last group), and p 7
+      const u32x2 nlw = *reinterpret_cast<const u32x2*>(
+          spotrec +
+          ((((long)k / 32) * b.groups + b.groups - 1) * 2) * 32 + k % 32);
+      u32x4 h0, h1;
+      h0[0] = nlw.x;
+      h0[1] = nlw.y;
+      h0[2] = 0u;
+      h0[3] = po[0] << 16;            // p 7
+      h1[0] = po[1] | (po[2] << 16);  // p 8, 9
+      h1[1] = pa[0] | (pa[1] << 16);  // p 10, 11
+      h1[2] = pa[2] | (pb[0] << 16);  // p 12, 13
+      h1[3] = pb[1] | (pb[2] << 16);  // p 14, 15
+      ot[((long)tile * 2 + 0) * NP + k] = h0;
+      ot[((long)tile * 2 + 1) * NP + k] = h1;
+      bnd = (float)bound;
+      mg = (float)mag;
+    }
   }
-  const int nl = b.nl;
-  const double i0 = (double)((tile % b.tiles_x) * kTileW + kAnchorI) - b.cx;
-  const double j0 = (double)((tile / b.tiles_x) * kTileH + kAnchorJ) - b.cy;
-  const double al = spot64[3 * (long)k + 1], be = spot64[3 * (long)k + 2];
-  double t = spot64[3 * (long)k] + al * i0 + be * j0;
-  double a = al, bs = be, bound = 0.0;
-  const double* tz = tilez + 3 * (long)tile * nl;
-  for (int s = 0; s < nl; ++s) {
-    const double c = w[(long)k * b.D + nlmode[s]] * kInv2PiD;
-    t += c * tz[3 * s];
-    a += c * tz[3 * s + 1];
-    bs += c * tz[3 * s + 2];
-    bound += fabs(c) * (double)rmax[(long)tile * nl + s];
+  // the wave's largest bounds, then one atomic per wave (non-negative
+  // floats order like their bit patterns)
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    bnd = fmaxf(bnd, __shfl_xor(bnd, m, kWave));
+    mg = fmaxf(mg, __shfl_xor(mg, m, kWave));
   }
-  t -= floor(t);
-  // |theta| over the tile: offset, slopes times the largest distance from
-  // the anchor, remainder, and the two record phases of at most 1/2 each
-  const double mag = 2.0 + kAnchorI * fabs(a) + kAnchorJ * fabs(bs) + bound;
-  unsigned po[3], pa[3], pb[3];
-  split3(t, po);
-  split3(a, pa);
-  split3(bs, pb);
-  // half 0: the spot record's nonlinear slots p 0..3 (so that the adjoint
-  // need not read the record's last group), and p 7
-  const u32x2 nlw = *reinterpret_cast<const u32x2*>(
-      spotrec + ((((long)k / 32) * b.groups + b.groups - 1) * 2) * 32 + k % 32);
-  u32x4 h0, h1;
-  h0[0] = nlw.x;
-  h0[1] = nlw.y;
-  h0[2] = 0u;
-  h0[3] = po[0] << 16;            // p 7
-  h1[0] = po[1] | (po[2] << 16);  // p 8, 9
-  h1[1] = pa[0] | (pa[1] << 16);  // p 10, 11
-  h1[2] = pa[2] | (pb[0] << 16);  // p 12, 13
-  h1[3] = pb[1] | (pb[2] << 16);  // p 14, 15
-  ot[((long)tile * 2 + 0) * NP + k] = h0;
-  ot[((long)tile * 2 + 1) * NP + k] = h1;
-  // non-negative floats order like their bit patterns
-  atomicMax(bound_bits, __float_as_uint((float)bound));
-  atomicMax(bound_bits + 1, __float_as_uint((float)mag));
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicMax(bound_bits, __float_as_uint(bnd));
+    atomicMax(bound_bits + 1, __float_as_uint(mg));
+  }
 }
 
 hipError_t launch_prep_spots(const Geom& b, int N, const double* d_w,
@@ -1101,6 +1117,41 @@ hipError_t launch_moments_finish(int N, int D, int ranges,
                      reinterpret_cast<const float2*>(partial),
                      reinterpret_cast<const float2*>(G),
                      reinterpret_cast<float2*>(M), grad);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Windowed Strehl proxy S' = max |E|^2 / sum |E|^2 over each window of win^2
+// consecutive spot fields (one wave per window; fixed-order reductions).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_window_strehl(
+    int n_windows, int win2, const float2* __restrict__ E,
+    float* __restrict__ S) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const long wnd = (long)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (wnd >= n_windows) return;  // wave-uniform
+  const float2* __restrict__ e = E + wnd * win2;
+  float mx = 0.0f, sum = 0.0f;
+  for (int j = lane; j < win2; j += kWave) {
+    const float I = e[j].x * e[j].x + e[j].y * e[j].y;
+    mx = fmaxf(mx, I);
+    sum += I;
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    mx = fmaxf(mx, __shfl_xor(mx, m, kWave));
+    sum += __shfl_xor(sum, m, kWave);
+  }
+  if (lane == 0) S[wnd] = sum > 0.0f ? mx / sum : 0.0f;
+}
+
+hipError_t launch_window_strehl(int n_windows, int win2, const float* E,
+                                float* S, hipStream_t s) {
+  const int per_block = 256 / kWave;
+  hipLaunchKernelGGL(k_window_strehl,
+                     dim3((unsigned)((n_windows + per_block - 1) / per_block)),
+                     dim3(256), 0, s, n_windows, win2,
+                     reinterpret_cast<const float2*>(E), S);
   return hipGetLastError();
 }
 

@@ -158,3 +158,22 @@ def test_principal_modes_errors():
         A.principal_modes(pw, cf, w2, 2)
     assert _lib.lib.ash_principal_modes(0, 1, 1, None, None, None, 0, None,
                                         None, None, None) == _lib.EINVAL
+
+
+def test_window_coefficients_match_oracle_and_errors():
+    rng = np.random.default_rng(31)
+    w = rng.normal(size=(4, 6))
+    a = A.window_coefficients(w, 2, 1, 0.3, -0.2, 7)
+    b = oracle.window_coefficients(w, 2, 1, 0.3, -0.2, 7)
+    np.testing.assert_array_equal(a, b)
+    out = np.zeros(4 * 49 * 6)
+    L = _lib.lib
+    assert L.ash_window_coefficients(4, 6, w.ctypes.data, 2, 1, 0.3, 0.2, 6,
+                                     out.ctypes.data) == _lib.EINVAL   # even
+    assert L.ash_window_coefficients(4, 6, w.ctypes.data, 2, 2, 0.3, 0.2, 7,
+                                     out.ctypes.data) == _lib.EINVAL   # ix == iy
+    assert L.ash_window_coefficients(4, 6, w.ctypes.data, 6, 1, 0.3, 0.2, 7,
+                                     out.ctypes.data) == _lib.EINVAL   # ix >= D
+    assert L.ash_window_coefficients(4, 6, w.ctypes.data, 2, 1, float("nan"),
+                                     0.2, 7, out.ctypes.data) == _lib.EINVAL
+    assert L.ash_window_strehl(None, None, 1, 1, None) == _lib.EINVAL
