@@ -408,7 +408,7 @@ __global__ void k_spot_records(Geom b, int N, const double* __restrict__ w,
 // with zero records to NP, a whole number of 32-spot blocks.  Also the
 // largest bound sum_s |c_s| max|Rm_s| (turns) of the in-tile remainder
 // phase, and a bound on |theta|.
-__global__ void k_spot_offsets(Geom b, int N, long total,
+__global__ __launch_bounds__(256) void k_spot_offsets(Geom b, int N, long total,
                                const double* __restrict__ spot64,
                                const double* __restrict__ w,
                                const int* __restrict__ nlmode,
@@ -417,10 +417,10 @@ __global__ void k_spot_offsets(Geom b, int N, long total,
                                const u32x4* __restrict__ spotrec,
                                unsigned* __restrict__ offtab,
                                unsigned* __restrict__ bound_bits) {
-  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int NP = (N + 31) / 32 * 32;  // spots padded to whole blocks
   float bnd = 0.0f, mg = 0.0f;  // this thread's bounds (0: none)
-  if (gid < total) {
+  for (long gid = (long)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+       gid += (long)gridDim.x * blockDim.x) {
     const int tile = (int)(gid / NP), k = (int)(gid % NP);
     u32x4* __restrict__ ot = reinterpret_cast<u32x4*>(offtab);
     if (k >= N) {
@@ -469,18 +469,29 @@ __global__ void k_spot_offsets(Geom b, int N, long total,
       h1[3] = pb[1] | (pb[2] << 16);  // p 14, 15
       ot[((long)tile * 2 + 0) * NP + k] = h0;
       ot[((long)tile * 2 + 1) * NP + k] = h1;
-      bnd = (float)bound;
-      mg = (float)mag;
+      bnd = fmaxf(bnd, (float)bound);
+      mg = fmaxf(mg, (float)mag);
     }
   }
-  // the wave's largest bounds, then one atomic per wave (non-negative
-  // floats order like their bit patterns)
+  // the block's largest bounds, then one atomic per block: atomics on one
+  // address serialise, so they are kept to a few thousand per launch
+  // (non-negative floats order like their bit patterns)
+  __shared__ float sh[2][256 / kWave];
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
     bnd = fmaxf(bnd, __shfl_xor(bnd, m, kWave));
     mg = fmaxf(mg, __shfl_xor(mg, m, kWave));
   }
   if ((threadIdx.x & (kWave - 1)) == 0) {
+    sh[0][threadIdx.x / kWave] = bnd;
+    sh[1][threadIdx.x / kWave] = mg;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x / kWave); ++i) {
+      bnd = fmaxf(bnd, sh[0][i]);
+      mg = fmaxf(mg, sh[1][i]);
+    }
     atomicMax(bound_bits, __float_as_uint(bnd));
     atomicMax(bound_bits + 1, __float_as_uint(mg));
   }
@@ -498,7 +509,8 @@ hipError_t launch_prep_spots(const Geom& b, int N, const double* d_w,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long total = (long)b.n_tiles * n_pad;
-  hipLaunchKernelGGL(k_spot_offsets, dim3((unsigned)((total + 255) / 256)),
+  const long blocks = (total + 255) / 256 < 8192 ? (total + 255) / 256 : 8192;
+  hipLaunchKernelGGL(k_spot_offsets, dim3((unsigned)blocks),
                      dim3(256), 0, s, b, N, total, spot64, d_w, d_nlmode,
                      tilez, rmax, reinterpret_cast<const u32x4*>(spotrec),
                      offtab, bound_bits);
