@@ -382,7 +382,7 @@ int make_fields(ash_batch* b, float* const* phase) {
     BCHK(b, btimed(b, ASH_PROF_FIELD, [&] {
            return launch_make_field(c->basis.g, phase[h], nullptr,
                                     c->buf.amp_t, c->buf.pixtab,
-                                    c->buf.field_t, b->stream);
+                                    c->buf.field_t, nullptr, b->stream);
          }), "make_field");
   }
   return ASH_OK;

@@ -143,6 +143,7 @@ void free_basis(ash_ctx* c) {
   dfree(b.pixtab);
   dfree(b.amp_t);
   dfree(b.field_t);
+  dfree(b.fmag_t);
   dfree(b.aff_dev);
   dfree(b.nlmode_dev);
   dfree(b.tilez);
@@ -458,6 +459,7 @@ int ash_set_basis(ash_ctx* c, int nx, int ny, double cx, double cy, double R,
   const size_t nl1 = (size_t)std::max(g.nl, 1);
   if ((rc = dalloc(c, &B.amp_t, npix, "amplitude")) ||
       (rc = dalloc(c, &B.field_t, 8 * npix, "nearfield")) ||
+      (rc = dalloc(c, &B.fmag_t, npix, "nearfield magnitudes")) ||
       (rc = dalloc(c, &B.aff_dev, 3 * (size_t)D, "basis affine terms")) ||
       (rc = dalloc(c, &B.nlmode_dev, nl1, "modes")) ||
       (rc = dalloc(c, &B.tilez, 3 * (size_t)g.n_tiles * nl1, "tile basis")) ||
@@ -666,11 +668,13 @@ int ash_forward(ash_ctx* c, const float* phase_dev, const float* field_dev,
   const int N = c->spots.N;
   HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
            return launch_make_field(g, phase_dev, field_dev, B.amp_t,
-                                    B.pixtab, B.field_t, c->stream);
+                                    B.pixtab, B.field_t,
+                                    field_dev ? B.fmag_t : nullptr, c->stream);
          }), "make_field");
   HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
            return launch_forward(g, N, c->plan, B.pixtab, B.field_t,
-                                 B.spotrec, B.offtab, B.partial, c->stream);
+                                 field_dev ? B.fmag_t : B.amp_t, B.spotrec,
+                                 B.offtab, B.partial, c->stream);
          }), "forward");
   HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
            return launch_reduce(N, c->plan, B.partial, B.red, c->stream);
@@ -692,7 +696,7 @@ static int moments(ash_ctx* c, const float* phase_dev, const float* G_dev,
   const int N = c->spots.N;
   HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
            return launch_make_field(g, phase_dev, nullptr, B.amp_t, B.pixtab,
-                                    B.field_t, c->stream);
+                                    B.field_t, nullptr, c->stream);
          }), "make_field");
   HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
            return launch_moments(g, N, c->plan.mom_groups, B.pixtab,
@@ -763,10 +767,10 @@ int ash_window_strehl(ash_ctx* c, const float* phase_dev, int n_windows,
   const int N = c->spots.N;
   HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
            return launch_make_field(g, phase_dev, nullptr, B.amp_t, B.pixtab,
-                                    B.field_t, c->stream);
+                                    B.field_t, nullptr, c->stream);
          }), "make_field");
   HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
-           return launch_forward(g, N, c->plan, B.pixtab, B.field_t,
+           return launch_forward(g, N, c->plan, B.pixtab, B.field_t, B.amp_t,
                                  B.spotrec, B.offtab, B.partial, c->stream);
          }), "forward");
   HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
@@ -834,7 +838,7 @@ static int wgs_loop(ash_ctx* c, float* phase_dev, float* weights_dev,
   const float eff_denom = (float)((double)g.nx * g.ny * c->basis.amp_sum2);
   HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
            return launch_make_field(g, phase_dev, nullptr, B.amp_t,
-                                    B.pixtab, B.field_t, c->stream);
+                                    B.pixtab, B.field_t, nullptr, c->stream);
          }), "make_field");
   for (int it = 0; it < n_iter; ++it) {
     const bool last = it == n_iter - 1;
@@ -846,7 +850,7 @@ static int wgs_loop(ash_ctx* c, float* phase_dev, float* weights_dev,
                      : it == fix_after - 1 ? kPhaseStore
                                            : kPhaseFixed;
     HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
-             return launch_forward(g, N, c->plan, B.pixtab, B.field_t,
+             return launch_forward(g, N, c->plan, B.pixtab, B.field_t, B.amp_t,
                                    B.spotrec, B.offtab, B.partial, c->stream);
            }), "forward");
     HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
@@ -963,13 +967,13 @@ int ash_adam_iterate(ash_ctx* c, float* phase_dev, float* m_dev, float* v_dev,
   const int n_tvp = g.n_tiles * kBlkPerTile;
   HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
            return launch_make_field(g, phase_dev, nullptr, B.amp_t,
-                                    B.pixtab, B.field_t, c->stream);
+                                    B.pixtab, B.field_t, nullptr, c->stream);
          }), "make_field");
   for (int it = 0; it < n_steps; ++it) {
     const int step = step0 + it + 1;
     const bool last = it == n_steps - 1;
     HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
-             return launch_forward(g, N, c->plan, B.pixtab, B.field_t,
+             return launch_forward(g, N, c->plan, B.pixtab, B.field_t, B.amp_t,
                                    B.spotrec, B.offtab, B.partial, c->stream);
            }), "forward");
     HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {

@@ -62,6 +62,7 @@ struct Buffers {
   unsigned short* pixtab = nullptr;  // [tile][group][half][kTile][8] bf16
   float* amp_t = nullptr;            // [n_tiles][kTile]
   unsigned* field_t = nullptr;  // nearfield [n_tiles * 16][half][32] u32x4
+  float* fmag_t = nullptr;      // [n_tiles][kTile] |f| of a complex input
   double* aff_dev = nullptr;         // [D][3]
   int* nlmode_dev = nullptr;         // [nl]
   double* tilez = nullptr;           // [n_tiles][nl][3] Z^nl, d/di, d/dj
@@ -125,12 +126,12 @@ hipError_t launch_prep_spots(const Geom& b, int N, const double* d_w,
 hipError_t launch_make_field(const Geom& b, const float* phase,
                              const float* field, const float* amp_t,
                              const unsigned short* pixtab, unsigned* nf_t,
-                             hipStream_t s);
+                             float* fmag, hipStream_t s);
 hipError_t launch_to_polar(int N, const float* y, unsigned* ypol,
                            hipStream_t s);
 hipError_t launch_forward(const Geom& b, int N, const FwdPlan& p,
                           const unsigned short* pixtab, const unsigned* nf_t,
-                          const unsigned short* spotrec,
+                          const float* mag, const unsigned short* spotrec,
                           const unsigned* offtab, float* partial,
                           hipStream_t s);
 hipError_t launch_reduce(int N, const FwdPlan& p, const float* partial,

@@ -72,6 +72,33 @@ __device__ __forceinline__ GLOBAL T* as_global(T* p) {
   return (GLOBAL T*)p;
 }
 
+// Buffer loads for the transforms' inner loops: a resource over a
+// wave-uniform base and extent (bytes), a per-lane offset fixed for the loop
+// and a wave-uniform offset stepped by scalar instructions, so that the loop
+// spends no vector instructions on addresses.  Reads past the extent return
+// zeros.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit dword access
+
+template <typename T>
+__device__ __forceinline__ rsrc_t make_rsrc(const GLOBAL T* base,
+                                            unsigned long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(const T*)base, (short)0,
+      (int)(bytes < 0x7FFFFFFFul ? bytes : 0x7FFFFFFFul), kRsrcWord3);
+}
+
+__device__ __forceinline__ u32x4 bload4(rsrc_t r, unsigned voff,
+                                        unsigned soff) {
+  return __builtin_bit_cast(
+      u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ float bload1f(rsrc_t r, unsigned voff,
+                                         unsigned soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 __host__ __device__ int slots_per_mode(int pieces) {
   return pieces == 2 ? 3 : 6;
 }
@@ -117,9 +144,9 @@ __device__ inline void split3f(float v, unsigned* p) {
 // Nearfield of the tile-ordered pixels, per 32-pixel block (tile row)
 // [tile * kBlkPerTile + row][half][32] u32x4.  Half 0: the words of half 0
 // of the pixel record's last group (its nonlinear slots p 0..3, the phase
-// pieces and a 1 at p 4..7).  Half 1: {magnitude bits, then words 1..3
-// of half 1 of the last group (di, di | di, dj | dj, dj as bf16)}; word 0
-// of half 1 (p 8, 9: 1, 1) is a constant.
+// pieces and a 1 at p 4..7).  Half 1: the words of half 1 of the last
+// group, {1 | 1, di | di, di | dj, dj | dj} as bf16 (p 8..15).  The
+// magnitudes are a separate per-pixel array in the same tile order.
 __host__ __device__ inline long nf_index(long tile, int pix, int half) {
   return ((tile * kBlkPerTile + pix / 32) * 2 + half) * 32 + pix % 32;
 }
@@ -137,15 +164,18 @@ __device__ inline u32x2 pixel_nl_words(const u32x4* pixtab, int G, long tile,
       pixtab + ((tile * G + G - 1) * 2) * kTile + pix);
 }
 
-// Spot fields of the adjoint, [NP] u32x4: {the phase pieces at p 4..6 of
-// the spot record's last group (words 2..3 of half 0), magnitude bits, 0}.
-// Entries past N stay zero.
+// Spot fields of the adjoint, [NP / 32][half][32] u32x4 like the spot
+// records: half 0 {the phase pieces at p 4..6 of the spot record's last
+// group (words 2..3 of half 0), magnitude bits, 0}, half 1 {0, 0,
+// magnitude bits, 0}, so that each lane half ORs its words in and reads the
+// magnitude without selecting.  Entries past N stay zero.
 __device__ inline void put_spot_field(unsigned* y, int k, float mag,
                                       float turns) {
   unsigned p[3];
   split3f(turns, p);
-  reinterpret_cast<u32x4*>(y)[k] =
-      u32x4{p[0] | (p[1] << 16), p[2], __float_as_uint(mag), 0u};
+  u32x4* y4 = reinterpret_cast<u32x4*>(y) + (long)(k / 32) * 64 + k % 32;
+  y4[0] = u32x4{p[0] | (p[1] << 16), p[2], __float_as_uint(mag), 0u};
+  y4[32] = u32x4{0u, 0u, __float_as_uint(mag), 0u};
 }
 
 // Slot f of a record of 16-slot groups: group f / 16, lane half (f % 16)/8,
@@ -527,7 +557,7 @@ __global__ void k_make_field(Geom b, long total,
                              const float2* __restrict__ field,
                              const float* __restrict__ amp_t,
                              const u32x4* __restrict__ pixtab,
-                             u32x4* __restrict__ nf) {
+                             u32x4* __restrict__ nf, float* __restrict__ fmag) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= total) return;
   const int tile = (int)(gid / kTile), pix = (int)(gid % kTile);
@@ -550,20 +580,21 @@ __global__ void k_make_field(Geom b, long total,
   const unsigned bdi = bf16_bits((float)(pix % kTileW - kAnchorI));
   const unsigned bdj = bf16_bits((float)(pix / kTileW - kAnchorJ));
   nf[nf_index(tile, pix, 1)] =
-      u32x4{__float_as_uint(mag), bdi | (bdi << 16), bdi | (bdj << 16),
+      u32x4{kBf16One | (kBf16One << 16), bdi | (bdi << 16), bdi | (bdj << 16),
             bdj | (bdj << 16)};
+  if (fmag) fmag[gid] = mag;
 }
 
 hipError_t launch_make_field(const Geom& b, const float* phase,
                              const float* field, const float* amp_t,
                              const unsigned short* pixtab, unsigned* nf_t,
-                             hipStream_t s) {
+                             float* fmag, hipStream_t s) {
   const long total = (long)b.n_tiles * kTile;
   hipLaunchKernelGGL(k_make_field, dim3((unsigned)((total + 255) / 256)),
                      dim3(256), 0, s, b, total, phase,
                      reinterpret_cast<const float2*>(field), amp_t,
                      reinterpret_cast<const u32x4*>(pixtab),
-                     reinterpret_cast<u32x4*>(nf_t));
+                     reinterpret_cast<u32x4*>(nf_t), fmag);
   return hipGetLastError();
 }
 
@@ -675,16 +706,14 @@ __device__ __forceinline__ void accumulate(const floatx16& th, float m,
 // blocks [b0, b1) (tile rows, tile order).  Operand A is the spot record,
 // B the pixel record of a block; each lane keeps 16 spot rows, and a
 // butterfly over the 32 lanes of each half-wave finishes the pixel sums,
-// written to row[k] for the block's spots k < N.  One load brings half 0
-// its nearfield record (the last group's nonlinear slots, the phase pieces
-// and 1) and half 1 the pixel's magnitude with its last-group words 1..3
-// (di, dj); half 1's word 0 (1, 1) is a constant, and the magnitude
-// crosses to half 0 with a lane-half swap.
+// written to row[k] for the block's spots k < N.  One load brings each
+// lane half its part of the nearfield record's last group, another the
+// magnitude of the lane's pixel (the same for both halves).
 // E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))).
 template <int G, bool kReduce>
 __device__ __forceinline__ void forward_range(
     int N, int mb, long b0, long b1, const GLOBAL u32x4* __restrict__ pixtab,
-    const GLOBAL u32x4* __restrict__ nf,
+    const GLOBAL u32x4* __restrict__ nf, const GLOBAL float* __restrict__ mag,
     const GLOBAL u32x4* __restrict__ spotrec,
     const GLOBAL u32x4* __restrict__ offtab, float2* __restrict__ row) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -695,6 +724,8 @@ __device__ __forceinline__ void forward_range(
   // addresses: a wave-uniform base plus a 32-bit lane offset, so that
   // loads take the scalar-base form
   const unsigned lane_pix = h * kTile + q, lane_spot = h * 32 + q;
+  const unsigned off_pix = lane_pix * 16u, off_spot = lane_spot * 16u,
+                 off_q = q * 4u;
   u32x4 S[G];
   const GLOBAL u32x4* __restrict__ sb = spotrec + (long)mb * G * 64;
 #pragma unroll
@@ -706,7 +737,6 @@ __device__ __forceinline__ void forward_range(
   for (int i = 0; i < 16; ++i) er[i] = ei[i] = 0.0f;
   const unsigned lane_ot = h * NP + q;
   const GLOBAL u32x4* __restrict__ ot_k = offtab + (long)mb * 32;
-  const unsigned one2 = kBf16One | (kBf16One << 16);
   // tiles of the range; the tile slots of the lane's spot once per tile
   for (long b = b0; b < b1;) {
     const long t = b / kBlkPerTile;
@@ -715,19 +745,18 @@ __device__ __forceinline__ void forward_range(
     S[G - 1] = (ot_k + t * 2 * NP)[lane_ot];
     S[G - 1][2] |= m2;
     S[G - 1][3] |= m3;
-    const GLOBAL u32x4* __restrict__ px = pixtab + t * G * 2 * kTile;
-    const GLOBAL u32x4* __restrict__ pn = nf + t * kBlkPerTile * 64;
+    const rsrc_t rx = make_rsrc(pixtab + t * G * 2 * kTile,
+                                (unsigned long)G * 2 * kTile * 16);
+    const rsrc_t rn = make_rsrc(nf + t * kBlkPerTile * 64,
+                                (unsigned long)kBlkPerTile * 64 * 16);
+    const rsrc_t rm = make_rsrc(mag + t * kTile, (unsigned long)kTile * 4);
     for (int r = r0; r < r1; ++r) {
       u32x4 X[G];
 #pragma unroll
       for (int g = 0; g < G - 1; ++g)
-        X[g] = (px + g * 2 * kTile + r * 32)[lane_pix];
-      const u32x4 rec = (pn + r * 64)[lane_spot];
-      X[G - 1] = rec;
-      if (h) X[G - 1][0] = one2;
-      // the magnitude sits in half 1's record; give half 0 its copy
-      const float m = __uint_as_float(
-          __builtin_amdgcn_permlane32_swap(rec.x, rec.x, false, false)[1]);
+        X[g] = bload4(rx, off_pix, (unsigned)(g * 2 * kTile + r * 32) * 16u);
+      X[G - 1] = bload4(rn, off_spot, (unsigned)r * 64u * 16u);
+      const float m = bload1f(rm, off_q, (unsigned)r * 32u * 4u);
       const floatx16 th = phase_block<G>(S, X);
       accumulate<true, kReduce>(th, m, er, ei);
     }
@@ -747,8 +776,9 @@ __device__ __forceinline__ void forward_range(
 template <int G, bool kReduce>
 __global__ __launch_bounds__(kBlock) void k_forward(
     int N, long n_blk, int groups, const u32x4* __restrict__ pixtab,
-    const unsigned* __restrict__ nf_t, const u32x4* __restrict__ spotrec,
-    const unsigned* __restrict__ offtab, float2* __restrict__ partial) {
+    const unsigned* __restrict__ nf_t, const float* __restrict__ mag,
+    const u32x4* __restrict__ spotrec, const unsigned* __restrict__ offtab,
+    float2* __restrict__ partial) {
   const int n_mb = (N + 31) / 32;
   const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
   // the wave index is uniform over the wave; say so, so that the range
@@ -761,7 +791,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(
   forward_range<G, kReduce>(N, mb, n_blk * gi / groups,
                             n_blk * (gi + 1) / groups, as_global(pixtab),
                             as_global(reinterpret_cast<const u32x4*>(nf_t)),
-                            as_global(spotrec),
+                            as_global(mag), as_global(spotrec),
                             as_global(reinterpret_cast<const u32x4*>(offtab)),
                             partial + (long)gi * N);
 }
@@ -769,7 +799,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(
 template <int G>
 static hipError_t fwd_g(bool reduce, int n_mb, int groups, hipStream_t s,
                         int N, long n_blk, const unsigned short* pixtab,
-                        const unsigned* nf_t, const unsigned short* spotrec,
+                        const unsigned* nf_t, const float* mag,
+                        const unsigned short* spotrec,
                         const unsigned* offtab, float* partial) {
   // groups is a multiple of kXcds (plan_forward); waves per XCD:
   const long per_xcd = (long)(groups / kXcds) * n_mb;
@@ -777,7 +808,7 @@ static hipError_t fwd_g(bool reduce, int n_mb, int groups, hipStream_t s,
   auto* const kern = reduce ? k_forward<G, true> : k_forward<G, false>;
   hipLaunchKernelGGL(kern, dim3((unsigned)(blocks_per_xcd * kXcds)),
                      dim3(kBlock), 0, s, N, n_blk, groups,
-                     reinterpret_cast<const u32x4*>(pixtab), nf_t,
+                     reinterpret_cast<const u32x4*>(pixtab), nf_t, mag,
                      reinterpret_cast<const u32x4*>(spotrec), offtab,
                      reinterpret_cast<float2*>(partial));
   return hipGetLastError();
@@ -816,7 +847,7 @@ int forward_blocks_per_cu(int groups) {
 
 hipError_t launch_forward(const Geom& b, int N, const FwdPlan& p,
                           const unsigned short* pixtab, const unsigned* nf_t,
-                          const unsigned short* spotrec,
+                          const float* mag, const unsigned short* spotrec,
                           const unsigned* offtab, float* partial,
                           hipStream_t s) {
   const int n_mb = (N + 31) / 32;
@@ -825,7 +856,7 @@ hipError_t launch_forward(const Geom& b, int N, const FwdPlan& p,
 #define X(n)                                                            \
   case n:                                                               \
     return fwd_g<n>(b.reduce != 0, n_mb, p.groups, s, N, n_blk, pixtab, \
-                    nf_t, spotrec, offtab, partial);
+                    nf_t, mag, spotrec, offtab, partial);
     ASH_G_CASES(X)
 #undef X
     default:
@@ -938,7 +969,6 @@ __device__ __forceinline__ void moments_range(
     for (int i = 0; i < 16; ++i) are[rt][i] = aim[rt][i] = 0.0f;
   const unsigned lane_ot = h * NP + q;
   const GLOBAL u32x4* __restrict__ ot_k = offtab + (long)mb * 32;
-  const unsigned one2 = kBf16One | (kBf16One << 16);
   for (long b = b0; b < b1;) {
     const long t = b / kBlkPerTile;
     const int r0 = (int)(b - t * kBlkPerTile);
@@ -946,25 +976,30 @@ __device__ __forceinline__ void moments_range(
     S[G - 1] = (ot_k + t * 2 * NP)[lane_ot];
     S[G - 1][2] |= m2;
     S[G - 1][3] |= m3;
-    const GLOBAL u32x4* __restrict__ px = pixtab + t * G * 2 * kTile;
-    const GLOBAL u32x4* __restrict__ pn = nf + t * kBlkPerTile * 64;
+    const rsrc_t rx = make_rsrc(pixtab + t * G * 2 * kTile,
+                                (unsigned long)G * 2 * kTile * 16);
+    const rsrc_t rn = make_rsrc(nf + t * kBlkPerTile * 64,
+                                (unsigned long)kBlkPerTile * 64 * 16);
+    const rsrc_t rt_ = make_rsrc(momtab + t * kBlkPerTile * 4 * D2,
+                                 (unsigned long)kBlkPerTile * 4 * D2 * 16);
     for (int r = r0; r < r1; ++r) {
       u32x4 X[G];
 #pragma unroll
       for (int g = 0; g < G - 1; ++g)
-        X[g] = (px + g * 2 * kTile + r * 32)[lane_pix];
-      X[G - 1] = (pn + r * 64)[lane_spot];
-      if (h) X[G - 1][0] = one2;
-      const GLOBAL u32x4* __restrict__ mt =
-          momtab + (t * kBlkPerTile + r) * 4 * D2;
+        X[g] = bload4(rx, lane_pix * 16u,
+                      (unsigned)(g * 2 * kTile + r * 32) * 16u);
+      X[G - 1] = bload4(rn, lane_spot * 16u, (unsigned)r * 64u * 16u);
+      // moment rows 32 rt + q of this lane; rows past 2D are zero
       u32x4 A[RT][2];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
           const int row = 32 * rt + q;
-          A[rt][kb] = row < D2 ? mt[(kb * 2 + h) * D2 + row]
-                               : u32x4{0u, 0u, 0u, 0u};
+          A[rt][kb] = row < D2
+                          ? bload4(rt_, (unsigned)((kb * 2 + h) * D2 + row) * 16u,
+                                   (unsigned)r * 4u * D2 * 16u)
+                          : u32x4{0u, 0u, 0u, 0u};
         }
       const floatx16 th = phase_block<G>(X, S);
       u32x4 ch[2], cl[2], sh[2], sl[2];
@@ -1525,26 +1560,28 @@ __device__ __forceinline__ void adjoint_row(
   const unsigned lane_ot = h * NP + q;
   // per spot block: the lane's spot record, groups 0..G-2 from the record
   // and the last group from the per-tile slots, with the spot-field phase
-  // (p 4..6) OR-ed in by half 0, which also loads the spot's magnitude and
-  // passes it to half 1 with a lane-half swap.  Spot tables are padded to
+  // (p 4..6) OR-ed in from half 0's spot-field entry (half 1's entry has
+  // zeros there); both carry the magnitude.  Spot tables are padded to
   // whole blocks with zero records.
   const GLOBAL u32x4* __restrict__ ot_t = offtab + (long)tile * 2 * NP;
   float gr[16], gi[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) gr[i] = gi[i] = 0.0f;
+  const unsigned off_spot = lane_spot * 16u, off_ot = lane_ot * 16u;
+  const rsrc_t rs = make_rsrc(spotrec, (unsigned long)NB * G * 64 * 16);
+  const rsrc_t ro = make_rsrc(ot_t, (unsigned long)2 * NP * 16);
+  const rsrc_t ry = make_rsrc(yrec, (unsigned long)NB * 64 * 16);
   for (int nb = 0; nb < NB; ++nb) {
     u32x4 S[G];
-    const GLOBAL u32x4* __restrict__ sb = spotrec + (long)nb * G * 64;
 #pragma unroll
-    for (int gg = 0; gg < G - 1; ++gg) S[gg] = sb[lane_spot + gg * 64];
-    u32x4 last = (ot_t + nb * 32)[lane_ot];
-    u32x4 yv = u32x4{0u, 0u, 0u, 0u};
-    if (!h) yv = (yrec + nb * 32)[q];
+    for (int gg = 0; gg < G - 1; ++gg)
+      S[gg] = bload4(rs, off_spot, (unsigned)(nb * G + gg) * 64u * 16u);
+    u32x4 last = bload4(ro, off_ot, (unsigned)nb * 32u * 16u);
+    const u32x4 yv = bload4(ry, off_spot, (unsigned)nb * 64u * 16u);
     last[2] |= yv[0];
     last[3] |= yv[1];
     S[G - 1] = last;
-    const float m = __uint_as_float(
-        __builtin_amdgcn_permlane32_swap(yv[2], yv[2], false, false)[0]);
+    const float m = __uint_as_float(yv[2]);
     const floatx16 th = phase_block<G>(X, S);
     accumulate<false, kReduce>(th, m, gr, gi);
   }
@@ -1687,7 +1724,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(
     const long b1 = min(b0 + d.L, d.n_blk);
     forward_range<G, kReduce>(
         d.N, it.z, b0, b1, as_global(d.pixtab),
-        as_global(reinterpret_cast<const u32x4*>(d.nf_t)), as_global(d.spotrec),
+        as_global(reinterpret_cast<const u32x4*>(d.nf_t)), as_global(d.amp_t),
+        as_global(d.spotrec),
         as_global(reinterpret_cast<const u32x4*>(d.offtab)),
         d.partial + (long)it.y * d.N);
   });
