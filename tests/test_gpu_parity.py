@@ -256,3 +256,65 @@ def test_wgs_full_run_figures(A):
     assert abs(st[-1, 0] - stats_ref[-1, 0]) < 1e-3
     assert abs(st[-1, 1] - stats_ref[-1, 1]) < 1e-3
     c.close()
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["auto", "full"])
+def test_largest_basis(A, full):
+    """The largest supported basis: 31 modes (ANSI 0-30, radial order 7),
+    28 of them non-linear, the longest record (12 matrix-core groups with 3
+    pieces)."""
+    nx, ny, N, modes = 128, 96, 40, list(range(31))
+    rng = np.random.default_rng(31)
+    geom = oracle.Geometry(nx, ny)
+    basis = oracle.ZernikeBasis(modes)
+    w = _spots(rng, nx, ny, N, modes, 0.05, geom.R)
+    amp = rng.uniform(0.2, 1.0, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    c = A.Context(0)
+    c.set_precision(full)
+    c.set_basis(nx, ny, modes=modes,
+                amp=torch.tensor(amp, dtype=torch.float32, device="cuda"))
+    c.set_spots(w)
+    info = c.info()
+    _say("  info", info)
+    assert info["nonlinear"] == 28
+    if full:
+        assert info["groups"] == 12
+    E = c.forward(phase=_cuda(phi, torch.float32)).cpu().numpy()
+    Eref = oracle.forward(amp * np.exp(1j * phi), w, basis, geom)
+    _say("  forward", field_errors(E, Eref))
+    assert_fields(E, Eref, what="forward, 31 modes")
+    y = (rng.normal(size=N) + 1j * rng.normal(size=N)).astype(np.complex64)
+    g = c.adjoint(_cuda(y, torch.complex64)).cpu().numpy()
+    gref = oracle.adjoint(y.astype(np.complex128), w, basis, geom)
+    _say("  adjoint", field_errors(g, gref))
+    assert_fields(g, gref, what="adjoint, 31 modes")
+    M = c.forward_moments(_cuda(phi, torch.float32)).cpu().numpy()
+    Mref = oracle.forward_moments(amp * np.exp(1j * phi), w, basis, geom)
+    for d in range(len(modes)):
+        assert_fields(M[:, d], Mref[:, d], what="moments, mode %d" % d)
+    c.close()
+
+
+def test_many_spots_small_slm(A):
+    """100 000 spots on a 64 x 48 SLM (more spots than pixels): sampled
+    spots of the forward and all pixels of the adjoint."""
+    nx, ny, N, modes = 64, 48, 100000, [1, 2, 3, 4, 5, 7]
+    rng = np.random.default_rng(100)
+    geom = oracle.Geometry(nx, ny)
+    basis = oracle.ZernikeBasis(modes)
+    w = _spots(rng, nx, ny, N, modes, 0.5, geom.R)
+    amp = rng.uniform(0.2, 1.0, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    c = _ctx(A, nx, ny, modes, w, amp=amp)
+    E = c.forward(phase=_cuda(phi, torch.float32)).cpu().numpy()
+    sel = np.sort(rng.choice(N, size=512, replace=False))
+    Eref = oracle.forward(amp * np.exp(1j * phi), w, basis, geom, spots=sel)
+    _say("  forward", field_errors(E[sel], Eref))
+    assert_fields(E[sel], Eref, what="forward, 1e5 spots")
+    y = (rng.normal(size=N) + 1j * rng.normal(size=N)).astype(np.complex64)
+    g = c.adjoint(_cuda(y, torch.complex64)).cpu().numpy()
+    gref = oracle.adjoint(y.astype(np.complex128), w, basis, geom)
+    _say("  adjoint", field_errors(g, gref))
+    assert_fields(g, gref, what="adjoint, 1e5 spots")
+    c.close()
