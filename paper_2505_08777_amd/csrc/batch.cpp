@@ -125,7 +125,7 @@ hipError_t btimed(ash_batch* b, int cat, F&& launch) {
     if (!b->pool.empty()) {
       e = b->pool.back();
       b->pool.pop_back();
-    } else if (hipEventCreate(&e) != hipSuccess) {
+    } else if (hipEventCreateWithFlags(&e, kProfEventFlags) != hipSuccess) {
       (void)hipGetLastError();
       e = nullptr;
     }

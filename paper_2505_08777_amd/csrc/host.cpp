@@ -64,7 +64,7 @@ hipEvent_t prof_event(ash_ctx* c) {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) {
+  if (hipEventCreateWithFlags(&e, kProfEventFlags) != hipSuccess) {
     (void)hipGetLastError();
     return nullptr;
   }

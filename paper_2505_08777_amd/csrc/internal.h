@@ -98,6 +98,11 @@ struct Buffers {
 // stored (store), or the stored phases (fixed).
 enum : int { kPhaseFree = 0, kPhaseStore = 1, kPhaseFixed = 2 };
 
+// Timing events: read only after a stream synchronisation, so they need no
+// system-scope fence (which writes back and invalidates caches at every
+// record and slows the work between them).
+constexpr unsigned kProfEventFlags = hipEventDisableSystemFence;
+
 struct FwdPlan {
   int groups = 0;  // pixel-block ranges (forward partial rows)
   int slices = 0;  // second-level reduction rows
