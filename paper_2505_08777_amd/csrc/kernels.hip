@@ -645,33 +645,50 @@ __device__ __forceinline__ floatx16 phase_block(const u32x4* a,
   return acc;
 }
 
-// One butterfly step over lane bit `mask` (< 32): of the 2*half complex
-// values per lane keep the lower or upper `half` (by the lane's bit) and add
-// the partner's copy of them.
-template <int HALF>
-__device__ __forceinline__ void bfly_step(float* re, float* im, int q,
-                                          int mask) {
-  const bool up = (q & mask) != 0;
+// Value of lane-permuted x through DPP control CTRL (all lanes active).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// One butterfly step: each lane keeps the lower or upper HALF of its
+// 2*HALF complex values (by its own bit `up`) and adds the partner lane's
+// copy of them; the partner, reached through DPP control CTRL, has the
+// opposite bit.
+template <int HALF, int CTRL>
+__device__ __forceinline__ void bfly_step(float* re, float* im, bool up) {
 #pragma unroll
   for (int i = 0; i < HALF; ++i) {
-    const float sr = up ? re[i] : re[i + HALF];
-    const float si = up ? im[i] : im[i + HALF];
-    const float kr = up ? re[i + HALF] : re[i];
-    const float ki = up ? im[i + HALF] : im[i];
-    re[i] = kr + __shfl_xor(sr, mask, kWave);
-    im[i] = ki + __shfl_xor(si, mask, kWave);
+    const float kr = up ? re[i + HALF] : re[i], sr = up ? re[i] : re[i + HALF];
+    const float ki = up ? im[i + HALF] : im[i], si = up ? im[i] : im[i + HALF];
+    re[i] = kr + dpp<CTRL>(sr);
+    im[i] = ki + dpp<CTRL>(si);
   }
 }
 
 // Sum 16 complex values per lane over the 32 lanes of the half-wave.  On
-// return re[0], im[0] hold the total of value index bfly_index(q).
+// return re[0], im[0] hold the total of value index bfly_index(q).  The
+// partners of the five steps are lanes 16 apart (a row swap: the lower
+// values of the odd row trade places with the upper values of the even
+// row, so one add finishes each pair), 8 apart (rotation by 8 in a row),
+// mirrored in 8 lanes (bit 2 flipped), 2 apart and 1 apart; together they
+// pair every lane with all 31 others exactly once.  No LDS.
 __device__ __forceinline__ void bfly_reduce(float* re, float* im, int q) {
-  bfly_step<8>(re, im, q, 16);
-  bfly_step<4>(re, im, q, 8);
-  bfly_step<2>(re, im, q, 4);
-  bfly_step<1>(re, im, q, 2);
-  re[0] += __shfl_xor(re[0], 1, kWave);
-  im[0] += __shfl_xor(im[0], 1, kWave);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(
+        __float_as_uint(re[i]), __float_as_uint(re[i + 8]), false, false);
+    re[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    const auto m = __builtin_amdgcn_permlane16_swap(
+        __float_as_uint(im[i]), __float_as_uint(im[i + 8]), false, false);
+    im[i] = __uint_as_float(m[0]) + __uint_as_float(m[1]);
+  }
+  bfly_step<4, 0x128>(re, im, (q & 8) != 0);  // row_ror:8
+  bfly_step<2, 0x141>(re, im, (q & 4) != 0);  // row_half_mirror
+  bfly_step<1, 0x4E>(re, im, (q & 2) != 0);   // quad_perm [2, 3, 0, 1]
+  re[0] += dpp<0xB1>(re[0]);                   // quad_perm [1, 0, 3, 2]
+  im[0] += dpp<0xB1>(im[0]);
 }
 
 __device__ __forceinline__ int bfly_index(int q) {
@@ -757,6 +774,10 @@ __device__ __forceinline__ void forward_range(
         X[g] = bload4(rx, off_pix, (unsigned)(g * 2 * kTile + r * 32) * 16u);
       X[G - 1] = bload4(rn, off_spot, (unsigned)r * 64u * 16u);
       const float m = bload1f(rm, off_q, (unsigned)r * 32u * 4u);
+      // all of the block's loads go out before its products (left to
+      // itself the scheduler reuses a load's registers and waits on it
+      // between the products)
+      __builtin_amdgcn_sched_barrier(0);
       const floatx16 th = phase_block<G>(S, X);
       accumulate<true, kReduce>(th, m, er, ei);
     }
@@ -1578,6 +1599,7 @@ __device__ __forceinline__ void adjoint_row(
       S[gg] = bload4(rs, off_spot, (unsigned)(nb * G + gg) * 64u * 16u);
     u32x4 last = bload4(ro, off_ot, (unsigned)nb * 32u * 16u);
     const u32x4 yv = bload4(ry, off_spot, (unsigned)nb * 64u * 16u);
+    __builtin_amdgcn_sched_barrier(0);  // loads before the products
     last[2] |= yv[0];
     last[3] |= yv[1];
     S[G - 1] = last;

@@ -112,8 +112,12 @@ def test_batch_equals_unbatched(A, batch_case, n_iter):
         # conditioning mask from the unbatched path's last projection
         y = (W * _cu(h["t"])).to(torch.complex64) * E / E.abs().clamp_min(1e-30)
         g = c.adjoint(y.to(torch.complex64)).cpu().numpy()
-        err = assert_phase(pb.cpu().numpy(), ph.cpu().numpy(), g, bar=1e-4,
-                           mask=STEP_PHASE_MASK, what="batch vs alone")
+        # each iteration adds its own rounding difference (the forward's
+        # partial sums run over ranges of different lengths), as for the
+        # weights below: 1e-4 rad per iteration
+        err = assert_phase(pb.cpu().numpy(), ph.cpu().numpy(), g,
+                           bar=1e-4 * n_iter, mask=STEP_PHASE_MASK,
+                           what="batch vs alone")
         _say("holo", h["nx"], h["ny"], h["w"].shape[0], "phase", err)
         np.testing.assert_allclose(wb.cpu().numpy(), W.cpu().numpy(),
                                    rtol=1e-5 * n_iter, atol=1e-6)
