@@ -1893,11 +1893,15 @@ FwdPlan plan_forward(int n_tiles, int N, int blocks_per_cu, int n_cu) {
   // About four rounds of resident waves, each wave a range of pixel
   // blocks: with several rounds the waves of a SIMD start at different
   // times, so their matrix-core and vector phases interleave (one round of
-  // long waves runs in lockstep and measured 15-20 % slower).  Ranges of at
-  // least 32 blocks keep the partial sums small.
+  // long waves runs in lockstep and measured 15-20 % slower).  Long ranges
+  // keep the partial sums small.
   const long waves = (long)blocks_per_cu * (kBlock / kWave) * n_cu;
   long want = 4 * waves / n_mb;
-  if (want > n_blk / 32) want = n_blk / 32;
+  // ranges of at least 32 blocks, or of down to 8 where fewer spots would
+  // otherwise leave resident slots idle
+  long cap = waves / n_mb < n_blk / 8 ? waves / n_mb : n_blk / 8;
+  if (cap < n_blk / 32) cap = n_blk / 32;
+  if (want > cap) want = cap;
   want = want / kXcds * kXcds;     // whole rounds over the XCDs
   if (want < kXcds) want = kXcds;  // (empty ranges give zeros)
   p.groups = (int)want;
