@@ -248,6 +248,17 @@ int ash_wgs_feedback(ash_ctx* ctx, float* phase_dev, float* weights_dev,
                      const float* measured_dev, const ash_wgs_params* params,
                      float* E_dev, float* stats_dev);
 
+/* The farfield phases stored by phase fixing, in turns (arg E / 2 pi, in
+ * [-1/2, 1/2]), copied verbatim so that a phase-fixed run can be
+ * checkpointed and resumed bitwise in a context with the same spots:
+ *   ash_get_fixed_phases copies them to psi_dev (device [N] float32);
+ *   ASH_ENOTREADY if none are stored.
+ *   ash_set_fixed_phases stores psi_dev (device [N] float32) as if an
+ *   iteration had stored them.
+ * Errors: ASH_EINVAL, ASH_ENOTREADY, ASH_EHIP. */
+int ash_get_fixed_phases(ash_ctx* ctx, float* psi_dev);
+int ash_set_fixed_phases(ash_ctx* ctx, const float* psi_dev);
+
 /* Phase gradient of a real loss of the spot fields (the backward of
  * ash_forward with respect to the phase):
  *   grad(x) = Im( conj(f(x)) * sum_n G_n exp(+i theta_n(x)) ),

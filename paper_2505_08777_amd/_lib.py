@@ -87,6 +87,8 @@ def _load():
         "ash_adjoint": (I, [P, P, P, P]),
         "ash_wgs_iterate": (I, [P, P, P, I, ctypes.POINTER(WgsParams), P, P]),
         "ash_wgs_feedback": (I, [P, P, P, P, ctypes.POINTER(WgsParams), P, P]),
+        "ash_get_fixed_phases": (I, [P, P]),
+        "ash_set_fixed_phases": (I, [P, P]),
         "ash_set_precision": (I, [P, I]),
         "ash_get_info": (I, [P, ctypes.POINTER(Info)]),
         "ash_profile_enable": (I, [P, I]),

@@ -210,6 +210,24 @@ class Context:
             st = st[:n_iter]
         return phase, weights, E, st
 
+    def fixed_phases(self, out=None):
+        """The stored farfield phases (turns), for checkpoints."""
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float32,
+                              device="cuda:%d" % self.device)
+        _dev(out, torch.float32, (self.N,), "out", self.device)
+        self._stream()
+        check(lib.ash_get_fixed_phases(self._h, _ptr(out)),
+              "ash_get_fixed_phases", self._h)
+        return out
+
+    def set_fixed_phases(self, psi):
+        """Restore stored farfield phases (turns) from a checkpoint."""
+        _dev(psi, torch.float32, (self.N,), "psi", self.device)
+        self._stream()
+        check(lib.ash_set_fixed_phases(self._h, _ptr(psi)),
+              "ash_set_fixed_phases", self._h)
+
     def wgs_feedback(self, phase, measured, weights=None, power=1.0,
                      fix_phase_after=0, want_E=True, want_stats=True):
         """One weighted-GS iteration whose weights follow the measured spot

@@ -883,6 +883,34 @@ int ash_wgs_iterate(ash_ctx* c, float* phase_dev, float* weights_dev,
                   nullptr);
 }
 
+int ash_get_fixed_phases(ash_ctx* c, float* psi_dev) {
+  if (!c) return ASH_EINVAL;
+  c->err.clear();
+  if (!psi_dev) return fail(c, ASH_EINVAL, "psi required");
+  if (!c->has_spots || !c->has_fixed)
+    return fail(c, ASH_ENOTREADY, "no stored farfield phases");
+  int rc = use_device(c);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(psi_dev, c->buf.fixph, c->spots.N * sizeof(float),
+                           hipMemcpyDeviceToDevice, c->stream),
+         "copying phases");
+  return ASH_OK;
+}
+
+int ash_set_fixed_phases(ash_ctx* c, const float* psi_dev) {
+  if (!c) return ASH_EINVAL;
+  c->err.clear();
+  if (!psi_dev) return fail(c, ASH_EINVAL, "psi required");
+  if (!c->has_spots) return fail(c, ASH_ENOTREADY, "spots must be set");
+  int rc = use_device(c);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->buf.fixph, psi_dev, c->spots.N * sizeof(float),
+                           hipMemcpyDeviceToDevice, c->stream),
+         "copying phases");
+  c->has_fixed = true;
+  return ASH_OK;
+}
+
 int ash_wgs_feedback(ash_ctx* c, float* phase_dev, float* weights_dev,
                      const float* measured_dev, const ash_wgs_params* params,
                      float* E_dev, float* stats_dev) {

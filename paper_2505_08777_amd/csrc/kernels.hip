@@ -150,6 +150,15 @@ __device__ inline void split3f(float v, unsigned* p) {
 __host__ __device__ inline long nf_index(long tile, int pix, int half) {
   return ((tile * kBlkPerTile + pix / 32) * 2 + half) * 32 + pix % 32;
 }
+// Phase (radians) to turns in [-1/2, 1/2]: a rounded multiply that is
+// never fused into a later operation, then the nearest whole turn removed,
+// so that every path writing a nearfield record from a phase (input phase,
+// WGS projection, Adam update) writes the same bits for the same phase.
+__device__ __forceinline__ float rad_to_turns(float rad) {
+  const float t = __fmul_rn(rad, kInv2Pi);
+  return t - rintf(t);
+}
+
 // Record of a pixel from its table nonlinear words and phase (turns).
 __device__ inline u32x4 nearfield_record(u32x2 nl, float turns) {
   unsigned p[3];
@@ -567,12 +576,11 @@ __global__ void k_make_field(Geom b, long total,
     const long p = (long)j * b.nx + i;
     if (phase) {
       mag = amp_t[gid];
-      turns = phase[p] * kInv2Pi;
-      turns -= rintf(turns);  // any phase: reduce to [-1/2, 1/2]
+      turns = rad_to_turns(phase[p]);  // any phase: reduced to [-1/2, 1/2]
     } else {
       const float2 f = field[p];
       mag = hypotf(f.x, f.y);
-      turns = atan2f(f.y, f.x) * kInv2Pi;
+      turns = rad_to_turns(atan2f(f.y, f.x));
     }
   }
   nf[nf_index(tile, pix, 0)] = nearfield_record(
@@ -1492,8 +1500,7 @@ __global__ void k_adam(Geom b, long total, float* __restrict__ phase,
   v[p] = vk;
   const float ph = phase[p] - lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
   phase[p] = ph;
-  float turns = ph * kInv2Pi;
-  turns -= rintf(turns);
+  const float turns = rad_to_turns(ph);
   // next nearfield record; the magnitudes stay
   nf_rec[nf_index(tile, pix, 0)] = nearfield_record(
       pixel_nl_words(pixtab, b.groups, tile, pix), turns);
@@ -1622,7 +1629,7 @@ __device__ __forceinline__ void adjoint_row(
       reinterpret_cast<u32x4*>(o.nf_t)[nf_index(tile, pix, 0)] =
           nearfield_record(
               pixel_nl_words((const u32x4*)pixtab, G, tile, pix),
-              ang * kInv2Pi);
+              rad_to_turns(ang));
     if (inside && (o.outs & kOutPhase)) o.phase[p] = ang;
   }
   if (inside && (o.outs & kOutG))

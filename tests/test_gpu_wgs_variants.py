@@ -130,3 +130,38 @@ def test_feedback_step_matches_oracle(A):
                                               what="feedback step %d" % it))
         np.testing.assert_allclose(st.cpu().numpy(), ref_st, rtol=1e-3, atol=1e-3)
     c.close()
+
+
+def test_resume_is_bitwise(A):
+    """Checkpoint and resume: 8 iterations in one call equal 3 + 5 in two
+    calls, and a phase-fixed run resumed in a fresh context from (phase,
+    weights, stored farfield phases) equals the uninterrupted run, bitwise
+    (the reductions have a fixed order)."""
+    d, geom, basis, amp, phi0, c = _setup(A)
+    N = d["w"].shape[0]
+    a = _cuda(phi0)
+    Wa = _cuda(np.ones(N))
+    c.wgs(a, 8, weights=Wa)
+    b = _cuda(phi0)
+    Wb = _cuda(np.ones(N))
+    c.wgs(b, 3, weights=Wb)
+    c.wgs(b, 5, weights=Wb)
+    assert torch.equal(a, b) and torch.equal(Wa, Wb)
+    # phase fixed after 3 iterations, 8 in all
+    p1 = _cuda(phi0)
+    W1 = _cuda(np.ones(N))
+    c.wgs(p1, 8, weights=W1, fix_phase_after=3)
+    p2 = _cuda(phi0)
+    W2 = _cuda(np.ones(N))
+    c.wgs(p2, 4, weights=W2, fix_phase_after=3)
+    psi = c.fixed_phases().clone()           # checkpoint
+    c2 = A.Context(0)
+    c2.set_basis(d["nx"], d["ny"], modes=d["modes"],
+                 amp=torch.tensor(d["amp"], dtype=torch.float32, device="cuda"))
+    c2.set_spots(d["w"], d["t"])
+    c2.set_fixed_phases(psi)                  # resume elsewhere
+    c2.wgs(p2, 4, weights=W2, fix_phase_after=-1)
+    assert torch.equal(p1, p2) and torch.equal(W1, W2)
+    assert torch.equal(c2.fixed_phases(), c.fixed_phases())
+    c2.close()
+    c.close()
