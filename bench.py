@@ -648,8 +648,9 @@ def main():
         calibrate_copy(args.calibrate_copy_mib)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(each GPU would run its own pixel slab; see DESIGN.md)",
+        print("bench.py measures one GPU; there is no multi-GPU path "
+              "(each GPU would run its own slab of pixel rows with the "
+              "full spot table and one small all-reduce of E per iteration)",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
