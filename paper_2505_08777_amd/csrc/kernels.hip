@@ -1305,6 +1305,36 @@ struct OpMin {
   __device__ float operator()(float a, float b) const { return fminf(a, b); }
 };
 
+// Several block reductions in one LDS pass (sh: NV floats per wave): value
+// i is combined with Op_i, in the order of block_reduce.
+template <typename Op0, typename Op1, typename Op2, typename Op3>
+__device__ void block_reduce4(float* v, float* sh) {
+  constexpr int NV = 4;
+  const Op0 o0;
+  const Op1 o1;
+  const Op2 o2;
+  const Op3 o3;
+  auto op = [&](int i, float a, float b) {
+    return i == 0 ? o0(a, b) : i == 1 ? o1(a, b) : i == 2 ? o2(a, b) : o3(a, b);
+  };
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) v[i] = op(i, v[i], __shfl_xor(v[i], w, kWave));
+  const int nw = blockDim.x / kWave, wave = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sh[i * nw + wave] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    float r = sh[i * nw];
+    for (int j = 1; j < nw; ++j) r = op(i, r, sh[i * nw + j]);
+    v[i] = r;
+  }
+  __syncthreads();
+}
+
 // The weighted-GS farfield update of one hologram by one block (sh: one
 // float of LDS per wave).
 // meas: amplitudes that replace |E_k| in the weight update (experimental
@@ -1319,12 +1349,20 @@ __device__ __forceinline__ void wgs_update_block(
     float* __restrict__ stats, float* sh, const float* __restrict__ meas,
     float* __restrict__ fixph, int phase_mode) {
   const int tid = threadIdx.x;
+  // with at most one spot per thread the spot's field and weight stay in
+  // registers between the passes
+  const bool one = N <= (int)blockDim.x;
+  float2 e1 = make_float2(0.0f, 0.0f);
+  float w1 = 0.0f;
   // pass 1: fields, |E|^2 and normalised intensities I = |E|^2 / t^2, and
   // the norm of the amplitudes that drive the weights
   float s_a2 = 0.0f, s_I = 0.0f, mx = 0.0f, mn = INFINITY, s_m2 = 0.0f;
   for (int k = tid; k < N; k += blockDim.x) {
     const float2 e = sum_slices(red, slices, N, k);
-    Ebuf[k] = e;
+    if (one)
+      e1 = e;
+    else
+      Ebuf[k] = e;
     if (E_extra) E_extra[k] = e;
     const float a2 = e.x * e.x + e.y * e.y;
     const float I = a2 / (t[k] * t[k]);
@@ -1337,17 +1375,16 @@ __device__ __forceinline__ void wgs_update_block(
       s_m2 += m * m;
     }
   }
-  const float sum_a2 = block_reduce(s_a2, sh, OpSum());
-  const float sum_I = block_reduce(s_I, sh, OpSum());
-  const float maxI = block_reduce(mx, sh, OpMax());
-  const float minI = block_reduce(mn, sh, OpMin());
+  float r1[4] = {s_a2, s_I, mx, mn};
+  block_reduce4<OpSum, OpSum, OpMax, OpMin>(r1, sh);
+  const float sum_a2 = r1[0], sum_I = r1[1], maxI = r1[2], minI = r1[3];
   const float norm_a =
       sqrtf(meas ? block_reduce(s_m2, sh, OpSum()) : sum_a2);
   const float meanI = sum_I / (float)N;
   // pass 2: spread of I, unnormalised weight update
   float s_v = 0.0f, s_w = 0.0f;
   for (int k = tid; k < N; k += blockDim.x) {
-    const float2 e = Ebuf[k];
+    const float2 e = one ? e1 : Ebuf[k];
     const float a2 = e.x * e.x + e.y * e.y;
     const float dI = a2 / (t[k] * t[k]) - meanI;
     s_v += dI * dI;
@@ -1357,22 +1394,27 @@ __device__ __forceinline__ void wgs_update_block(
       const float r = (a / norm_a) / (t[k] / t_norm);
       wk = (power == 1.0f) ? wk / r : wk * powf(r, -power);
     }
-    W[k] = wk;
+    if (one)
+      w1 = wk;
+    else
+      W[k] = wk;
     s_w += wk;
   }
-  const float var = block_reduce(s_v, sh, OpSum()) / (float)N;
-  const float mean_w = block_reduce(s_w, sh, OpSum()) / (float)N;
+  float r2[4] = {s_v, s_w, 0.0f, 0.0f};
+  block_reduce4<OpSum, OpSum, OpSum, OpSum>(r2, sh);
+  const float var = r2[0] / (float)N;
+  const float mean_w = r2[1] / (float)N;
   // pass 3: normalise weights, farfield projection y = W t exp(i psi) with
   // psi = arg E (arg 0 = 0) or the stored phase, in polar form (W t,
   // psi / 2 pi in pieces)
   for (int k = tid; k < N; k += blockDim.x) {
-    const float wk = W[k] / mean_w;
+    const float wk = (one ? w1 : W[k]) / mean_w;
     W[k] = wk;
     float turns;
     if (phase_mode == kPhaseFixed) {
       turns = fixph[k];
     } else {
-      const float2 e = Ebuf[k];
+      const float2 e = one ? e1 : Ebuf[k];
       turns = atan2f(e.y, e.x) * kInv2Pi;
       if (phase_mode == kPhaseStore) fixph[k] = turns;
     }
@@ -1394,7 +1436,7 @@ __global__ __launch_bounds__(kUpd) void k_wgs_update(
     float2* __restrict__ Ebuf, float2* __restrict__ E_extra,
     float* __restrict__ stats, const float* __restrict__ meas,
     float* __restrict__ fixph, int phase_mode) {
-  __shared__ float sh[kUpd / kWave];
+  __shared__ float sh[4 * kUpd / kWave];
   wgs_update_block(N, slices, red, t, t_norm, W, power, eff_denom, ypol, Ebuf,
                    E_extra, stats, sh, meas, fixph, phase_mode);
 }
@@ -1799,7 +1841,7 @@ __global__ __launch_bounds__(64) void k_batch_reduce(
 
 __global__ __launch_bounds__(kUpd) void k_batch_update(
     const HoloDesc* __restrict__ hd, float power) {
-  __shared__ float sh[kUpd / kWave];
+  __shared__ float sh[4 * kUpd / kWave];
   const HoloDesc& d = hd[blockIdx.x];
   wgs_update_block(d.N, d.slices, d.red, d.target, d.t_norm, d.W, power,
                    d.eff_denom, d.ypol, d.Ebuf, nullptr, nullptr, sh, nullptr,
