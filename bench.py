@@ -110,6 +110,14 @@ def parse():
     ap.add_argument("--iters", type=int, default=None,
                     help="WGS iterations per step (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the WGS step captured once in a HIP graph "
+                         "and replayed (default for plain256, whose loop is "
+                         "launch-bound)")
+    ap.add_argument("--event-stride", type=int, default=8,
+                    help="WGS workloads: bracket one transform launch in "
+                         "every this many with HIP events (each event pair "
+                         "costs stream time)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many "
                          "MiB (for scaling HBM byte counters), then exit")
@@ -206,6 +214,36 @@ def coef_issue_ceiling(groups):
     16-pixel K blocks) per 32 x 32 block."""
     c = 32 * ISSUE_CYCLES["trans"] + (groups + 8) * ISSUE_CYCLES["mfma"]
     return SIMDS * CLOCK_HZ * 1024 / c
+
+
+def graph_replay(ctx, d, n_iter, steps):
+    """The WGS step captured in a HIP graph (through torch's capture on the
+    library's stream) and replayed `steps` times: the loop without host
+    launch costs.  No compute call of the library allocates, synchronises
+    or records a memset, so the step can be captured as it is."""
+    import torch
+    dev = torch.device("cuda:0")
+    N = d["w"].shape[0]
+    ph = torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
+    W = torch.ones(N, dtype=torch.float32, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ctx.wgs(ph, n_iter, weights=W, want_E=False, want_stats=False)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ctx.wgs(ph, n_iter, weights=W, want_E=False, want_stats=False)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    return {"wgs_iters_per_s": n_iter * steps / T,
+            "ms_per_step": 1e3 * T / steps,
+            "evals_per_s": 2.0 * N * d["nx"] * d["ny"] * n_iter * steps / T}
 
 
 def bench_coef(args, d):
@@ -521,7 +559,8 @@ def bench_adam(args, d):
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
-    ctx.profile(True, categories=("forward", "adjoint"))
+    ctx.profile(True, categories=("forward", "adjoint"),
+                stride=args.event_stride)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -556,6 +595,7 @@ def bench_adam(args, d):
                     for k, v in prof.items()},
         "issue_model": issue_model(N * P / (ms_avg * 1e-3), info["groups"]),
         "loss_first_last": [float(L[0]), float(L[-1])],
+        "event_stride": args.event_stride,
         "layout": info,
     }
     if not args.no_cpu_baseline:
@@ -706,8 +746,10 @@ def main():
         ctx.wgs(phase, n_iter, weights=weights, want_E=False, want_stats=False)
     torch.cuda.synchronize()
 
-    # timed region: K steps, the transform kernels bracketed by HIP events
-    ctx.profile(True, categories=("forward", "adjoint"))
+    # timed region: K steps, one transform launch in every event_stride
+    # bracketed by HIP events
+    ctx.profile(True, categories=("forward", "adjoint"),
+                stride=args.event_stride)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -755,10 +797,13 @@ def main():
         "wgs_iters_per_s": n_iter * args.steps / T,
         "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
         "ms_per_step_without_events": 1e3 * (t3 - t2) / args.steps,
+        "event_stride": args.event_stride,
         "roofline": roofline,
         "issue_model": issue_model(N * P / (ms_avg * 1e-3), info["groups"]),
         "kernels": kernels, "layout": info,
     }
+    if args.graph or args.workload == "plain256":
+        out["graph_replay"] = graph_replay(ctx, d, n_iter, args.steps)
     if principal is not None:
         out["config"].update(modes=principal["modes_in"],
                              principal_modes=principal["K"],

@@ -471,6 +471,13 @@ int ash_batch_profile_read(ash_batch* batch, double* ms_out,
 int ash_profile_enable(ash_ctx* ctx, int mask);
 int ash_profile_read(ash_ctx* ctx, double* ms_out, int64_t* launches_out);
 
+/* Time one launch in every `stride` (>= 1, default 1) of each selected
+ * category, counted from the last ash_profile_enable: each event pair
+ * costs stream time, and for short kernels a sample measures their
+ * average duration with little of that cost.  launches_out then counts
+ * the timed launches.  Errors: ASH_EINVAL (stride < 1). */
+int ash_profile_stride(ash_ctx* ctx, int stride);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,6 +93,7 @@ def _load():
         "ash_get_info": (I, [P, ctypes.POINTER(Info)]),
         "ash_profile_enable": (I, [P, I]),
         "ash_profile_read": (I, [P, P, P]),
+        "ash_profile_stride": (I, [P, I]),
         "ash_phase_grad": (I, [P, P, P, P]),
         "ash_forward_moments": (I, [P, P, P]),
         "ash_coef_grad": (I, [P, P, P, P]),

@@ -72,9 +72,12 @@ class Context:
 
     PROFILE_CATEGORIES = ("forward", "adjoint", "reduce", "field")
 
-    def profile(self, enable=True, categories=None):
+    def profile(self, enable=True, categories=None, stride=1):
         """Bracket the kernels of the given categories (default all) with
-        HIP events; see profile_read."""
+        HIP events, one launch in every `stride` of each category; see
+        profile_read."""
+        check(lib.ash_profile_stride(self._h, int(stride)),
+              "ash_profile_stride", self._h)
         mask = 0
         if enable:
             cats = self.PROFILE_CATEGORIES if categories is None else categories

@@ -75,6 +75,7 @@ hipEvent_t prof_event(ash_ctx* c) {
 template <typename F>
 hipError_t timed(ash_ctx* c, int cat, F&& launch) {
   if (!(c->prof_mask & (1 << cat))) return launch();
+  if (c->prof_seen[cat]++ % c->prof_stride != 0) return launch();
   hipEvent_t a = prof_event(c), b = prof_event(c);
   if (a) (void)hipEventRecord(a, c->stream);
   hipError_t e = launch();
@@ -1044,6 +1045,14 @@ int ash_profile_enable(ash_ctx* c, int mask) {
   if (!c) return ASH_EINVAL;
   if (mask & ~ASH_PROF_ALL) return fail(c, ASH_EINVAL, "unknown category bits");
   c->prof_mask = mask;
+  for (long& n : c->prof_seen) n = 0;
+  return ASH_OK;
+}
+
+int ash_profile_stride(ash_ctx* c, int stride) {
+  if (!c) return ASH_EINVAL;
+  if (stride < 1) return fail(c, ASH_EINVAL, "stride must be >= 1");
+  c->prof_stride = stride;
   return ASH_OK;
 }
 

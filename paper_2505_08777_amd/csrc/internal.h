@@ -249,6 +249,8 @@ struct ash_ctx {
   int n_cu = 0;
   int precision = ASH_PRECISION_AUTO;
   int prof_mask = 0;  // categories timed with events (bit 1 << category)
+  int prof_stride = 1;          // time one launch in every prof_stride
+  long prof_seen[4] = {0, 0, 0, 0};  // launches per category since enable
   std::vector<ash_prof_rec> prof;     // recorded pairs (in use)
   std::vector<hipEvent_t> prof_pool;  // free events
   hipStream_t stream = nullptr;
