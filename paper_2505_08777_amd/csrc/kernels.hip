@@ -1279,17 +1279,19 @@ hipError_t launch_finish_E(int N, const FwdPlan& p, const float* red, float* E,
 // ---------------------------------------------------------------------------
 constexpr int kUpd = 1024;
 
-// Reduction over the block (any multiple of 64 threads, sh: one float per
-// wave): a butterfly within each wave, then the waves' results in wave
-// order; every thread returns the same value.
+// Reduction over a block of kUpd threads (sh: one float per wave): a
+// butterfly within each wave, then the waves' results in wave order; every
+// thread returns the same value.  The wave count is a constant, so the LDS
+// reads all go out before the first combine.
 template <typename Op>
 __device__ float block_reduce(float v, float* sh, Op op) {
+  constexpr int nw = kUpd / kWave;
 #pragma unroll
   for (int w = 32; w >= 1; w >>= 1) v = op(v, __shfl_xor(v, w, kWave));
-  const int nw = blockDim.x / kWave;
   if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = v;
   __syncthreads();
   float r = sh[0];
+#pragma unroll
   for (int i = 1; i < nw; ++i) r = op(r, sh[i]);
   __syncthreads();
   return r;
@@ -1305,8 +1307,9 @@ struct OpMin {
   __device__ float operator()(float a, float b) const { return fminf(a, b); }
 };
 
-// Several block reductions in one LDS pass (sh: NV floats per wave): value
-// i is combined with Op_i, in the order of block_reduce.
+// Several block reductions in one LDS pass over a block of kUpd threads
+// (sh: NV floats per wave): value i is combined with Op_i, in the order of
+// block_reduce.
 template <typename Op0, typename Op1, typename Op2, typename Op3>
 __device__ void block_reduce4(float* v, float* sh) {
   constexpr int NV = 4;
@@ -1321,7 +1324,8 @@ __device__ void block_reduce4(float* v, float* sh) {
   for (int i = 0; i < NV; ++i)
 #pragma unroll
     for (int w = 32; w >= 1; w >>= 1) v[i] = op(i, v[i], __shfl_xor(v[i], w, kWave));
-  const int nw = blockDim.x / kWave, wave = threadIdx.x / kWave;
+  constexpr int nw = kUpd / kWave;
+  const int wave = threadIdx.x / kWave;
   if ((threadIdx.x & (kWave - 1)) == 0)
 #pragma unroll
     for (int i = 0; i < NV; ++i) sh[i * nw + wave] = v[i];
@@ -1329,6 +1333,7 @@ __device__ void block_reduce4(float* v, float* sh) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     float r = sh[i * nw];
+#pragma unroll
     for (int j = 1; j < nw; ++j) r = op(i, r, sh[i * nw + j]);
     v[i] = r;
   }
@@ -1353,19 +1358,23 @@ __device__ __forceinline__ void wgs_update_block(
   // registers between the passes
   const bool one = N <= (int)blockDim.x;
   float2 e1 = make_float2(0.0f, 0.0f);
-  float w1 = 0.0f;
+  float w1 = 0.0f, t1 = 0.0f;
   // pass 1: fields, |E|^2 and normalised intensities I = |E|^2 / t^2, and
   // the norm of the amplitudes that drive the weights
   float s_a2 = 0.0f, s_I = 0.0f, mx = 0.0f, mn = INFINITY, s_m2 = 0.0f;
   for (int k = tid; k < N; k += blockDim.x) {
+    const float tk = t[k];
     const float2 e = sum_slices(red, slices, N, k);
-    if (one)
+    if (one) {
       e1 = e;
-    else
+      t1 = tk;
+      w1 = W[k];
+    } else {
       Ebuf[k] = e;
+    }
     if (E_extra) E_extra[k] = e;
     const float a2 = e.x * e.x + e.y * e.y;
-    const float I = a2 / (t[k] * t[k]);
+    const float I = a2 / (tk * tk);
     s_a2 += a2;
     s_I += I;
     mx = fmaxf(mx, I);
@@ -1385,13 +1394,14 @@ __device__ __forceinline__ void wgs_update_block(
   float s_v = 0.0f, s_w = 0.0f;
   for (int k = tid; k < N; k += blockDim.x) {
     const float2 e = one ? e1 : Ebuf[k];
+    const float tk = one ? t1 : t[k];
     const float a2 = e.x * e.x + e.y * e.y;
-    const float dI = a2 / (t[k] * t[k]) - meanI;
+    const float dI = a2 / (tk * tk) - meanI;
     s_v += dI * dI;
     const float a = meas ? fmaxf(meas[k], 0.0f) : sqrtf(a2);
-    float wk = W[k];
+    float wk = one ? w1 : W[k];
     if (a > 0.0f && norm_a > 0.0f) {
-      const float r = (a / norm_a) / (t[k] / t_norm);
+      const float r = (a / norm_a) / (tk / t_norm);
       wk = (power == 1.0f) ? wk / r : wk * powf(r, -power);
     }
     if (one)
@@ -1409,6 +1419,7 @@ __device__ __forceinline__ void wgs_update_block(
   // psi / 2 pi in pieces)
   for (int k = tid; k < N; k += blockDim.x) {
     const float wk = (one ? w1 : W[k]) / mean_w;
+    const float tk = one ? t1 : t[k];
     W[k] = wk;
     float turns;
     if (phase_mode == kPhaseFixed) {
@@ -1418,7 +1429,7 @@ __device__ __forceinline__ void wgs_update_block(
       turns = atan2f(e.y, e.x) * kInv2Pi;
       if (phase_mode == kPhaseStore) fixph[k] = turns;
     }
-    put_spot_field(ypol, k, wk * t[k], turns);
+    put_spot_field(ypol, k, wk * tk, turns);
   }
   if (stats && tid == 0) {
     stats[0] = eff_denom > 0.0f ? sum_a2 / eff_denom : 0.0f;
@@ -1507,8 +1518,19 @@ __global__ __launch_bounds__(kUpd) void k_loss_finish(
     int n, const float* __restrict__ tvp, float tv_sum_scale,
     const float* __restrict__ lossbuf, float* __restrict__ loss_out) {
   __shared__ float sh[kUpd / kWave];
+  // this thread's values in index order, eight loads in flight
   float acc = 0.0f, comp = 0.0f;
-  for (int k = threadIdx.x; k < n; k += kUpd) kahan_add(acc, comp, tvp[k]);
+  for (int k0 = threadIdx.x; k0 < n; k0 += 8 * kUpd) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + u * kUpd;
+      v[u] = k < n ? tvp[k] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u * kUpd < n) kahan_add(acc, comp, v[u]);
+  }
   const float tv = block_reduce(acc, sh, OpSum());
   if (threadIdx.x == 0) loss_out[0] = lossbuf[0] + tv_sum_scale * tv;
 }
