@@ -19,7 +19,11 @@ OK = 0
 EINVAL, ESHAPE, ENOTREADY, EUNSUPPORTED, ENOMEM, EHIP = -1, -2, -3, -4, -5, -6
 
 MAX_MODES = 32
+MAX_NONLINEAR = 28
 MAX_MONOMIALS = 128
+MAX_DEGREE = 12
+MAX_SIDE = 65536
+MAX_SPOTS = 1048576
 
 
 class AshError(RuntimeError):

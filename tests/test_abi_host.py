@@ -44,6 +44,16 @@ def test_status_codes_match_header():
     assert _lib.strerror(-99) == "unknown error"
 
 
+def test_limits_match_header():
+    src = open(HEADER).read()
+    lim = dict((m.group(1), int(m.group(2))) for m in
+               re.finditer(r"#define ASH_MAX_([A-Z]+) (\d+)", src))
+    assert lim == {"MODES": _lib.MAX_MODES, "NONLINEAR": _lib.MAX_NONLINEAR,
+                   "MONOMIALS": _lib.MAX_MONOMIALS,
+                   "DEGREE": _lib.MAX_DEGREE, "SIDE": _lib.MAX_SIDE,
+                   "SPOTS": _lib.MAX_SPOTS}
+
+
 @pytest.mark.parametrize("ansi", range(0, 66))
 def test_zernike_expansion_matches_radial_formula(ansi):
     pw, cf = A.zernike_monomials(ansi)

@@ -318,3 +318,71 @@ def test_many_spots_small_slm(A):
     _say("  adjoint", field_errors(g, gref))
     assert_fields(g, gref, what="adjoint, 1e5 spots")
     c.close()
+
+
+def test_maximum_spot_count(A):
+    """The largest supported spot count (2^20) on one 64 x 16 tile: sampled
+    spots of the forward, sampled pixels of the adjoint (each a sum over
+    all 2^20 spots), and one spot more is refused with the context kept."""
+    from paper_2505_08777_amd import _lib
+    nx, ny, modes = 64, 16, [1, 2, 4]
+    N = _lib.MAX_SPOTS
+    rng = np.random.default_rng(2020)
+    geom = oracle.Geometry(nx, ny)
+    basis = oracle.ZernikeBasis(modes)
+    w = _spots(rng, nx, ny, N, modes, 0.7, geom.R)
+    amp = rng.uniform(0.2, 1.0, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    c = _ctx(A, nx, ny, modes, w, amp=amp)
+    E = c.forward(phase=_cuda(phi, torch.float32)).cpu().numpy()
+    sel = np.sort(np.concatenate([[0, N - 1], rng.choice(N, size=510, replace=False)]))
+    Eref = oracle.forward(amp * np.exp(1j * phi), w, basis, geom, spots=sel)
+    _say("  forward", field_errors(E[sel], Eref))
+    assert_fields(E[sel], Eref, what="forward, 2^20 spots")
+    y = (rng.normal(size=N) + 1j * rng.normal(size=N)).astype(np.complex64)
+    g = c.adjoint(_cuda(y, torch.complex64)).cpu().numpy().reshape(-1)
+    pix = np.sort(rng.choice(nx * ny, size=48, replace=False))
+    gref = oracle.adjoint(y.astype(np.complex128), w, basis, geom, pixels=pix)
+    _say("  adjoint", field_errors(g[pix], gref))
+    assert_fields(g[pix], gref, what="adjoint, 2^20 spots")
+    w_more = np.zeros((N + 1, len(modes)))
+    assert _lib.lib.ash_set_spots(c._h, N + 1, w_more.ctypes.data,
+                                  None) == _lib.EUNSUPPORTED
+    E2 = c.forward(phase=_cuda(phi, torch.float32)).cpu().numpy()
+    assert np.array_equal(E, E2)
+    c.close()
+
+
+@pytest.mark.parametrize("nx,ny", [(65536, 16), (16, 65536)])
+def test_maximum_side(A, nx, ny):
+    """The largest supported side (65536 pixels): every pixel of both
+    transforms for a few spots, and one pixel more is refused."""
+    from paper_2505_08777_amd import _lib
+    assert max(nx, ny) == _lib.MAX_SIDE
+    modes, N = [1, 2, 4, 5], 6
+    rng = np.random.default_rng(nx + 3 * ny)
+    geom = oracle.Geometry(nx, ny, R=max(nx, ny) / 2.0)  # pupil along the strip
+    basis = oracle.ZernikeBasis(modes)
+    w = _spots(rng, nx, ny, N, modes, 0.5, geom.R)
+    amp = rng.uniform(0.2, 1.0, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    c = _ctx(A, nx, ny, modes, w, amp=amp, R=geom.R)
+    E = c.forward(phase=_cuda(phi, torch.float32)).cpu().numpy()
+    Eref = oracle.forward(amp * np.exp(1j * phi), w, basis, geom)
+    _say("  forward", field_errors(E, Eref))
+    assert_fields(E, Eref, what="forward, side %d" % max(nx, ny))
+    y = (rng.normal(size=N) + 1j * rng.normal(size=N)).astype(np.complex64)
+    g = c.adjoint(_cuda(y, torch.complex64)).cpu().numpy()
+    gref = oracle.adjoint(y.astype(np.complex128), w, basis, geom)
+    _say("  adjoint", field_errors(g, gref))
+    assert_fields(g, gref, what="adjoint, side %d" % max(nx, ny))
+    c.close()
+    c = A.Context(0)
+    pw, cf = A.zernike_table(modes)
+    pw = np.ascontiguousarray(pw, np.int32)
+    cf = np.ascontiguousarray(cf, np.float64)
+    bx, by = (nx + 1, ny) if nx > ny else (nx, ny + 1)
+    assert _lib.lib.ash_set_basis(c._h, bx, by, bx / 2.0, by / 2.0, 8.0,
+                                  len(modes), pw.shape[0], pw.ctypes.data,
+                                  cf.ctypes.data, None) == _lib.EUNSUPPORTED
+    c.close()
