@@ -386,3 +386,73 @@ def test_maximum_side(A, nx, ny):
                                   len(modes), pw.shape[0], pw.ctypes.data,
                                   cf.ctypes.data, None) == _lib.EUNSUPPORTED
     c.close()
+
+
+def _disk_peak_valley(d, n=801):
+    """Peak-to-valley of the orthonormal Zernike with ANSI index d over the
+    unit disk (dense grid)."""
+    x, y = np.meshgrid(np.linspace(-1, 1, n), np.linspace(-1, 1, n))
+    inside = x ** 2 + y ** 2 <= 1.0
+    z = oracle.zernike_nm(*oracle.ansi_to_nm(d), x[inside], y[inside])
+    return float(z.max() - z.min())
+
+
+def test_paper_magnitudes_pyramid_and_astigmatism(A):
+    """Inputs at the magnitudes the paper reports: a Zernike pyramid (one
+    spot per mode of radial orders 2-4, each carrying +-5 rad peak-valley of
+    its own mode over the pupil, "Aberration-Space Holography"), and a field
+    of spots whose astigmatism Z_5 reaches -30 rad (Fig. 4's principal-mode
+    discussion) on top of unit-size other aberrations."""
+    # pyramid: 12 spots, basis = tilts + ANSI 3..14
+    nx = ny = 384
+    pyr = list(range(3, 15))
+    modes = [1, 2] + pyr
+    geom = oracle.Geometry(nx, ny)
+    basis = oracle.ZernikeBasis(modes)
+    w = np.zeros((len(pyr), len(modes)))
+    k = 0
+    for n_rad, first in ((2, 3), (3, 6), (4, 10)):
+        for col in range(n_rad + 1):
+            u = 24.0 * (col - n_rad / 2.0)
+            v = 24.0 * (n_rad - 3)
+            w[k, 0] = np.pi * v * geom.R / ny
+            w[k, 1] = np.pi * u * geom.R / nx
+            w[k, 2 + k] = 10.0 / _disk_peak_valley(first + col)
+            k += 1
+    rng = np.random.default_rng(141)
+    amp = rng.uniform(0.2, 1.0, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    c = _ctx(A, nx, ny, modes, w, amp=amp)
+    E = c.forward(phase=_cuda(phi, torch.float32)).cpu().numpy()
+    Eref = oracle.forward(amp * np.exp(1j * phi), w, basis, geom)
+    _say("  pyramid forward", field_errors(E, Eref))
+    assert_fields(E, Eref, what="pyramid forward")
+    y = (rng.normal(size=len(pyr)) + 1j * rng.normal(size=len(pyr))).astype(np.complex64)
+    g = c.adjoint(_cuda(y, torch.complex64)).cpu().numpy()
+    gref = oracle.adjoint(y.astype(np.complex128), w, basis, geom)
+    _say("  pyramid adjoint", field_errors(g, gref))
+    assert_fields(g, gref, what="pyramid adjoint")
+    c.close()
+    # astigmatism down to -30 rad over the field, 10-mode basis
+    nx = ny = 512
+    N = 300
+    modes = [1, 2, 3, 4, 5, 6, 7, 8, 9, 12]
+    geom = oracle.Geometry(nx, ny)
+    basis = oracle.ZernikeBasis(modes)
+    rng = np.random.default_rng(341)
+    w = _spots(rng, nx, ny, N, modes, 1.0, geom.R)
+    w[:, modes.index(5)] = rng.uniform(-30.0, -20.0, N)
+    amp = rng.uniform(0.2, 1.0, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    c = _ctx(A, nx, ny, modes, w, amp=amp)
+    _say("  info", c.info())
+    E = c.forward(phase=_cuda(phi, torch.float32)).cpu().numpy()
+    Eref = oracle.forward(amp * np.exp(1j * phi), w, basis, geom)
+    _say("  astigmatism forward", field_errors(E, Eref))
+    assert_fields(E, Eref, what="astigmatism forward")
+    y = (rng.normal(size=N) + 1j * rng.normal(size=N)).astype(np.complex64)
+    g = c.adjoint(_cuda(y, torch.complex64)).cpu().numpy()
+    gref = oracle.adjoint(y.astype(np.complex128), w, basis, geom)
+    _say("  astigmatism adjoint", field_errors(g, gref))
+    assert_fields(g, gref, what="astigmatism adjoint")
+    c.close()
