@@ -92,8 +92,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="field1024",
                     choices=["plain256", "field1024", "volume1920",
-                             "grad1024", "batch64", "principal1024",
-                             "coefgrad1024", "feedback1024", "quality1024"],
+                             "grad1024", "batch64", "batch64small",
+                             "principal1024", "coefgrad1024", "feedback1024",
+                             "quality1024"],
                     help="grad1024 times the differentiable form (Adam steps "
                          "of the spot-amplitude loss with TV); principal1024 "
                          "the WGS loop on 8 principal isoplanatic modes of a "
@@ -103,8 +104,9 @@ def parse():
                          "simulated spot measurements with phase fixing; "
                          "quality1024 the windowed Strehl proxy of three "
                          "corrections; "
-                         "batch64 the "
-                         "batched form (64 holograms' WGS loops together)")
+                         "batch64 the batched form (64 holograms' WGS "
+                         "loops together), batch64small the same for 64 "
+                         "small holograms (256..512, 5..200 spots)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batch64: skip the autotuner (default range length)")
     ap.add_argument("--iters", type=int, default=None,
@@ -530,6 +532,53 @@ def bench_quality(args, d):
     print(json.dumps(out), flush=True)
 
 
+def autograd_descent(A, ctx, d, n_steps):
+    """The same descent through torch autograd: the spot fields from
+    `propagate` (its backward is the adjoint kernel with the gradient
+    epilogue), the loss and its TV term in torch ops, torch.optim.Adam.
+    Returns the rate and the loss at every step (before its update)."""
+    import numpy as np
+    import torch
+    amp = np.asarray(d["amp"], np.float64)
+    N = d["w"].shape[0]
+    s = float(np.sqrt(amp.size * np.sum(amp ** 2) / N))
+    t = torch.tensor(d["t"], dtype=torch.float32, device="cuda:0")
+    two_pi = 2.0 * np.pi
+
+    def wrap(x):
+        return x - two_pi * torch.round(x / two_pi)
+
+    def loss_of(ph):
+        E = A.propagate(ph, ctx)
+        spot = torch.sum((torch.abs(E / s) ** 2 - t) ** 2)
+        dx = torch.nn.functional.pad(wrap(ph[:, 1:] - ph[:, :-1]), (0, 1))
+        dy = torch.nn.functional.pad(wrap(ph[1:, :] - ph[:-1, :]), (0, 0, 0, 1))
+        tv = torch.mean(torch.sqrt(dx * dx + dy * dy + d["tv_eps"] ** 2))
+        return spot + d["lam"] * tv
+
+    def run(k):
+        ph = torch.tensor(d["phi0"], dtype=torch.float32, device="cuda:0",
+                          requires_grad=True)
+        opt = torch.optim.Adam([ph], lr=d["lr"], betas=d["betas"],
+                               eps=d["adam_eps"])
+        losses = []
+        for _ in range(k):
+            opt.zero_grad(set_to_none=False)
+            L = loss_of(ph)
+            L.backward()
+            opt.step()
+            losses.append(L.detach())
+        return torch.stack(losses)
+
+    run(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = run(n_steps)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    return n_steps / T, losses.cpu().numpy()
+
+
 def bench_adam(args, d):
     """Adam descent of the 1024 x 1024, 1000-spot loss: a step is the
     workload's Adam updates (forward, loss, adjoint with the phase gradient
@@ -598,6 +647,22 @@ def bench_adam(args, d):
         "event_stride": args.event_stride,
         "layout": info,
     }
+    # the same descent through torch autograd, and the plain WGS loop, on
+    # this context
+    rate, La = autograd_descent(A, ctx, d, n_steps)
+    out["autograd"] = {
+        "adam_steps_per_s": rate,
+        "loss_first_last": [float(La[0]), float(La[-1])],
+        "max_rel_loss_diff_vs_fused": float(np.max(np.abs(La - L) / L)),
+        "fused_speedup": out["adam_steps_per_s"] / rate}
+    ph = phi0.clone()
+    W = torch.ones(N, dtype=torch.float32, device=dev)
+    ctx.wgs(ph, 10, weights=W, want_E=False, want_stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.wgs(ph, n_steps, weights=W, want_E=False, want_stats=False)
+    torch.cuda.synchronize()
+    out["plain_wgs_iters_per_s"] = n_steps / (time.perf_counter() - t0)
     if not args.no_cpu_baseline:
         rng = np.random.default_rng(12345)
         pix = np.sort(rng.choice(P, size=min(P, 16384), replace=False))
@@ -608,9 +673,11 @@ def bench_adam(args, d):
 
 
 def bench_batch(args, holos):
-    """64 holograms (sides 512..2048, N log-uniform in [10, 5000], 12
-    modes): a step is the workload's 50 WGS iterations of every hologram
-    in the batched persistent launches, continuing from the last phases."""
+    """64 holograms (batch64: sides 512..2048, N log-uniform in [10, 5000];
+    batch64small: sides 256..512, N in [5, 200]; 12 modes): a step is the
+    workload's WGS iterations (50, 20) of every hologram in the batched
+    persistent launches, continuing from the last phases; the same loops
+    run one context at a time are timed beside it."""
     import numpy as np
     import torch
     import paper_2505_08777_amd as A
@@ -663,7 +730,7 @@ def bench_batch(args, holos):
         "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "batch64", "holograms": len(holos),
+        "config": {"workload": args.workload, "holograms": len(holos),
                    "sum_N_P": evals, "modes": D,
                    "wgs_iters_per_step": n_iter},
         "wgs_iters_per_s_per_hologram": n_iter * args.steps / T,
@@ -676,6 +743,18 @@ def bench_batch(args, holos):
         "issue_model": issue_model(evals / (ms_avg * 1e-3), groups),
         "layout": info, "tune_s": tune_s,
     }
+    # the same holograms' loops run one context at a time (plain loop)
+    ph2 = [p.clone() for p in phases]
+    w2 = [w.clone() for w in weights]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, p, w in zip(ctxs, ph2, w2):
+        c.wgs(p, n_iter, weights=w, want_E=False, want_stats=False)
+    torch.cuda.synchronize()
+    Tp = time.perf_counter() - t0
+    out["plain_loop"] = {"ms_per_step": 1e3 * Tp,
+                         "evals_per_s": 2.0 * evals * n_iter / Tp,
+                         "batch_speedup": Tp / (T / args.steps)}
     b.close()
     for c in ctxs:
         c.close()
@@ -707,7 +786,7 @@ def main():
     d = workloads.make(args.workload)
     if args.workload == "grad1024":
         return bench_adam(args, d)
-    if args.workload == "batch64":
+    if args.workload in ("batch64", "batch64small"):
         return bench_batch(args, d)
     n_iter = args.iters or d["n_iter"]
     nx, ny = d["nx"], d["ny"]

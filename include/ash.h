@@ -418,7 +418,8 @@ int ash_batch_set_stream(ash_batch* batch, void* stream);
  *   params       as for ash_wgs_iterate (NULL = power 1).
  * Each hologram's results equal its own ash_wgs_iterate up to the FP32
  * summation order of the forward partial sums.  The call synchronises the
- * stream once at its start (descriptor upload).
+ * stream once at its start (descriptor upload) and keeps 2 KB of queue
+ * counters per iteration and record shape on the device, grown on demand.
  * Errors: ASH_EINVAL, ASH_ENOTREADY, ASH_ENOMEM, ASH_EHIP. */
 int ash_batch_wgs(ash_batch* batch, float* const* phase_dev,
                   float* const* weights_dev, int n_iter,

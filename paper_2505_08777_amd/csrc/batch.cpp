@@ -337,14 +337,16 @@ int check_members(ash_batch* b) {
   return ASH_OK;
 }
 
-// Enqueue one forward phase (all record shapes) with counters ctr[cls][8].
+// Enqueue one forward phase (all record shapes) with counters
+// ctr[cls][8][kCtrPad].
 int enqueue_forward(ash_batch* b, int* ctr) {
   for (size_t k = 0; k < b->cls.size(); ++k) {
     const Cls& c = b->cls[k];
     BCHK(b, btimed(b, ASH_PROF_FORWARD, [&] {
            return launch_batch_forward(c.G, c.reduce != 0, c.fwd_grid,
                                        b->d_desc, b->d_items + c.fwd_off,
-                                       b->d_qoff + c.qoff_fwd, ctr + 8 * k,
+                                       b->d_qoff + c.qoff_fwd,
+                                       ctr + (size_t)k * kXcds * kCtrPad,
                                        b->stream);
          }), "batch forward");
   }
@@ -389,9 +391,9 @@ int make_fields(ash_batch* b, float* const* phase) {
 }
 
 // Zeroed take counters for `launches` persistent launches of 8 queues per
-// record shape.
+// record shape, kCtrPad ints apart.
 int counters(ash_batch* b, size_t launches, int** out) {
-  const size_t n = launches * b->cls.size() * kXcds;
+  const size_t n = launches * b->cls.size() * kXcds * kCtrPad;
   int rc = bgrow(b, &b->d_ctr, &b->cap_ctr, n, "queue counters");
   if (rc) return rc;
   BCHK(b, hipMemsetAsync(b->d_ctr, 0, n * sizeof(int), b->stream),
@@ -503,7 +505,7 @@ int ash_batch_wgs(ash_batch* b, float* const* phase_dev,
     return rc;
   int* ctr = nullptr;
   if ((rc = counters(b, (size_t)n_iter, &ctr))) return rc;
-  const size_t per = b->cls.size() * kXcds;
+  const size_t per = b->cls.size() * kXcds * kCtrPad;
   if ((rc = make_fields(b, phase_dev))) return rc;
   for (int it = 0; it < n_iter; ++it) {
     if ((rc = enqueue_forward(b, ctr + it * per)) ||
@@ -551,7 +553,8 @@ int ash_batch_tune(ash_batch* b, float* const* phase_dev,
         hipError_t e = launch_batch_forward(
             c.G, c.reduce != 0, c.fwd_grid, b->d_desc,
             b->d_items + c.fwd_off, b->d_qoff + c.qoff_fwd,
-            ctr + (size_t)r * b->cls.size() * kXcds + 8 * k, b->stream);
+            ctr + ((size_t)r * b->cls.size() + k) * kXcds * kCtrPad,
+            b->stream);
         if (e != hipSuccess) rc = bhip(b, e, "tuning forward");
         if (!rc && (rc = enqueue_reduce_update(b, 1.0f, false))) break;
       }

@@ -222,8 +222,11 @@ struct HoloDesc {
 
 // Work items: forward {holo, range, spot block, 0} in 8 per-XCD queues
 // items[qoff[x] .. qoff[x+1]) of a persistent launch, with take counters
-// ctr[x]; adjoint blocks {holo, tile * 4 + quarter, 0, 0} (holo < 0: idle);
-// reduce blocks {holo, first spot, slice, 0}.
+// ctr[x * kCtrPad] (one counter per 256 bytes: atomics on one cache line
+// serialise, so the queues' counters do not share lines); adjoint blocks
+// {holo, tile * 4 + quarter, 0, 0} (holo < 0: idle); reduce blocks {holo,
+// first spot, slice, 0}.
+constexpr int kCtrPad = 64;
 hipError_t launch_batch_forward(int G, bool reduce, int grid,
                                 const HoloDesc* d, const int4* items,
                                 const int* qoff, int* ctr, hipStream_t s);

@@ -1774,7 +1774,11 @@ hipError_t launch_adjoint(const Geom& b, int N, const unsigned short* pixtab,
 // Each wave takes items from its XCD's queue (block id mod 8, as blocks
 // reach the XCDs round-robin), then from the other queues in turn; it asks
 // for the next item before computing the current one so that the atomic's
-// latency is hidden.  Every wave stops after the eighth queue runs dry.
+// latency is hidden.  Before its first take from a queue a wave reads the
+// queue's counter and passes over a queue already drained: counters only
+// grow, so a stale read costs one take and never skips an item, while the
+// many waves that find every queue drained at the end cost loads, not
+// serialised atomics.  Every wave stops after the eighth queue.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wave_take(int* ctr) {
   int v = 0;
@@ -1796,11 +1800,15 @@ __device__ __forceinline__ void drain_queues(const int4* __restrict__ items,
   const int home = blockIdx.x % kXcds;
   for (int qi = 0; qi < kXcds; ++qi) {
     const int x = (home + qi) % kXcds;
+    int* const c = ctr + x * kCtrPad;
     const int base = qoff[x], cnt = qoff[x + 1] - base;
-    int idx = wave_take(ctr + x);
+    const int seen = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (seen >= cnt) continue;
+    int idx = wave_take(c);
     while (idx < cnt) {
       const int4 it = uniform_item(items, (long)base + idx);
-      const int nxt = wave_take(ctr + x);
+      const int nxt = wave_take(c);
       work(it);
       idx = nxt;
     }

@@ -254,6 +254,18 @@ def batch64_specs(seed=None, H=64):
             for s, n, q in zip(sides, Ns.astype(int), seeds)]
 
 
+def batch64small_specs(seed=None, H=64):
+    """64 small holograms (sides 256..512, N log-uniform in [5, 200], 20
+    iterations): each one far too small to fill the GPU by itself."""
+    seed = BASE_SEED + 11 if seed is None else seed
+    rng = np.random.default_rng(seed)
+    sides = rng.choice((256, 384, 512), size=H)
+    Ns = np.rint(np.exp(rng.uniform(math.log(5), math.log(200), size=H)))
+    seeds = rng.integers(0, 2 ** 31, size=H)
+    return [dict(side=int(s), N=int(n), seed=int(q), n_iter=20)
+            for s, n, q in zip(sides, Ns.astype(int), seeds)]
+
+
 def batch_hologram(spec):
     n, N, seed = spec["side"], spec["N"], spec["seed"]
     rng = np.random.default_rng(seed)
@@ -263,13 +275,15 @@ def batch_hologram(spec):
     w = np.zeros((N, len(modes)))
     w[:, 0], w[:, 1] = tilt_coefs(u, v, n, n)
     w[:, 2:] = rng.normal(0.0, 0.7, size=(N, len(modes) - 2))
-    return _pack("batch64", seed, n, n, modes, w, np.ones(N), rng, 50,
-                 u=u, v=v)
+    return _pack("batch64", seed, n, n, modes, w, np.ones(N), rng,
+                 spec.get("n_iter", 50), u=u, v=v)
 
 
 def make(name, seed=None):
     if name == "batch64":
         return [batch_hologram(s) for s in batch64_specs(seed)]
+    if name == "batch64small":
+        return [batch_hologram(s) for s in batch64small_specs(seed)]
     return {"plain256": plain256, "field1024": field1024,
             "volume1920": volume1920, "grad1024": grad1024,
             "principal1024": principal1024,
