@@ -721,9 +721,13 @@ def bench_batch(args, holos):
     evals = info["evals_per_transform"]
     value = 2.0 * evals * n_iter * args.steps / T
     dom = max(("forward", "adjoint"), key=lambda k: prof[k][0])
-    # every launch of a phase covers all holograms of its record shape
-    ms_avg = prof[dom][0] / max(prof[dom][1], 1)
-    groups = info["groups"][0] if info["groups"] else 0
+    # a phase is one launch per record shape, each over all holograms of
+    # that shape: the unit timed is the phase (all its launches)
+    shapes = max(info["shapes"], 1)
+    ms_avg = prof[dom][0] / max(prof[dom][1] // shapes, 1)
+    # the ceiling of the fewest matrix-core groups among the shapes (the
+    # highest), so the fraction is a lower estimate when shapes differ
+    groups = min(info["groups"]) if info["groups"] else 0
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -736,7 +740,7 @@ def bench_batch(args, holos):
         "wgs_iters_per_s_per_hologram": n_iter * args.steps / T,
         "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
         "roofline": alu_roofline("k_batch_%s" % dom, evals, ms_avg,
-                                 prof[dom][1], D, groups),
+                                 prof[dom][1] // shapes, D, groups),
         "kernels": {k: {"total_ms": v[0], "launches": v[1],
                         "avg_ms": v[0] / v[1] if v[1] else None}
                     for k, v in prof.items()},
