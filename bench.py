@@ -160,7 +160,7 @@ def profiled_traffic(workload, kernel, summary="wgs_kernels"):
     return val, os.path.relpath(path, ROOT)
 
 
-CPU_MIN_S, CPU_MAX_S, CPU_MAX_PAIRS = 10.0, 30.0, 5
+CPU_MIN_S, CPU_MAX_S, CPU_MAX_PAIRS = 10.0, 30.0, 8
 
 
 def cpu_baseline(ctx, d, w=None, basis=None):
