@@ -839,6 +839,16 @@ def main():
     else:
         ctx.set_basis(nx, ny, modes=d["modes"], amp=amp_t)
         ctx.set_spots(d["w"], d["t"])
+    # a spot update (new coefficient matrix, pixel tables untouched), as
+    # between holograms of a dynamic display: host call to results ready
+    set_spots_ms = None
+    if principal is None:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            ctx.set_spots(d["w"], d["t"])
+        torch.cuda.synchronize()
+        set_spots_ms = 1e3 * (time.perf_counter() - t0) / 5
     info = ctx.info()
     phase = torch.tensor(d["phi0"], dtype=torch.float32, device=dev)
     weights = torch.ones(N, dtype=torch.float32, device=dev)
@@ -901,7 +911,7 @@ def main():
         "event_stride": args.event_stride,
         "roofline": roofline,
         "issue_model": issue_model(N * P / (ms_avg * 1e-3), info["groups"]),
-        "kernels": kernels, "layout": info,
+        "kernels": kernels, "layout": info, "set_spots_ms": set_spots_ms,
     }
     if args.graph or args.workload == "plain256":
         out["graph_replay"] = graph_replay(ctx, d, n_iter, args.steps)
