@@ -15,11 +15,13 @@ import pytest
 
 import oracle
 import oracle.grad as ograd
+import oracle.principal as oprincipal
 import oracle.quality as oquality
 import oracle.transform as otransform
 import oracle.wgs as owgs
 import oracle.zernike as ozernike
 import test_oracle_pins as pins
+import test_oracle_principal as ppins
 
 # every pin, with the parameters it is collected with
 PIN_CALLS = [
@@ -51,14 +53,19 @@ PIN_CALLS = [
     ("test_window_strehl_of_a_perfect_spot_closed_form",
      {"step": 0.5, "win": 7}),
     ("test_window_strehl_invariances_and_layout", {}),
-]
+] + [(ppins, name, {}) for name in (
+    "test_known_spectrum_and_eckart_young", "test_rank_k_matrix_is_exact",
+    "test_full_rank_keeps_phases_and_k0_keeps_linear_part",
+    "test_phase_change_within_cauchy_schwarz_bound",
+    "test_rank_one_direction")]
 
 
 def _failing_pins():
     failed = []
-    for name, kw in PIN_CALLS:
+    for call in PIN_CALLS:
+        mod, name, kw = call if len(call) == 3 else (pins,) + call
         try:
-            getattr(pins, name)(**kw)
+            getattr(mod, name)(**kw)
         except pytest.skip.Exception:
             continue
         except Exception:  # an assertion or an error both count
@@ -174,6 +181,21 @@ def _window_axes_swapped(mp):
                 lambda w, ix, iy, dwx, dwy, win: wc(w, iy, ix, dwy, dwx, win))
 
 
+def _principal_trailing(mp):
+    def wrong(w, basis, K):
+        w = np.asarray(w, dtype=np.float64)
+        lin = oprincipal.linear_modes(basis)
+        keep, rot = np.flatnonzero(lin), np.flatnonzero(~lin)
+        WR = w[:, rot]
+        _, sv, Vt = np.linalg.svd(WR, full_matrices=True)
+        sigma = np.zeros(rot.size)
+        sigma[:sv.size] = sv
+        VK = Vt[::-1][:K].T                  # the trailing singular vectors
+        wK = np.concatenate([w[:, keep], WR @ VK], axis=1)
+        return wK, oprincipal.RotatedBasis(basis, keep, rot, VK), sigma
+    _patch_both(mp, oprincipal, "principal_modes", wrong)
+
+
 MUTATIONS = {
     "kernel phase sign": _kernel_sign,
     "transposed pupil coordinates": _transposed_coords,
@@ -187,6 +209,7 @@ MUTATIONS = {
     "moments conjugated": _moment_conjugate,
     "windowed Strehl of amplitudes, not intensities": _strehl_amplitudes,
     "window offsets on swapped axes": _window_axes_swapped,
+    "principal modes from the trailing singular vectors": _principal_trailing,
 }
 
 
