@@ -746,6 +746,10 @@ def bench_batch(args, holos):
     # the ceiling of the fewest matrix-core groups among the shapes (the
     # highest), so the fraction is a lower estimate when shapes differ
     groups = min(info["groups"]) if info["groups"] else 0
+    kname = "k_batch_%s<%d, false>" % (dom, groups)
+    traffic, traffic_src = (profiled_traffic(args.workload, kname,
+                                             summary="batch_kernels")
+                            if shapes == 1 else (None, None))
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -757,8 +761,9 @@ def bench_batch(args, holos):
                    "wgs_iters_per_step": n_iter},
         "wgs_iters_per_s_per_hologram": n_iter * args.steps / T,
         "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
-        "roofline": alu_roofline("k_batch_%s" % dom, evals, ms_avg,
-                                 prof[dom][1] // shapes, D, groups),
+        "roofline": alu_roofline(kname, evals, ms_avg,
+                                 prof[dom][1] // shapes, D, groups,
+                                 traffic, traffic_src),
         "kernels": {k: {"total_ms": v[0], "launches": v[1],
                         "avg_ms": v[0] / v[1] if v[1] else None}
                     for k, v in prof.items()},
