@@ -459,6 +459,8 @@ def bench_feedback(args, d):
                     for k, v in prof.items()},
         "layout": info,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["parity"] = cpu_baseline(model, d)
     model.close()
     system.close()
     print(json.dumps(out), flush=True)
@@ -548,6 +550,30 @@ def bench_quality(args, d):
                     for k, v in prof.items()},
         "layout": info,
     }
+    if not args.no_cpu_baseline:
+        # S' of two spots' windows of the anisoplanatic hologram, by the
+        # oracle (441 kernels over every pixel each); the GPU's are in S
+        import oracle
+        geom = oracle.Geometry(nx, ny)
+        basis = oracle.ZernikeBasis(d["modes"])
+        f = (d["amp"].astype(np.float32).astype(np.float64)
+             * np.exp(1j * holo["anisoplanatic"].cpu().numpy().astype(np.float64)))
+        sel = [centre, int(np.argmax(d["u"] ** 2 + d["v"] ** 2))]
+        t0 = time.perf_counter()
+        Sref = oracle.spot_quality(f, truth, basis, geom, ix=1, iy=0, win=win,
+                                   step=step_bins, spots=sel,
+                                   workers=len(os.sched_getaffinity(0)))
+        Tc = time.perf_counter() - t0
+        Sg = S_all["anisoplanatic"][sel]
+        out["cpu_baseline"] = {
+            "value": len(sel) * win * win * P / Tc, "unit": "evals/s",
+            "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+            "sample": "the windows of %d spots (%d kernels over all %d "
+                      "pixels) in %.1f s, FP64 numpy"
+                      % (len(sel), len(sel) * win * win, P, Tc)}
+        out["parity"] = {"spots": sel,
+                         "strehl_max_rel": float(np.max(np.abs(Sg - Sref) / Sref)),
+                         "bar": 1e-4}
     cam.close()
     print(json.dumps(out), flush=True)
 
@@ -683,6 +709,19 @@ def bench_adam(args, d):
     ctx.wgs(ph, n_steps, weights=W, want_E=False, want_stats=False)
     torch.cuda.synchronize()
     out["plain_wgs_iters_per_s"] = n_steps / (time.perf_counter() - t0)
+    # the gradient alone (ash_phase_grad: the adjoint with the gradient
+    # epilogue), as the autograd backward calls it
+    G = torch.ones(N, dtype=torch.complex64, device=dev)
+    gout = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+    ctx.phase_grad(phi0, G, out=gout)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        ctx.phase_grad(phi0, G, out=gout)
+    torch.cuda.synchronize()
+    Tg = (time.perf_counter() - t0) / 20
+    out["phase_grad"] = {"per_s": 1.0 / Tg, "ms": 1e3 * Tg,
+                         "evals_per_s": N * P / Tg}
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity"] = cpu_baseline(ctx, d)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
@@ -783,6 +822,13 @@ def bench_batch(args, holos):
                          "evals_per_s": 2.0 * evals * n_iter / Tp,
                          "batch_speedup": Tp / (T / args.steps)}
     b.close()
+    if not args.no_cpu_baseline:
+        # the oracle on the hologram with the fewest evaluations, its
+        # context's transforms beside it (the batch runs the same kernels)
+        h = int(np.argmin([x["w"].shape[0] * x["nx"] * x["ny"] for x in holos]))
+        out["cpu_baseline"], out["parity"] = cpu_baseline(ctxs[h], holos[h])
+        out["parity"]["hologram"] = {"index": h, "N": holos[h]["w"].shape[0],
+                                     "side": holos[h]["nx"]}
     for c in ctxs:
         c.close()
     print(json.dumps(out), flush=True)
