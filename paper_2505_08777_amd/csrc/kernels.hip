@@ -1234,22 +1234,51 @@ hipError_t launch_window_strehl(int n_windows, int win2, const float* E,
 // ---------------------------------------------------------------------------
 // Reductions of the forward partials (fixed order, compensated).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_reduce(int N, int groups, int rows,
-                                               const float2* __restrict__ part,
-                                               float2* __restrict__ red) {
-  const int k = blockIdx.x * 64 + threadIdx.x;
-  if (k >= N) return;
-  const int g0 = blockIdx.y * rows;
-  const int g1 = min(g0 + rows, groups);
-  red[(long)blockIdx.y * N + k] =
-      kahan_sum_strided(part + (long)g0 * N + k, N, g1 - g0);
+// Threads of the single-block kernels (reduction, weighted-GS update, loss).
+constexpr int kUpd = 1024;
+
+// One block of kUpd threads per kRedSpots spots: thread t takes spot
+// k0 + t % kRedSpots and the rows t / kRedSpots + j * kRedPhases, so
+// consecutive threads read consecutive spots of one row; each thread sums
+// its rows in order (compensated), then the kRedPhases row phases of a
+// spot combine in a fixed order: two butterfly steps over the four phases
+// in a wave, then the waves' sums in wave order.
+constexpr int kRedSpots = 16, kRedPhases = kUpd / kRedSpots;
+
+__global__ __launch_bounds__(kUpd) void k_reduce(
+    int N, int groups, const float2* __restrict__ part,
+    float2* __restrict__ red) {
+  __shared__ float2 sh[kUpd / kWave][kRedSpots];
+  const int sp = threadIdx.x % kRedSpots, rp = threadIdx.x / kRedSpots;
+  const int k = blockIdx.x * kRedSpots + sp;
+  const int rows = rp < groups ? (groups - 1 - rp) / kRedPhases + 1 : 0;
+  float2 v = make_float2(0.0f, 0.0f);
+  if (k < N)
+    v = kahan_sum_strided(part + (long)rp * N + k, (long)kRedPhases * N,
+                          rows);
+#pragma unroll
+  for (int w = kRedSpots; w < kWave; w <<= 1) {
+    v.x += __shfl_xor(v.x, w, kWave);
+    v.y += __shfl_xor(v.y, w, kWave);
+  }
+  const int wave = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) < kRedSpots) sh[wave][sp] = v;
+  __syncthreads();
+  if (threadIdx.x < kRedSpots && k < N) {
+    float2 r = sh[0][sp];
+#pragma unroll
+    for (int i = 1; i < kUpd / kWave; ++i) {
+      r.x += sh[i][sp].x;
+      r.y += sh[i][sp].y;
+    }
+    red[k] = r;
+  }
 }
 
 hipError_t launch_reduce(int N, const FwdPlan& p, const float* partial,
                          float* red, hipStream_t s) {
-  dim3 grid((N + 63) / 64, p.slices);
-  hipLaunchKernelGGL(k_reduce, grid, dim3(64), 0, s, N, p.groups,
-                     p.rows_per_slice,
+  hipLaunchKernelGGL(k_reduce, dim3((N + kRedSpots - 1) / kRedSpots),
+                     dim3(kUpd), 0, s, N, p.groups,
                      reinterpret_cast<const float2*>(partial),
                      reinterpret_cast<float2*>(red));
   return hipGetLastError();
@@ -1277,7 +1306,6 @@ hipError_t launch_finish_E(int N, const FwdPlan& p, const float* red, float* E,
 // ---------------------------------------------------------------------------
 // Weighted-GS farfield update (one block).
 // ---------------------------------------------------------------------------
-constexpr int kUpd = 1024;
 
 // Reduction over a block of kUpd threads (sh: one float per wave): a
 // butterfly within each wave, then the waves' results in wave order; every
@@ -1986,8 +2014,8 @@ FwdPlan plan_forward(int n_tiles, int N, int blocks_per_cu, int n_cu) {
   want = want / kXcds * kXcds;     // whole rounds over the XCDs
   if (want < kXcds) want = kXcds;  // (empty ranges give zeros)
   p.groups = (int)want;
-  p.rows_per_slice = 32;
-  p.slices = (p.groups + p.rows_per_slice - 1) / p.rows_per_slice;
+  p.rows_per_slice = p.groups;  // k_reduce sums all ranges of a spot
+  p.slices = 1;
   return p;
 }
 
