@@ -82,7 +82,7 @@ struct Buffers {
   double* spot64 = nullptr;           // [N][3] constant, alpha, beta (turns)
   unsigned* bound = nullptr;          // [2] float bits: remainder, |phase|
   float* partial = nullptr;           // [groups][N][2]
-  float* red = nullptr;               // [slices][N][2]
+  float* red = nullptr;               // [N][2] reduced forward sums
   // differentiable form
   float* grad = nullptr;              // [P] phase gradient
   float* tvp = nullptr;               // [n_tiles * kBlkPerTile] TV sums
@@ -105,8 +105,7 @@ constexpr unsigned kProfEventFlags = hipEventDisableSystemFence;
 
 struct FwdPlan {
   int groups = 0;  // pixel-block ranges (forward partial rows)
-  int slices = 0;  // second-level reduction rows
-  int rows_per_slice = 0;
+  int slices = 1;  // rows of red per spot: k_reduce sums all ranges at once
   int mom_groups = 0;  // pixel-block ranges of the moment transform
 };
 

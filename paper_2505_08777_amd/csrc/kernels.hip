@@ -2014,8 +2014,6 @@ FwdPlan plan_forward(int n_tiles, int N, int blocks_per_cu, int n_cu) {
   want = want / kXcds * kXcds;     // whole rounds over the XCDs
   if (want < kXcds) want = kXcds;  // (empty ranges give zeros)
   p.groups = (int)want;
-  p.rows_per_slice = p.groups;  // k_reduce sums all ranges of a spot
-  p.slices = 1;
   return p;
 }
 
