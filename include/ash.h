@@ -76,6 +76,7 @@ extern "C" {
 #define ASH_MAX_DEGREE 12      /* p + q of any monomial x^p y^q              */
 #define ASH_MAX_SIDE 65536     /* nx, ny                                     */
 #define ASH_MAX_SPOTS 1048576  /* N                                          */
+#define ASH_MAX_PRINCIPAL_MODES 66 /* D of ash_principal_modes' input          */
 
 typedef struct ash_ctx ash_ctx;
 
@@ -153,10 +154,13 @@ int ash_zernike_monomials(int ansi, int cap, int32_t* pow_out,
  *              (same mono_pow), contiguous with row stride n_mono.
  *   w_out      [N][D_out] new coefficients, contiguous with row stride
  *              D_out (a [N][D] buffer is large enough).
- * Pass mono_out / w_out to ash_set_basis / ash_set_spots.  Errors:
- * ASH_EINVAL (sizes < 1, null pointers, non-finite values, negative
- * exponents, K outside 0 .. n_rot), ASH_EUNSUPPORTED (D, n_mono or N above
- * the limits). */
+ * Pass mono_out / w_out to ash_set_basis / ash_set_spots.  The input may
+ * hold up to ASH_MAX_PRINCIPAL_MODES modes (the paper's 44-mode
+ * calibration, say): only the output, n_keep + K modes, has to fit the
+ * transforms' ASH_MAX_MODES / ASH_MAX_NONLINEAR.  Errors: ASH_EINVAL (sizes
+ * < 1, null pointers, non-finite values, negative exponents, K outside
+ * 0 .. n_rot), ASH_EUNSUPPORTED (D above ASH_MAX_PRINCIPAL_MODES, n_mono
+ * above ASH_MAX_MONOMIALS, N above ASH_MAX_SPOTS). */
 int ash_principal_modes(int N, int D, int n_mono, const int32_t* mono_pow,
                         const double* mono_coef, const double* w, int K,
                         int* D_out, double* sigma, double* mono_out,

@@ -24,6 +24,7 @@ MAX_MONOMIALS = 128
 MAX_DEGREE = 12
 MAX_SIDE = 65536
 MAX_SPOTS = 1048576
+MAX_PRINCIPAL_MODES = 66
 
 
 class AshError(RuntimeError):

@@ -69,7 +69,8 @@ extern "C" int ash_principal_modes(int N, int D, int n_mono,
   if (N < 1 || D < 1 || n_mono < 1 || !mono_pow || !mono_coef || !w ||
       !D_out || !sigma || !mono_out || !w_out)
     return ASH_EINVAL;
-  if (D > ASH_MAX_MODES || n_mono > ASH_MAX_MONOMIALS || N > ASH_MAX_SPOTS)
+  if (D > ASH_MAX_PRINCIPAL_MODES || n_mono > ASH_MAX_MONOMIALS ||
+      N > ASH_MAX_SPOTS)
     return ASH_EUNSUPPORTED;
   for (long k = 0; k < (long)D * n_mono; ++k)
     if (!isfinite(mono_coef[k])) return ASH_EINVAL;

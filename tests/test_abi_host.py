@@ -47,11 +47,12 @@ def test_status_codes_match_header():
 def test_limits_match_header():
     src = open(HEADER).read()
     lim = dict((m.group(1), int(m.group(2))) for m in
-               re.finditer(r"#define ASH_MAX_([A-Z]+) (\d+)", src))
+               re.finditer(r"#define ASH_MAX_([A-Z_]+) (\d+)", src))
     assert lim == {"MODES": _lib.MAX_MODES, "NONLINEAR": _lib.MAX_NONLINEAR,
                    "MONOMIALS": _lib.MAX_MONOMIALS,
                    "DEGREE": _lib.MAX_DEGREE, "SIDE": _lib.MAX_SIDE,
-                   "SPOTS": _lib.MAX_SPOTS}
+                   "SPOTS": _lib.MAX_SPOTS,
+                   "PRINCIPAL_MODES": _lib.MAX_PRINCIPAL_MODES}
 
 
 @pytest.mark.parametrize("ansi", range(0, 66))
@@ -153,6 +154,35 @@ def test_principal_modes_rank_k_exact():
     th = oracle.kernel_phase(w, oracle.ZernikeBasis(PM_MODES), geom, idx)
     thK = oracle.kernel_phase(wK, oracle.MonomialBasis(pw, cfK), geom, idx)
     assert np.max(np.abs(thK - th)) < 1e-10
+
+
+def test_principal_modes_of_a_44_mode_calibration():
+    """The paper's calibration size: 44 modes (ANSI 1-44, radial orders up
+    to 8; tilts kept), rotated onto K = 8 principal modes, against the
+    oracle; the output fits the transforms (2 + 8 modes)."""
+    modes = list(range(1, 45))
+    rng = np.random.default_rng(44)
+    N, nr = 120, 42
+    WR = rng.normal(size=(N, 6)) @ rng.normal(size=(6, nr)) \
+        + 0.05 * rng.normal(size=(N, nr))
+    w = np.concatenate([rng.uniform(-40, 40, size=(N, 2)), WR], axis=1)
+    pw, cf = A.zernike_table(modes)
+    assert cf.shape[0] == 44 > _lib.MAX_MODES
+    cfK, wK, sigma = A.principal_modes(pw, cf, w, 8)
+    assert cfK.shape[0] == 10 and wK.shape == (N, 10)
+    wr, br, sr = oracle.principal_modes(w, oracle.ZernikeBasis(modes), 8)
+    np.testing.assert_allclose(sigma, sr, rtol=1e-10, atol=1e-12 * sr[0])
+    geom = oracle.Geometry(36, 28)
+    idx = np.arange(geom.P)
+    th = oracle.kernel_phase(wK, oracle.MonomialBasis(pw, cfK), geom, idx)
+    th_ref = oracle.kernel_phase(wr, br, geom, idx)
+    assert np.max(np.abs(th - th_ref)) < 1e-9 * max(1.0, np.max(np.abs(th_ref)))
+    # one mode more than the limit is refused
+    big = list(range(0, _lib.MAX_PRINCIPAL_MODES + 1))
+    pwb, cfb = A.zernike_table(big)
+    wb = rng.normal(size=(5, len(big)))
+    with pytest.raises(A.AshError):
+        A.principal_modes(pwb, cfb, wb, 1)
 
 
 def test_principal_modes_errors():

@@ -40,11 +40,11 @@ def _order(ansi):
     return n
 
 
-def _smooth_w(rng, nx, ny, N, modes, rank=None, noise=0.05):
+def _smooth_w(rng, nx, ny, N, modes, rank=None, noise=0.05, decay=1):
     """Positions uniform over the Nyquist field; the aberration block is a
     smooth function of position plus noise (or of a given rank), scaled by
-    1.2/(n-1) for radial order n so that the phase stays sampled within a
-    pixel tile."""
+    1.2/(n-1)**decay for radial order n so that the phase stays sampled
+    within a pixel tile."""
     u = rng.uniform(-nx / 2, nx / 2, N)
     v = rng.uniform(-ny / 2, ny / 2, N)
     lin = [d for d in modes if d <= 2]
@@ -58,8 +58,8 @@ def _smooth_w(rng, nx, ny, N, modes, rank=None, noise=0.05):
     R = min(nx, ny) / 2
     for k, d in enumerate(lin):
         w[:, k] = {0: rng.normal(size=N), 1: np.pi * v * R / ny, 2: np.pi * u * R / nx}[d]
-    w[:, len(lin):] = WR * np.array([1.2 / (_order(d) - 1) for d in modes
-                                     if d > 2])
+    w[:, len(lin):] = WR * np.array([1.2 / (_order(d) - 1) ** decay
+                                     for d in modes if d > 2])
     return w
 
 
@@ -80,15 +80,19 @@ def _run(A, nx, ny, modes, w, K, amp, phi, y, full=False):
 
 
 @pytest.mark.parametrize("full", [False, True], ids=["auto", "full"])
-@pytest.mark.parametrize("nx,ny,N,modes,K", [
-    (256, 200, 90, list(range(15)), 5),
-    (256, 192, 300, [1, 2] + list(range(3, 28)), 8),
-    (64, 48, 20, [1, 2, 4, 12], 1),
+@pytest.mark.parametrize("nx,ny,N,modes,K,decay", [
+    (256, 200, 90, list(range(15)), 5, 1),
+    (256, 192, 300, [1, 2] + list(range(3, 28)), 8, 1),
+    # a 44-mode calibration (radial orders to 8, coefficients falling as
+    # 1/(n-1)^2) on a square pupil
+    (256, 256, 300, list(range(1, 45)), 8, 2),
+    (64, 48, 20, [1, 2, 4, 12], 1, 1),
 ])
-def test_principal_transforms_match_oracle(A, nx, ny, N, modes, K, full):
+def test_principal_transforms_match_oracle(A, nx, ny, N, modes, K, decay,
+                                           full):
     _say("case", nx, ny, N, len(modes), K, full)
     rng = np.random.default_rng(nx + ny + N)
-    w = _smooth_w(rng, nx, ny, N, modes)
+    w = _smooth_w(rng, nx, ny, N, modes, decay=decay)
     amp = rng.uniform(0.2, 1.0, size=(ny, nx)).astype(np.float32).astype(np.float64)
     phi = rng.uniform(-np.pi, np.pi, size=(ny, nx)).astype(np.float32).astype(np.float64)
     y = (rng.normal(size=N) + 1j * rng.normal(size=N)).astype(np.complex64)
