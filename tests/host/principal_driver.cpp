@@ -72,7 +72,8 @@ int main() {
   CHECK(ash_principal_modes(1, 9, 1, pw, cf, w, 10, &Dk, sig, mono, wk) == ASH_EINVAL);
   CHECK(ash_principal_modes(1, 9, 1, pw, cf, w, -1, &Dk, sig, mono, wk) == ASH_EINVAL);
   CHECK(ash_principal_modes(0, 9, 1, pw, cf, w, 1, &Dk, sig, mono, wk) == ASH_EINVAL);
-  CHECK(ash_principal_modes(1, 40, 1, pw, cf, w, 1, &Dk, sig, mono, wk) == ASH_EUNSUPPORTED);
+  CHECK(ash_principal_modes(1, ASH_MAX_PRINCIPAL_MODES + 1, 1, pw, cf, w, 1, &Dk,
+                            sig, mono, wk) == ASH_EUNSUPPORTED);
   double wn[9] = {1, 2, 3, 4, NAN, 6, 7, 8, 9};
   CHECK(ash_principal_modes(1, 9, 1, pw, cf, wn, 1, &Dk, sig, mono, wk) == ASH_EINVAL);
   if (fails) return 1;
