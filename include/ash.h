@@ -46,6 +46,11 @@
  *     never by ash_forward, ash_adjoint or ash_wgs_iterate.
  *   - Compute calls are asynchronous on the context's stream.  A context is
  *     not thread-safe: use one context per host thread / stream.
+ *   - The single-context compute calls (transforms, WGS iterations, the
+ *     gradients and the Adam descent) neither synchronise nor record
+ *     memsets, and after their first call on a set-up they allocate
+ *     nothing, so a caller can capture them in a HIP graph and replay it.
+ *     The batched calls synchronise once per call and cannot be captured.
  *
  * Errors
  *   Every call returns ASH_OK (0) or a negative ASH_E* code.  Argument
