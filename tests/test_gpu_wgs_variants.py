@@ -165,3 +165,64 @@ def test_resume_is_bitwise(A):
     assert torch.equal(c2.fixed_phases(), c.fixed_phases())
     c2.close()
     c.close()
+
+
+def test_many_spot_update_paths_match_oracle(A):
+    """More spots than the update block has threads (2500 > 1024, so fields
+    and weights go through memory): a free step, a phase-storing step then
+    a phase-fixed step, and a feedback step, each against the oracle."""
+    nx, ny, N = 96, 64, 2500
+    modes = [1, 2, 3, 4, 5]
+    rng = np.random.default_rng(2500)
+    geom = oracle.Geometry(nx, ny)
+    basis = oracle.ZernikeBasis(modes)
+    w = rng.normal(0, 0.4, size=(N, len(modes)))
+    w[:, 0] = np.pi * rng.uniform(-ny / 2, ny / 2, N) * geom.R / ny
+    w[:, 1] = np.pi * rng.uniform(-nx / 2, nx / 2, N) * geom.R / nx
+    t = rng.uniform(0.5, 1.0, N).astype(np.float32).astype(np.float64)
+    amp = rng.uniform(0.2, 1.0, (ny, nx)).astype(np.float32).astype(np.float64)
+    phi0 = rng.uniform(-np.pi, np.pi, (ny, nx)).astype(np.float32).astype(np.float64)
+    # start from the oracle's state after three iterations (from a random
+    # phase some spots are nearly dark, and a step's phase is then
+    # ill-conditioned in theirs)
+    _, _, _, _, kept = oracle.wgs_run(phi0, t, amp, w, basis, geom, 4,
+                                      keep=(3,))
+    phi = kept[3][0].astype(np.float32).astype(np.float64)
+    W0 = kept[3][1].astype(np.float32).astype(np.float64)
+    c = A.Context(0)
+    c.set_basis(nx, ny, modes=modes, amp=_cuda(amp))
+    c.set_spots(w, t)
+
+    def check(what, ph, Wg, Eg, ref):
+        ref_phi, ref_W, ref_E, y = ref
+        _say("  %s fields" % what, field_errors(Eg.cpu().numpy(), ref_E))
+        assert_fields(Eg.cpu().numpy(), ref_E, what=what + " fields")
+        np.testing.assert_allclose(Wg.cpu().numpy(), ref_W, rtol=2e-4)
+        gref = oracle.adjoint(y, w, basis, geom)
+        assert_phase(ph.cpu().numpy(), ref_phi, gref, mask=STEP_PHASE_MASK,
+                     what=what + " phase")
+
+    def ref_step(measured=None, fixed_phase=None):
+        r_phi, r_W, r_E, _ = oracle.wgs_step(phi, W0, t, amp, w, basis, geom,
+                                             measured=measured,
+                                             fixed_phase=fixed_phase)
+        y, _ = oracle.wgs_farfield(r_E, W0, t, measured=measured,
+                                   fixed_phase=fixed_phase)
+        return r_phi, r_W, r_E, y
+
+    # free step, storing its farfield phases
+    ph = _cuda(phi)
+    _, Wg, Eg, _ = c.wgs(ph, 1, weights=_cuda(W0), fix_phase_after=1)
+    E_free = oracle.forward(amp * np.exp(1j * phi), w, basis, geom)
+    check("free", ph, Wg, Eg, ref_step())
+    # the stored phases used from the same start
+    ph = _cuda(phi)
+    _, Wg, Eg, _ = c.wgs(ph, 1, weights=_cuda(W0), fix_phase_after=-1)
+    check("fixed", ph, Wg, Eg, ref_step(fixed_phase=np.angle(E_free)))
+    # feedback: measured amplitudes replace |E| in the weight update
+    meas = (rng.uniform(0.7, 1.3, N) * np.abs(E_free)).astype(np.float32)
+    meas = meas.astype(np.float64)
+    ph = _cuda(phi)
+    _, Wg, Eg, _ = c.wgs_feedback(ph, _cuda(meas), weights=_cuda(W0))
+    check("feedback", ph, Wg, Eg, ref_step(measured=meas))
+    c.close()
