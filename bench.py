@@ -139,16 +139,21 @@ def calibrate_copy(mib):
           flush=True)
 
 
-def profiled_traffic(workload, kernel, summary="wgs_kernels"):
+def kernel_source_sha256():
+    src = os.path.join(ROOT, "paper_2505_08777_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()
+
+
+def profiled_traffic(workload, kernel, summary="wgs_kernels", profiles=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
     of this workload (FETCH_SIZE and WRITE_SIZE, scaled by what they read
     for a plain copy), or None when the summary was taken on other kernel
     source than the one built here."""
-    path = os.path.join(ROOT, "profiles", "%s_%s.txt" % (summary, workload))
-    src = os.path.join(ROOT, "paper_2505_08777_amd", "csrc", "kernels.hip")
+    profiles = profiles or os.path.join(ROOT, "profiles")
+    path = os.path.join(profiles, "%s_%s.txt" % (summary, workload))
     if not os.path.exists(path):
         return None, None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = kernel_source_sha256()
     rec, val = None, None
     for line in open(path):
         if line.startswith("kernels_hip_sha256:"):

@@ -42,14 +42,15 @@
  *     work that uses it has finished.  *_host arrays are read before the
  *     call returns.
  *   - The library owns the context and all scratch memory.  Scratch is
- *     allocated only by ash_set_basis / ash_set_spots (and batched set-up),
- *     never by ash_forward, ash_adjoint or ash_wgs_iterate.
+ *     allocated only by ash_set_basis / ash_set_spots (and the batch's
+ *     create / tune / load_tuning calls), never by a single-context compute
+ *     call (transforms, WGS, gradients, Adam, moments, window quality).
  *   - Compute calls are asynchronous on the context's stream.  A context is
  *     not thread-safe: use one context per host thread / stream.
  *   - The single-context compute calls (transforms, WGS iterations, the
- *     gradients and the Adam descent) neither synchronise nor record
- *     memsets, and after their first call on a set-up they allocate
- *     nothing, so a caller can capture them in a HIP graph and replay it.
+ *     gradients and the Adam descent) neither synchronise, nor record
+ *     memsets, nor allocate, so a caller can capture them in a HIP graph
+ *     and replay it.
  *     The batched calls synchronise once per call and cannot be captured.
  *
  * Errors
@@ -320,10 +321,15 @@ int ash_coef_grad(ash_ctx* ctx, const float* phase_dev, const float* G_dev,
  *
  * ash_window_coefficients (host-only): expand w (host [N][D] float64) into
  * w_out (host [N*win*win][D]), spot-major with the window's x offset
- * fastest: row (k*win + b)*win + a is w[k] with w[k][ix] += (a - win/2) dwx
- * and w[k][iy] += (b - win/2) dwy (radians; dwx = pi s R / nx moves the x
- * tilt Z_2 = 2 xh by s DFT bins).  win odd; ix != iy the x / y tilt modes.
- * Errors: ASH_EINVAL, ASH_EUNSUPPORTED (N*win*win > ASH_MAX_SPOTS).
+ * fastest: row (k*win + b)*win + a is w[k] with the spot moved by
+ * ((a - win/2) step, (b - win/2) step) DFT bins of an nx x ny SLM:
+ * w[k][ix] += (a - win/2) dwx, w[k][iy] += (b - win/2) dwy, with
+ * dwx = pi step R / nx and dwy = pi step R / ny (radians), the coefficient
+ * change that moves the orthonormal tilts Z = 2 xh (mode ix) and Z = 2 yh
+ * (mode iy) of a pupil of radius R pixels by `step` bins.  win odd;
+ * ix != iy.  Errors: ASH_EINVAL (sizes < 1, even win, bad mode indices,
+ * R <= 0 or non-finite R / step), ASH_EUNSUPPORTED (N*win*win >
+ * ASH_MAX_SPOTS).
  *
  * ash_window_strehl: with the context's spots set to such an expansion
  * (N = n_windows * win * win), the forward transform of A exp(i phase)
@@ -332,7 +338,8 @@ int ash_coef_grad(ash_ctx* ctx, const float* phase_dev, const float* G_dev,
  * device [n_windows] float32.  Errors: ASH_EINVAL, ASH_ENOTREADY,
  * ASH_ESHAPE (spot count not n_windows*win*win), ASH_EHIP. */
 int ash_window_coefficients(int N, int D, const double* w, int ix, int iy,
-                            double dwx, double dwy, int win, double* w_out);
+                            int nx, int ny, double R, double step, int win,
+                            double* w_out);
 int ash_window_strehl(ash_ctx* ctx, const float* phase_dev, int n_windows,
                       int win, float* S_dev);
 
@@ -359,7 +366,7 @@ typedef struct ash_adam_params {
  * Paper: Methods, "Computational Scaling"; the loss, TV term and Adam are
  * stated readings (the paper names gradient descent only).
  * Errors: ASH_EINVAL (null arrays, n_steps or step0 < 0, parameters out of
- * range, zero source amplitude), ASH_ENOTREADY, ASH_ENOMEM, ASH_EHIP. */
+ * range, zero source amplitude), ASH_ENOTREADY, ASH_EHIP. */
 int ash_adam_iterate(ash_ctx* ctx, float* phase_dev, float* m_dev,
                      float* v_dev, int step0, int n_steps,
                      const ash_adam_params* params, float* loss_dev,

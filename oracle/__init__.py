@@ -40,7 +40,8 @@ from .wgs import wgs_farfield, wgs_step, wgs_run, wgs_stats
 from .grad import (spot_norm, spot_loss, tv_loss, total_loss, loss_grad,
                    fd_grad, adam_step, adam_run, forward_moments, coef_grad)
 from .principal import linear_modes, RotatedBasis, principal_modes
-from .quality import window_coefficients, window_strehl, spot_quality
+from .quality import (window_coefficients, window_spacing, window_strehl,
+                      spot_quality)
 
 __all__ = [
     "ansi_to_nm", "nm_to_ansi", "noll_to_nm", "noll_to_ansi", "zernike_nm",
@@ -48,5 +49,5 @@ __all__ = [
     "adjoint", "wgs_farfield", "wgs_step", "wgs_run", "wgs_stats", "spot_norm", "spot_loss",
     "tv_loss", "total_loss", "loss_grad", "fd_grad", "adam_step", "adam_run",
     "linear_modes", "RotatedBasis", "principal_modes", "forward_moments",
-    "coef_grad", "window_coefficients", "window_strehl", "spot_quality",
+    "coef_grad", "window_coefficients", "window_spacing", "window_strehl", "spot_quality",
 ]

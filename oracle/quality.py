@@ -36,6 +36,14 @@ def window_coefficients(w, ix, iy, dwx, dwy, win):
     return out.reshape(N * win * win, -1)
 
 
+def window_spacing(geom, step):
+    """Coefficient changes (dwx, dwy) in radians that move a spot by `step`
+    DFT bins along x and y: one bin is a phase slope of 2 pi / n per pixel,
+    and the orthonormal tilts 2 xh, 2 yh have slope 2 / R per unit
+    coefficient."""
+    return np.pi * step * geom.R / geom.nx, np.pi * step * geom.R / geom.ny
+
+
 def window_strehl(E, N, win):
     """S'_k = max |E|^2 / sum |E|^2 over spot k's window (0 for a dark one)."""
     I = np.abs(np.asarray(E, dtype=np.complex128)).reshape(N, win * win) ** 2
@@ -49,8 +57,7 @@ def spot_quality(f, w, basis, geom, ix, iy, win=21, step=0.25, spots=None,
     w = np.asarray(w, dtype=np.float64)
     if spots is not None:
         w = w[np.asarray(spots)]
-    dwx = np.pi * step * geom.R / geom.nx
-    dwy = np.pi * step * geom.R / geom.ny
+    dwx, dwy = window_spacing(geom, step)
     ww = window_coefficients(w, ix, iy, dwx, dwy, win)
     E = forward(f, ww, basis, geom, workers=workers)
     return window_strehl(E, w.shape[0], win)

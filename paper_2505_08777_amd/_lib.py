@@ -102,7 +102,7 @@ def _load():
         "ash_phase_grad": (I, [P, P, P, P]),
         "ash_forward_moments": (I, [P, P, P]),
         "ash_coef_grad": (I, [P, P, P, P]),
-        "ash_window_coefficients": (I, [I, I, P, I, I, D, D, I, P]),
+        "ash_window_coefficients": (I, [I, I, P, I, I, I, I, D, D, I, P]),
         "ash_window_strehl": (I, [P, P, I, I, P]),
         "ash_adam_iterate": (I, [P, P, P, P, I, I, ctypes.POINTER(AdamParams),
                                  P, P]),

@@ -7,7 +7,6 @@ torch supplies device memory (tensors) and the stream.  Pixel arrays are
 """
 
 import ctypes
-import math
 
 import numpy as np
 import torch
@@ -47,6 +46,11 @@ class Context:
         self.cx = self.cy = self.R = None
         self.modes = None
         self.target = None
+        # bumped by every set_basis / set_spots (generation) and by every
+        # set_basis (basis_generation): a backward pass checks that the basis
+        # and spots its forward used are still the context's
+        self.generation = 0
+        self.basis_generation = 0
 
     # -- lifetime ---------------------------------------------------------
     def close(self):
@@ -135,6 +139,8 @@ class Context:
         self.cx, self.cy, self.R = float(cx), float(cy), float(R)
         self.N = None
         self.target = None
+        self.generation += 1
+        self.basis_generation += 1
 
     def set_spots(self, w, target=None):
         w = np.ascontiguousarray(w, dtype=np.float64)
@@ -151,6 +157,7 @@ class Context:
               "ash_set_spots", self._h)
         self.N = w.shape[0]
         self.target = t
+        self.generation += 1
 
     # -- transforms ---------------------------------------------------------
     def forward(self, phase=None, field=None, out=None):
@@ -345,16 +352,23 @@ class Propagate(torch.autograd.Function):
 
     The backward is the library's adjoint with the phase-gradient epilogue:
     grad_phase = Im(conj(f) sum_n G_n exp(+i theta_n)), where G is torch's
-    gradient of the loss with respect to the complex E."""
+    gradient of the loss with respect to the complex E.  It needs the
+    context's basis and spots of the forward: a set_basis or set_spots
+    between the two makes the backward raise."""
 
     @staticmethod
     def forward(ctx, phase, context):
         ctx.context = context
+        ctx.generation = context.generation
         ctx.save_for_backward(phase)
         return context.forward(phase=phase.contiguous())
 
     @staticmethod
     def backward(ctx, grad_E):
+        if ctx.context.generation != ctx.generation:
+            raise RuntimeError(
+                "propagate: the context's basis or spots changed between the "
+                "forward and the backward; the gradient would use the new ones")
         (phase,) = ctx.saved_tensors
         G = grad_E.to(torch.complex64).contiguous()
         return ctx.context.phase_grad(phase.contiguous(), G), None
@@ -367,26 +381,39 @@ class PropagateSpots(torch.autograd.Function):
     The forward sets the context's spots to w (keeping its targets); the
     backward returns the phase gradient of Propagate and
     dL/dw[k, d] = Im(conj(G_k) M[k, d]) from the library's moment
-    transform (ash_coef_grad)."""
+    transform (ash_coef_grad).  If the context's spots changed after the
+    forward (another propagate with other w, say), the backward sets them
+    back to this forward's w and targets first; a changed basis raises."""
 
     @staticmethod
     def forward(ctx, phase, w, context):
         context.set_spots(w.detach().to("cpu", torch.float64).numpy(),
                           context.target)
         ctx.context = context
+        ctx.generation = context.generation
+        ctx.basis_generation = context.basis_generation
+        ctx.target = context.target
         ctx.save_for_backward(phase, w)
         return context.forward(phase=phase.contiguous())
 
     @staticmethod
     def backward(ctx, grad_E):
         phase, w = ctx.saved_tensors
+        c = ctx.context
+        if c.generation != ctx.generation:
+            if c.basis_generation != ctx.basis_generation:
+                raise RuntimeError(
+                    "propagate: the context's basis changed between the "
+                    "forward and the backward")
+            c.set_spots(w.detach().to("cpu", torch.float64).numpy(),
+                        ctx.target)
+            ctx.generation = c.generation
         G = grad_E.to(torch.complex64).contiguous()
         gp = gw = None
         if ctx.needs_input_grad[0]:
-            gp = ctx.context.phase_grad(phase.contiguous(), G)
+            gp = c.phase_grad(phase.contiguous(), G)
         if ctx.needs_input_grad[1]:
-            gw = ctx.context.coef_grad(phase.contiguous(), G).to(w.device,
-                                                                 w.dtype)
+            gw = c.coef_grad(phase.contiguous(), G).to(w.device, w.dtype)
         return gp, gw, None
 
 
@@ -398,15 +425,16 @@ def propagate(phase, context, w=None):
     return PropagateSpots.apply(phase, w, context)
 
 
-def window_coefficients(w, ix, iy, dwx, dwy, win):
-    """Coefficients of the win x win window points of every spot (see
+def window_coefficients(w, ix, iy, nx, ny, R, step, win):
+    """Coefficients of the win x win window points of every spot, `step`
+    DFT bins apart on an nx x ny SLM with pupil radius R (see
     ash_window_coefficients): [N * win * win, D] float64."""
     w = np.ascontiguousarray(w, dtype=np.float64)
     N, D = w.shape
     out = np.empty((N * win * win, D), dtype=np.float64)
     check(lib.ash_window_coefficients(N, D, w.ctypes.data, int(ix), int(iy),
-                                      float(dwx), float(dwy), int(win),
-                                      out.ctypes.data),
+                                      int(nx), int(ny), float(R), float(step),
+                                      int(win), out.ctypes.data),
           "ash_window_coefficients")
     return out
 
@@ -415,9 +443,8 @@ def spot_quality(camera, phase, w, ix, iy, win=21, step=0.25):
     """S' of win x win farfield windows sampled every `step` DFT bins around
     the spots w, seen through `camera` (a context holding the system's basis
     and amplitude; its spots are replaced by the windows)."""
-    dwx = math.pi * step * camera.R / camera.nx
-    dwy = math.pi * step * camera.R / camera.ny
-    ww = window_coefficients(w, ix, iy, dwx, dwy, win)
+    ww = window_coefficients(w, ix, iy, camera.nx, camera.ny, camera.R, step,
+                             win)
     camera.set_spots(ww)
     return camera.window_strehl(phase, np.asarray(w).shape[0], win)
 

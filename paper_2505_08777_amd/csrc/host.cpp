@@ -156,7 +156,7 @@ void free_basis(ash_ctx* c) {
   dfree(b.grad);
   dfree(b.tvp);
   dfree(b.lossbuf);
-  b.cap_pixtab = b.cap_grad = b.cap_tvp = 0;
+  b.cap_pixtab = 0;
   c->has_basis = false;
   c->basis = Basis();
 }
@@ -469,7 +469,10 @@ int ash_set_basis(ash_ctx* c, int nx, int ny, double cx, double cy, double R,
       (rc = dalloc(c, &B.d_nlcoef, std::max(nlcoef.size(), (size_t)1),
                    "monomial coefficients")) ||
       (rc = dalloc(c, &B.d_coef, (size_t)D * n_mono, "basis coefficients")) ||
-      (rc = dalloc(c, &B.momtab, npix * 2 * (size_t)D, "moment table"))) {
+      (rc = dalloc(c, &B.momtab, npix * 2 * (size_t)D, "moment table")) ||
+      (rc = dalloc(c, &B.grad, P, "gradient")) ||
+      (rc = dalloc(c, &B.tvp, (size_t)g.n_tiles * kBlkPerTile, "TV sums")) ||
+      (rc = dalloc(c, &B.lossbuf, 1, "loss"))) {
     free_basis(c);
     return rc;
   }
@@ -564,6 +567,7 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
     dfree(B.y);
     dfree(B.Ebuf);
     dfree(B.spot64);
+    dfree(B.fixph);
     B.cap_spots = 0;
     if ((rc = dalloc(c, &B.target, (size_t)N, "targets")) ||
         (rc = dalloc(c, &B.y, 8 * n_pad, "spot fields")) ||
@@ -733,12 +737,16 @@ int ash_coef_grad(ash_ctx* c, const float* phase_dev, const float* G_dev,
 }
 
 int ash_window_coefficients(int N, int D, const double* w, int ix, int iy,
-                            double dwx, double dwy, int win, double* w_out) {
+                            int nx, int ny, double R, double step, int win,
+                            double* w_out) {
   if (N < 1 || D < 1 || !w || !w_out || win < 1 || win % 2 == 0 || ix < 0 ||
-      iy < 0 || ix >= D || iy >= D || ix == iy || !isfinite(dwx) ||
-      !isfinite(dwy))
+      iy < 0 || ix >= D || iy >= D || ix == iy || nx < 1 || ny < 1 ||
+      !isfinite(R) || !(R > 0.0) || !isfinite(step))
     return ASH_EINVAL;
   if ((long)N * win * win > ASH_MAX_SPOTS) return ASH_EUNSUPPORTED;
+  // one DFT bin along x is a phase slope of 2 pi / nx per pixel; the tilt
+  // Z = 2 xh = 2 (i - cx) / R has slope 2 / R per unit coefficient
+  const double dwx = M_PI * step * R / nx, dwy = M_PI * step * R / ny;
   const int h = win / 2;
   for (int k = 0; k < N; ++k)
     for (int b = 0; b < win; ++b)
@@ -923,23 +931,6 @@ int ash_wgs_feedback(ash_ctx* c, float* phase_dev, float* weights_dev,
                   measured_dev);
 }
 
-namespace {
-
-// Buffers of the differentiable form (sized by the basis).
-int grad_buffers(ash_ctx* c) {
-  Buffers& B = c->buf;
-  const Geom& g = c->basis.g;
-  int rc;
-  if ((rc = grow(c, &B.grad, &B.cap_grad, (size_t)g.nx * g.ny, "gradient")) ||
-      (rc = grow(c, &B.tvp, &B.cap_tvp, (size_t)g.n_tiles * kBlkPerTile,
-                 "TV sums")))
-    return rc;
-  if (!B.lossbuf && (rc = dalloc(c, &B.lossbuf, 1, "loss"))) return rc;
-  return ASH_OK;
-}
-
-}  // namespace
-
 int ash_phase_grad(ash_ctx* c, const float* phase_dev, const float* G_dev,
                    float* grad_dev) {
   if (!c) return ASH_EINVAL;
@@ -985,7 +976,6 @@ int ash_adam_iterate(ash_ctx* c, float* phase_dev, float* m_dev, float* v_dev,
   if (n_steps == 0) return ASH_OK;
   int rc = use_device(c);
   if (rc) return rc;
-  if ((rc = grad_buffers(c))) return rc;
   const Geom& g = c->basis.g;
   Buffers& B = c->buf;
   const int N = c->spots.N;

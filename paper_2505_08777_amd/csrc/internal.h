@@ -87,7 +87,6 @@ struct Buffers {
   float* grad = nullptr;              // [P] phase gradient
   float* tvp = nullptr;               // [n_tiles * kBlkPerTile] TV sums
   float* lossbuf = nullptr;           // [1] spot term of the loss
-  size_t cap_grad = 0, cap_tvp = 0;
   float* mom_partial = nullptr;  // [ranges][2D][NP] moment range sums
   float* fixph = nullptr;        // [NP] stored farfield phases (turns)
   size_t cap_spots = 0, cap_spotrec = 0, cap_w = 0, cap_off = 0,

@@ -203,17 +203,23 @@ def test_principal_modes_errors():
 def test_window_coefficients_match_oracle_and_errors():
     rng = np.random.default_rng(31)
     w = rng.normal(size=(4, 6))
-    a = A.window_coefficients(w, 2, 1, 0.3, -0.2, 7)
-    b = oracle.window_coefficients(w, 2, 1, 0.3, -0.2, 7)
-    np.testing.assert_array_equal(a, b)
+    for nx, ny, R, step in ((64, 48, 24.0, 0.3), (1920, 1200, 600.0, -0.25)):
+        geom = oracle.Geometry(nx, ny, R=R)
+        a = A.window_coefficients(w, 2, 1, nx, ny, R, step, 7)
+        b = oracle.window_coefficients(w, 2, 1,
+                                       *oracle.window_spacing(geom, step), 7)
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-14)
     out = np.zeros(4 * 49 * 6)
     L = _lib.lib
-    assert L.ash_window_coefficients(4, 6, w.ctypes.data, 2, 1, 0.3, 0.2, 6,
-                                     out.ctypes.data) == _lib.EINVAL   # even
-    assert L.ash_window_coefficients(4, 6, w.ctypes.data, 2, 2, 0.3, 0.2, 7,
-                                     out.ctypes.data) == _lib.EINVAL   # ix == iy
-    assert L.ash_window_coefficients(4, 6, w.ctypes.data, 6, 1, 0.3, 0.2, 7,
-                                     out.ctypes.data) == _lib.EINVAL   # ix >= D
-    assert L.ash_window_coefficients(4, 6, w.ctypes.data, 2, 1, float("nan"),
-                                     0.2, 7, out.ctypes.data) == _lib.EINVAL
+
+    def call(ix=2, iy=1, nx=64, ny=48, R=24.0, step=0.3, win=7):
+        return L.ash_window_coefficients(4, 6, w.ctypes.data, ix, iy, nx, ny,
+                                         R, step, win, out.ctypes.data)
+    assert call() == _lib.OK
+    assert call(win=6) == _lib.EINVAL           # even window
+    assert call(iy=2) == _lib.EINVAL            # ix == iy
+    assert call(ix=6) == _lib.EINVAL            # ix >= D
+    assert call(step=float("nan")) == _lib.EINVAL
+    assert call(R=0.0) == _lib.EINVAL
+    assert call(nx=0) == _lib.EINVAL
     assert L.ash_window_strehl(None, None, 1, 1, None) == _lib.EINVAL

@@ -44,11 +44,16 @@ def test_issue_ceiling_and_flop_count():
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
 
 
-def test_profiled_traffic_follows_the_kernel_source():
-    val, src = bench.profiled_traffic("field1024", "k_adjoint<3, false>")
-    assert src == os.path.join("profiles", "wgs_kernels_field1024.txt")
-    # the committed summary was taken on the current kernels, so its bytes
-    # are used; an unknown workload or kernel gives none
-    assert val is not None and val > 0
-    assert bench.profiled_traffic("nosuch", "k_forward<3, false>") == (None, None)
-    assert bench.profiled_traffic("field1024", "k_nosuch")[0] is None
+def test_profiled_traffic_follows_the_kernel_source(tmp_path):
+    # a summary taken on the current kernel source gives its bytes; one
+    # taken on other source, an unknown workload or kernel give none
+    k = "k_adjoint<3, false>"
+    for name, sha in (("now", bench.kernel_source_sha256()), ("old", "0" * 64)):
+        (tmp_path / ("wgs_kernels_%s.txt" % name)).write_text(
+            "kernels_hip_sha256: %s\ntraffic_bytes_per_launch[%s]: 1.5e8 bytes\n"
+            % (sha, k))
+    val, src = bench.profiled_traffic("now", k, profiles=str(tmp_path))
+    assert val == 1.5e8 and src.endswith("wgs_kernels_now.txt")
+    assert bench.profiled_traffic("old", k, profiles=str(tmp_path))[0] is None
+    assert bench.profiled_traffic("now", "k_nosuch", profiles=str(tmp_path))[0] is None
+    assert bench.profiled_traffic("nosuch", k, profiles=str(tmp_path)) == (None, None)

@@ -152,3 +152,48 @@ def test_grad1024_sampled_moments(A):
     _say("  coef grad", field_errors(g[sel], gref))
     assert_fields(g[sel], gref, what="sampled coefficient gradient")
     c.close()
+
+
+def test_backward_after_spot_change(A):
+    """Two propagate calls with different w before one backward: each
+    backward uses its own forward's spots (PropagateSpots sets them back),
+    and a phase-only propagate whose context changed spots refuses."""
+    nx, ny, N, modes = 96, 64, 40, [1, 2, 3, 4, 5, 6]
+    rng = np.random.default_rng(77)
+    geom = oracle.Geometry(nx, ny)
+    basis = oracle.ZernikeBasis(modes)
+    w1 = _spots(rng, nx, ny, N, modes, 0.5, geom.R)
+    w2 = _spots(rng, nx, ny, N, modes, 0.5, geom.R)
+    amp = rng.uniform(0.2, 1.0, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    G = (rng.normal(size=N) + 1j * rng.normal(size=N)).astype(np.complex64)
+    c = A.Context(0)
+    c.set_basis(nx, ny, modes=modes,
+                amp=torch.tensor(amp, dtype=torch.float32, device="cuda"))
+    c.set_spots(w1)
+    Gt = torch.tensor(G, device="cuda")
+    ph1 = torch.tensor(phi, dtype=torch.float32, device="cuda", requires_grad=True)
+    ph2 = torch.tensor(phi, dtype=torch.float32, device="cuda", requires_grad=True)
+    wt1 = torch.tensor(w1, dtype=torch.float64, requires_grad=True)
+    wt2 = torch.tensor(w2, dtype=torch.float64, requires_grad=True)
+    E1 = A.propagate(ph1, c, w=wt1)
+    E2 = A.propagate(ph2, c, w=wt2)      # the context now holds w2
+    # L = Re(sum conj(G) E) has field gradient G
+    torch.sum(torch.real(torch.conj(Gt) * E1)).backward()
+    f = amp * np.exp(1j * phi)
+    gw = oracle.coef_grad(f, w1, basis, geom, G.astype(np.complex128))
+    gp = np.imag(np.conj(f) * oracle.adjoint(G.astype(np.complex128), w1, basis, geom))
+    _say("  first backward: dL/dw", field_errors(wt1.grad.numpy(), gw),
+         "dL/dphi", field_errors(ph1.grad.cpu().numpy(), gp))
+    assert_fields(wt1.grad.numpy(), gw, what="dL/dw of the first forward")
+    assert_fields(ph1.grad.cpu().numpy(), gp, what="dL/dphi of the first forward")
+    torch.sum(torch.real(torch.conj(Gt) * E2)).backward()
+    gw2 = oracle.coef_grad(f, w2, basis, geom, G.astype(np.complex128))
+    assert_fields(wt2.grad.numpy(), gw2, what="dL/dw of the second forward")
+    # phase-only propagate: a set_spots between forward and backward refuses
+    ph3 = torch.tensor(phi, dtype=torch.float32, device="cuda", requires_grad=True)
+    E3 = A.propagate(ph3, c)
+    c.set_spots(w1)
+    with pytest.raises(RuntimeError):
+        torch.sum(torch.real(torch.conj(Gt) * E3)).backward()
+    c.close()

@@ -375,11 +375,20 @@ def test_wgs_stats_definitions():
     t = np.array([1.0, 1.0, 2.0])
     amp = np.ones((2, 3))
     st = oracle.wgs_stats(E, t, amp)
-    I = np.array([25.0, 1.0, 1.0])
+    # I = |E|^2 / t^2 = [25, 1, 1]: mean 9, deviations (16, -8, -8), population
+    # variance (256 + 64 + 64) / 3 = 128, so the spread is 8 sqrt(2) / 9
     assert st[0] == pytest.approx(30.0 / (6 * 6))
     assert st[1] == pytest.approx(1 - 24 / 26)
-    assert st[2] == pytest.approx(np.std(I) / np.mean(I))
+    assert st[2] == pytest.approx(8.0 * np.sqrt(2.0) / 9.0, rel=1e-15)
     assert st[3] == pytest.approx(30.0)
+    # I = [1, 3]: mean 2, population std 1, spread 1/2; equal intensities
+    # have spread 0 and uniformity 1
+    st2 = oracle.wgs_stats(np.array([1.0 + 0j, 0 + 3j]), np.array([1.0, np.sqrt(3.0)]),
+                           np.ones(4))
+    assert st2[2] == pytest.approx(0.5, rel=1e-15)
+    st3 = oracle.wgs_stats(np.array([2.0 + 0j, -2j, 1 + 0j]), np.array([1.0, 1.0, 0.5]),
+                           np.ones(4))
+    assert st3[2] == 0.0 and st3[1] == 1.0
 
 
 def _bins_case(seed=17, N=9):
