@@ -213,6 +213,22 @@ int ash_set_spots(ash_ctx* ctx, int N, const double* w_host,
 int ash_forward(ash_ctx* ctx, const float* phase_dev, const float* field_dev,
                 float* E_dev);
 
+/* ash_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same transform, arguments and result as ash_forward, computed by the
+ * same kernels, with the forward's partial sums and their reduction held in
+ * a device-resident array inside the library (16 MiB per GPU, held until
+ * the process ends) instead of the context's buffers.  The call allocates
+ * nothing, neither records a memset nor synchronises.  Every call on one
+ * GPU shares that array: calls that overlap in time on one GPU (two streams,
+ * two contexts) race and their results are undefined; calls ordered on one
+ * stream are safe.  Nothing in the array has to start at zero (every entry
+ * read is written first by the same call).  Errors: as ash_forward, plus
+ * ASH_EUNSUPPORTED when the set-up's partial sums (forward ranges x N x 8
+ * bytes, plus N x 8) exceed 16 MiB (ash_get_info gives the ranges). */
+int ash_forward_noalloc(ash_ctx* ctx, const float* phase_dev,
+                        const float* field_dev, float* E_dev);
+
 /* Adjoint transform g(x) = sum_n y_n exp(+i theta_n(x)).
  *   y_dev          device [N][2] float32 spot fields.
  *   g_dev          device [ny][nx][2] float32 output, or NULL.

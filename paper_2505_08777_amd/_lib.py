@@ -89,6 +89,7 @@ def _load():
         "ash_set_basis": (I, [P, I, I, D, D, D, I, I, P, P, P]),
         "ash_set_spots": (I, [P, I, P, P]),
         "ash_forward": (I, [P, P, P, P]),
+        "ash_forward_noalloc": (I, [P, P, P, P]),
         "ash_adjoint": (I, [P, P, P, P]),
         "ash_wgs_iterate": (I, [P, P, P, I, ctypes.POINTER(WgsParams), P, P]),
         "ash_wgs_feedback": (I, [P, P, P, P, ctypes.POINTER(WgsParams), P, P]),

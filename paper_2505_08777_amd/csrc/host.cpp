@@ -332,6 +332,13 @@ int ash_create(ash_ctx** out, int device, void* stream) {
     (void)hipGetLastError();
     return create_fail(ASH_EHIP, "device query: compute unit count");
   }
+  // the device address of the allocation-free forward's scratch
+  e = resolve_static_scratch(device);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return create_fail(ASH_EHIP, std::string("resolving the static scratch: ") +
+                                     hipGetErrorString(e));
+  }
   ash_ctx* c = new (std::nothrow) ash_ctx();
   if (!c) return create_fail(ASH_ENOMEM, "host allocation");
   g_create_err.clear();
@@ -686,6 +693,52 @@ int ash_forward(ash_ctx* c, const float* phase_dev, const float* field_dev,
          }), "reduce");
   HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
            return launch_finish_E(N, c->plan, B.red, E_dev, c->stream);
+         }), "finish");
+  return ASH_OK;
+}
+
+int ash_forward_noalloc(ash_ctx* c, const float* phase_dev,
+                        const float* field_dev, float* E_dev) {
+  if (!c) return ASH_EINVAL;
+  c->err.clear();
+  if (!c->has_basis || !c->has_spots)
+    return fail(c, ASH_ENOTREADY, "basis and spots must be set");
+  if ((phase_dev == nullptr) == (field_dev == nullptr) || !E_dev)
+    return fail(c, ASH_EINVAL, "exactly one of phase/field, and E, required");
+  const int N = c->spots.N;
+  // partial sums [ranges][N] and their reduction [N], both float2, the
+  // reduction starting on a 256-byte boundary
+  const size_t part_bytes = (size_t)c->plan.groups * N * 2 * sizeof(float);
+  const size_t red_off = (part_bytes + 255) / 256 * 256;
+  const size_t need = red_off + (size_t)N * 2 * sizeof(float);
+  if (need > kStaticScratchBytes)
+    return fail(c, ASH_EUNSUPPORTED,
+                "the static scratch holds " +
+                    std::to_string(kStaticScratchBytes) + " bytes; this "
+                    "set-up's partial sums need " + std::to_string(need));
+  unsigned char* scr = static_cast<unsigned char*>(static_scratch(c->device));
+  if (!scr) return fail(c, ASH_EHIP, "static scratch not resolved");
+  int rc = use_device(c);
+  if (rc) return rc;
+  const Geom& g = c->basis.g;
+  Buffers& B = c->buf;
+  float* partial = reinterpret_cast<float*>(scr);
+  float* red = reinterpret_cast<float*>(scr + red_off);
+  HIPCHK(c, timed(c, ASH_PROF_FIELD, [&] {
+           return launch_make_field(g, phase_dev, field_dev, B.amp_t,
+                                    B.pixtab, B.field_t,
+                                    field_dev ? B.fmag_t : nullptr, c->stream);
+         }), "make_field");
+  HIPCHK(c, timed(c, ASH_PROF_FORWARD, [&] {
+           return launch_forward(g, N, c->plan, B.pixtab, B.field_t,
+                                 field_dev ? B.fmag_t : B.amp_t, B.spotrec,
+                                 B.offtab, partial, c->stream);
+         }), "forward");
+  HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+           return launch_reduce(N, c->plan, partial, red, c->stream);
+         }), "reduce");
+  HIPCHK(c, timed(c, ASH_PROF_REDUCE, [&] {
+           return launch_finish_E(N, c->plan, red, E_dev, c->stream);
          }), "finish");
   return ASH_OK;
 }

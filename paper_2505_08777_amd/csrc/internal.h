@@ -108,6 +108,14 @@ struct FwdPlan {
   int mom_groups = 0;  // pixel-block ranges of the moment transform
 };
 
+// Size of the device-resident scratch of the allocation-free forward.
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+// Resolve (once per device; that device is made current for the call) and
+// look up the device address of that scratch.  static_scratch returns null
+// for a device whose address was never resolved.
+hipError_t resolve_static_scratch(int device);
+void* static_scratch(int device);
+
 // Resident forward blocks per CU for a compiled record length.
 int forward_blocks_per_cu(int groups);
 FwdPlan plan_forward(int n_tiles, int N, int blocks_per_cu, int n_cu);

@@ -43,6 +43,8 @@
 // otherwise.  One v_mfma_f32_32x32x16_bf16 takes 16 slots.
 #include <math.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace ash {
@@ -1991,6 +1993,48 @@ int batch_blocks_per_cu(int G, bool reduce, bool forward) {
     default:
       return 1;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Device-resident scratch of the allocation-free forward
+// (ash_forward_noalloc): the forward's partial sums and their reduction live
+// in this file-scope array instead of context buffers.  Host code never
+// passes `scratch` itself to a kernel (in host code the name is a host-side
+// stand-in, not a device address): its device address is resolved once per
+// device with hipGetSymbolAddress, with that device current, and kept here.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t resolve_static_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != device) {
+    const hipError_t e2 = hipSetDevice(cur);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_addr[device] = p;
+  return hipSuccess;
+}
+
+void* static_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_addr[device];
 }
 
 FwdPlan plan_forward(int n_tiles, int N, int blocks_per_cu, int n_cu) {
