@@ -198,8 +198,16 @@ int ash_set_basis(ash_ctx* ctx, int nx, int ny, double cx, double cy,
  * May be called between iterations without touching pixel data (paper:
  * Methods, "Computational Scaling", agile spot updates).  Runs an FP64
  * device kernel that wraps each spot's constant and tilt terms per pixel
- * tile.  Errors: ASH_ENOTREADY (no basis), ASH_EINVAL (N < 1, null w,
- * non-finite values, t <= 0), ASH_EUNSUPPORTED, ASH_ENOMEM, ASH_EHIP. */
+ * tile and bounds the phase each kernel spans inside a 32 x 16 pixel tile
+ * (ash_info.theta_bound, turns).  Spots whose bound exceeds 256 turns are
+ * refused with ASH_EUNSUPPORTED: such kernels change by several turns
+ * between neighbouring pixels (aliased many times over), and the FP32
+ * accumulation of the in-tile phase would miss 1e-4 relative on the fields.
+ * After that refusal the context has no spots, and ash_get_info reports the
+ * refused spots' bounds.  Errors: ASH_ENOTREADY (no basis), ASH_EINVAL
+ * (N < 1, null w, non-finite values, t <= 0), ASH_EUNSUPPORTED (N above
+ * ASH_MAX_SPOTS, phase bound above 256 turns, record too long),
+ * ASH_ENOMEM, ASH_EHIP. */
 int ash_set_spots(ash_ctx* ctx, int N, const double* w_host,
                   const float* target_host);
 
@@ -407,7 +415,8 @@ typedef struct ash_info {
   int32_t groups;        /* 16-slot groups = matrix-core ops per 32x32    */
   int32_t fwd_ranges;    /* pixel-block ranges of the forward transform   */
   float rm_bound;        /* max over tiles/spots of sum |c_s| max|Rm_s|   */
-  float theta_bound;     /* bound on |phase| (turns) of any spot-pixel pair */
+  float theta_bound;     /* bound on |phase| (turns) of any spot-pixel pair
+                            inside a tile; at most 256 (ash_set_spots)    */
   int32_t range_reduce;  /* 1: phases reduced to one turn before sin/cos,
                             0: bound <= 64 turns, the hardware reduces    */
 } ash_info;

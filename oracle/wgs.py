@@ -83,8 +83,9 @@ def wgs_farfield(E, weights, t, power=1.0, measured=None, fixed_phase=None):
 
 
 def wgs_step(phi, weights, t, amp, w, basis, geom, power=1.0, workers=None,
-             measured=None, fixed_phase=None):
-    """One WGS iteration. Returns (phi_new, weights_new, E, stats)."""
+             measured=None, fixed_phase=None, return_y=False):
+    """One WGS iteration. Returns (phi_new, weights_new, E, stats), and the
+    farfield projection y (phi_new = arg F_c^{-1} y) last if return_y."""
     phi = np.asarray(phi, dtype=np.float64)
     amp = np.asarray(amp, dtype=np.float64)
     t = np.asarray(t, dtype=np.float64)
@@ -94,6 +95,8 @@ def wgs_step(phi, weights, t, amp, w, basis, geom, power=1.0, workers=None,
     y, W = wgs_farfield(E, weights, t, power, measured, fixed_phase)
     g = adjoint(y, w, basis, geom, workers=workers)
     phi_new = np.arctan2(g.imag, g.real)
+    if return_y:
+        return phi_new, W, E, wgs_stats(E, t, amp), y
     return phi_new, W, E, wgs_stats(E, t, amp)
 
 

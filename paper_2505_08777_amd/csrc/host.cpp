@@ -214,6 +214,14 @@ constexpr float kTwoPieceBound = 0.5f;
 // hardware sine and cosine reduce exactly over |x| <= 256 turns.
 constexpr float kNoReduceBound = 64.0f;
 
+// Largest in-tile phase (turns) the FP32 accumulation of the phase keeps
+// within the field bar: its rounding error grows about 2e-7 relative per
+// turn of the bound (measured: 4.9e-5 at 215 turns, 8.6e-5 at 425, 1.2e-4
+// at 845).  A bound above this means kernel phases that change by several
+// turns between neighbouring pixels of a 32 x 16 tile: kernels aliased many
+// times over, which are refused rather than computed inaccurately.
+constexpr float kMaxPhaseBound = 256.0f;
+
 }  // namespace
 
 extern "C" {
@@ -614,6 +622,14 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
     float bound, theta_bound;
     memcpy(&bound, &bound_bits[0], 4);
     memcpy(&theta_bound, &bound_bits[1], 4);
+    c->spots.rm_bound = bound;
+    c->spots.theta_bound = theta_bound;
+    if (!(theta_bound <= kMaxPhaseBound))
+      return fail(c, ASH_EUNSUPPORTED,
+                  "in-tile phase bound " + std::to_string(theta_bound) +
+                      " turns exceeds " + std::to_string(kMaxPhaseBound) +
+                      ": kernels aliased between neighbouring pixels "
+                      "(lower the coefficients or raise R)");
     g.reduce = theta_bound <= kNoReduceBound ? 0 : 1;
     const int pieces =
         (c->precision == ASH_PRECISION_AUTO && bound <= kTwoPieceBound) ? 2
@@ -637,8 +653,6 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "preparing spots");
     }
-    c->spots.rm_bound = bound;
-    c->spots.theta_bound = theta_bound;
   }
   {
     FwdPlan plan = plan_forward(g.n_tiles, N, forward_blocks_per_cu(g.groups),

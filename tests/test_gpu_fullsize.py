@@ -6,21 +6,28 @@ launch plan).  Each forward output depends on one spot and each adjoint
 output on one pixel, so sampled outputs from the FP64 oracle are exact
 references: 64 spots over all pixels, and 4096 pixels over all spots.  At
 1024 x 1024 one whole WGS step is also checked on the sampled pixels (the
-oracle's forward there runs over every spot).
+oracle's forward there runs over every spot), from the random start and
+from the oracle's own states at iterations 1, 10 and 99; at 1920 x 1200
+one step from the random start, the oracle's forward over every spot.
 """
 
+import json
+import os
 import sys
 
 import numpy as np
 import pytest
 
 import oracle
+import stepcheck
 import workloads
 from tolerance import (assert_fields, assert_phase, field_errors,
                        STEP_PHASE_MASK)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _say(*a):
@@ -76,22 +83,57 @@ def test_fullsize_sampled_transforms(A, name):
     c.close()
 
 
-def test_fullsize_wgs_step_field1024(A):
+def _golden_state(k):
+    with open(os.path.join(GOLDEN, "field1024_states.json")) as fh:
+        st = json.load(fh)["states"][str(k)]
+    return (np.asarray(st["y_re"]) + 1j * np.asarray(st["y_im"]),
+            np.asarray(st["W"]))
+
+
+@pytest.mark.parametrize("k", [0, 1, 10, 99])
+def test_fullsize_wgs_step_field1024(A, k):
+    """One WGS step at 1024 x 1024 with 400 spots from the state entering
+    iteration k of the oracle's own run (k = 0: the workload's random start
+    phase, unit weights; later states from tests/golden/field1024_states.json,
+    written by the oracle), against the oracle's step from the same state:
+    all fields, all weights, phases at 4096 sampled pixels."""
     d, c, geom, basis, amp, phi = _setup(A, "field1024")
     N = d["w"].shape[0]
     t = d["t"].astype(np.float32).astype(np.float64)
+    W = np.ones(N)
+    if k > 0:
+        y_prev, W = _golden_state(k)
+        phi = np.angle(oracle.adjoint(y_prev, d["w"], basis, geom))
+        phi = phi.astype(np.float32).astype(np.float64)
+        W = W.astype(np.float32).astype(np.float64)
+    _say("state entering iteration", k)
+    ph = torch.tensor(phi, dtype=torch.float32, device="cuda")
+    Wt = torch.tensor(W, dtype=torch.float32, device="cuda")
+    _, Wg, Eg, _ = c.wgs(ph, 1, weights=Wt)
+    rng = np.random.default_rng(1024 + k)
+    pix = np.sort(rng.choice(geom.P, size=4096, replace=False))
+    ref = stepcheck.reference_step(phi, W, t, amp, d["w"], basis, geom,
+                                   pixels=pix)
+    stepcheck.check_step("field1024 step %d" % k, ph, Wg, Eg, ref, t,
+                         pixels=pix)
+    c.close()
+
+
+def test_fullsize_wgs_step_volume1920(A):
+    """One WGS step at 1920 x 1200 with 2000 spots from the workload's random
+    start phase: the oracle's forward over every spot and pixel (4.6 G
+    evaluations), its weight update, and its adjoint at 4096 sampled
+    pixels, against the GPU's step in the benchmarked set-up."""
+    d, c, geom, basis, amp, phi = _setup(A, "volume1920")
+    N = d["w"].shape[0]
+    t = d["t"].astype(np.float32).astype(np.float64)
+    _say("case volume1920 step 0", c.info())
     ph = torch.tensor(phi, dtype=torch.float32, device="cuda")
     Wt = torch.ones(N, dtype=torch.float32, device="cuda")
     _, Wg, Eg, _ = c.wgs(ph, 1, weights=Wt)
-    Eref = oracle.forward(amp * np.exp(1j * phi), d["w"], basis, geom)
-    _say("  forward (all spots)", field_errors(Eg.cpu().numpy(), Eref))
-    assert_fields(Eg.cpu().numpy(), Eref, what="wgs forward")
-    y, W = oracle.wgs_farfield(Eref, np.ones(N), t)
-    np.testing.assert_allclose(Wg.cpu().numpy(), W, rtol=2e-4)
-    rng = np.random.default_rng(1024)
+    rng = np.random.default_rng(1920)
     pix = np.sort(rng.choice(geom.P, size=4096, replace=False))
-    gref = oracle.adjoint(y, d["w"], basis, geom, pixels=pix)
-    got = ph.cpu().numpy().reshape(-1)[pix]
-    _say("  phase", assert_phase(got, np.angle(gref), gref,
-                                 mask=STEP_PHASE_MASK, what="wgs step phase"))
+    ref = stepcheck.reference_step(phi, np.ones(N), t, amp, d["w"], basis,
+                                   geom, pixels=pix)
+    stepcheck.check_step("volume1920 step 0", ph, Wg, Eg, ref, t, pixels=pix)
     c.close()

@@ -456,3 +456,59 @@ def test_paper_magnitudes_pyramid_and_astigmatism(A):
     _say("  astigmatism adjoint", field_errors(g, gref))
     assert_fields(g, gref, what="astigmatism adjoint")
     c.close()
+
+
+def test_phase_bound_guard(A):
+    """A high-order basis on a small pupil (ANSI 0-27, radial order 6, on
+    R = 38 pixels of a 128 x 96 SLM, corners at rho ~ 2.1): scaled so the
+    in-tile phase bound is about 140 turns the transforms still meet the
+    field bar in both precisions; scaled to about 530 turns (kernels
+    changing by several turns between neighbouring pixels) set_spots is
+    refused and the context holds no spots."""
+    from paper_2505_08777_amd import _lib
+    nx, ny, R, N = 128, 96, 38.0, 60
+    modes = list(range(28))
+    rng = np.random.default_rng(6)
+    geom = oracle.Geometry(nx, ny, R=R)
+    basis = oracle.ZernikeBasis(modes)
+    w0 = rng.normal(0, 1.0, size=(N, len(modes)))
+    w0[:, 1] = np.pi * rng.uniform(-ny / 2, ny / 2, N) * R / ny
+    w0[:, 2] = np.pi * rng.uniform(-nx / 2, nx / 2, N) * R / nx
+    nl = [k for k in modes if k not in (0, 1, 2)]
+    amp = rng.uniform(0.2, 1.0, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    phi = rng.uniform(-np.pi, np.pi, size=(ny, nx)).astype(np.float32).astype(np.float64)
+    y = (rng.normal(size=N) + 1j * rng.normal(size=N)).astype(np.complex64)
+    c = A.Context(0)
+    c.set_basis(nx, ny, modes=modes, R=R,
+                amp=torch.tensor(amp, dtype=torch.float32, device="cuda"))
+    # the remainder bound is linear in the non-linear coefficients
+    w = w0.copy()
+    w[:, nl] *= 1e-3
+    c.set_spots(w)
+    rm1 = c.info()["rm_bound"]
+    for full in (False, True):
+        w = w0.copy()
+        w[:, nl] *= 1e-3 * 80.0 / rm1
+        c.set_precision(full)
+        c.set_spots(w)
+        info = c.info()
+        _say("  accepted", "full" if full else "auto", info)
+        assert 64 < info["theta_bound"] <= 256 and info["range_reduce"] == 1
+        E = c.forward(phase=_cuda(phi, torch.float32)).cpu().numpy()
+        Eref = oracle.forward(amp * np.exp(1j * phi), w, basis, geom)
+        g = c.adjoint(_cuda(y, torch.complex64)).cpu().numpy()
+        gref = oracle.adjoint(y.astype(np.complex128), w, basis, geom)
+        _say("    forward", field_errors(E, Eref), "adjoint", field_errors(g, gref))
+        assert_fields(E, Eref, what="forward below the phase bound")
+        assert_fields(g, gref, what="adjoint below the phase bound")
+    w = w0.copy()
+    w[:, nl] *= 1e-3 * 320.0 / rm1
+    with pytest.raises(A.AshError) as exc:
+        c.set_spots(w)
+    _say("  refused:", exc.value, c.info())
+    assert exc.value.code == _lib.EUNSUPPORTED
+    assert c.info()["theta_bound"] > 256
+    with pytest.raises(A.AshError) as exc:
+        c.forward(phase=_cuda(phi, torch.float32))
+    assert exc.value.code == _lib.ENOTREADY
+    c.close()

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+import stepcheck
 import workloads
 from tolerance import assert_fields, assert_phase, field_errors, STEP_PHASE_MASK
 
@@ -167,10 +168,15 @@ def test_resume_is_bitwise(A):
     c.close()
 
 
-def test_many_spot_update_paths_match_oracle(A):
+@pytest.mark.parametrize("start", ["random", "iteration3"])
+def test_many_spot_update_paths_match_oracle(A, start):
     """More spots than the update block has threads (2500 > 1024, so fields
-    and weights go through memory): a free step, a phase-storing step then
-    a phase-fixed step, and a feedback step, each against the oracle."""
+    and weights go through memory): a free step, a phase-fixed step and a
+    feedback step, each against the oracle's step from the same state,
+    judged in stages (fields, then weights and phases at the bars the field
+    errors imply through the step).  From the random start phase some spots
+    are nearly dark and the step is ill-conditioned in them; from the
+    oracle's state after three iterations it is not."""
     nx, ny, N = 96, 64, 2500
     modes = [1, 2, 3, 4, 5]
     rng = np.random.default_rng(2500)
@@ -182,47 +188,39 @@ def test_many_spot_update_paths_match_oracle(A):
     t = rng.uniform(0.5, 1.0, N).astype(np.float32).astype(np.float64)
     amp = rng.uniform(0.2, 1.0, (ny, nx)).astype(np.float32).astype(np.float64)
     phi0 = rng.uniform(-np.pi, np.pi, (ny, nx)).astype(np.float32).astype(np.float64)
-    # start from the oracle's state after three iterations (from a random
-    # phase some spots are nearly dark, and a step's phase is then
-    # ill-conditioned in theirs)
-    _, _, _, _, kept = oracle.wgs_run(phi0, t, amp, w, basis, geom, 4,
-                                      keep=(3,))
-    phi = kept[3][0].astype(np.float32).astype(np.float64)
-    W0 = kept[3][1].astype(np.float32).astype(np.float64)
+    if start == "random":
+        phi, W0 = phi0, np.ones(N)
+    else:
+        _, _, _, _, kept = oracle.wgs_run(phi0, t, amp, w, basis, geom, 4,
+                                          keep=(3,))
+        phi = kept[3][0].astype(np.float32).astype(np.float64)
+        W0 = kept[3][1].astype(np.float32).astype(np.float64)
     c = A.Context(0)
     c.set_basis(nx, ny, modes=modes, amp=_cuda(amp))
     c.set_spots(w, t)
-
-    def check(what, ph, Wg, Eg, ref):
-        ref_phi, ref_W, ref_E, y = ref
-        _say("  %s fields" % what, field_errors(Eg.cpu().numpy(), ref_E))
-        assert_fields(Eg.cpu().numpy(), ref_E, what=what + " fields")
-        np.testing.assert_allclose(Wg.cpu().numpy(), ref_W, rtol=2e-4)
-        gref = oracle.adjoint(y, w, basis, geom)
-        assert_phase(ph.cpu().numpy(), ref_phi, gref, mask=STEP_PHASE_MASK,
-                     what=what + " phase")
-
-    def ref_step(measured=None, fixed_phase=None):
-        r_phi, r_W, r_E, _ = oracle.wgs_step(phi, W0, t, amp, w, basis, geom,
-                                             measured=measured,
-                                             fixed_phase=fixed_phase)
-        y, _ = oracle.wgs_farfield(r_E, W0, t, measured=measured,
-                                   fixed_phase=fixed_phase)
-        return r_phi, r_W, r_E, y
+    _say("start", start)
 
     # free step, storing its farfield phases
     ph = _cuda(phi)
     _, Wg, Eg, _ = c.wgs(ph, 1, weights=_cuda(W0), fix_phase_after=1)
-    E_free = oracle.forward(amp * np.exp(1j * phi), w, basis, geom)
-    check("free", ph, Wg, Eg, ref_step())
-    # the stored phases used from the same start
+    ref = stepcheck.reference_step(phi, W0, t, amp, w, basis, geom)
+    free = stepcheck.check_step("free", ph, Wg, Eg, ref, t)
+    E_free = ref[0]
+    # the stored phases used from the same start: they are the GPU's own
+    # free-step phases, against the oracle's arg E of that step
     ph = _cuda(phi)
     _, Wg, Eg, _ = c.wgs(ph, 1, weights=_cuda(W0), fix_phase_after=-1)
-    check("fixed", ph, Wg, Eg, ref_step(fixed_phase=np.angle(E_free)))
+    ref = stepcheck.reference_step(phi, W0, t, amp, w, basis, geom,
+                                   fixed_phase=np.angle(E_free))
+    stepcheck.check_step("fixed", ph, Wg, Eg, ref, t,
+                         dpsi=free["abs_dE"] / np.abs(E_free))
     # feedback: measured amplitudes replace |E| in the weight update
     meas = (rng.uniform(0.7, 1.3, N) * np.abs(E_free)).astype(np.float32)
     meas = meas.astype(np.float64)
     ph = _cuda(phi)
     _, Wg, Eg, _ = c.wgs_feedback(ph, _cuda(meas), weights=_cuda(W0))
-    check("feedback", ph, Wg, Eg, ref_step(measured=meas))
+    ref = stepcheck.reference_step(phi, W0, t, amp, w, basis, geom,
+                                   measured=meas)
+    stepcheck.check_step("feedback", ph, Wg, Eg, ref, t,
+                         weights_from_fields=False)
     c.close()
