@@ -38,51 +38,118 @@ def flops_per_eval(D):
     return 2 * D + 11
 
 
-# Issue costs on gfx950 in cycles per wave64 instruction per SIMD at the
-# nominal 2.4 GHz, from microbenchmarks: FP32 FMA, hardware sine or cosine,
-# and one 32x32x16 bf16 matrix-core product (vector and matrix-core issue
-# do not overlap).  A 32 x 32 block of evaluations needs 32 sines and
-# cosines, 32 FMAs and `groups` matrix-core products at the least.
-ISSUE_CYCLES = {"fma": 2.68, "trans": 9.03, "mfma": 36.0}
+# Issue costs of the instructions every evaluation needs, in cycles of the
+# nominal 2.4 GHz clock per wave64 instruction per SIMD: an FP32 FMA, a
+# hardware sine or cosine, and one 32x32x16 bf16 matrix-core product.  They
+# are measured when the benchmark starts, by the committed microbenchmark
+# (libash_ubench.so, include/ash_ubench.h), not typed in.  A 32 x 32 block
+# of evaluations needs 32 sines and cosines, 32 FMAs and `groups`
+# matrix-core products at the least (vector and matrix-core issue do not
+# overlap on this chip).
+ISSUE = {}
 SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
+# BASELINE's slot model: 256 CUs x 64 lanes x 2.4 GHz FP32 issue slots/s
+SLOT_RATE = 256 * 64 * 2.4e9
 
 
-def issue_ceiling(groups):
+MIX = {}   # (groups, reduce, moments) -> (evals/s, waves per SIMD)
+
+
+def measure_issue_costs(device=0):
+    from paper_2505_08777_amd.ubench import issue_rates
+    r = issue_rates(device)
+    ISSUE.clear()
+    ISSUE.update(r)
+    return r
+
+
+def mix_ceiling(groups, reduce=False, moments=False):
+    """The transforms' issue ceiling: evaluations/s of their irreducible
+    instruction mix on every SIMD (libash_ubench's k_mix, measured on first
+    use), and the occupancy it was reached at."""
+    key = (int(groups), bool(reduce), bool(moments))
+    if key not in MIX:
+        from paper_2505_08777_amd.ubench import mix_ceiling as measure
+        MIX[key] = measure(*key)
+    return MIX[key]
+
+
+def issue_ceiling(groups, cycles=None):
     """Evaluations/s if every SIMD issued only the irreducible work."""
-    c = (32 * ISSUE_CYCLES["trans"] + 32 * ISSUE_CYCLES["fma"]
-         + groups * ISSUE_CYCLES["mfma"])
-    return SIMDS * CLOCK_HZ * 1024 / c
+    c = cycles or ISSUE
+    per_block = 32 * c["trans"] + 32 * c["fma"] + groups * c["mfma"]
+    return SIMDS * CLOCK_HZ * 1024 / per_block
+
+
+def dtype_label(info):
+    """The arithmetic of the path: FP32 values and sums, with the phase a
+    sum of exact products of bf16 pieces on the matrix cores."""
+    return ("f32 (phase: bf16-piece products on the matrix cores with FP32 "
+            "accumulation, remainder terms in %s pieces, offsets / slopes / "
+            "nearfield phases in 3; FP64 tile offsets at set-up)"
+            % (info["pieces"],))
 
 
 def alu_roofline(kernel, evals_per_launch, ms_avg, launches, D, groups,
-                 traffic=None, traffic_src=None):
+                 traffic=None, traffic_src=None, reduce=False, moments=False,
+                 flops=None, ceiling=None):
     """Roofline of a transform kernel in algorithmic FP32 flops.
 
-    The peak is the issue ceiling (irreducible sines, cosines, FMAs and
-    matrix-core products per 32 x 32 block on 1024 SIMDs at 2.4 GHz)
-    expressed in the same algorithmic flops per evaluation; the FP32
-    vector peak is given beside it.  Part of each evaluation runs on the
-    matrix cores, so the fraction of the vector peak alone can pass 1.
+    The peak is the issue ceiling: the evaluations per second of the
+    transform's irreducible instruction mix (per 32 x 32 block: `groups`
+    matrix-core products for the phases, 32 sines and cosines, 32 FMAs, or
+    for the moment transform 8 more products instead of the FMAs) measured
+    on all 1024 SIMDs at start-up, expressed in the same algorithmic flops
+    per evaluation.  The FP32 vector peak is given beside it: part of each
+    evaluation runs on the matrix cores, so the fraction of the vector peak
+    alone can pass 1.
     """
-    F = flops_per_eval(D)
+    F = flops if flops is not None else flops_per_eval(D)
+    ceil, occ = ceiling or mix_ceiling(groups, reduce, moments)
     achieved = evals_per_launch * F / (ms_avg * 1e-3) / 1e12
-    peak = F * issue_ceiling(groups) / 1e12
+    peak = F * ceil / 1e12
     return {"bound": "alu", "kernel": kernel, "achieved": achieved,
             "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": traffic, "traffic_unit": "bytes/launch",
             "traffic_source": traffic_src, "avg_launch_ms": ms_avg,
             "launches": launches, "flops_per_eval": F,
             "evals_per_launch": evals_per_launch,
-            "peak_basis": "issue ceiling, %d matrix-core groups" % groups,
+            "peak_basis": "issue ceiling: the irreducible instruction mix of "
+                          "a 32x32 block (%d matrix-core products, 32 "
+                          "sines/cosines, %s) measured on all SIMDs at "
+                          "start-up (libash_ubench k_mix, %d waves/SIMD): "
+                          "%.4g evaluations/s"
+                          % (groups, "8 more products" if moments
+                             else "32 FMAs", occ, ceil),
+            "ceiling_evals_per_s": ceil,
             "fp32_vector_peak": FP32_VECTOR_PEAK_TFLOPS,
             "frac_of_fp32_vector_peak": achieved / FP32_VECTOR_PEAK_TFLOPS}
 
 
-def issue_model(evals_per_s, groups):
-    ceil = issue_ceiling(groups)
-    return {"ceiling_evals_per_s": ceil, "achieved_evals_per_s": evals_per_s,
-            "frac": evals_per_s / ceil, "groups": groups,
-            "cycles": ISSUE_CYCLES}
+def issue_model(evals_per_s, groups, cycles=None):
+    """The additive model: the separate issue costs of the block's sines,
+    cosines, FMAs and matrix-core products summed (an upper bound on the
+    block's cost, since the three units overlap partly)."""
+    c = cycles or ISSUE
+    ceil = issue_ceiling(groups, c)
+    return {"additive_ceiling_evals_per_s": ceil,
+            "achieved_evals_per_s": evals_per_s,
+            "frac_of_additive": evals_per_s / ceil, "groups": groups,
+            "cycles": {k: c[k] for k in ("fma", "trans", "mfma")}}
+
+
+def slot_model(evals_per_s, D, cycles=None):
+    """BASELINE's slot model of '% FP32 VALU peak': per evaluation (D + 4)/2
+    packed-FMA slots + 1 range reduction + r_sin + r_cos, r = the measured
+    transcendental cost in FMA slots, against 256 x 64 x 2.4e9 slots/s."""
+    c = cycles or ISSUE
+    r = c["trans"] / c["fma"]
+    s_eval = (D + 4) / 2.0 + 1.0 + 2.0 * r
+    return {"pct": 100.0 * evals_per_s * s_eval / SLOT_RATE,
+            "slots_per_eval": s_eval, "r_trans": r,
+            "note": "prices the D phase multiply-adds on the vector unit; "
+                    "here they run on the matrix cores, so this reads above "
+                    "100 %"}
 
 
 def parse():
@@ -90,7 +157,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="field1024",
+    ap.add_argument("--workload", default="volume1920",
                     choices=["plain256", "field1024", "volume1920",
                              "grad1024", "batch64", "batch64small",
                              "principal1024", "coefgrad1024", "feedback1024",
@@ -120,6 +187,9 @@ def parse():
                     help="WGS workloads: bracket one transform launch in "
                          "every this many with HIP events (each event pair "
                          "costs stream time)")
+    ap.add_argument("--ubench", action="store_true",
+                    help="only measure the issue costs (libash_ubench) and "
+                         "print them, then exit")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many "
                          "MiB (for scaling HBM byte counters), then exit")
@@ -165,19 +235,85 @@ def profiled_traffic(workload, kernel, summary="wgs_kernels", profiles=None):
     return val, os.path.relpath(path, ROOT)
 
 
+def profiled_counters(workload, kernel, summary="wgs_kernels", profiles=None):
+    """Per-dispatch counters of `kernel` (display name, e.g.
+    'k_forward<3, false>') from the committed summary's counter table, or
+    None when the summary was taken on other kernel source."""
+    profiles = profiles or os.path.join(ROOT, "profiles")
+    path = os.path.join(profiles, "%s_%s.txt" % (summary, workload))
+    if not os.path.exists(path):
+        return None
+    rec, cols, vals = None, None, {}
+    for line in open(path):
+        if line.startswith("kernels_hip_sha256:"):
+            rec = line.split(":", 1)[1].strip()
+        cells = [x.strip() for x in line.strip().strip("|").split("|")]
+        if cells and cells[0] == "counter":
+            cols = [c.replace("ash::", "") for c in cells[1:]]
+        elif cols and len(cells) == len(cols) + 1 and cells[0].isupper() \
+                and kernel in cols:
+            try:
+                vals[cells[0]] = float(cells[1 + cols.index(kernel)])
+            except ValueError:
+                pass
+    if rec != kernel_source_sha256() or not vals:
+        return None
+    return vals
+
+
+def issue_utilisation(counters, evals_per_launch, ms_avg, cycles=None):
+    """Instructions per evaluation from the counters, and the fraction of
+    the SIMDs' issue cycles (1024 SIMDs at 2.4 GHz over the measured launch
+    time) that they take at the measured issue costs."""
+    if not counters:
+        return None
+    c = cycles or ISSUE
+    valu = counters.get("SQ_INSTS_VALU", 0.0)
+    trans = counters.get("SQ_INSTS_VALU_TRANS_F32", 0.0)
+    mfma = counters.get("SQ_INSTS_MFMA", 0.0)
+    need = trans * c["trans"] + (valu - trans) * c["fma"] + mfma * c["mfma"]
+    avail = SIMDS * CLOCK_HZ * ms_avg * 1e-3
+    return {"valu_per_eval": valu / evals_per_launch,
+            "trans_per_eval": trans / evals_per_launch,
+            "mfma_per_eval": mfma / evals_per_launch,
+            "minimum_valu_per_eval": 64.0 / 1024,
+            "issue_utilisation": need / avail,
+            "trans_issue_share": trans * c["trans"] / avail,
+            "mfma_issue_share": mfma * c["mfma"] / avail,
+            "source": "rocprofv3 counters of the committed summary, costs "
+                      "measured at start-up"}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 CPU_MIN_S, CPU_MAX_S, CPU_MAX_PAIRS = 10.0, 30.0, 8
+# evaluations per sample pair: forward of sampled spots over every pixel,
+# adjoint of every spot at sampled pixels
+SAMPLE_FWD_EVALS, SAMPLE_ADJ_EVALS = 6e8, 1.5e8
 
 
-def cpu_baseline(ctx, d, w=None, basis=None):
+def cpu_baseline(ctx, d, w=None, basis=None, full_ctx=None):
     """The FP64 oracle on a bounded sample of the same workload.
 
-    Sample: transform pairs at the workload's seeded start phase, each one
-    full forward transform (all spots, all pixels) and the adjoint of the
-    farfield projection y = t E/|E| of the oracle's fields over all pixels,
-    in chunks; pairs repeat until CPU_MIN_S seconds have passed (at most
-    CPU_MAX_PAIRS), and an adjoint stops at a chunk boundary once CPU_MAX_S
-    have passed.  The GPU runs the same two transforms on the same inputs;
-    its errors against the first pair are returned beside the timing."""
+    Sample pairs: the forward transform of the workload's seeded start phase
+    for a random subset of spots (all of them when spots x pixels is at
+    most 6e8) over every pixel, and the adjoint of a farfield shaped like
+    the loop's projection (target amplitudes, random phases) over every
+    spot at a random subset of pixels (at most 1.5e8 evaluations); pairs
+    repeat until CPU_MIN_S seconds have passed (at most CPU_MAX_PAIRS).
+    Every output of a transform depends on one spot or one pixel, so the
+    sampled outputs are exact references: the GPU's transforms of the same
+    inputs are compared with the first pair (with `full_ctx`, also those of
+    a context in full precision)."""
     import numpy as np
     import torch
     import oracle
@@ -193,54 +329,48 @@ def cpu_baseline(ctx, d, w=None, basis=None):
     phi32 = d["phi0"].astype(np.float32)
     f = amp32 * np.exp(1j * phi32.astype(np.float64))
     N, P = w.shape[0], geom.P
-    chunk = max(4096, (1 << 26) // max(N, 1))
-    evals, pairs, pix_done = 0, 0, 0
-    Eref = gref = None
+    S = min(N, max(1, int(SAMPLE_FWD_EVALS // P)))
+    Q = min(P, max(1, int(SAMPLE_ADJ_EVALS // N)))
+    rng = np.random.default_rng(2505)
+    evals, pairs, first = 0, 0, None
     t0 = time.perf_counter()
     while pairs < CPU_MAX_PAIRS:
-        E1 = oracle.forward(f, w, basis, geom, workers=cores)
-        evals += N * P
-        y = (d["t"] * E1 / np.abs(E1)).astype(np.complex64)
-        parts = []
-        for p0 in range(0, P, chunk):
-            pix = np.arange(p0, min(P, p0 + chunk))
-            parts.append(oracle.adjoint(y.astype(np.complex128), w, basis,
-                                        geom, pixels=pix, workers=cores))
-            evals += N * len(pix)
-            if time.perf_counter() - t0 >= CPU_MAX_S:
-                break
+        sel = np.sort(rng.choice(N, S, replace=False)) if S < N else np.arange(N)
+        pix = np.sort(rng.choice(P, Q, replace=False)) if Q < P else np.arange(P)
+        y = (d["t"] * np.exp(1j * rng.uniform(-np.pi, np.pi, N))).astype(np.complex64)
+        Eref = oracle.forward(f, w, basis, geom, spots=sel, workers=cores)
+        gref = oracle.adjoint(y.astype(np.complex128), w, basis, geom,
+                              pixels=pix, workers=cores)
+        evals += S * P + N * Q
         pairs += 1
-        if Eref is None:
-            Eref, yref, gref = E1, y, np.concatenate(parts)
+        if first is None:
+            first = (sel, pix, y, Eref, gref)
         if time.perf_counter() - t0 >= CPU_MIN_S:
             break
     T = time.perf_counter() - t0
+    sel, pix, y, Eref, gref = first
     dev = torch.device("cuda:0")
-    E = ctx.forward(phase=torch.tensor(phi32, device=dev)).cpu().numpy()
-    g = ctx.adjoint(torch.tensor(yref, device=dev)).reshape(-1)
-    g = g[:len(gref)].cpu().numpy()
-    fe = field_errors(E, Eref)
-    ge = field_errors(g, gref)
+
+    def errors(c):
+        E = c.forward(phase=torch.tensor(phi32, device=dev)).cpu().numpy()[sel]
+        g = c.adjoint(torch.tensor(y, device=dev)).cpu().numpy().reshape(-1)[pix]
+        fe, ge = field_errors(E, Eref), field_errors(g, gref)
+        return {"forward_max_rel": fe[0], "forward_norm_rel": fe[1],
+                "adjoint_max_rel": ge[0], "adjoint_norm_rel": ge[1],
+                "pieces": c.info()["pieces"]}
+
     obj = {"value": evals / T, "unit": "evals/s", "cores": cores,
-           "kind": "oracle",
-           "sample": "%d transform pair(s) of %d spots x %d pixels, each a "
-                     "full forward and the adjoint at %s pixels: %.3g evals "
-                     "in %.1f s, FP64 numpy on %d threads"
-                     % (pairs, N, P, "all" if len(gref) == P else
-                        "the first %d" % len(gref), evals, T, cores)}
-    parity = {"forward_max_rel": fe[0], "forward_norm_rel": fe[1],
-              "adjoint_max_rel": ge[0], "adjoint_norm_rel": ge[1],
-              "adjoint_pixels": len(gref), "bar": 1e-4}
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": "%d sample pair(s), each the forward of %d of %d spots "
+                     "over all %d pixels and the adjoint of all spots at %d "
+                     "pixels: %.3g evals in %.1f s, FP64 numpy on %d threads"
+                     % (pairs, S, N, P, Q, evals, T, cores)}
+    parity = errors(ctx)
+    parity.update({"spots_sampled": S, "pixels_sampled": Q, "bar": 1e-4,
+                   "precision": "auto"})
+    if full_ctx is not None:
+        parity["full_precision"] = errors(full_ctx)
     return obj, parity
-
-
-def coef_issue_ceiling(groups):
-    """Evaluations/s of the moment transform if every SIMD issued only its
-    sines, cosines and matrix-core products (G for the phase, 8 for the two
-    bf16 pieces of the cosines and sines against the moment table, over two
-    16-pixel K blocks) per 32 x 32 block."""
-    c = 32 * ISSUE_CYCLES["trans"] + (groups + 8) * ISSUE_CYCLES["mfma"]
-    return SIMDS * CLOCK_HZ * 1024 / c
 
 
 def graph_replay(ctx, d, n_iter, steps):
@@ -319,9 +449,6 @@ def bench_coef(args, d):
     groups = info["groups"]
     kname = "k_moments<%d, %d>" % (groups, 2 if 2 * D > 32 else 1)
     F = 6 * D + 3       # phase 2D, reduction 1, sin + cos, 4D moment flops
-    achieved = N * P * F / (ms_avg * 1e-3) / 1e12
-    ceil = coef_issue_ceiling(groups)
-    peak = F * ceil / 1e12
     traffic, traffic_src = profiled_traffic("coefgrad1024", kname,
                                             "coef_grad_kernels")
     out = {
@@ -329,20 +456,15 @@ def bench_coef(args, d):
                   "coefficients)", "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype_label(info),
         "data": "synthetic",
         "config": {"workload": "coefgrad1024", "slm": "%dx%d" % (nx, ny),
                    "spots": N, "modes": D, "calls_per_step": n_calls},
         "coef_grads_per_s": n_calls * args.steps / T,
-        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved,
-                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": traffic, "traffic_unit": "bytes/launch",
-                     "traffic_source": traffic_src, "avg_launch_ms": ms_avg,
-                     "launches": prof["forward"][1], "flops_per_eval": F,
-                     "evals_per_launch": N * P,
-                     "peak_basis": "issue ceiling: 32 sines and cosines, "
-                                   "%d + 8 matrix-core products per block"
-                                   % groups},
+        "roofline": alu_roofline(kname, N * P, ms_avg, prof["forward"][1], D,
+                                 groups, traffic, traffic_src,
+                                 reduce=bool(info["range_reduce"]),
+                                 moments=True, flops=F),
         "kernels": {k: {"total_ms": v[0], "launches": v[1],
                         "avg_ms": v[0] / v[1] if v[1] else None}
                     for k, v in prof.items()},
@@ -450,7 +572,7 @@ def bench_feedback(args, d):
         "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * T / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": dtype_label(info), "data": "synthetic",
         "config": {"workload": "feedback1024", "slm": "%dx%d" % (nx, ny),
                    "spots": N, "modes": D, "loop_iters_per_step": n_iter,
                    "fix_phase_after": fix},
@@ -458,7 +580,8 @@ def bench_feedback(args, d):
         "system_uniformity": {"feedback_loop": u_fb,
                               "model_only_wgs": u_model},
         "roofline": alu_roofline(kname, N * P, ms_avg, prof[dom][1], D,
-                                 info["groups"]),
+                                 info["groups"],
+                                 reduce=bool(info["range_reduce"])),
         "kernels": {k: {"total_ms": v[0], "launches": v[1],
                         "avg_ms": v[0] / v[1] if v[1] else None}
                     for k, v in prof.items()},
@@ -539,7 +662,7 @@ def bench_quality(args, d):
         "value": n_k * P * args.steps / T, "unit": "evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype_label(info),
         "data": "synthetic",
         "config": {"workload": "quality1024", "slm": "%dx%d" % (nx, ny),
                    "spots": N, "modes": D, "window": win,
@@ -549,7 +672,8 @@ def bench_quality(args, d):
         "relative_strehl_min": {name: float(v.min()) / top
                                 for name, v in S_all.items()},
         "roofline": alu_roofline(kname, n_k * P, ms_avg, prof["forward"][1],
-                                 D, info["groups"]),
+                                 D, info["groups"],
+                                 reduce=bool(info["range_reduce"])),
         "kernels": {k: {"total_ms": v[0], "launches": v[1],
                         "avg_ms": v[0] / v[1] if v[1] else None}
                     for k, v in prof.items()},
@@ -682,14 +806,17 @@ def bench_adam(args, d):
         "metric": METRIC, "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype_label(info),
         "data": "synthetic",
         "config": {"workload": "grad1024", "slm": "%dx%d" % (nx, ny),
                    "spots": N, "modes": D, "adam_steps_per_step": n_steps},
         "adam_steps_per_s": n_steps * args.steps / T,
-        "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
+        "algorithmic_flops_pct_of_fp32_vector_peak":
+            100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
+        "baseline_slot_model": slot_model(value, D),
         "roofline": alu_roofline(kname, N * P, ms_avg, prof[dom][1], D,
-                                 info["groups"], traffic, traffic_src),
+                                 info["groups"], traffic, traffic_src,
+                                 reduce=bool(info["range_reduce"])),
         "kernels": {k: {"total_ms": v[0], "launches": v[1],
                         "avg_ms": v[0] / v[1] if v[1] else None}
                     for k, v in prof.items()},
@@ -758,12 +885,25 @@ def bench_batch(args, holos):
               for d in holos]
     weights = [torch.ones(d["w"].shape[0], dtype=torch.float32, device=dev)
                for d in holos]
-    tune_s = None
+    tune_s, forms = None, None
     if not args.no_tune:
+        import tempfile
         t0 = time.perf_counter()
-        b.tune(phases)
-        torch.cuda.synchronize()
-        tune_s = time.perf_counter() - t0
+        with tempfile.TemporaryDirectory() as tmp:
+            table = os.path.join(tmp, "tune.txt")
+            b.tune(phases, table_out=table)
+            torch.cuda.synchronize()
+            tune_s = time.perf_counter() - t0
+            forms = {"table": [l.strip() for l in open(table)
+                               if not l.startswith("#")]}
+        for line in forms["table"]:
+            f = line.split()
+            if f[0] == "form":
+                forms["chosen"] = "one_launch" if f[1] == "1" else "per_phase"
+                forms["per_phase_ms_per_iteration"] = float(f[2])
+            if f[0] == "persist":
+                forms.setdefault("one_launch_ms_per_iteration", 0.0)
+                forms["one_launch_ms_per_iteration"] += float(f[5])
     info = b.info()
     for _ in range(args.warmup):
         b.wgs(phases, n_iter, weights=weights)
@@ -782,15 +922,26 @@ def bench_batch(args, holos):
     F = flops_per_eval(D)
     evals = info["evals_per_transform"]
     value = 2.0 * evals * n_iter * args.steps / T
-    dom = max(("forward", "adjoint"), key=lambda k: prof[k][0])
-    # a phase is one launch per record shape, each over all holograms of
-    # that shape: the unit timed is the phase (all its launches)
     shapes = max(info["shapes"], 1)
-    ms_avg = prof[dom][0] / max(prof[dom][1] // shapes, 1)
     # the ceiling of the fewest matrix-core groups among the shapes (the
     # highest), so the fraction is a lower estimate when shapes differ
     groups = min(info["groups"]) if info["groups"] else 0
-    kname = "k_batch_%s<%d, false>" % (dom, groups)
+    if info["one_launch"]:
+        # one launch per record shape runs every iteration of its
+        # holograms (forward, update, adjoint): the unit timed is a call
+        kname = "k_batch_persist<%d, false>" % groups
+        calls = max(prof["forward"][1] // shapes, 1)
+        ms_avg = prof["forward"][0] / calls
+        evals_launch = 2.0 * evals * n_iter
+        launches = calls
+    else:
+        # a phase is one launch per record shape, each over all holograms
+        # of that shape: the unit timed is the phase (all its launches)
+        dom = max(("forward", "adjoint"), key=lambda k: prof[k][0])
+        kname = "k_batch_%s<%d, false>" % (dom, groups)
+        launches = prof[dom][1] // shapes
+        ms_avg = prof[dom][0] / max(launches, 1)
+        evals_launch = evals
     traffic, traffic_src = (profiled_traffic(args.workload, kname,
                                              summary="batch_kernels")
                             if shapes == 1 else (None, None))
@@ -798,21 +949,22 @@ def bench_batch(args, holos):
         "metric": METRIC, "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype_label({"pieces": "-".join(
+            str(p) for p in sorted({c.info()["pieces"] for c in ctxs}))}),
         "data": "synthetic",
         "config": {"workload": args.workload, "holograms": len(holos),
                    "sum_N_P": evals, "modes": D,
                    "wgs_iters_per_step": n_iter},
         "wgs_iters_per_s_per_hologram": n_iter * args.steps / T,
-        "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
-        "roofline": alu_roofline(kname, evals, ms_avg,
-                                 prof[dom][1] // shapes, D, groups,
-                                 traffic, traffic_src),
+        "algorithmic_flops_pct_of_fp32_vector_peak":
+            100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
+        "roofline": alu_roofline(kname, evals_launch, ms_avg, launches, D,
+                                 groups, traffic, traffic_src),
         "kernels": {k: {"total_ms": v[0], "launches": v[1],
                         "avg_ms": v[0] / v[1] if v[1] else None}
                     for k, v in prof.items()},
-        "issue_model": issue_model(evals / (ms_avg * 1e-3), groups),
-        "layout": info, "tune_s": tune_s,
+        "issue_model": issue_model(evals_launch / (ms_avg * 1e-3), groups),
+        "layout": info, "tune_s": tune_s, "forms": forms,
     }
     # the same holograms' loops run one context at a time (plain loop)
     ph2 = [p.clone() for p in phases]
@@ -844,6 +996,9 @@ def main():
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib)
         return
+    if args.ubench and args.gpus == 1:
+        print(json.dumps({"issue_cycles": measure_issue_costs()}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU; there is no multi-GPU path "
               "(each GPU would run its own slab of pixel rows with the "
@@ -855,6 +1010,7 @@ def main():
     import workloads
     import paper_2505_08777_amd as A
 
+    measure_issue_costs()
     if args.workload == "coefgrad1024":
         return bench_coef(args, workloads.grad1024())
     if args.workload == "feedback1024":
@@ -948,7 +1104,10 @@ def main():
                               "true" if info["range_reduce"] else "false")
     traffic, traffic_src = profiled_traffic(args.workload, kname)
     roofline = alu_roofline(kname, N * P, ms_avg, prof[dom][1], D,
-                            info["groups"], traffic, traffic_src)
+                            info["groups"], traffic, traffic_src,
+                            reduce=bool(info["range_reduce"]))
+    counters = issue_utilisation(profiled_counters(args.workload, kname),
+                                 N * P, ms_avg)
     kernels = {k: {"total_ms": v[0], "launches": v[1],
                    "avg_ms": v[0] / v[1] if v[1] else None}
                for k, v in prof.items()}
@@ -957,16 +1116,19 @@ def main():
         "metric": METRIC, "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype_label(info),
         "data": "synthetic",
         "config": {"workload": args.workload, "slm": "%dx%d" % (nx, ny),
                    "spots": N, "modes": D, "wgs_iters_per_step": n_iter},
         "wgs_iters_per_s": n_iter * args.steps / T,
-        "pct_fp32_valu_peak": 100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
+        "algorithmic_flops_pct_of_fp32_vector_peak":
+            100.0 * value * F / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
+        "baseline_slot_model": slot_model(value, D),
         "ms_per_step_without_events": 1e3 * (t3 - t2) / args.steps,
         "event_stride": args.event_stride,
         "roofline": roofline,
         "issue_model": issue_model(N * P / (ms_avg * 1e-3), info["groups"]),
+        "counters": counters,
         "kernels": kernels, "layout": info, "set_spots_ms": set_spots_ms,
     }
     if args.graph or args.workload == "plain256":
@@ -1005,7 +1167,15 @@ def main():
             out["cpu_baseline"], out["parity"] = cpu_baseline(
                 ctx, d, w=wr, basis=br)
         else:
-            out["cpu_baseline"], out["parity"] = cpu_baseline(ctx, d)
+            # the same transforms in full precision (3 pieces for every
+            # remainder term) beside the default
+            full = A.Context(0)
+            full.set_precision(True)
+            full.set_basis(nx, ny, modes=d["modes"], amp=amp_t)
+            full.set_spots(d["w"], d["t"])
+            out["cpu_baseline"], out["parity"] = cpu_baseline(
+                ctx, d, full_ctx=full)
+            full.close()
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -423,17 +423,32 @@ typedef struct ash_info {
 int ash_get_info(const ash_ctx* ctx, ash_info* out);
 
 /* ---- Batched form ----------------------------------------------------
- * Many holograms' weighted-GS loops run together.  Each phase of an
- * iteration is one persistent launch over the work items of all holograms
- * (one launch per record shape present): the forward over (hologram, pixel
- * range, 32-spot block) items, a fixed-order reduction and the weight
- * updates of all holograms, and the adjoint over (hologram, tile row)
- * items.  Items sit in eight per-XCD queues (longest first, balanced by
- * work); resident waves take them with an atomic counter and move to the
- * other queues when theirs runs dry.  The forward range length (pixel
- * blocks per item) is the tuned parameter.
+ * Many holograms' weighted-GS loops run together, in one of two forms.
+ *
+ * One launch (members of at most 512 spots, on a device with cooperative
+ * launches): one cooperative launch per record shape runs every iteration
+ * of its holograms.  Each resident block owns a contiguous range of one
+ * hologram's 32-pixel blocks (the blocks shared out over the holograms in
+ * proportion to their work) and, per iteration, adds up its range's
+ * forward sums, meets the hologram's other blocks at a barrier (a counter
+ * per hologram), computes the whole hologram's weight update from all
+ * blocks' sums, and runs the adjoint of its range.  Its pixel blocks per
+ * forward unit (chunk) and resident blocks per CU are tuned.
+ *
+ * Launches per phase (any members): each phase of an iteration is one
+ * persistent launch over the work items of all holograms of a record
+ * shape: the forward over (hologram, pixel range, 32-spot block) items, a
+ * fixed-order reduction and the weight updates of all holograms, and the
+ * adjoint over (hologram, tile row) items.  Forward items sit in eight
+ * per-XCD queues (longest first, balanced by work); resident waves take
+ * them with an atomic counter and move to the other queues when theirs runs
+ * dry.  The forward range length (pixel blocks per item) is tuned.
+ *
+ * A batch starts in the one-launch form when its members allow it;
+ * ash_batch_tune keeps the faster form for the batch at hand and
+ * ash_batch_set_form chooses one.
  * Paper: Methods, "Computational Scaling" (many holograms); the batched
- * persistent form is this library's. */
+ * forms are this library's. */
 typedef struct ash_batch ash_batch;
 
 /* A batch of H holograms, each a context with its basis and spots set, all
@@ -456,20 +471,30 @@ int ash_batch_set_stream(ash_batch* batch, void* stream);
  *                [ny_h][nx_h] float32 phase, in: start, out: final.
  *   weights_dev  host array of H device pointers, [N_h] float32 weights,
  *                in/out (start with 1).
- *   params       as for ash_wgs_iterate (NULL = power 1).
+ *   params       as for ash_wgs_iterate (NULL = power 1; phase fixing is
+ *                not supported in a batch).
  * Each hologram's results equal its own ash_wgs_iterate up to the FP32
- * summation order of the forward partial sums.  The call synchronises the
- * stream once at its start (descriptor upload) and keeps 2 KB of queue
- * counters per iteration and record shape on the device, grown on demand.
- * Errors: ASH_EINVAL, ASH_ENOTREADY, ASH_ENOMEM, ASH_EHIP. */
+ * summation order of the forward sums.  The call synchronises the stream
+ * at its start (descriptor upload); the one-launch form also at its end
+ * (to read the barriers' error flag: a barrier that waits more than 10 s
+ * ends the launch and the call returns ASH_EHIP).  The per-phase form keeps
+ * 2 KB of queue counters per iteration and record shape on the device,
+ * grown on demand.  Errors: ASH_EINVAL, ASH_ENOTREADY, ASH_EUNSUPPORTED,
+ * ASH_ENOMEM, ASH_EHIP. */
 int ash_batch_wgs(ash_batch* batch, float* const* phase_dev,
                   float* const* weights_dev, int n_iter,
                   const ash_wgs_params* params);
 
-/* Autotuner: for each record shape, times the forward plus its reduction on
- * the batch at the given phases for range lengths of 16, 32, 64, 128, 256
- * and 512 pixel blocks, keeps the fastest, and writes the table
- * "groups range_reduce range_blocks ms" to table_out (if not NULL).
+/* Autotuner.  For each record shape, times the per-phase form's forward
+ * plus its reduction for range lengths of 16, 32, 64, 128, 256 and 512
+ * pixel blocks and keeps the fastest; when the one-launch form is possible,
+ * times two iterations of it for chunks of 4, 8, 16 and 32 pixel blocks and
+ * 1 up to the most resident blocks per CU that fit, keeps the fastest, times
+ * two iterations of the per-phase form, and selects the faster form.  The
+ * timed iterations run on copies of the phases (the caller's are left
+ * untouched).  The table written to table_out (if not NULL) holds lines
+ * "groups range_reduce range_blocks ms", "persist groups range_reduce chunk
+ * blocks_per_cu ms_per_iteration" and "form one_launch ms_per_iteration".
  * Errors: ASH_EINVAL (null phases, unwritable file), ASH_ENOTREADY,
  * ASH_ENOMEM, ASH_EHIP. */
 int ash_batch_tune(ash_batch* batch, float* const* phase_dev,
@@ -478,6 +503,12 @@ int ash_batch_tune(ash_batch* batch, float* const* phase_dev,
  * are ignored).  Errors: ASH_EINVAL (unreadable file), ASH_ENOMEM. */
 int ash_batch_load_tuning(ash_batch* batch, const char* table_in);
 
+/* Choose the form: one_launch = 1 the one-launch form, 0 the launches per
+ * phase.  Errors: ASH_EINVAL, ASH_EUNSUPPORTED (one launch requested for
+ * members of more than 512 spots or on a device without cooperative
+ * launches). */
+int ash_batch_set_form(ash_batch* batch, int one_launch);
+
 typedef struct ash_batch_info {
   int32_t holograms;
   int32_t shapes;           /* record shapes (one launch each per phase)   */
@@ -485,6 +516,10 @@ typedef struct ash_batch_info {
   int32_t range_blocks[4];  /* their forward range lengths                 */
   int64_t items;            /* forward + adjoint work items                */
   double evals_per_transform;  /* sum over holograms of N * P              */
+  int32_t one_launch;       /* 1: the one-launch form (see ash_batch_wgs)  */
+  int32_t chunk[4];         /* its pixel blocks per forward unit, per shape*/
+  int32_t blocks_per_cu[4]; /* its resident blocks per CU (grid / CUs)     */
+  int32_t grid[4];          /* its blocks per launch                       */
 } ash_batch_info;
 int ash_batch_get_info(const ash_batch* batch, ash_batch_info* out);
 

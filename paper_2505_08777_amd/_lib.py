@@ -59,7 +59,11 @@ class BatchInfo(ctypes.Structure):
                 ("groups", ctypes.c_int32 * 4),
                 ("range_blocks", ctypes.c_int32 * 4),
                 ("items", ctypes.c_int64),
-                ("evals_per_transform", ctypes.c_double)]
+                ("evals_per_transform", ctypes.c_double),
+                ("one_launch", ctypes.c_int32),
+                ("chunk", ctypes.c_int32 * 4),
+                ("blocks_per_cu", ctypes.c_int32 * 4),
+                ("grid", ctypes.c_int32 * 4)]
 
 
 PRECISION_AUTO = 0
@@ -114,6 +118,7 @@ def _load():
         "ash_batch_wgs": (I, [P, P, P, I, ctypes.POINTER(WgsParams)]),
         "ash_batch_tune": (I, [P, P, ctypes.c_char_p]),
         "ash_batch_load_tuning": (I, [P, ctypes.c_char_p]),
+        "ash_batch_set_form": (I, [P, I]),
         "ash_batch_get_info": (I, [P, ctypes.POINTER(BatchInfo)]),
         "ash_batch_profile_enable": (I, [P, I]),
         "ash_batch_profile_read": (I, [P, P, P]),

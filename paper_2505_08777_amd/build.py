@@ -16,6 +16,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libash.so")
 
 SOURCES = ["host.cpp", "batch.cpp", "principal.cpp", "kernels.hip"]
+# the issue-rate microbenchmarks behind the transforms' issue ceiling
+UBENCH_SOURCES = ["ubench.hip"]
+UBENCH_LIB = os.path.join(PKG, "libash_ubench.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for all device code: hipcc -O3 would
@@ -27,20 +30,25 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I", INCLUDE, "-I", CSRC]
 
 
-def build(verbose=False):
-    objdir = os.path.join(PKG, "_build")
-    os.makedirs(objdir, exist_ok=True)
+def _link(sources, lib, objdir, verbose):
     objs = []
-    for src in SOURCES:
+    for src in sources:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC] + FLAGS + (["-x", "hip"] if src.endswith(".hip") else []) \
             + ["-c", os.path.join(CSRC, src), "-o", obj]
         _run(cmd, verbose)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs,
          verbose)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose=False):
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    _link(SOURCES, LIB, objdir, verbose)
+    _link(UBENCH_SOURCES, UBENCH_LIB, objdir, verbose)
     return LIB
 
 

@@ -523,6 +523,12 @@ class Batch:
             "ash_batch_tune")
         return self.info()
 
+    def set_form(self, one_launch):
+        """One launch per record shape for all iterations (True), or one
+        launch per phase of every iteration (False)."""
+        self._check(lib.ash_batch_set_form(self._h, int(bool(one_launch))),
+                    "ash_batch_set_form")
+
     def load_tuning(self, table_in):
         self._check(lib.ash_batch_load_tuning(self._h, table_in.encode()),
                     "ash_batch_load_tuning")
@@ -536,7 +542,11 @@ class Batch:
                 "groups": list(out.groups)[:min(n, 4)],
                 "range_blocks": list(out.range_blocks)[:min(n, 4)],
                 "items": out.items,
-                "evals_per_transform": out.evals_per_transform}
+                "evals_per_transform": out.evals_per_transform,
+                "one_launch": bool(out.one_launch),
+                "chunk": list(out.chunk)[:min(n, 4)],
+                "blocks_per_cu": list(out.blocks_per_cu)[:min(n, 4)],
+                "grid": list(out.grid)[:min(n, 4)]}
 
     def profile(self, enable=True, categories=None):
         mask = 0

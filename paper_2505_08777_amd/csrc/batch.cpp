@@ -22,6 +22,14 @@ namespace {
 
 constexpr int kDefaultRange = 64;  // pixel blocks per forward item (untuned)
 constexpr int kTuneCandidates[] = {16, 32, 64, 128, 256, 512};
+// One-launch form: pixel blocks per forward unit (untuned), the candidates
+// of the tuner, and the iterations it times per candidate.
+constexpr int kDefaultChunk = 8;
+constexpr int kChunkCandidates[] = {4, 8, 16, 32};
+constexpr int kPersistTuneIters = 2;
+// Relative cost of a pixel block's adjoint epilogue (butterfly over the
+// spots, arg g, next nearfield record) in 32 x 32 evaluation blocks.
+constexpr double kEpilogueBlocks = 1.25;
 
 // One record shape (matrix-core groups, range reduction) of the batch.
 struct Cls {
@@ -32,6 +40,12 @@ struct Cls {
   size_t fwd_off = 0, adj_off = 0;  // first item of each phase
   int qoff_fwd = 0;                 // index of its 9 queue offsets in qoff
   int fwd_grid = 0, adj_grid = 0;
+  // one-launch form
+  int chunk = kDefaultChunk;  // pixel blocks per forward unit
+  int bpc = 0;                // resident blocks per CU (0: as many as fit)
+  int p_grid = 0;             // blocks of its launch
+  size_t p_lds = 0;           // dynamic LDS per block
+  size_t p_holo = 0, p_blk = 0;  // first descriptor and block of its arrays
 };
 
 struct Snap {  // what the batch's plan depends on, per member
@@ -63,6 +77,20 @@ struct ash_batch {
   int* d_ctr = nullptr;
   size_t cap_partial = 0, cap_red = 0, cap_items = 0, cap_rblk = 0,
          cap_qoff = 0, cap_ctr = 0;
+  // one-launch form (possible when every member has at most kPersistSpots
+  // spots and the device launches cooperative grids); one_launch selects it
+  bool persist = false;
+  bool one_launch = false;
+  std::vector<PHolo> pholo;  // per member, in class order
+  std::vector<PBlock> pblk;
+  std::vector<int> pmember;  // member of each pholo entry
+  PHolo* d_pholo = nullptr;
+  PBlock* d_pblk = nullptr;
+  float2* d_prows = nullptr;
+  unsigned* d_pyblk = nullptr;
+  int* d_pctr = nullptr;  // per member barrier counter, then the error flag
+  size_t cap_pholo = 0, cap_pblk = 0, cap_prows = 0, cap_pyblk = 0,
+         cap_pctr = 0;
   // timing
   int prof_mask = 0;
   std::vector<ash_prof_rec> prof;
@@ -173,6 +201,125 @@ std::vector<std::vector<int>> lpt(const std::vector<double>& work) {
     load[best] += work[u];
   }
   return q;
+}
+
+// The one-launch plan: per record shape, the resident blocks of its launch
+// shared out over its holograms in proportion to their work per iteration
+// (forward and adjoint blocks of evaluations and the adjoint's per-row
+// epilogue), each block a contiguous range of its hologram's 32-pixel
+// blocks; the blocks' partial-sum rows, spot-field records and barrier
+// counters.
+int plan_persist(ash_batch* b) {
+  b->pholo.clear();
+  b->pblk.clear();
+  b->pmember.clear();
+  size_t rows = 0, yblk = 0;
+  for (auto& c : b->cls) {
+    int maxN = 1;
+    for (int h : c.holos) maxN = std::max(maxN, b->m[h]->spots.N);
+    c.p_lds = persist_lds_bytes(maxN);
+    int occ = persist_blocks_per_cu(c.G, c.reduce != 0, c.p_lds);
+    if (occ <= 0) return bfail(b, ASH_EUNSUPPORTED, "no resident block fits");
+    if (c.bpc > 0) occ = std::min(occ, c.bpc);
+    c.p_grid = occ * b->n_cu;
+    std::vector<double> work;
+    double total = 0.0;
+    for (int h : c.holos) {
+      const ash_ctx* m = b->m[h];
+      const double n_blk = (double)m->basis.g.n_tiles * kBlkPerTile;
+      const double n_mb = (m->spots.N + 31) / 32;
+      work.push_back(n_blk * (2.0 * n_mb + kEpilogueBlocks));
+      total += work.back();
+    }
+    const int Hc = (int)c.holos.size();
+    if (Hc > c.p_grid)
+      return bfail(b, ASH_EUNSUPPORTED, "more holograms than resident blocks");
+    // blocks per hologram: at least one, at most one per pixel block, the
+    // rest by largest remainder of the proportional share
+    std::vector<long> nb(Hc, 1);
+    std::vector<std::pair<double, int>> rem;
+    long given = Hc;
+    for (int i = 0; i < Hc; ++i) {
+      const long cap = (long)b->m[c.holos[i]]->basis.g.n_tiles * kBlkPerTile;
+      const double share = (double)(c.p_grid - Hc) * work[i] / total;
+      const long extra = std::min(cap - 1, (long)floor(share));
+      nb[i] += extra;
+      given += extra;
+      rem.push_back({share - floor(share), i});
+    }
+    std::sort(rem.begin(), rem.end(), [](const std::pair<double, int>& x,
+                                         const std::pair<double, int>& y) {
+      return x.first > y.first || (x.first == y.first && x.second < y.second);
+    });
+    for (size_t r = 0; r < rem.size() && given < c.p_grid; ++r) {
+      const int i = rem[r].second;
+      const long cap = (long)b->m[c.holos[i]]->basis.g.n_tiles * kBlkPerTile;
+      if (nb[i] < cap) {
+        ++nb[i];
+        ++given;
+      }
+    }
+    c.p_grid = (int)given;
+    c.p_holo = b->pholo.size();
+    c.p_blk = b->pblk.size();
+    for (int i = 0; i < Hc; ++i) {
+      const int h = c.holos[i];
+      ash_ctx* m = b->m[h];
+      const Geom& g = m->basis.g;
+      Buffers& B = m->buf;
+      PHolo d;
+      d.pixtab = reinterpret_cast<const u32x4*>(B.pixtab);
+      d.nf_t = B.field_t;
+      d.spotrec = reinterpret_cast<const u32x4*>(B.spotrec);
+      d.offtab = B.offtab;
+      d.amp_t = B.amp_t;
+      d.target = B.target;
+      d.W = nullptr;
+      d.phase = nullptr;
+      d.n_blk = (long)g.n_tiles * kBlkPerTile;
+      d.N = m->spots.N;
+      d.nx = g.nx;
+      d.ny = g.ny;
+      d.tiles_x = g.tiles_x;
+      d.groups = g.groups;
+      d.n_blocks = (int)nb[i];
+      d.t_norm = (float)sqrt(m->spots.t_norm2);
+      const int NP = (d.N + 31) / 32 * 32;
+      d.rows = reinterpret_cast<float2*>(rows);  // offsets for now
+      d.yblk = reinterpret_cast<unsigned*>(yblk);
+      d.ctr = reinterpret_cast<int*>((size_t)b->pholo.size() * kCtrPad);
+      rows += (size_t)2 * nb[i] * d.N;
+      yblk += (size_t)nb[i] * NP * 8;
+      for (long j = 0; j < nb[i]; ++j) {
+        PBlock pb;
+        pb.holo = i;
+        pb.j = (int)j;
+        pb.b0 = d.n_blk * j / nb[i];
+        pb.b1 = d.n_blk * (j + 1) / nb[i];
+        b->pblk.push_back(pb);
+      }
+      b->pholo.push_back(d);
+      b->pmember.push_back(h);
+    }
+  }
+  int rc;
+  const size_t n_ctr = (b->pholo.size() + 1) * kCtrPad;
+  if ((rc = bgrow(b, &b->d_pholo, &b->cap_pholo, b->pholo.size(),
+                  "descriptors")) ||
+      (rc = bgrow(b, &b->d_pblk, &b->cap_pblk, b->pblk.size(), "blocks")) ||
+      (rc = bgrow(b, &b->d_prows, &b->cap_prows, rows, "partial sums")) ||
+      (rc = bgrow(b, &b->d_pyblk, &b->cap_pyblk, yblk, "spot fields")) ||
+      (rc = bgrow(b, &b->d_pctr, &b->cap_pctr, n_ctr, "barrier counters")))
+    return rc;
+  for (auto& d : b->pholo) {
+    d.rows = b->d_prows + reinterpret_cast<size_t>(d.rows);
+    d.yblk = b->d_pyblk + reinterpret_cast<size_t>(d.yblk);
+    d.ctr = b->d_pctr + reinterpret_cast<size_t>(d.ctr);
+  }
+  BCHK(b, hipMemcpy(b->d_pblk, b->pblk.data(), b->pblk.size() * sizeof(PBlock),
+                    hipMemcpyHostToDevice),
+       "uploading the batch plan");
+  return ASH_OK;
 }
 
 // Build descriptors (without the per-call phase and weight pointers),
@@ -310,7 +457,7 @@ int plan(ash_batch* b) {
     e = hipMemcpy(b->d_qoff, b->qoff.data(), b->qoff.size() * sizeof(int),
                   hipMemcpyHostToDevice);
   if (e != hipSuccess) return bhip(b, e, "uploading the batch plan");
-  return ASH_OK;
+  return b->persist ? plan_persist(b) : ASH_OK;
 }
 
 // Upload the descriptors with this call's phase and weight pointers.
@@ -402,6 +549,177 @@ int counters(ash_batch* b, size_t launches, int** out) {
   return ASH_OK;
 }
 
+// Upload the one-launch descriptors with this call's phase and weight
+// pointers, and zero the barrier counters and the error flag.
+int upload_persist(ash_batch* b, float* const* phase, float* const* W) {
+  for (size_t i = 0; i < b->pholo.size(); ++i) {
+    const int h = b->pmember[i];
+    b->pholo[i].phase = phase[h];
+    b->pholo[i].W = W[h];
+  }
+  BCHK(b, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  BCHK(b, hipMemcpy(b->d_pholo, b->pholo.data(),
+                    b->pholo.size() * sizeof(PHolo), hipMemcpyHostToDevice),
+       "uploading descriptors");
+  return ASH_OK;
+}
+
+// One launch per record shape runs all n_iter iterations of its holograms;
+// then the stream is synchronised and the barriers' error flag read.
+int run_persist(ash_batch* b, int n_iter, float power) {
+  const size_t n_ctr = (b->pholo.size() + 1) * kCtrPad;
+  int* err = b->d_pctr + b->pholo.size() * kCtrPad;
+  BCHK(b, hipMemsetAsync(b->d_pctr, 0, n_ctr * sizeof(int), b->stream),
+       "clearing barrier counters");
+  for (const Cls& c : b->cls) {
+    BCHK(b, btimed(b, ASH_PROF_FORWARD, [&] {
+           return launch_batch_persist(c.G, c.reduce != 0, c.p_grid, c.p_lds,
+                                       b->d_pholo + c.p_holo,
+                                       b->d_pblk + c.p_blk, n_iter, power,
+                                       c.chunk, err, b->stream);
+         }), "batch launch");
+  }
+  int flag = 0;
+  BCHK(b, hipMemcpyAsync(&flag, err, sizeof(int), hipMemcpyDeviceToHost,
+                         b->stream), "reading the barrier flag");
+  BCHK(b, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  if (flag)
+    return bfail(b, ASH_EHIP, "a barrier of the one-launch batch exceeded "
+                              "its time limit; results are incomplete");
+  return ASH_OK;
+}
+
+// Tuner of the one-launch form: per record shape, every (chunk, resident
+// blocks per CU) pair times one launch of kPersistTuneIters iterations on
+// copies of the caller's phases (unit weights), and the fastest is kept.
+int tune_persist(ash_batch* b, float* const* phase_dev,
+                 std::vector<float>* best_ms) {
+  const size_t H = b->m.size();
+  std::vector<float*> ph(H, nullptr), W(H, nullptr);
+  int rc = ASH_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    for (size_t h = 0; h < H; ++h) {
+      bfree(ph[h]);
+      bfree(W[h]);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  for (size_t h = 0; h < H && !rc; ++h) {
+    const size_t P = (size_t)b->m[h]->basis.g.nx * b->m[h]->basis.g.ny;
+    if (hipMalloc(reinterpret_cast<void**>(&ph[h]), P * sizeof(float)) !=
+            hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&W[h]),
+                  b->m[h]->spots.N * sizeof(float)) != hipSuccess) {
+      (void)hipGetLastError();
+      rc = bfail(b, ASH_ENOMEM, "out of device memory for tuning copies");
+    }
+  }
+  if (!rc && (hipEventCreate(&e0) != hipSuccess ||
+              hipEventCreate(&e1) != hipSuccess))
+    rc = bfail(b, ASH_EHIP, "hipEventCreate");
+  best_ms->assign(b->cls.size(), 0.0f);
+  const std::vector<float> ones(kPersistSpots, 1.0f);
+  int* err = nullptr;
+  for (size_t k = 0; k < b->cls.size() && !rc; ++k) {
+    Cls& c = b->cls[k];
+    const int max_bpc = persist_blocks_per_cu(
+        c.G, c.reduce != 0, c.p_lds ? c.p_lds : persist_lds_bytes(kPersistSpots));
+    int best_chunk = c.chunk, best_bpc = c.bpc;
+    float best_t = -1.0f;
+    for (int chunk : kChunkCandidates) {
+      for (int bpc = 1; bpc <= max_bpc && !rc; ++bpc) {
+        c.chunk = chunk;
+        c.bpc = bpc;
+        if ((rc = plan_persist(b))) break;
+        if ((rc = upload_persist(b, ph.data(), W.data()))) break;
+        err = b->d_pctr + b->pholo.size() * kCtrPad;
+        for (size_t h = 0; h < H && !rc; ++h) {
+          const size_t P = (size_t)b->m[h]->basis.g.nx * b->m[h]->basis.g.ny;
+          if (hipMemcpyAsync(ph[h], phase_dev[h], P * sizeof(float),
+                             hipMemcpyDeviceToDevice, b->stream) != hipSuccess ||
+              hipMemcpyAsync(W[h], ones.data(),
+                             b->m[h]->spots.N * sizeof(float),
+                             hipMemcpyHostToDevice, b->stream) != hipSuccess)
+            rc = bfail(b, ASH_EHIP, "copying tuning inputs");
+        }
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipMemsetAsync(b->d_pctr, 0,
+                           (b->pholo.size() + 1) * kCtrPad * sizeof(int),
+                           b->stream) != hipSuccess ||
+            hipEventRecord(e0, b->stream) != hipSuccess ||
+            launch_batch_persist(c.G, c.reduce != 0, c.p_grid, c.p_lds,
+                                 b->d_pholo + c.p_holo, b->d_pblk + c.p_blk,
+                                 kPersistTuneIters, 1.0f, c.chunk, err,
+                                 b->stream) != hipSuccess ||
+            hipEventRecord(e1, b->stream) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          (void)hipGetLastError();
+          rc = bfail(b, ASH_EHIP, "timing a one-launch candidate");
+          break;
+        }
+        int flag = 0;
+        if (hipMemcpy(&flag, err, sizeof(int), hipMemcpyDeviceToHost) !=
+                hipSuccess || flag) {
+          rc = bfail(b, ASH_EHIP, "a tuning launch's barrier timed out");
+          break;
+        }
+        if (best_t < 0.0f || ms < best_t) {
+          best_t = ms;
+          best_chunk = chunk;
+          best_bpc = bpc;
+        }
+      }
+      if (rc) break;
+    }
+    c.chunk = best_chunk;
+    c.bpc = best_bpc;
+    (*best_ms)[k] = best_t / kPersistTuneIters;
+  }
+  // the same iterations in launches per phase, on the same copies, with
+  // the range lengths tuned before: the faster form is kept
+  float ms_phase = 0.0f;
+  if (!rc) {
+    int* ctr = nullptr;
+    for (size_t h = 0; h < H && !rc; ++h) {
+      const size_t P = (size_t)b->m[h]->basis.g.nx * b->m[h]->basis.g.ny;
+      if (hipMemcpyAsync(ph[h], phase_dev[h], P * sizeof(float),
+                         hipMemcpyDeviceToDevice, b->stream) != hipSuccess ||
+          hipMemcpyAsync(W[h], ones.data(), b->m[h]->spots.N * sizeof(float),
+                         hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        rc = bfail(b, ASH_EHIP, "copying tuning inputs");
+    }
+    if (!rc) rc = upload_desc(b, ph.data(), W.data());
+    if (!rc) rc = counters(b, kPersistTuneIters, &ctr);
+    if (!rc && hipEventRecord(e0, b->stream) != hipSuccess)
+      rc = bfail(b, ASH_EHIP, "hipEventRecord");
+    if (!rc) rc = make_fields(b, ph.data());
+    const size_t per = b->cls.size() * kXcds * kCtrPad;
+    for (int it = 0; it < kPersistTuneIters && !rc; ++it) {
+      if ((rc = enqueue_forward(b, ctr + it * per)) ||
+          (rc = enqueue_reduce_update(b, 1.0f, true)) ||
+          (rc = enqueue_adjoint(b, it == kPersistTuneIters - 1)))
+        break;
+    }
+    if (!rc && (hipEventRecord(e1, b->stream) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms_phase, e0, e1) != hipSuccess))
+      rc = bfail(b, ASH_EHIP, "timing the phase launches");
+  }
+  if (!rc) {
+    float ms_one = 0.0f;
+    for (float x : *best_ms) ms_one += x;
+    ms_phase /= kPersistTuneIters;
+    b->one_launch = ms_one <= ms_phase;
+    best_ms->push_back(ms_phase);
+  }
+  cleanup();
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -437,6 +755,18 @@ int ash_batch_create(ash_batch** out, int H, ash_ctx* const* members,
     it->holos.push_back(h);
   }
   int rc = buse(b);
+  // every member small enough for the one-launch form, and a device that
+  // launches cooperative grids
+  int coop = 0;
+  if (!rc && hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch,
+                                   b->device) != hipSuccess) {
+    (void)hipGetLastError();
+    coop = 0;
+  }
+  b->persist = coop != 0;
+  for (int h = 0; h < H; ++h)
+    if (members[h]->spots.N > kPersistSpots) b->persist = false;
+  b->one_launch = b->persist;
   if (!rc) {
     if (hipMalloc(reinterpret_cast<void**>(&b->d_desc),
                   H * sizeof(HoloDesc)) != hipSuccess) {
@@ -465,6 +795,11 @@ int ash_batch_destroy(ash_batch* b) {
   bfree(b->d_rblk);
   bfree(b->d_qoff);
   bfree(b->d_ctr);
+  bfree(b->d_pholo);
+  bfree(b->d_pblk);
+  bfree(b->d_prows);
+  bfree(b->d_pyblk);
+  bfree(b->d_pctr);
   for (auto& r : b->prof) {
     (void)hipEventDestroy(r.start);
     (void)hipEventDestroy(r.stop);
@@ -500,6 +835,12 @@ int ash_batch_wgs(ash_batch* b, float* const* phase_dev,
     return bfail(b, ASH_EUNSUPPORTED, "phase fixing runs per hologram");
   if (n_iter == 0) return ASH_OK;
   int rc;
+  if (b->one_launch) {
+    if ((rc = buse(b)) || (rc = check_members(b)) ||
+        (rc = upload_persist(b, phase_dev, weights_dev)))
+      return rc;
+    return run_persist(b, n_iter, power);
+  }
   if ((rc = buse(b)) || (rc = check_members(b)) ||
       (rc = upload_desc(b, phase_dev, weights_dev)))
     return rc;
@@ -570,10 +911,17 @@ int ash_batch_tune(ash_batch* b, float* const* phase_dev,
     b->cls[k].L = best;
     best_ms[k] = best_t / kTimed;
   }
-  b->prof_mask = saved_mask;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (!rc) rc = plan(b);
+  // the one-launch form: its chunk and blocks per CU, then the faster of
+  // the two forms
+  std::vector<float> pms;
+  if (!rc && b->persist) {
+    rc = tune_persist(b, phase_dev, &pms);
+    if (!rc) rc = plan(b);
+  }
+  b->prof_mask = saved_mask;
   if (rc) return rc;
   if (table_out) {
     FILE* f = fopen(table_out, "w");
@@ -582,6 +930,16 @@ int ash_batch_tune(ash_batch* b, float* const* phase_dev,
     for (size_t k = 0; k < b->cls.size(); ++k)
       fprintf(f, "%d %d %d %.4f\n", b->cls[k].G, b->cls[k].reduce,
               b->cls[k].L, best_ms[k]);
+    if (b->persist) {
+      fprintf(f, "# persist groups range_reduce chunk blocks_per_cu "
+                 "ms_per_iteration\n");
+      for (size_t k = 0; k < b->cls.size(); ++k)
+        fprintf(f, "persist %d %d %d %d %.4f\n", b->cls[k].G,
+                b->cls[k].reduce, b->cls[k].chunk, b->cls[k].bpc, pms[k]);
+      fprintf(f, "# form (1: one launch, 0: launches per phase), "
+                 "ms_per_iteration of the launches per phase\n");
+      fprintf(f, "form %d %.4f\n", b->one_launch ? 1 : 0, pms.back());
+    }
     fclose(f);
   }
   return ASH_OK;
@@ -596,7 +954,21 @@ int ash_batch_load_tuning(ash_batch* b, const char* table_in) {
   int n_set = 0;
   while (fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
-    int G = 0, red = 0, L = 0;
+    int G = 0, red = 0, L = 0, bpc = 0;
+    if (sscanf(line, "form %d", &L) == 1) {
+      b->one_launch = b->persist && L == 1;
+      continue;
+    }
+    if (sscanf(line, "persist %d %d %d %d", &G, &red, &L, &bpc) == 4) {
+      if (L < 1 || L > (1 << 20) || bpc < 0 || bpc > 64) continue;
+      for (auto& c : b->cls)
+        if (c.G == G && c.reduce == red) {
+          c.chunk = L;
+          c.bpc = bpc;
+          ++n_set;
+        }
+      continue;
+    }
     if (sscanf(line, "%d %d %d", &G, &red, &L) != 3) continue;
     if (L < 1 || L > (1 << 20)) continue;
     for (auto& c : b->cls)
@@ -611,6 +983,17 @@ int ash_batch_load_tuning(ash_batch* b, const char* table_in) {
   return rc ? rc : ASH_OK;
 }
 
+int ash_batch_set_form(ash_batch* b, int one_launch) {
+  if (!b || (one_launch != 0 && one_launch != 1)) return ASH_EINVAL;
+  b->err.clear();
+  if (one_launch && !b->persist)
+    return bfail(b, ASH_EUNSUPPORTED,
+                 "the one-launch form needs members of at most 512 spots "
+                 "and a device with cooperative launches");
+  b->one_launch = one_launch != 0;
+  return ASH_OK;
+}
+
 int ash_batch_get_info(const ash_batch* b, ash_batch_info* out) {
   if (!b || !out) return ASH_EINVAL;
   memset(out, 0, sizeof *out);
@@ -622,6 +1005,12 @@ int ash_batch_get_info(const ash_batch* b, ash_batch_info* out) {
   }
   out->items = (int64_t)b->items.size();
   out->evals_per_transform = b->evals_per_transform;
+  out->one_launch = b->one_launch ? 1 : 0;
+  for (size_t k = 0; k < b->cls.size() && k < 4; ++k) {
+    out->chunk[k] = b->cls[k].chunk;
+    out->blocks_per_cu[k] = b->one_launch ? b->cls[k].p_grid / b->n_cu : 0;
+    out->grid[k] = b->one_launch ? b->cls[k].p_grid : 0;
+  }
   return ASH_OK;
 }
 

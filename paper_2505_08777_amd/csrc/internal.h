@@ -246,6 +246,48 @@ hipError_t launch_batch_update(int H, const HoloDesc* d, float power,
 // Resident blocks per CU of the persistent kernels.
 int batch_blocks_per_cu(int G, bool reduce, bool forward);
 
+// ---- batched form in one launch (holograms of at most kPersistSpots) ----
+// Every block owns a contiguous range of one hologram's 32-pixel blocks and
+// runs all iterations: the forward over its range (partial sums per block),
+// a barrier with the hologram's other blocks, the weight update of the
+// whole hologram from all blocks' partial sums (every block computes it,
+// the same way, so no second barrier is needed), and the adjoint of its
+// range.
+constexpr int kPersistSpots = 512;
+
+struct PHolo {
+  const u32x4* pixtab;
+  unsigned* nf_t;          // nearfield records (built from `phase` first)
+  const u32x4* spotrec;
+  const unsigned* offtab;
+  const float* amp_t;
+  const float* target;
+  float* W;                // spot weights (caller's), in/out
+  float* phase;            // phase (caller's), in/out
+  float2* rows;            // [2][n_blocks][N] per-block forward sums
+  unsigned* yblk;          // [n_blocks][NP * 8] per-block spot-field records
+  int* ctr;                // barrier counter (zero at launch)
+  long n_blk;              // 32-pixel blocks (tile rows)
+  int N, nx, ny, tiles_x, groups, n_blocks;
+  float t_norm;
+};
+// Block `j` of hologram `holo` owns pixel blocks [b0, b1).
+struct PBlock {
+  int holo, j;
+  long b0, b1;
+};
+// Units of a block's forward: (chunk of `chunk` pixel blocks, spot block),
+// taken by its waves in turn.  `err` is set when a barrier waits longer
+// than its time limit (then every block leaves the loop).
+hipError_t launch_batch_persist(int G, bool reduce, int grid, size_t lds,
+                                const PHolo* hd, const PBlock* blks,
+                                int n_iter, float power, int chunk, int* err,
+                                hipStream_t s);
+// Resident blocks per CU of the persistent kernel with `lds` bytes of
+// dynamic LDS, and its LDS need for N spots.
+int persist_blocks_per_cu(int G, bool reduce, size_t lds);
+size_t persist_lds_bytes(int N);
+
 }  // namespace ash
 
 struct ash_prof_rec {

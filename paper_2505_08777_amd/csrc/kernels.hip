@@ -563,19 +563,18 @@ hipError_t launch_prep_spots(const Geom& b, int N, const double* d_w,
 // with the basis amplitude or from a complex field; spot-field records
 // {|y|, phase pieces}.
 // ---------------------------------------------------------------------------
-__global__ void k_make_field(Geom b, long total,
-                             const float* __restrict__ phase,
-                             const float2* __restrict__ field,
-                             const float* __restrict__ amp_t,
-                             const u32x4* __restrict__ pixtab,
-                             u32x4* __restrict__ nf, float* __restrict__ fmag) {
-  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= total) return;
+// Nearfield record of pixel `pix` of `tile` (tile-order index gid).
+__device__ __forceinline__ void make_field_at(
+    int nx, int ny, int tiles_x, int G, long gid,
+    const float* __restrict__ phase, const float2* __restrict__ field,
+    const float* __restrict__ amp_t, const u32x4* __restrict__ pixtab,
+    u32x4* __restrict__ nf, float* __restrict__ fmag) {
   const int tile = (int)(gid / kTile), pix = (int)(gid % kTile);
-  int i, j;
+  const int i = (tile % tiles_x) * kTileW + pix % kTileW;
+  const int j = (tile / tiles_x) * kTileH + pix / kTileW;
   float mag = 0.0f, turns = 0.0f;
-  if (pixel_ij(b, tile, pix, &i, &j)) {
-    const long p = (long)j * b.nx + i;
+  if (i < nx && j < ny) {
+    const long p = (long)j * nx + i;
     if (phase) {
       mag = amp_t[gid];
       turns = rad_to_turns(phase[p]);  // any phase: reduced to [-1/2, 1/2]
@@ -585,14 +584,26 @@ __global__ void k_make_field(Geom b, long total,
       turns = rad_to_turns(atan2f(f.y, f.x));
     }
   }
-  nf[nf_index(tile, pix, 0)] = nearfield_record(
-      pixel_nl_words(pixtab, b.groups, tile, pix), turns);
+  nf[nf_index(tile, pix, 0)] =
+      nearfield_record(pixel_nl_words(pixtab, G, tile, pix), turns);
   const unsigned bdi = bf16_bits((float)(pix % kTileW - kAnchorI));
   const unsigned bdj = bf16_bits((float)(pix / kTileW - kAnchorJ));
   nf[nf_index(tile, pix, 1)] =
       u32x4{kBf16One | (kBf16One << 16), bdi | (bdi << 16), bdi | (bdj << 16),
             bdj | (bdj << 16)};
   if (fmag) fmag[gid] = mag;
+}
+
+__global__ void k_make_field(Geom b, long total,
+                             const float* __restrict__ phase,
+                             const float2* __restrict__ field,
+                             const float* __restrict__ amp_t,
+                             const u32x4* __restrict__ pixtab,
+                             u32x4* __restrict__ nf, float* __restrict__ fmag) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  make_field_at(b.nx, b.ny, b.tiles_x, b.groups, gid, phase, field, amp_t,
+                pixtab, nf, fmag);
 }
 
 hipError_t launch_make_field(const Geom& b, const float* phase,
@@ -737,7 +748,7 @@ __device__ __forceinline__ void accumulate(const floatx16& th, float m,
 // lane half its part of the nearfield record's last group, another the
 // magnitude of the lane's pixel (the same for both halves).
 // E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))).
-template <int G, bool kReduce>
+template <int G, bool kReduce, bool kAdd = false>
 __device__ __forceinline__ void forward_range(
     int N, int mb, long b0, long b1, const GLOBAL u32x4* __restrict__ pixtab,
     const GLOBAL u32x4* __restrict__ nf, const GLOBAL float* __restrict__ mag,
@@ -795,7 +806,14 @@ __device__ __forceinline__ void forward_range(
   }
   bfly_reduce(er, ei, q);
   const int ko = mb * 32 + mfma_row(bfly_index(q), h);
-  if ((q & 1) == 0 && ko < N) row[ko] = make_float2(er[0], ei[0]);
+  if ((q & 1) == 0 && ko < N) {
+    if (kAdd) {  // the wave's own running sums (each spot one lane)
+      const float2 o = row[ko];
+      row[ko] = make_float2(o.x + er[0], o.y + ei[0]);
+    } else {
+      row[ko] = make_float2(er[0], ei[0]);
+    }
+  }
 }
 
 // Forward of one hologram: wave = 32 spots x a contiguous range of pixel
@@ -1309,13 +1327,13 @@ hipError_t launch_finish_E(int N, const FwdPlan& p, const float* red, float* E,
 // Weighted-GS farfield update (one block).
 // ---------------------------------------------------------------------------
 
-// Reduction over a block of kUpd threads (sh: one float per wave): a
+// Reduction over a block of NT threads (sh: one float per wave): a
 // butterfly within each wave, then the waves' results in wave order; every
 // thread returns the same value.  The wave count is a constant, so the LDS
 // reads all go out before the first combine.
-template <typename Op>
+template <int NT = kUpd, typename Op>
 __device__ float block_reduce(float v, float* sh, Op op) {
-  constexpr int nw = kUpd / kWave;
+  constexpr int nw = NT / kWave;
 #pragma unroll
   for (int w = 32; w >= 1; w >>= 1) v = op(v, __shfl_xor(v, w, kWave));
   if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = v;
@@ -1337,10 +1355,11 @@ struct OpMin {
   __device__ float operator()(float a, float b) const { return fminf(a, b); }
 };
 
-// Several block reductions in one LDS pass over a block of kUpd threads
+// Several block reductions in one LDS pass over a block of NT threads
 // (sh: NV floats per wave): value i is combined with Op_i, in the order of
 // block_reduce.
-template <typename Op0, typename Op1, typename Op2, typename Op3>
+template <typename Op0, typename Op1, typename Op2, typename Op3,
+          int NT = kUpd>
 __device__ void block_reduce4(float* v, float* sh) {
   constexpr int NV = 4;
   const Op0 o0;
@@ -1354,7 +1373,7 @@ __device__ void block_reduce4(float* v, float* sh) {
   for (int i = 0; i < NV; ++i)
 #pragma unroll
     for (int w = 32; w >= 1; w >>= 1) v[i] = op(i, v[i], __shfl_xor(v[i], w, kWave));
-  constexpr int nw = kUpd / kWave;
+  constexpr int nw = NT / kWave;
   const int wave = threadIdx.x / kWave;
   if ((threadIdx.x & (kWave - 1)) == 0)
 #pragma unroll
@@ -1370,12 +1389,14 @@ __device__ void block_reduce4(float* v, float* sh) {
   __syncthreads();
 }
 
-// The weighted-GS farfield update of one hologram by one block (sh: one
-// float of LDS per wave).
+// The weighted-GS farfield update of one hologram by one block of NT
+// threads (sh: four floats of LDS per wave).  W and Ebuf may be global or
+// LDS (generic) pointers.
 // meas: amplitudes that replace |E_k| in the weight update (experimental
 // feedback), or null.  phase_mode: kPhaseFree projects onto arg E_k;
 // kPhaseStore also stores arg E_k (turns) in fixph; kPhaseFixed projects
 // onto the stored phases (phase-fixed weighted GS).
+template <int NT = kUpd>
 __device__ __forceinline__ void wgs_update_block(
     int N, int slices, const float2* __restrict__ red,
     const float* __restrict__ t, float t_norm, float* __restrict__ W,
@@ -1415,10 +1436,10 @@ __device__ __forceinline__ void wgs_update_block(
     }
   }
   float r1[4] = {s_a2, s_I, mx, mn};
-  block_reduce4<OpSum, OpSum, OpMax, OpMin>(r1, sh);
+  block_reduce4<OpSum, OpSum, OpMax, OpMin, NT>(r1, sh);
   const float sum_a2 = r1[0], sum_I = r1[1], maxI = r1[2], minI = r1[3];
   const float norm_a =
-      sqrtf(meas ? block_reduce(s_m2, sh, OpSum()) : sum_a2);
+      sqrtf(meas ? block_reduce<NT>(s_m2, sh, OpSum()) : sum_a2);
   const float meanI = sum_I / (float)N;
   // pass 2: spread of I, unnormalised weight update
   float s_v = 0.0f, s_w = 0.0f;
@@ -1441,7 +1462,7 @@ __device__ __forceinline__ void wgs_update_block(
     s_w += wk;
   }
   float r2[4] = {s_v, s_w, 0.0f, 0.0f};
-  block_reduce4<OpSum, OpSum, OpSum, OpSum>(r2, sh);
+  block_reduce4<OpSum, OpSum, OpSum, OpSum, NT>(r2, sh);
   const float var = r2[0] / (float)N;
   const float mean_w = r2[1] / (float)N;
   // pass 3: normalise weights, farfield projection y = W t exp(i psi) with
@@ -1967,6 +1988,196 @@ hipError_t launch_batch_update(int H, const HoloDesc* d, float power,
                                hipStream_t s) {
   hipLaunchKernelGGL(k_batch_update, dim3(H), dim3(kUpd), 0, s, d, power);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched form in one launch.  The blocks of a hologram meet once per
+// iteration at a barrier (a counter per hologram; release before the count,
+// acquire after it, at device scope, so that the partial sums written on
+// any accelerator die are seen on the others).  The launch is cooperative,
+// so all blocks are resident and every block reaches every barrier; a
+// barrier that waits longer than kBarrierTicks sets *err and every block
+// leaves, so the kernel ends in any case.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long kBarrierTicks = 1000000000ull;  // 10 s at 100 MHz
+
+size_t persist_lds_bytes(int N) {
+  const int NP = (N + 31) / 32 * 32;
+  // per-wave forward sums [4][NP] float2 (reused for the fields E in the
+  // update) and the weights [NP]
+  return (size_t)NP * (4 * 8 + 4);
+}
+
+// Wait until the counter reaches `target` (thread 0); false on error.
+__device__ __forceinline__ bool persist_barrier(int* ctr, int target,
+                                                int* err) {
+  __shared__ int ok;
+  __syncthreads();  // the block's writes are done
+  if (threadIdx.x == 0) {
+    __threadfence();  // release at device scope
+    atomicAdd(ctr, 1);
+    int good = 1;
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE,
+                             __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        good = 0;
+        break;
+      }
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTicks) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    ok = good;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok != 0;
+}
+
+template <int G, bool kReduce>
+__global__ __launch_bounds__(kBlock) void k_batch_persist(
+    const PHolo* __restrict__ hd, const PBlock* __restrict__ blks, int n_iter,
+    float power, int chunk, int* __restrict__ err) {
+  extern __shared__ float lds[];
+  __shared__ float sh[4 * kBlock / kWave];
+  const int bi = blockIdx.x;
+  const int holo = __builtin_amdgcn_readfirstlane(blks[bi].holo);
+  const int j = __builtin_amdgcn_readfirstlane(blks[bi].j);
+  const long b0 = blks[bi].b0, b1 = blks[bi].b1;
+  const PHolo& d = hd[holo];
+  const int N = d.N, NP = (N + 31) / 32 * 32, n_mb = NP / 32;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+  float2* wrow = reinterpret_cast<float2*>(lds);  // [4][NP]
+  float* Ws = lds + 8 * NP;                         // [NP]
+  unsigned* yb = d.yblk + (long)j * NP * 8;
+  // the block's weights, its spot-field records past N (zero) and the
+  // nearfield records of its pixels from the start phase
+  for (int k = tid; k < N; k += kBlock) Ws[k] = d.W[k];
+  for (int k = N + tid; k < NP; k += kBlock) {
+    u32x4* y4 = reinterpret_cast<u32x4*>(yb) + (long)(k / 32) * 64 + k % 32;
+    y4[0] = u32x4{0u, 0u, 0u, 0u};
+    y4[32] = u32x4{0u, 0u, 0u, 0u};
+  }
+  for (long gid = b0 * 32 + tid; gid < b1 * 32; gid += kBlock)
+    make_field_at(d.nx, d.ny, d.tiles_x, G, gid, d.phase, nullptr, d.amp_t,
+                  d.pixtab, reinterpret_cast<u32x4*>(d.nf_t), nullptr);
+  __threadfence_block();
+  __syncthreads();
+  const long rows = b1 - b0;
+  const long n_chunks = (rows + chunk - 1) / chunk;
+  for (int it = 0; it < n_iter; ++it) {
+    // forward: units (chunk, spot block) in turn over the four waves; each
+    // wave adds its units' sums into its own row
+    for (int k = tid; k < 4 * NP; k += kBlock) wrow[k] = make_float2(0.f, 0.f);
+    __syncthreads();
+    for (long u = wave; u < n_chunks * n_mb; u += kBlock / kWave) {
+      const long c = u / n_mb;
+      const int mb = (int)(u - c * n_mb);
+      const long r0 = b0 + c * chunk;
+      const long r1 = r0 + chunk < b1 ? r0 + chunk : b1;
+      forward_range<G, kReduce, true>(
+          N, mb, r0, r1, as_global(d.pixtab),
+          as_global(reinterpret_cast<const u32x4*>(d.nf_t)),
+          as_global(d.amp_t), as_global(d.spotrec),
+          as_global(reinterpret_cast<const u32x4*>(d.offtab)),
+          wrow + (long)wave * NP);
+    }
+    __syncthreads();
+    float2* rows_it = d.rows + (long)(it & 1) * d.n_blocks * N;
+    for (int k = tid; k < N; k += kBlock) {  // the waves' sums in order
+      float2 v = wrow[k];
+#pragma unroll
+      for (int w = 1; w < kBlock / kWave; ++w) {
+        v.x += wrow[(long)w * NP + k].x;
+        v.y += wrow[(long)w * NP + k].y;
+      }
+      rows_it[(long)j * N + k] = v;
+    }
+    if (!persist_barrier(d.ctr, d.n_blocks * (it + 1), err)) return;
+    // the weight update of the whole hologram from all blocks' sums, into
+    // this block's weights and spot-field records
+    wgs_update_block<kBlock>(N, d.n_blocks, rows_it, d.target, d.t_norm, Ws,
+                             power, 0.0f, yb, wrow, nullptr, nullptr, sh,
+                             nullptr, nullptr, kPhaseFree);
+    __threadfence_block();
+    __syncthreads();
+    // adjoint of the block's pixel blocks: the next nearfield, or the
+    // phase after the last iteration
+    AdjOut o;
+    o.outs = it == n_iter - 1 ? kOutPhase : kOutField;
+    o.phase = d.phase;
+    o.nf_t = d.nf_t;
+    for (long b = b0 + wave; b < b1; b += kBlock / kWave)
+      adjoint_row<G, kReduce>(
+          N, d.nx, d.ny, d.tiles_x, (int)(b / kBlkPerTile),
+          (int)(b % kBlkPerTile) * 32, 0, as_global(d.pixtab),
+          as_global(d.spotrec),
+          as_global(reinterpret_cast<const u32x4*>(d.offtab)),
+          as_global(reinterpret_cast<const u32x4*>(yb)), as_global(d.amp_t),
+          o);
+    __threadfence_block();
+    __syncthreads();
+  }
+  if (j == 0)
+    for (int k = tid; k < N; k += kBlock) d.W[k] = Ws[k];
+}
+
+template <int G, bool kReduce>
+static hipError_t bpersist_g(int grid, size_t lds, const PHolo* hd,
+                             const PBlock* blks, int n_iter, float power,
+                             int chunk, int* err, hipStream_t s) {
+  void* args[] = {(void*)&hd, (void*)&blks, (void*)&n_iter, (void*)&power,
+                  (void*)&chunk, (void*)&err};
+  return hipLaunchCooperativeKernel(
+      reinterpret_cast<const void*>(&k_batch_persist<G, kReduce>),
+      dim3(grid), dim3(kBlock), args, (unsigned)lds, s);
+}
+
+hipError_t launch_batch_persist(int G, bool reduce, int grid, size_t lds,
+                                const PHolo* hd, const PBlock* blks,
+                                int n_iter, float power, int chunk, int* err,
+                                hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  switch (G) {
+#define X(n)                                                                \
+  case n:                                                                   \
+    return reduce ? bpersist_g<n, true>(grid, lds, hd, blks, n_iter, power, \
+                                        chunk, err, s)                      \
+                  : bpersist_g<n, false>(grid, lds, hd, blks, n_iter, power,\
+                                         chunk, err, s);
+    ASH_G_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <int G, bool kReduce>
+static int persist_occ(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, k_batch_persist<G, kReduce>, kBlock, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+int persist_blocks_per_cu(int G, bool reduce, size_t lds) {
+  switch (G) {
+#define X(n) \
+  case n:    \
+    return reduce ? persist_occ<n, true>(lds) : persist_occ<n, false>(lds);
+    ASH_G_CASES(X)
+#undef X
+    default:
+      return 0;
+  }
 }
 
 template <typename K>

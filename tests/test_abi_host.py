@@ -17,18 +17,28 @@ from paper_2505_08777_amd import _lib  # noqa: E402
 import oracle  # noqa: E402
 
 
-def declared_symbols():
-    src = open(HEADER).read()
+def declared_symbols(header=HEADER):
+    src = open(header).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(ash_[a-z_0-9]+)\s*\(", src)))
+
+
+# each header of include/ and the library that implements it
+LIBS = {"ash.h": "libash.so", "ash_ubench.h": "libash_ubench.so"}
 
 
 def test_exports_every_declared_symbol():
     syms = declared_symbols()
     assert "ash_forward" in syms and "ash_wgs_iterate" in syms
-    lib = ctypes.CDLL(_lib.LIB_PATH)
-    missing = [s for s in syms if not hasattr(lib, s)]
-    assert not missing, missing
+    headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include"))
+                     if f.endswith(".h"))
+    assert headers == sorted(LIBS)
+    for h in headers:
+        lib = ctypes.CDLL(os.path.join(os.path.dirname(_lib.LIB_PATH), LIBS[h]))
+        syms = declared_symbols(os.path.join(ROOT, "include", h))
+        assert syms
+        missing = [s for s in syms if not hasattr(lib, s)]
+        assert not missing, (h, missing)
 
 
 def test_status_codes_match_header():

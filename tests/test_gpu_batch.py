@@ -124,10 +124,13 @@ def test_batch_shapes(A, batch_case):
     b.close()
 
 
+@pytest.mark.parametrize("one_launch", [True, False], ids=["one_launch", "per_phase"])
 @pytest.mark.parametrize("n_iter", [1, 3])
-def test_batch_equals_unbatched(A, batch_case, n_iter):
+def test_batch_equals_unbatched(A, batch_case, n_iter, one_launch):
     holos, ctxs = batch_case
     b = A.Batch(ctxs)
+    b.set_form(one_launch)
+    assert b.info()["one_launch"] == one_launch
     ph_b = [_cu(h["phi"]) for h in holos]
     W_b = [torch.ones(h["w"].shape[0], device="cuda") for h in holos]
     b.wgs(ph_b, n_iter, weights=W_b)
@@ -167,12 +170,21 @@ def test_batch_tuning_table(A, batch_case, tmp_path):
     path = str(tmp_path / "tune.txt")
     inf = b.tune(ph, table_out=path)
     _say(inf, open(path).read())
+    # these members are small: the tuner sets both forms' parameters (range
+    # lengths; chunk and resident blocks per CU of the one-launch form) and
+    # keeps the faster form
     assert all(L in (16, 32, 64, 128, 256, 512) for L in inf["range_blocks"])
+    assert all(L in (4, 8, 16, 32) for L in inf["chunk"])
     rows = [l.split() for l in open(path) if not l.startswith("#")]
-    assert len(rows) == inf["shapes"]
+    assert sum(r[0] == "persist" for r in rows) == inf["shapes"]
+    assert sum(r[0] == "form" for r in rows) == 1
+    assert sum(r[0].isdigit() for r in rows) == inf["shapes"]
     b2 = A.Batch(ctxs)
     b2.load_tuning(path)
-    assert b2.info()["range_blocks"] == inf["range_blocks"]
+    i2 = b2.info()
+    assert i2["chunk"] == inf["chunk"] and i2["grid"] == inf["grid"]
+    assert i2["one_launch"] == inf["one_launch"]
+    assert i2["range_blocks"] == inf["range_blocks"]
     # the tuned batch still computes the same step
     p1 = [_cu(h["phi"]) for h in holos]
     p2 = [_cu(h["phi"]) for h in holos]
@@ -265,6 +277,82 @@ def test_batch64_members(A):
         gref = oracle.adjoint(y.astype(np.complex128), d["w"], basis, geom, pixels=pix)
         _say("  adjoint at 4096 pixels", field_errors(g[pix], gref))
         assert_fields(g[pix], gref, what="batch64 member %d adjoint" % h)
+    b.close()
+    for c in ctxs:
+        c.close()
+
+
+def _members(A, holos):
+    ctxs = []
+    for d in holos:
+        c = A.Context(0)
+        c.set_basis(d["nx"], d["ny"], modes=d["modes"],
+                    amp=torch.tensor(d["amp"], dtype=torch.float32, device="cuda"))
+        c.set_spots(d["w"], d["t"])
+        ctxs.append(c)
+    return ctxs
+
+
+def test_batch64small_one_launch(A):
+    """64 small holograms (256..512 pixels a side, 5..200 spots) in one
+    launch per record shape, two iterations: every member against its own
+    unbatched run, the three smallest and the three largest (by N * P)
+    against the oracle's first step."""
+    holos = workloads.make("batch64small")
+    ctxs = _members(A, holos)
+    b = A.Batch(ctxs)
+    b.set_form(True)
+    inf = b.info()
+    _say(inf)
+    assert inf["one_launch"] and sum(inf["grid"]) > 64
+    # one iteration against the oracle (three smallest and three largest)
+    ph = [_cu(d["phi0"]) for d in holos]
+    W = [torch.ones(d["w"].shape[0], device="cuda") for d in holos]
+    b.wgs(ph, 1, weights=W)
+    torch.cuda.synchronize()
+    order = np.argsort([d["w"].shape[0] * d["nx"] * d["ny"] for d in holos])
+    rng = np.random.default_rng(6464)
+    for h in list(order[:3]) + list(order[-3:]):
+        d = holos[h]
+        geom = oracle.Geometry(d["nx"], d["ny"])
+        basis = oracle.ZernikeBasis(d["modes"])
+        amp = d["amp"].astype(np.float32).astype(np.float64)
+        phi = d["phi0"].astype(np.float32).astype(np.float64)
+        t = d["t"].astype(np.float32).astype(np.float64)
+        N = d["w"].shape[0]
+        E = ctxs[h].forward(phase=_cu(phi))
+        pix = np.sort(rng.choice(geom.P, size=4096, replace=False))
+        ref = stepcheck.reference_step(phi, np.ones(N), t, amp, d["w"], basis,
+                                       geom, pixels=pix)
+        stepcheck.check_step("batch64small member %d (%d^2, %d spots)"
+                             % (h, d["nx"], N), ph[h], W[h], E, ref, t,
+                             pixels=pix)
+    # two more iterations of every member against its own run
+    ph2 = [p.clone() for p in ph]
+    W2 = [w.clone() for w in W]
+    b.wgs(ph, 2, weights=W)
+    worst = (0.0, 0.0)
+    for h, (d, c) in enumerate(zip(holos, ctxs)):
+        p1, w1 = ph2[h], W2[h]
+        _, w1, E1, _ = c.wgs(p1, 2, weights=w1)
+        err = _batch_vs_alone(c, d["t"], ph[h], W[h], p1, w1, E1,
+                              "batch64small member %d vs alone" % h, n_iter=2)
+        worst = (max(worst[0], err[0]), max(worst[1], err[1]))
+    _say("one launch vs alone over 64 members: phase %.2e rad, weights %.2e" % worst)
+    b.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_batch64_uses_phase_launches(A):
+    """Members with more spots than the one-launch form holds run as one
+    launch per phase (the batch64 test covers their results)."""
+    d = max(workloads.make("batch64"), key=lambda x: x["w"].shape[0])
+    ctxs = _members(A, [d])
+    b = A.Batch(ctxs)
+    assert d["w"].shape[0] > 512 and not b.info()["one_launch"]
+    with pytest.raises(A.AshError):
+        b.set_form(True)
     b.close()
     for c in ctxs:
         c.close()
