@@ -1684,6 +1684,55 @@ __device__ inline float tv_grad_at(const float* __restrict__ ph, int nx,
 // order, or the phase gradient (see AdjOut).  `wv` indexes the per-wave TV
 // sums.
 // ---------------------------------------------------------------------------
+// Epilogue of an adjoint row: the butterfly over the spot columns leaves
+// h = g(x) of pixel p0 + (row of the lane) in every even lane, which writes
+// what `o` asks for.
+template <int G>
+__device__ __forceinline__ void adjoint_epilogue(
+    float* gr, float* gi, int nx, int ny, int tiles_x, int tile, int p0,
+    long wv, const GLOBAL u32x4* __restrict__ pixtab,
+    const GLOBAL float* __restrict__ amp_t, const AdjOut& o) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int h = lane >> 5, q = lane & 31;
+  bfly_reduce(gr, gi, q);
+  // one result per lane pair; the odd lane of a pair idles in the epilogue
+  const bool lead = (q & 1) == 0;
+  const int pix = p0 + mfma_row(bfly_index(q), h);
+  const int i = (tile % tiles_x) * kTileW + pix % kTileW;
+  const int j = (tile / tiles_x) * kTileH + pix / kTileW;
+  const bool inside = lead && i < nx && j < ny;
+  const long p = (long)j * nx + i;
+  const float vr = gr[0], vi = gi[0];
+  if (lead && (o.outs & (kOutField | kOutPhase))) {
+    const float ang = atan2f(vi, vr);  // atan2(0, 0) = 0
+    if (o.outs & kOutField)  // next nearfield: the magnitudes stay
+      reinterpret_cast<u32x4*>(o.nf_t)[nf_index(tile, pix, 0)] =
+          nearfield_record(
+              pixel_nl_words((const u32x4*)pixtab, G, tile, pix),
+              rad_to_turns(ang));
+    if (inside && (o.outs & kOutPhase)) o.phase[p] = ang;
+  }
+  if (inside && (o.outs & kOutG))
+    reinterpret_cast<float2*>(o.g)[p] = make_float2(vr, vi);
+  if (o.outs & kOutGrad) {
+    float term = 0.0f;
+    if (inside) {
+      // Im(conj(f) h) with f = A exp(i phi)
+      float sn, cs;
+      sincosf(o.phase_in[p], &sn, &cs);
+      float gv = amp_t[(long)tile * kTile + pix] * (cs * vi - sn * vr);
+      if (o.tv_scale != 0.0f)
+        gv += o.tv_scale * tv_grad_at(o.phase_in, nx, ny, i, j, o.tv_eps, &term);
+      o.grad[p] = gv;
+    }
+    if (o.tvp) {  // this wave's TV terms, in a fixed order
+#pragma unroll
+      for (int w = 32; w >= 1; w >>= 1) term += __shfl_xor(term, w, kWave);
+      if (lane == 0) o.tvp[wv] = term;
+    }
+  }
+}
+
 template <int G, bool kReduce>
 __device__ __forceinline__ void adjoint_row(
     int N, int nx, int ny, int tiles_x, int tile, int p0, long wv,
@@ -1729,45 +1778,8 @@ __device__ __forceinline__ void adjoint_row(
     const floatx16 th = phase_block<G>(X, S);
     accumulate<false, kReduce>(th, m, gr, gi);
   }
-  bfly_reduce(gr, gi, q);
-  // one result per lane pair; the odd lane of a pair idles in the epilogue
-  const bool lead = (q & 1) == 0;
-  const int pix = p0 + mfma_row(bfly_index(q), h);
-  const int i = (tile % tiles_x) * kTileW + pix % kTileW;
-  const int j = (tile / tiles_x) * kTileH + pix / kTileW;
-  const bool inside = lead && i < nx && j < ny;
-  const long p = (long)j * nx + i;
-  const float vr = gr[0], vi = gi[0];
-  if (lead && (o.outs & (kOutField | kOutPhase))) {
-    const float ang = atan2f(vi, vr);  // atan2(0, 0) = 0
-    if (o.outs & kOutField)  // next nearfield: the magnitudes stay
-      reinterpret_cast<u32x4*>(o.nf_t)[nf_index(tile, pix, 0)] =
-          nearfield_record(
-              pixel_nl_words((const u32x4*)pixtab, G, tile, pix),
-              rad_to_turns(ang));
-    if (inside && (o.outs & kOutPhase)) o.phase[p] = ang;
-  }
-  if (inside && (o.outs & kOutG))
-    reinterpret_cast<float2*>(o.g)[p] = make_float2(vr, vi);
-  if (o.outs & kOutGrad) {
-    float term = 0.0f;
-    if (inside) {
-      // Im(conj(f) h) with f = A exp(i phi)
-      float sn, cs;
-      sincosf(o.phase_in[p], &sn, &cs);
-      float gv = amp_t[(long)tile * kTile + pix] * (cs * vi - sn * vr);
-      if (o.tv_scale != 0.0f)
-        gv += o.tv_scale * tv_grad_at(o.phase_in, nx, ny, i, j, o.tv_eps, &term);
-      o.grad[p] = gv;
-    }
-    if (o.tvp) {  // this wave's TV terms, in a fixed order
-#pragma unroll
-      for (int w = 32; w >= 1; w >>= 1) term += __shfl_xor(term, w, kWave);
-      if (lane == 0) o.tvp[wv] = term;
-    }
-  }
+  adjoint_epilogue<G>(gr, gi, nx, ny, tiles_x, tile, p0, wv, pixtab, amp_t, o);
 }
-
 
 // Adjoint of one hologram: the four waves of a block are four rows of one
 // tile; blocks reach the XCDs round-robin, so each XCD gets a contiguous run
