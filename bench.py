@@ -176,6 +176,10 @@ def parse():
                          "small holograms (256..512, 5..200 spots)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batch64: skip the autotuner (default range length)")
+    ap.add_argument("--form", choices=["tuned", "one_launch", "per_phase"],
+                    default="tuned",
+                    help="batch workloads: run the form the tuner chose, or "
+                         "force one (after tuning)")
     ap.add_argument("--iters", type=int, default=None,
                     help="WGS iterations per step (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -904,6 +908,8 @@ def bench_batch(args, holos):
             if f[0] == "persist":
                 forms.setdefault("one_launch_ms_per_iteration", 0.0)
                 forms["one_launch_ms_per_iteration"] += float(f[5])
+    if args.form != "tuned":
+        b.set_form(args.form == "one_launch")
     info = b.info()
     for _ in range(args.warmup):
         b.wgs(phases, n_iter, weights=weights)
@@ -934,6 +940,15 @@ def bench_batch(args, holos):
         ms_avg = prof["forward"][0] / calls
         evals_launch = 2.0 * evals * n_iter
         launches = calls
+    elif info["fused"]:
+        # every iteration after the first: one fused launch per record
+        # shape (the adjoint and the next forward, both transforms of all
+        # its holograms), timed alone under the adjoint category; the unit
+        # timed is the fused phase (all its launches)
+        kname = "k_batch_fused<%d, false>" % groups
+        launches = prof["adjoint"][1] // shapes
+        ms_avg = prof["adjoint"][0] / max(launches, 1)
+        evals_launch = 2.0 * evals
     else:
         # a phase is one launch per record shape, each over all holograms
         # of that shape: the unit timed is the phase (all its launches)

@@ -442,7 +442,14 @@ int ash_get_info(const ash_ctx* ctx, ash_info* out);
  * adjoint over (hologram, tile row) items.  Forward items sit in eight
  * per-XCD queues (longest first, balanced by work); resident waves take
  * them with an atomic counter and move to the other queues when theirs runs
- * dry.  The forward range length (pixel blocks per item) is tuned.
+ * dry.  The forward range length (pixel blocks per item) is tuned.  When
+ * every member has at most 512 spots, the adjoint of each iteration but the
+ * last and the forward of the next are one launch over (hologram, pixel
+ * range) items: per 32-pixel block the adjoint over all spots, the phase
+ * it projects to, and the block's terms of the next forward, so the pixel
+ * records are read once per iteration and no nearfield records are
+ * written (the forward sums then differ from the separate kernels' in
+ * FP32 summation order only).
  *
  * A batch starts in the one-launch form when its members allow it;
  * ash_batch_tune keeps the faster form for the batch at hand and
@@ -486,7 +493,8 @@ int ash_batch_wgs(ash_batch* batch, float* const* phase_dev,
                   const ash_wgs_params* params);
 
 /* Autotuner.  For each record shape, times the per-phase form's forward
- * plus its reduction for range lengths of 16, 32, 64, 128, 256 and 512
+ * (the fused launch when the batch fuses) plus its reduction for range
+ * lengths of 16, 32, 64, 128, 256 and 512
  * pixel blocks and keeps the fastest; when the one-launch form is possible,
  * times two iterations of it for chunks of 4, 8, 16 and 32 pixel blocks and
  * 1 up to the most resident blocks per CU that fit, keeps the fastest, times
@@ -520,10 +528,15 @@ typedef struct ash_batch_info {
   int32_t chunk[4];         /* its pixel blocks per forward unit, per shape*/
   int32_t blocks_per_cu[4]; /* its resident blocks per CU (grid / CUs)     */
   int32_t grid[4];          /* its blocks per launch                       */
+  int32_t fused;            /* 1: per-phase iterations fuse the adjoint
+                               with the next forward (members <= 512 spots)*/
 } ash_batch_info;
 int ash_batch_get_info(const ash_batch* batch, ash_batch_info* out);
 
-/* Event timing of the batch's launches, as ash_profile_enable/read. */
+/* Event timing of the batch's launches, as ash_profile_enable/read.  With
+ * fused launches (ash_batch_info.fused), ASH_PROF_ADJOINT times the fused
+ * adjoint-and-forward launches and ASH_PROF_FORWARD the first forward and
+ * the last adjoint of each ash_batch_wgs call. */
 int ash_batch_profile_enable(ash_batch* batch, int mask);
 int ash_batch_profile_read(ash_batch* batch, double* ms_out,
                            int64_t* launches_out);

@@ -63,7 +63,8 @@ class BatchInfo(ctypes.Structure):
                 ("one_launch", ctypes.c_int32),
                 ("chunk", ctypes.c_int32 * 4),
                 ("blocks_per_cu", ctypes.c_int32 * 4),
-                ("grid", ctypes.c_int32 * 4)]
+                ("grid", ctypes.c_int32 * 4),
+                ("fused", ctypes.c_int32)]
 
 
 PRECISION_AUTO = 0

@@ -546,7 +546,8 @@ class Batch:
                 "one_launch": bool(out.one_launch),
                 "chunk": list(out.chunk)[:min(n, 4)],
                 "blocks_per_cu": list(out.blocks_per_cu)[:min(n, 4)],
-                "grid": list(out.grid)[:min(n, 4)]}
+                "grid": list(out.grid)[:min(n, 4)],
+                "fused": bool(out.fused)}
 
     def profile(self, enable=True, categories=None):
         mask = 0

@@ -1,6 +1,8 @@
 // Host side of the batched form: many holograms' WGS loops run together,
 // each phase of an iteration one persistent launch over the work items of
-// all holograms (per record shape), with per-XCD work queues.
+// all holograms (per record shape), with per-XCD work queues.  When every
+// member has at most kFusedSpots spots, each iteration's adjoint and the
+// next iteration's forward are one fused launch.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -37,9 +39,10 @@ struct Cls {
   int reduce = 0;
   int L = kDefaultRange;
   std::vector<int> holos;
-  size_t fwd_off = 0, adj_off = 0;  // first item of each phase
-  int qoff_fwd = 0;                 // index of its 9 queue offsets in qoff
-  int fwd_grid = 0, adj_grid = 0;
+  size_t fwd_off = 0, adj_off = 0, fus_off = 0;  // first item of each phase
+  int qoff_fwd = 0, qoff_fus = 0;  // index of its 9 queue offsets in qoff
+  int fwd_grid = 0, adj_grid = 0, fus_grid = 0;
+  int np_max = 32;  // largest padded spot count of its holograms
   // one-launch form
   int chunk = kDefaultChunk;  // pixel blocks per forward unit
   int bpc = 0;                // resident blocks per CU (0: as many as fit)
@@ -67,6 +70,9 @@ struct ash_batch {
   std::vector<int4> items, rblk;
   std::vector<int> qoff;
   double evals_per_transform = 0.0;
+  // every member has at most kFusedSpots spots: an iteration's adjoint and
+  // the next forward run as one fused launch
+  bool fused = false;
   // device
   HoloDesc* d_desc = nullptr;
   float2* d_partial = nullptr;
@@ -289,7 +295,7 @@ int plan_persist(ash_batch* b) {
       d.yblk = reinterpret_cast<unsigned*>(yblk);
       d.ctr = reinterpret_cast<int*>((size_t)b->pholo.size() * kCtrPad);
       rows += (size_t)2 * nb[i] * d.N;
-      yblk += (size_t)nb[i] * NP * 8;
+      yblk += (size_t)nb[i] * NP * 9;
       for (long j = 0; j < nb[i]; ++j) {
         PBlock pb;
         pb.holo = i;
@@ -387,7 +393,7 @@ int plan(ash_batch* b) {
         work.push_back((double)len * n_mb);
       }
     }
-    auto q = lpt(work);
+    std::vector<std::vector<int>> q = lpt(work);
     c.fwd_off = b->items.size();
     c.qoff_fwd = (int)b->qoff.size();
     for (int x = 0; x < kXcds; ++x) {
@@ -400,6 +406,24 @@ int plan(ash_batch* b) {
       }
     }
     b->qoff.push_back((int)(b->items.size() - c.fwd_off));
+    // fused adjoint and next forward: one item per unit (holo, range)
+    c.np_max = 32;
+    for (int h : c.holos)
+      c.np_max = std::max(c.np_max, (b->desc[h].N + 31) / 32 * 32);
+    if (b->fused) {
+      q = lpt(work);
+      c.fus_off = b->items.size();
+      c.qoff_fus = (int)b->qoff.size();
+      for (int x = 0; x < kXcds; ++x) {
+        b->qoff.push_back((int)(b->items.size() - c.fus_off));
+        for (int u : q[x])
+          b->items.push_back(make_int4(units[u].x, units[u].y, 0, 0));
+      }
+      b->qoff.push_back((int)(b->items.size() - c.fus_off));
+      c.fus_grid = std::max(
+          kXcds, fused_blocks_per_cu(c.G, c.reduce != 0, c.np_max) * b->n_cu /
+                     kXcds * kXcds);
+    }
     // adjoint: unit = (holo, tile), one block per quarter tile (four rows,
     // one per wave).  Blocks reach the XCDs round-robin, so block j * 8 + x
     // takes the j-th block of XCD x's list (longest first); shorter lists
@@ -485,11 +509,11 @@ int check_members(ash_batch* b) {
 }
 
 // Enqueue one forward phase (all record shapes) with counters
-// ctr[cls][8][kCtrPad].
-int enqueue_forward(ash_batch* b, int* ctr) {
+// ctr[cls][8][kCtrPad], timed under category `cat`.
+int enqueue_forward(ash_batch* b, int* ctr, int cat = ASH_PROF_FORWARD) {
   for (size_t k = 0; k < b->cls.size(); ++k) {
     const Cls& c = b->cls[k];
-    BCHK(b, btimed(b, ASH_PROF_FORWARD, [&] {
+    BCHK(b, btimed(b, cat, [&] {
            return launch_batch_forward(c.G, c.reduce != 0, c.fwd_grid,
                                        b->d_desc, b->d_items + c.fwd_off,
                                        b->d_qoff + c.qoff_fwd,
@@ -513,16 +537,57 @@ int enqueue_reduce_update(ash_batch* b, float power, bool update) {
   return ASH_OK;
 }
 
-int enqueue_adjoint(ash_batch* b, int last) {
+int enqueue_adjoint(ash_batch* b, int last, int cat = ASH_PROF_ADJOINT) {
   for (size_t k = 0; k < b->cls.size(); ++k) {
     const Cls& c = b->cls[k];
-    BCHK(b, btimed(b, ASH_PROF_ADJOINT, [&] {
+    BCHK(b, btimed(b, cat, [&] {
            return launch_batch_adjoint(c.G, c.reduce != 0, c.adj_grid,
                                        b->d_desc, b->d_items + c.adj_off,
                                        last, b->stream);
          }), "batch adjoint");
   }
   return ASH_OK;
+}
+
+// Enqueue one fused launch per record shape (this iteration's adjoint and
+// the next forward) with counters ctr[cls][8][kCtrPad].
+int enqueue_fused(ash_batch* b, int* ctr) {
+  for (size_t k = 0; k < b->cls.size(); ++k) {
+    const Cls& c = b->cls[k];
+    BCHK(b, btimed(b, ASH_PROF_ADJOINT, [&] {
+           return launch_batch_fused(c.G, c.reduce != 0, c.fus_grid, c.np_max,
+                                     b->d_desc, b->d_items + c.fus_off,
+                                     b->d_qoff + c.qoff_fus,
+                                     ctr + (size_t)k * kXcds * kCtrPad,
+                                     b->stream);
+         }), "batch fused adjoint and forward");
+  }
+  return ASH_OK;
+}
+
+// The launches of n_iter iterations after the nearfield records are made,
+// with take counters for n_iter queue launches.  Fused: the first forward,
+// then per iteration the update and either the fused adjoint and next
+// forward or, after the last, the adjoint alone (the first forward and
+// the last adjoint are timed under ASH_PROF_FORWARD, the fused launches
+// under ASH_PROF_ADJOINT).
+int enqueue_iterations(ash_batch* b, int n_iter, float power, int* ctr) {
+  const size_t per = b->cls.size() * kXcds * kCtrPad;
+  int rc = ASH_OK;
+  if (!b->fused) {
+    for (int it = 0; it < n_iter && !rc; ++it)
+      if (!(rc = enqueue_forward(b, ctr + it * per)) &&
+          !(rc = enqueue_reduce_update(b, power, true)))
+        rc = enqueue_adjoint(b, it == n_iter - 1);
+    return rc;
+  }
+  if ((rc = enqueue_forward(b, ctr, ASH_PROF_FORWARD))) return rc;
+  for (int it = 0; it < n_iter && !rc; ++it) {
+    if ((rc = enqueue_reduce_update(b, power, true))) break;
+    rc = it + 1 < n_iter ? enqueue_fused(b, ctr + (it + 1) * per)
+                         : enqueue_adjoint(b, 1, ASH_PROF_FORWARD);
+  }
+  return rc;
 }
 
 int make_fields(ash_batch* b, float* const* phase) {
@@ -697,13 +762,7 @@ int tune_persist(ash_batch* b, float* const* phase_dev,
     if (!rc && hipEventRecord(e0, b->stream) != hipSuccess)
       rc = bfail(b, ASH_EHIP, "hipEventRecord");
     if (!rc) rc = make_fields(b, ph.data());
-    const size_t per = b->cls.size() * kXcds * kCtrPad;
-    for (int it = 0; it < kPersistTuneIters && !rc; ++it) {
-      if ((rc = enqueue_forward(b, ctr + it * per)) ||
-          (rc = enqueue_reduce_update(b, 1.0f, true)) ||
-          (rc = enqueue_adjoint(b, it == kPersistTuneIters - 1)))
-        break;
-    }
+    if (!rc) rc = enqueue_iterations(b, kPersistTuneIters, 1.0f, ctr);
     if (!rc && (hipEventRecord(e1, b->stream) != hipSuccess ||
                 hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&ms_phase, e0, e1) != hipSuccess))
@@ -767,6 +826,9 @@ int ash_batch_create(ash_batch** out, int H, ash_ctx* const* members,
   for (int h = 0; h < H; ++h)
     if (members[h]->spots.N > kPersistSpots) b->persist = false;
   b->one_launch = b->persist;
+  b->fused = true;
+  for (int h = 0; h < H; ++h)
+    if (members[h]->spots.N > kFusedSpots) b->fused = false;
   if (!rc) {
     if (hipMalloc(reinterpret_cast<void**>(&b->d_desc),
                   H * sizeof(HoloDesc)) != hipSuccess) {
@@ -845,16 +907,10 @@ int ash_batch_wgs(ash_batch* b, float* const* phase_dev,
       (rc = upload_desc(b, phase_dev, weights_dev)))
     return rc;
   int* ctr = nullptr;
-  if ((rc = counters(b, (size_t)n_iter, &ctr))) return rc;
-  const size_t per = b->cls.size() * kXcds * kCtrPad;
-  if ((rc = make_fields(b, phase_dev))) return rc;
-  for (int it = 0; it < n_iter; ++it) {
-    if ((rc = enqueue_forward(b, ctr + it * per)) ||
-        (rc = enqueue_reduce_update(b, power, true)) ||
-        (rc = enqueue_adjoint(b, it == n_iter - 1)))
-      return rc;
-  }
-  return ASH_OK;
+  if ((rc = counters(b, (size_t)n_iter, &ctr)) ||
+      (rc = make_fields(b, phase_dev)))
+    return rc;
+  return enqueue_iterations(b, n_iter, power, ctr);
 }
 
 int ash_batch_tune(ash_batch* b, float* const* phase_dev,
@@ -890,12 +946,18 @@ int ash_batch_tune(ash_batch* b, float* const* phase_dev,
       for (int r = 0; r < kWarm + kTimed && !rc; ++r) {
         if (r == kWarm && hipEventRecord(e0, b->stream) != hipSuccess)
           rc = bfail(b, ASH_EHIP, "hipEventRecord");
+        // the launch that dominates an iteration: the fused adjoint and
+        // forward (on the spot fields the members hold), else the forward
         const Cls& c = b->cls[k];
-        hipError_t e = launch_batch_forward(
-            c.G, c.reduce != 0, c.fwd_grid, b->d_desc,
-            b->d_items + c.fwd_off, b->d_qoff + c.qoff_fwd,
-            ctr + ((size_t)r * b->cls.size() + k) * kXcds * kCtrPad,
-            b->stream);
+        int* const cr = ctr + ((size_t)r * b->cls.size() + k) * kXcds * kCtrPad;
+        hipError_t e =
+            b->fused
+                ? launch_batch_fused(c.G, c.reduce != 0, c.fus_grid, c.np_max,
+                                     b->d_desc, b->d_items + c.fus_off,
+                                     b->d_qoff + c.qoff_fus, cr, b->stream)
+                : launch_batch_forward(c.G, c.reduce != 0, c.fwd_grid,
+                                       b->d_desc, b->d_items + c.fwd_off,
+                                       b->d_qoff + c.qoff_fwd, cr, b->stream);
         if (e != hipSuccess) rc = bhip(b, e, "tuning forward");
         if (!rc && (rc = enqueue_reduce_update(b, 1.0f, false))) break;
       }
@@ -926,7 +988,8 @@ int ash_batch_tune(ash_batch* b, float* const* phase_dev,
   if (table_out) {
     FILE* f = fopen(table_out, "w");
     if (!f) return bfail(b, ASH_EINVAL, std::string("cannot write ") + table_out);
-    fprintf(f, "# groups range_reduce range_blocks forward_plus_reduce_ms\n");
+    fprintf(f, "# groups range_reduce range_blocks %s_plus_reduce_ms\n",
+            b->fused ? "fused" : "forward");
     for (size_t k = 0; k < b->cls.size(); ++k)
       fprintf(f, "%d %d %d %.4f\n", b->cls[k].G, b->cls[k].reduce,
               b->cls[k].L, best_ms[k]);
@@ -1006,6 +1069,7 @@ int ash_batch_get_info(const ash_batch* b, ash_batch_info* out) {
   out->items = (int64_t)b->items.size();
   out->evals_per_transform = b->evals_per_transform;
   out->one_launch = b->one_launch ? 1 : 0;
+  out->fused = b->fused ? 1 : 0;
   for (size_t k = 0; k < b->cls.size() && k < 4; ++k) {
     out->chunk[k] = b->cls[k].chunk;
     out->blocks_per_cu[k] = b->one_launch ? b->cls[k].p_grid / b->n_cu : 0;

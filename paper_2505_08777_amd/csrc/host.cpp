@@ -585,7 +585,7 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
     dfree(B.fixph);
     B.cap_spots = 0;
     if ((rc = dalloc(c, &B.target, (size_t)N, "targets")) ||
-        (rc = dalloc(c, &B.y, 8 * n_pad, "spot fields")) ||
+        (rc = dalloc(c, &B.y, 9 * n_pad, "spot fields")) ||
         (rc = dalloc(c, &B.fixph, n_pad, "fixed phases")) ||
         (rc = dalloc(c, &B.Ebuf, 2 * (size_t)N, "spot fields")) ||
         (rc = dalloc(c, &B.spot64, 3 * (size_t)N, "spot offsets")))
@@ -608,7 +608,7 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
     if (e == hipSuccess) e = hipMemsetAsync(B.bound, 0, 8, c->stream);
     // spot-field records: the padding past N stays zero
     if (e == hipSuccess)
-      e = hipMemsetAsync(B.y, 0, 8 * n_pad * sizeof(unsigned), c->stream);
+      e = hipMemsetAsync(B.y, 0, 9 * n_pad * sizeof(unsigned), c->stream);
     if (e == hipSuccess)
       e = launch_prep_spots(g, N, B.w64, B.aff_dev, B.nlmode_dev, B.tilez,
                             B.rmax, B.spotrec, B.spot64, B.offtab, B.bound,

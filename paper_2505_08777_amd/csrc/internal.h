@@ -245,6 +245,15 @@ hipError_t launch_batch_update(int H, const HoloDesc* d, float power,
                                hipStream_t s);
 // Resident blocks per CU of the persistent kernels.
 int batch_blocks_per_cu(int G, bool reduce, bool forward);
+// Fused adjoint and next forward (per-phase form, members of at most
+// kFusedSpots spots): units {holo, range, 0, 0} in 8 per-XCD queues like the
+// forward's; np_max is the largest padded spot count of the launch's
+// holograms (a multiple of 32), which sizes the LDS of each wave.
+constexpr int kFusedSpots = 512;
+hipError_t launch_batch_fused(int G, bool reduce, int grid, int np_max,
+                              const HoloDesc* d, const int4* items,
+                              const int* qoff, int* ctr, hipStream_t s);
+int fused_blocks_per_cu(int G, bool reduce, int np_max);
 
 // ---- batched form in one launch (holograms of at most kPersistSpots) ----
 // Every block owns a contiguous range of one hologram's 32-pixel blocks and
@@ -265,7 +274,7 @@ struct PHolo {
   float* W;                // spot weights (caller's), in/out
   float* phase;            // phase (caller's), in/out
   float2* rows;            // [2][n_blocks][N] per-block forward sums
-  unsigned* yblk;          // [n_blocks][NP * 8] per-block spot-field records
+  unsigned* yblk;          // [n_blocks][NP * 9] per-block spot-field records
   int* ctr;                // barrier counter (zero at launch)
   long n_blk;              // 32-pixel blocks (tile rows)
   int N, nx, ny, tiles_x, groups, n_blocks;

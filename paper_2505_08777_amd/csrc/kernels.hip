@@ -50,6 +50,7 @@
 namespace ash {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr float kInv2Pi = 0.15915494309189533577f;
@@ -179,14 +180,17 @@ __device__ inline u32x2 pixel_nl_words(const u32x4* pixtab, int G, long tile,
 // records: half 0 {the phase pieces at p 4..6 of the spot record's last
 // group (words 2..3 of half 0), magnitude bits, 0}, half 1 {0, 0,
 // magnitude bits, 0}, so that each lane half ORs its words in and reads the
-// magnitude without selecting.  Entries past N stay zero.
-__device__ inline void put_spot_field(unsigned* y, int k, float mag,
+// magnitude without selecting; then the magnitudes once more as a dense
+// array of NP floats (words 8 NP + k), for kernels that need one per spot
+// row of a lane.  Entries past N stay zero.
+__device__ inline void put_spot_field(unsigned* y, int N, int k, float mag,
                                       float turns) {
   unsigned p[3];
   split3f(turns, p);
   u32x4* y4 = reinterpret_cast<u32x4*>(y) + (long)(k / 32) * 64 + k % 32;
   y4[0] = u32x4{p[0] | (p[1] << 16), p[2], __float_as_uint(mag), 0u};
   y4[32] = u32x4{0u, 0u, __float_as_uint(mag), 0u};
+  reinterpret_cast<float*>(y)[(long)(N + 31) / 32 * 32 * 8 + k] = mag;
 }
 
 // Slot f of a record of 16-slot groups: group f / 16, lane half (f % 16)/8,
@@ -624,7 +628,7 @@ __global__ void k_to_polar(int N, const float2* __restrict__ y,
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
   const float2 v = y[k];
-  put_spot_field(ypol, k, hypotf(v.x, v.y), atan2f(v.y, v.x) * kInv2Pi);
+  put_spot_field(ypol, N, k, hypotf(v.x, v.y), atan2f(v.y, v.x) * kInv2Pi);
 }
 
 hipError_t launch_to_polar(int N, const float* y, unsigned* ypol,
@@ -1480,7 +1484,7 @@ __device__ __forceinline__ void wgs_update_block(
       turns = atan2f(e.y, e.x) * kInv2Pi;
       if (phase_mode == kPhaseStore) fixph[k] = turns;
     }
-    put_spot_field(ypol, k, wk * tk, turns);
+    put_spot_field(ypol, N, k, wk * tk, turns);
   }
   if (stats && tid == 0) {
     stats[0] = eff_denom > 0.0f ? sum_a2 / eff_denom : 0.0f;
@@ -1539,7 +1543,7 @@ __device__ __forceinline__ void spot_loss_block(int N, int slices,
     const float d = hr * hr + hi * hi - t[k];
     kahan_add(acc, comp, d * d);
     const float c = 4.0f * d * inv_s;
-    put_spot_field(ypol, k, fabsf(c) * hypotf(hr, hi),
+    put_spot_field(ypol, N, k, fabsf(c) * hypotf(hr, hi),
                    atan2f(c * hi, c * hr) * kInv2Pi);
   }
   const float L = block_reduce(acc, sh, OpSum());
@@ -1941,6 +1945,243 @@ __global__ __launch_bounds__(kUpd) void k_batch_update(
                    nullptr, kPhaseFree);
 }
 
+// ---------------------------------------------------------------------------
+// Fused adjoint and next forward.  Inside a weighted-GS loop the adjoint of
+// iteration n gives each pixel its phase of iteration n + 1, and that pixel's
+// terms of the next forward need nothing else; so one pass over a range of
+// pixel blocks (tile rows) runs, per block, the adjoint over all spots, the
+// projection onto the phase, and the block's share of the next forward, from
+// one load of the pixel records.  The pixel table, the dominant memory
+// stream of holograms with few spots, is then read once per iteration
+// instead of twice, and no nearfield records are written.
+//
+// Both halves keep their sums inside the lanes.  The adjoint takes the
+// forward's operand order (rows: 16 spots per lane, lane: pixel) and weights
+// each spot row by its magnitude from a table staged in LDS; the forward
+// takes the adjoint's order (rows: 16 pixels per lane, lane: spot) and
+// weights each pixel row by its basis amplitude.  Lane l and lane l + 32
+// hold the two row halves of one column, joined by one permlane32 swap, so
+// the per-block butterfly of the separate kernels disappears.  The
+// forward's running sums of the range, one per lane and spot block, live in
+// LDS.
+// ---------------------------------------------------------------------------
+// LDS floats per wave: the spot magnitudes [NP], the forward sums
+// [NP / 32][64] complex.
+__host__ __device__ inline long fused_lds_floats(int np_max) {
+  return (long)np_max * 5;
+}
+
+// Lane-half join: in every lane, the value of lane l % 32 plus the value of
+// lane l % 32 + 32 (the same order in both halves).
+__device__ __forceinline__ float join_halves(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x),
+                                                  __float_as_uint(x), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sum, with per-value weights w, of w cos(2 pi theta) and w sin(2 pi theta)
+// over one 32x32 block of phases (16 per lane) into four running pairs.
+template <bool kReduce>
+__device__ __forceinline__ void accumulate_rows(const floatx16& th,
+                                                const floatx4* w, float* sr,
+                                                float* si) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const float r = kReduce ? __builtin_amdgcn_fractf(th[i]) : th[i];
+    const float m = w[i >> 2][i & 3];
+    sr[i & 3] = fmaf(m, __builtin_amdgcn_cosf(r), sr[i & 3]);
+    si[i & 3] = fmaf(m, __builtin_amdgcn_sinf(r), si[i & 3]);
+  }
+}
+
+// One wave: pixel blocks [b0, b1) of a hologram with N spots.  yrec: the
+// spot-field records of this iteration (the dense magnitudes follow them);
+// ymag_s, acc_s: the wave's LDS; row: the range's forward sums of the next
+// iteration, E_k for k < N.
+template <int G, bool kReduce>
+__device__ __forceinline__ void fused_range(
+    int N, long b0, long b1, const GLOBAL u32x4* __restrict__ pixtab,
+    const GLOBAL u32x4* __restrict__ spotrec,
+    const GLOBAL u32x4* __restrict__ offtab,
+    const GLOBAL u32x4* __restrict__ yrec,
+    const GLOBAL float* __restrict__ amp_t, float* ymag_s, float2* acc_s,
+    float2* __restrict__ row) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int h = lane >> 5, q = lane & 31;
+  const int NB = (N + 31) / 32, NP = NB * 32;
+  const GLOBAL float* __restrict__ ymag =
+      reinterpret_cast<const GLOBAL float*>(yrec + (long)NB * 64);
+  for (int k = lane; k < NP; k += kWave) ymag_s[k] = ymag[k];
+  for (int nb = 0; nb < NB; ++nb)
+    acc_s[nb * kWave + lane] = make_float2(0.0f, 0.0f);
+  // a wave's LDS operations complete in order; the fences keep the
+  // compiler from moving the table's reads above its writes
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const floatx4* ym4 = reinterpret_cast<const floatx4*>(ymag_s);
+  const unsigned off_pix = (unsigned)(h * kTile + q) * 16u;
+  const unsigned off_spot = (unsigned)(h * 32 + q) * 16u;
+  const unsigned off_ot = (unsigned)(h * NP + q) * 16u;
+  const unsigned off_amp = (unsigned)h * 16u;
+  // -1 at p 4..6 of the spot record's last group against the pixel phase
+  const unsigned m2 = h ? 0u : (kBf16MinusOne | (kBf16MinusOne << 16));
+  const unsigned m3 = h ? 0u : kBf16MinusOne;
+  const rsrc_t rs = make_rsrc(spotrec, (unsigned long)NB * G * 64 * 16);
+  const rsrc_t ry = make_rsrc(yrec, (unsigned long)NB * 64 * 16);
+  for (long b = b0; b < b1;) {
+    const long t = b / kBlkPerTile;
+    const int r0 = (int)(b - t * kBlkPerTile);
+    const int r1 = (int)min((long)kBlkPerTile, r0 + (b1 - b));
+    const rsrc_t rx = make_rsrc(pixtab + t * G * 2 * kTile,
+                                (unsigned long)G * 2 * kTile * 16);
+    const rsrc_t ro = make_rsrc(offtab + t * 2 * NP, (unsigned long)2 * NP * 16);
+    const rsrc_t ra = make_rsrc(amp_t + t * kTile, (unsigned long)kTile * 4);
+    for (int r = r0; r < r1; ++r) {
+      u32x4 X[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        X[g] = bload4(rx, off_pix, (unsigned)(g * 2 * kTile + r * 32) * 16u);
+      // adjoint: g(x) = sum_k |y_k| exp(2 pi i (tau_k(x) + psi_k))
+      float ar[4] = {0.0f, 0.0f, 0.0f, 0.0f}, ai[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int nb = 0; nb < NB; ++nb) {
+        u32x4 S[G];
+#pragma unroll
+        for (int g = 0; g < G - 1; ++g)
+          S[g] = bload4(rs, off_spot, (unsigned)(nb * G + g) * 64u * 16u);
+        u32x4 last = bload4(ro, off_ot, (unsigned)nb * 32u * 16u);
+        const u32x4 yv = bload4(ry, off_spot, (unsigned)nb * 64u * 16u);
+        floatx4 w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[j] = ym4[nb * 8 + 2 * j + h];
+        __builtin_amdgcn_sched_barrier(0);  // loads before the products
+        last[2] |= yv[0];
+        last[3] |= yv[1];
+        S[G - 1] = last;
+        const floatx16 th = phase_block<G>(S, X);
+        accumulate_rows<kReduce>(th, w, ar, ai);
+      }
+      const float gr = join_halves((ar[0] + ar[1]) + (ar[2] + ar[3]));
+      const float gi = join_halves((ai[0] + ai[1]) + (ai[2] + ai[3]));
+      // the pixel's next phase (as the adjoint's epilogue writes it) in
+      // the last group of its record
+      const u32x4 rec = nearfield_record(u32x2{X[G - 1][0], X[G - 1][1]},
+                                         rad_to_turns(atan2f(gi, gr)));
+      if (h == 0) {
+        X[G - 1][2] = rec[2];
+        X[G - 1][3] = rec[3];
+      }
+      // forward of the next iteration: E_k += sum_x A(x) exp(-2 pi i
+      // (tau_k(x) - phi(x))) over the block's 32 pixels
+      floatx4 a[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        a[j] = __builtin_bit_cast(
+            floatx4, bload4(ra, off_amp, (unsigned)(r * 32 + 8 * j) * 4u));
+      for (int nb = 0; nb < NB; ++nb) {
+        u32x4 S[G];
+#pragma unroll
+        for (int g = 0; g < G - 1; ++g)
+          S[g] = bload4(rs, off_spot, (unsigned)(nb * G + g) * 64u * 16u);
+        u32x4 last = bload4(ro, off_ot, (unsigned)nb * 32u * 16u);
+        float2 o = acc_s[nb * kWave + lane];
+        __builtin_amdgcn_sched_barrier(0);
+        last[2] |= m2;
+        last[3] |= m3;
+        S[G - 1] = last;
+        const floatx16 th = phase_block<G>(X, S);
+        float fr[4] = {0.0f, 0.0f, 0.0f, 0.0f}, fi[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        accumulate_rows<kReduce>(th, a, fr, fi);
+        o.x += (fr[0] + fr[1]) + (fr[2] + fr[3]);
+        o.y += (fi[0] + fi[1]) + (fi[2] + fi[3]);
+        acc_s[nb * kWave + lane] = o;
+      }
+    }
+    b += r1 - r0;
+  }
+  for (int nb = 0; nb < NB; ++nb) {
+    const float2 o = acc_s[nb * kWave + lane];
+    const float er = join_halves(o.x), ei = -join_halves(o.y);
+    const int k = nb * 32 + q;
+    if (h == 0 && k < N) row[k] = make_float2(er, ei);
+  }
+}
+
+// Fused launch of a batch: each wave takes units {holo, range} from the
+// queues (as the forward) and runs fused_range over the range, writing the
+// range's row of forward partial sums.
+template <int G, bool kReduce>
+__global__ __launch_bounds__(kBlock) void k_batch_fused(
+    const HoloDesc* __restrict__ hd, const int4* __restrict__ items,
+    const int* __restrict__ qoff, int* __restrict__ ctr, int np_max) {
+  extern __shared__ float lds[];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  float* const base = lds + (long)wave * fused_lds_floats(np_max);
+  drain_queues(items, qoff, ctr, [&](const int4& it) {
+    const HoloDesc& d = hd[it.x];
+    const long b0 = (long)it.y * d.L;
+    const long b1 = min(b0 + d.L, d.n_blk);
+    fused_range<G, kReduce>(
+        d.N, b0, b1, as_global(d.pixtab), as_global(d.spotrec),
+        as_global(reinterpret_cast<const u32x4*>(d.offtab)),
+        as_global(reinterpret_cast<const u32x4*>(d.ypol)), as_global(d.amp_t),
+        base, reinterpret_cast<float2*>(base + np_max),
+        d.partial + (long)it.y * d.N);
+  });
+}
+
+template <int G, bool kReduce>
+static hipError_t bfus_g(int grid, int np_max, const HoloDesc* d,
+                         const int4* items, const int* qoff, int* ctr,
+                         hipStream_t s) {
+  const size_t lds = (size_t)(kBlock / kWave) * fused_lds_floats(np_max) * 4;
+  hipLaunchKernelGGL((k_batch_fused<G, kReduce>), dim3(grid), dim3(kBlock),
+                     lds, s, d, items, qoff, ctr, np_max);
+  return hipGetLastError();
+}
+
+template <int G, bool kReduce>
+static int fus_blocks_per_cu(int np_max) {
+  const size_t lds = (size_t)(kBlock / kWave) * fused_lds_floats(np_max) * 4;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, k_batch_fused<G, kReduce>, kBlock, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n > 0 ? n : 1;
+}
+
+hipError_t launch_batch_fused(int G, bool reduce, int grid, int np_max,
+                              const HoloDesc* d, const int4* items,
+                              const int* qoff, int* ctr, hipStream_t s) {
+  if (np_max < 32 || np_max > kFusedSpots || np_max % 32) return hipErrorInvalidValue;
+  switch (G) {
+#define X(n)                                                                 \
+  case n:                                                                    \
+    return reduce ? bfus_g<n, true>(grid, np_max, d, items, qoff, ctr, s)    \
+                  : bfus_g<n, false>(grid, np_max, d, items, qoff, ctr, s);
+    ASH_G_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+int fused_blocks_per_cu(int G, bool reduce, int np_max) {
+  switch (G) {
+#define X(n)                                                  \
+  case n:                                                     \
+    return reduce ? fus_blocks_per_cu<n, true>(np_max)        \
+                  : fus_blocks_per_cu<n, false>(np_max);
+    ASH_G_CASES(X)
+#undef X
+    default:
+      return 1;
+  }
+}
+
 template <int G, bool kReduce>
 static hipError_t bfwd_g(int grid, const HoloDesc* d, const int4* items,
                          const int* qoff, int* ctr, hipStream_t s) {
@@ -2066,7 +2307,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_persist(
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   float2* wrow = reinterpret_cast<float2*>(lds);  // [4][NP]
   float* Ws = lds + 8 * NP;                         // [NP]
-  unsigned* yb = d.yblk + (long)j * NP * 8;
+  unsigned* yb = d.yblk + (long)j * NP * 9;
   // the block's weights, its spot-field records past N (zero) and the
   // nearfield records of its pixels from the start phase
   for (int k = tid; k < N; k += kBlock) Ws[k] = d.W[k];
@@ -2074,6 +2315,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_persist(
     u32x4* y4 = reinterpret_cast<u32x4*>(yb) + (long)(k / 32) * 64 + k % 32;
     y4[0] = u32x4{0u, 0u, 0u, 0u};
     y4[32] = u32x4{0u, 0u, 0u, 0u};
+    reinterpret_cast<float*>(yb)[(long)NP * 8 + k] = 0.0f;
   }
   for (long gid = b0 * 32 + tid; gid < b1 * 32; gid += kBlock)
     make_field_at(d.nx, d.ny, d.tiles_x, G, gid, d.phase, nullptr, d.amp_t,

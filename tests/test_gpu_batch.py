@@ -131,6 +131,9 @@ def test_batch_equals_unbatched(A, batch_case, n_iter, one_launch):
     b = A.Batch(ctxs)
     b.set_form(one_launch)
     assert b.info()["one_launch"] == one_launch
+    # every member has at most 512 spots: the per-phase iterations after
+    # the first run as fused adjoint-and-forward launches
+    assert b.info()["fused"]
     ph_b = [_cu(h["phi"]) for h in holos]
     W_b = [torch.ones(h["w"].shape[0], device="cuda") for h in holos]
     b.wgs(ph_b, n_iter, weights=W_b)
@@ -344,6 +347,33 @@ def test_batch64small_one_launch(A):
         c.close()
 
 
+def test_batch64small_fused(A):
+    """The same 64 holograms in launches per phase, where every iteration
+    after the first fuses the adjoint with the next forward: three
+    iterations of every member against its own unbatched run."""
+    holos = workloads.make("batch64small")
+    ctxs = _members(A, holos)
+    b = A.Batch(ctxs)
+    b.set_form(False)
+    inf = b.info()
+    assert inf["fused"] and not inf["one_launch"]
+    ph = [_cu(d["phi0"]) for d in holos]
+    W = [torch.ones(d["w"].shape[0], device="cuda") for d in holos]
+    b.wgs(ph, 3, weights=W)
+    worst = (0.0, 0.0)
+    for h, (d, c) in enumerate(zip(holos, ctxs)):
+        p1 = _cu(d["phi0"])
+        _, w1, E1, _ = c.wgs(p1, 3)
+        err = _batch_vs_alone(c, d["t"], ph[h], W[h], p1, w1, E1,
+                              "batch64small member %d fused vs alone" % h,
+                              n_iter=3)
+        worst = (max(worst[0], err[0]), max(worst[1], err[1]))
+    _say("fused vs alone over 64 members: phase %.2e rad, weights %.2e" % worst)
+    b.close()
+    for c in ctxs:
+        c.close()
+
+
 def test_batch64_uses_phase_launches(A):
     """Members with more spots than the one-launch form holds run as one
     launch per phase (the batch64 test covers their results)."""
@@ -351,6 +381,7 @@ def test_batch64_uses_phase_launches(A):
     ctxs = _members(A, [d])
     b = A.Batch(ctxs)
     assert d["w"].shape[0] > 512 and not b.info()["one_launch"]
+    assert not b.info()["fused"]
     with pytest.raises(A.AshError):
         b.set_form(True)
     b.close()
