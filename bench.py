@@ -941,14 +941,15 @@ def bench_batch(args, holos):
         evals_launch = 2.0 * evals * n_iter
         launches = calls
     elif info["fused"]:
-        # every iteration after the first: one fused launch per record
-        # shape (the adjoint and the next forward, both transforms of all
-        # its holograms), timed alone under the adjoint category; the unit
-        # timed is the fused phase (all its launches)
+        # every transform in fused launches, timed under the adjoint
+        # category: per call and record shape n_iter + 1 launches holding
+        # 2 n_iter transforms of its holograms (the first only a forward,
+        # the last only an adjoint); the unit timed is a launch of all
+        # shapes, with the work of the average launch
         kname = "k_batch_fused<%d, false>" % groups
         launches = prof["adjoint"][1] // shapes
         ms_avg = prof["adjoint"][0] / max(launches, 1)
-        evals_launch = 2.0 * evals
+        evals_launch = 2.0 * evals * n_iter / (n_iter + 1)
     else:
         # a phase is one launch per record shape, each over all holograms
         # of that shape: the unit timed is the phase (all its launches)

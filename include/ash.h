@@ -443,13 +443,16 @@ int ash_get_info(const ash_ctx* ctx, ash_info* out);
  * per-XCD queues (longest first, balanced by work); resident waves take
  * them with an atomic counter and move to the other queues when theirs runs
  * dry.  The forward range length (pixel blocks per item) is tuned.  When
- * every member has at most 512 spots, the adjoint of each iteration but the
- * last and the forward of the next are one launch over (hologram, pixel
- * range) items: per 32-pixel block the adjoint over all spots, the phase
- * it projects to, and the block's terms of the next forward, so the pixel
- * records are read once per iteration and no nearfield records are
- * written (the forward sums then differ from the separate kernels' in
- * FP32 summation order only).
+ * every member has at most 512 spots, the transforms are fused launches
+ * over (hologram, pixel range) items instead: per 32-pixel block the
+ * adjoint of this iteration over all spots, the phase it projects to, and
+ * the block's terms of the next iteration's forward, so the pixel records
+ * are read once per iteration and no nearfield records are built (the
+ * first launch of a call runs only the forward of the start phases, the
+ * last only the adjoint, which writes the phases).  A hologram of B 32-spot
+ * blocks takes ranges of about 1/B of the tuned length, so that items hold
+ * about equal work.  Results differ from the separate kernels' in FP32
+ * summation order only.
  *
  * A batch starts in the one-launch form when its members allow it;
  * ash_batch_tune keeps the faster form for the batch at hand and
@@ -485,17 +488,17 @@ int ash_batch_set_stream(ash_batch* batch, void* stream);
  * at its start (descriptor upload); the one-launch form also at its end
  * (to read the barriers' error flag: a barrier that waits more than 10 s
  * ends the launch and the call returns ASH_EHIP).  The per-phase form keeps
- * 2 KB of queue counters per iteration and record shape on the device,
- * grown on demand.  Errors: ASH_EINVAL, ASH_ENOTREADY, ASH_EUNSUPPORTED,
+ * 2 KB of queue counters per iteration (and one more) and record shape on
+ * the device, grown on demand.  Errors: ASH_EINVAL, ASH_ENOTREADY, ASH_EUNSUPPORTED,
  * ASH_ENOMEM, ASH_EHIP. */
 int ash_batch_wgs(ash_batch* batch, float* const* phase_dev,
                   float* const* weights_dev, int n_iter,
                   const ash_wgs_params* params);
 
 /* Autotuner.  For each record shape, times the per-phase form's forward
- * (the fused launch when the batch fuses) plus its reduction for range
- * lengths of 16, 32, 64, 128, 256 and 512
- * pixel blocks and keeps the fastest; when the one-launch form is possible,
+ * plus its reduction for range lengths of 16, 32, 64, 128, 256 and 512
+ * pixel blocks (fused: an adjoint-and-forward launch for 4, 8, 16, 32, 64
+ * and 128) and keeps the fastest; when the one-launch form is possible,
  * times two iterations of it for chunks of 4, 8, 16 and 32 pixel blocks and
  * 1 up to the most resident blocks per CU that fit, keeps the fastest, times
  * two iterations of the per-phase form, and selects the faster form.  The
@@ -521,7 +524,8 @@ typedef struct ash_batch_info {
   int32_t holograms;
   int32_t shapes;           /* record shapes (one launch each per phase)   */
   int32_t groups[4];        /* matrix-core groups of the first 4 shapes    */
-  int32_t range_blocks[4];  /* their forward range lengths                 */
+  int32_t range_blocks[4];  /* their forward range lengths (fused: for a
+                               hologram of one 32-spot block)             */
   int64_t items;            /* forward + adjoint work items                */
   double evals_per_transform;  /* sum over holograms of N * P              */
   int32_t one_launch;       /* 1: the one-launch form (see ash_batch_wgs)  */
@@ -534,9 +538,10 @@ typedef struct ash_batch_info {
 int ash_batch_get_info(const ash_batch* batch, ash_batch_info* out);
 
 /* Event timing of the batch's launches, as ash_profile_enable/read.  With
- * fused launches (ash_batch_info.fused), ASH_PROF_ADJOINT times the fused
- * adjoint-and-forward launches and ASH_PROF_FORWARD the first forward and
- * the last adjoint of each ash_batch_wgs call. */
+ * fused launches (ash_batch_info.fused), ASH_PROF_ADJOINT times all of
+ * them (n_iter + 1 per record shape and ash_batch_wgs call: both
+ * transforms of every hologram in all but the first and the last, which
+ * hold the first forward and the last adjoint). */
 int ash_batch_profile_enable(ash_batch* batch, int mask);
 int ash_batch_profile_read(ash_batch* batch, double* ms_out,
                            int64_t* launches_out);

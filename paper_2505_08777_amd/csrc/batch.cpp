@@ -24,6 +24,10 @@ namespace {
 
 constexpr int kDefaultRange = 64;  // pixel blocks per forward item (untuned)
 constexpr int kTuneCandidates[] = {16, 32, 64, 128, 256, 512};
+// Fused launches: pixel blocks per unit of a hologram of one 32-spot block
+// (one of B blocks takes about 1/B of it), untuned and the candidates.
+constexpr int kDefaultFusedRange = 16;
+constexpr int kFusedCandidates[] = {4, 8, 16, 32, 64, 128};
 // One-launch form: pixel blocks per forward unit (untuned), the candidates
 // of the tuner, and the iterations it times per candidate.
 constexpr int kDefaultChunk = 8;
@@ -337,9 +341,17 @@ int plan(ash_batch* b) {
   b->desc.assign(H, HoloDesc());
   size_t part = 0, red = 0;
   b->evals_per_transform = 0.0;
+  // range lengths: the class's; fused, the class's divided by the
+  // hologram's spot blocks, so that units hold about equal work, and even
+  // (the fused kernel takes pixel blocks in pairs)
   std::vector<int> L_of(H, kDefaultRange);
-  for (auto& c : b->cls)
-    for (int h : c.holos) L_of[h] = c.L;
+  for (auto& c : b->cls) {
+    if (b->fused) c.L += c.L & 1;
+    for (int h : c.holos) {
+      const int nb = (b->m[h]->spots.N + 31) / 32;
+      L_of[h] = b->fused ? std::max(2, (c.L / nb + 1) & ~1) : c.L;
+    }
+  }
   for (int h = 0; h < H; ++h) {
     ash_ctx* c = b->m[h];
     const Geom& g = c->basis.g;
@@ -394,6 +406,24 @@ int plan(ash_batch* b) {
       }
     }
     std::vector<std::vector<int>> q = lpt(work);
+    c.np_max = 32;
+    for (int h : c.holos)
+      c.np_max = std::max(c.np_max, (b->desc[h].N + 31) / 32 * 32);
+    if (b->fused) {
+      // every launch fused: one item per unit (holo, range)
+      c.fus_off = b->items.size();
+      c.qoff_fus = (int)b->qoff.size();
+      for (int x = 0; x < kXcds; ++x) {
+        b->qoff.push_back((int)(b->items.size() - c.fus_off));
+        for (int u : q[x])
+          b->items.push_back(make_int4(units[u].x, units[u].y, 0, 0));
+      }
+      b->qoff.push_back((int)(b->items.size() - c.fus_off));
+      c.fus_grid = std::max(
+          kXcds, fused_blocks_per_cu(c.G, c.reduce != 0, c.np_max) * b->n_cu /
+                     kXcds * kXcds);
+      continue;
+    }
     c.fwd_off = b->items.size();
     c.qoff_fwd = (int)b->qoff.size();
     for (int x = 0; x < kXcds; ++x) {
@@ -406,24 +436,6 @@ int plan(ash_batch* b) {
       }
     }
     b->qoff.push_back((int)(b->items.size() - c.fwd_off));
-    // fused adjoint and next forward: one item per unit (holo, range)
-    c.np_max = 32;
-    for (int h : c.holos)
-      c.np_max = std::max(c.np_max, (b->desc[h].N + 31) / 32 * 32);
-    if (b->fused) {
-      q = lpt(work);
-      c.fus_off = b->items.size();
-      c.qoff_fus = (int)b->qoff.size();
-      for (int x = 0; x < kXcds; ++x) {
-        b->qoff.push_back((int)(b->items.size() - c.fus_off));
-        for (int u : q[x])
-          b->items.push_back(make_int4(units[u].x, units[u].y, 0, 0));
-      }
-      b->qoff.push_back((int)(b->items.size() - c.fus_off));
-      c.fus_grid = std::max(
-          kXcds, fused_blocks_per_cu(c.G, c.reduce != 0, c.np_max) * b->n_cu /
-                     kXcds * kXcds);
-    }
     // adjoint: unit = (holo, tile), one block per quarter tile (four rows,
     // one per wave).  Blocks reach the XCDs round-robin, so block j * 8 + x
     // takes the j-th block of XCD x's list (longest first); shorter lists
@@ -549,47 +561,6 @@ int enqueue_adjoint(ash_batch* b, int last, int cat = ASH_PROF_ADJOINT) {
   return ASH_OK;
 }
 
-// Enqueue one fused launch per record shape (this iteration's adjoint and
-// the next forward) with counters ctr[cls][8][kCtrPad].
-int enqueue_fused(ash_batch* b, int* ctr) {
-  for (size_t k = 0; k < b->cls.size(); ++k) {
-    const Cls& c = b->cls[k];
-    BCHK(b, btimed(b, ASH_PROF_ADJOINT, [&] {
-           return launch_batch_fused(c.G, c.reduce != 0, c.fus_grid, c.np_max,
-                                     b->d_desc, b->d_items + c.fus_off,
-                                     b->d_qoff + c.qoff_fus,
-                                     ctr + (size_t)k * kXcds * kCtrPad,
-                                     b->stream);
-         }), "batch fused adjoint and forward");
-  }
-  return ASH_OK;
-}
-
-// The launches of n_iter iterations after the nearfield records are made,
-// with take counters for n_iter queue launches.  Fused: the first forward,
-// then per iteration the update and either the fused adjoint and next
-// forward or, after the last, the adjoint alone (the first forward and
-// the last adjoint are timed under ASH_PROF_FORWARD, the fused launches
-// under ASH_PROF_ADJOINT).
-int enqueue_iterations(ash_batch* b, int n_iter, float power, int* ctr) {
-  const size_t per = b->cls.size() * kXcds * kCtrPad;
-  int rc = ASH_OK;
-  if (!b->fused) {
-    for (int it = 0; it < n_iter && !rc; ++it)
-      if (!(rc = enqueue_forward(b, ctr + it * per)) &&
-          !(rc = enqueue_reduce_update(b, power, true)))
-        rc = enqueue_adjoint(b, it == n_iter - 1);
-    return rc;
-  }
-  if ((rc = enqueue_forward(b, ctr, ASH_PROF_FORWARD))) return rc;
-  for (int it = 0; it < n_iter && !rc; ++it) {
-    if ((rc = enqueue_reduce_update(b, power, true))) break;
-    rc = it + 1 < n_iter ? enqueue_fused(b, ctr + (it + 1) * per)
-                         : enqueue_adjoint(b, 1, ASH_PROF_FORWARD);
-  }
-  return rc;
-}
-
 int make_fields(ash_batch* b, float* const* phase) {
   for (size_t h = 0; h < b->m.size(); ++h) {
     ash_ctx* c = b->m[h];
@@ -601,6 +572,51 @@ int make_fields(ash_batch* b, float* const* phase) {
   }
   return ASH_OK;
 }
+
+// Enqueue one fused launch per record shape (mode: the first forward, an
+// adjoint and the next forward, the last adjoint) with counters
+// ctr[cls][8][kCtrPad].
+int enqueue_fused(ash_batch* b, int mode, int* ctr) {
+  for (size_t k = 0; k < b->cls.size(); ++k) {
+    const Cls& c = b->cls[k];
+    BCHK(b, btimed(b, ASH_PROF_ADJOINT, [&] {
+           return launch_batch_fused(c.G, c.reduce != 0, c.fus_grid, c.np_max,
+                                     mode, b->d_desc, b->d_items + c.fus_off,
+                                     b->d_qoff + c.qoff_fus,
+                                     ctr + (size_t)k * kXcds * kCtrPad,
+                                     b->stream);
+         }), "batch fused adjoint and forward");
+  }
+  return ASH_OK;
+}
+
+// The launches of n_iter >= 1 iterations from the phases in the
+// descriptors, with take counters for n_iter + 1 queue launches.  Fused:
+// the first forward, then per iteration the update and a fused launch (the
+// adjoint and the next forward; after the last iteration the adjoint
+// alone), all timed under ASH_PROF_ADJOINT.  Otherwise the nearfield
+// records, then per iteration forward, update and adjoint.
+int enqueue_iterations(ash_batch* b, float* const* phase, int n_iter,
+                       float power, int* ctr) {
+  const size_t per = b->cls.size() * kXcds * kCtrPad;
+  int rc = ASH_OK;
+  if (!b->fused) {
+    if ((rc = make_fields(b, phase))) return rc;
+    for (int it = 0; it < n_iter && !rc; ++it)
+      if (!(rc = enqueue_forward(b, ctr + it * per)) &&
+          !(rc = enqueue_reduce_update(b, power, true)))
+        rc = enqueue_adjoint(b, it == n_iter - 1);
+    return rc;
+  }
+  if ((rc = enqueue_fused(b, kFusedFirst, ctr))) return rc;
+  for (int it = 0; it < n_iter && !rc; ++it) {
+    if ((rc = enqueue_reduce_update(b, power, true))) break;
+    rc = enqueue_fused(b, it + 1 < n_iter ? kFusedMid : kFusedLast,
+                       ctr + (it + 1) * per);
+  }
+  return rc;
+}
+
 
 // Zeroed take counters for `launches` persistent launches of 8 queues per
 // record shape, kCtrPad ints apart.
@@ -758,11 +774,10 @@ int tune_persist(ash_batch* b, float* const* phase_dev,
         rc = bfail(b, ASH_EHIP, "copying tuning inputs");
     }
     if (!rc) rc = upload_desc(b, ph.data(), W.data());
-    if (!rc) rc = counters(b, kPersistTuneIters, &ctr);
+    if (!rc) rc = counters(b, kPersistTuneIters + 1, &ctr);
     if (!rc && hipEventRecord(e0, b->stream) != hipSuccess)
       rc = bfail(b, ASH_EHIP, "hipEventRecord");
-    if (!rc) rc = make_fields(b, ph.data());
-    if (!rc) rc = enqueue_iterations(b, kPersistTuneIters, 1.0f, ctr);
+    if (!rc) rc = enqueue_iterations(b, ph.data(), kPersistTuneIters, 1.0f, ctr);
     if (!rc && (hipEventRecord(e1, b->stream) != hipSuccess ||
                 hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&ms_phase, e0, e1) != hipSuccess))
@@ -829,6 +844,7 @@ int ash_batch_create(ash_batch** out, int H, ash_ctx* const* members,
   b->fused = true;
   for (int h = 0; h < H; ++h)
     if (members[h]->spots.N > kFusedSpots) b->fused = false;
+  for (auto& c : b->cls) c.L = b->fused ? kDefaultFusedRange : kDefaultRange;
   if (!rc) {
     if (hipMalloc(reinterpret_cast<void**>(&b->d_desc),
                   H * sizeof(HoloDesc)) != hipSuccess) {
@@ -907,10 +923,8 @@ int ash_batch_wgs(ash_batch* b, float* const* phase_dev,
       (rc = upload_desc(b, phase_dev, weights_dev)))
     return rc;
   int* ctr = nullptr;
-  if ((rc = counters(b, (size_t)n_iter, &ctr)) ||
-      (rc = make_fields(b, phase_dev)))
-    return rc;
-  return enqueue_iterations(b, n_iter, power, ctr);
+  if ((rc = counters(b, (size_t)n_iter + 1, &ctr))) return rc;
+  return enqueue_iterations(b, phase_dev, n_iter, power, ctr);
 }
 
 int ash_batch_tune(ash_batch* b, float* const* phase_dev,
@@ -920,10 +934,12 @@ int ash_batch_tune(ash_batch* b, float* const* phase_dev,
   if (!phase_dev) return bfail(b, ASH_EINVAL, "phases required");
   int rc;
   if ((rc = buse(b)) || (rc = check_members(b))) return rc;
-  if ((rc = upload_desc(b, phase_dev, nullptr)) ||
-      (rc = make_fields(b, phase_dev)))
-    return rc;
-  const int n_cand = (int)(sizeof(kTuneCandidates) / sizeof(int));
+  if ((rc = upload_desc(b, phase_dev, nullptr))) return rc;
+  if (!b->fused && (rc = make_fields(b, phase_dev))) return rc;
+  const int* const cand = b->fused ? kFusedCandidates : kTuneCandidates;
+  const int n_cand = b->fused
+                         ? (int)(sizeof(kFusedCandidates) / sizeof(int))
+                         : (int)(sizeof(kTuneCandidates) / sizeof(int));
   constexpr int kWarm = 1, kTimed = 3;
   std::vector<float> best_ms(b->cls.size(), 0.0f);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -938,7 +954,7 @@ int ash_batch_tune(ash_batch* b, float* const* phase_dev,
     int best = b->cls[k].L;
     float best_t = -1.0f;
     for (int ci = 0; ci < n_cand && !rc; ++ci) {
-      b->cls[k].L = kTuneCandidates[ci];
+      b->cls[k].L = cand[ci];
       if ((rc = plan(b)) || (rc = upload_desc(b, phase_dev, nullptr))) break;
       int* ctr = nullptr;
       if ((rc = counters(b, kWarm + kTimed, &ctr))) break;
@@ -953,7 +969,8 @@ int ash_batch_tune(ash_batch* b, float* const* phase_dev,
         hipError_t e =
             b->fused
                 ? launch_batch_fused(c.G, c.reduce != 0, c.fus_grid, c.np_max,
-                                     b->d_desc, b->d_items + c.fus_off,
+                                     kFusedMid, b->d_desc,
+                                     b->d_items + c.fus_off,
                                      b->d_qoff + c.qoff_fus, cr, b->stream)
                 : launch_batch_forward(c.G, c.reduce != 0, c.fwd_grid,
                                        b->d_desc, b->d_items + c.fwd_off,
@@ -967,7 +984,7 @@ int ash_batch_tune(ash_batch* b, float* const* phase_dev,
         rc = bfail(b, ASH_EHIP, "timing");
       if (!rc && (best_t < 0.0f || ms < best_t)) {
         best_t = ms;
-        best = kTuneCandidates[ci];
+        best = cand[ci];
       }
     }
     b->cls[k].L = best;

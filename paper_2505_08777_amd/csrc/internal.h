@@ -249,9 +249,12 @@ int batch_blocks_per_cu(int G, bool reduce, bool forward);
 // kFusedSpots spots): units {holo, range, 0, 0} in 8 per-XCD queues like the
 // forward's; np_max is the largest padded spot count of the launch's
 // holograms (a multiple of 32), which sizes the LDS of each wave.
+// Modes: the first forward (phase from the descriptors' phase arrays),
+// an adjoint and the next forward, the last adjoint (writes the phase).
 constexpr int kFusedSpots = 512;
+constexpr int kFusedFirst = 0, kFusedMid = 1, kFusedLast = 2;
 hipError_t launch_batch_fused(int G, bool reduce, int grid, int np_max,
-                              const HoloDesc* d, const int4* items,
+                              int mode, const HoloDesc* d, const int4* items,
                               const int* qoff, int* ctr, hipStream_t s);
 int fused_blocks_per_cu(int G, bool reduce, int np_max);
 

@@ -1995,13 +1995,99 @@ __device__ __forceinline__ void accumulate_rows(const floatx16& th,
   }
 }
 
-// One wave: pixel blocks [b0, b1) of a hologram with N spots.  yrec: the
-// spot-field records of this iteration (the dense magnitudes follow them);
-// ymag_s, acc_s: the wave's LDS; row: the range's forward sums of the next
-// iteration, E_k for k < N.
+// Adjoint of a pair of pixel blocks (records X0: row r, X1: row r + 1)
+// over NB spot blocks: on return lane half h holds g(x) of pixel q of row
+// r + h.  The magnitudes of the spot rows come from ym4 (LDS).
+template <int G, bool kReduce>
+__device__ __forceinline__ float2 adjoint_pair(
+    int NB, const u32x4* X0, const u32x4* X1, rsrc_t rs, rsrc_t ro, rsrc_t ry,
+    const floatx4* ym4, unsigned off_spot, unsigned off_ot, int h) {
+  float ar[4] = {0.0f, 0.0f, 0.0f, 0.0f}, ai[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  float br[4] = {0.0f, 0.0f, 0.0f, 0.0f}, bi[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int nb = 0; nb < NB; ++nb) {
+    u32x4 S[G];
+#pragma unroll
+    for (int g = 0; g < G - 1; ++g)
+      S[g] = bload4(rs, off_spot, (unsigned)(nb * G + g) * 64u * 16u);
+    u32x4 last = bload4(ro, off_ot, (unsigned)nb * 32u * 16u);
+    const u32x4 yv = bload4(ry, off_spot, (unsigned)nb * 64u * 16u);
+    floatx4 w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = ym4[nb * 8 + 2 * j + h];
+    __builtin_amdgcn_sched_barrier(0);  // loads before the products
+    last[2] |= yv[0];
+    last[3] |= yv[1];
+    S[G - 1] = last;
+    const floatx16 th0 = phase_block<G>(S, X0);
+    const floatx16 th1 = phase_block<G>(S, X1);
+    accumulate_rows<kReduce>(th0, w, ar, ai);
+    accumulate_rows<kReduce>(th1, w, br, bi);
+  }
+  const auto jr = __builtin_amdgcn_permlane32_swap(
+      __float_as_uint((ar[0] + ar[1]) + (ar[2] + ar[3])),
+      __float_as_uint((br[0] + br[1]) + (br[2] + br[3])), false, false);
+  const auto ji = __builtin_amdgcn_permlane32_swap(
+      __float_as_uint((ai[0] + ai[1]) + (ai[2] + ai[3])),
+      __float_as_uint((bi[0] + bi[1]) + (bi[2] + bi[3])), false, false);
+  return make_float2(__uint_as_float(jr[0]) + __uint_as_float(jr[1]),
+                     __uint_as_float(ji[0]) + __uint_as_float(ji[1]));
+}
+
+// Forward terms of a pair of pixel blocks (records with their phases, X0:
+// row r, X1: row r + 1 of the tile whose amplitudes ra covers) over NB spot
+// blocks, added to the lane's running sums acc_s[nb][lane] (LDS): the sums
+// over the lane's 16 pixel rows of both blocks of A(x) cos(2 pi theta) and
+// A(x) sin(2 pi theta), theta = tau_k(x) - phi(x).
+template <int G, bool kReduce>
+__device__ __forceinline__ void forward_pair(
+    int NB, int r, const u32x4* X0, const u32x4* X1, rsrc_t rs, rsrc_t ro,
+    rsrc_t ra, unsigned off_spot, unsigned off_ot, unsigned off_amp,
+    unsigned m2, unsigned m3, float2* acc_s, int lane) {
+  floatx4 a0[4], a1[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    a0[j] = __builtin_bit_cast(
+        floatx4, bload4(ra, off_amp, (unsigned)(r * 32 + 8 * j) * 4u));
+    a1[j] = __builtin_bit_cast(
+        floatx4, bload4(ra, off_amp, (unsigned)(r * 32 + 32 + 8 * j) * 4u));
+  }
+  for (int nb = 0; nb < NB; ++nb) {
+    u32x4 S[G];
+#pragma unroll
+    for (int g = 0; g < G - 1; ++g)
+      S[g] = bload4(rs, off_spot, (unsigned)(nb * G + g) * 64u * 16u);
+    u32x4 last = bload4(ro, off_ot, (unsigned)nb * 32u * 16u);
+    float2 o = acc_s[nb * kWave + lane];
+    __builtin_amdgcn_sched_barrier(0);
+    last[2] |= m2;
+    last[3] |= m3;
+    S[G - 1] = last;
+    const floatx16 th0 = phase_block<G>(X0, S);
+    const floatx16 th1 = phase_block<G>(X1, S);
+    float fr[4] = {0.0f, 0.0f, 0.0f, 0.0f}, fi[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    accumulate_rows<kReduce>(th0, a0, fr, fi);
+    accumulate_rows<kReduce>(th1, a1, fr, fi);
+    o.x += (fr[0] + fr[1]) + (fr[2] + fr[3]);
+    o.y += (fi[0] + fi[1]) + (fi[2] + fi[3]);
+    acc_s[nb * kWave + lane] = o;
+  }
+}
+
+// One wave: pixel blocks [b0, b1) of a hologram with N spots, two blocks
+// (rows r and r + 1 of a tile) at a time; b0 and b1 are even, so a pair
+// never leaves its tile.  yrec: the spot-field records of this iteration
+// (the dense magnitudes follow them); ymag_s, acc_s: the wave's LDS; row:
+// the range's forward sums of the next iteration, E_k for k < N.  Each
+// spot block's records are loaded once for both rows, whose products form
+// two independent matrix-core chains; after the adjoint's join, lane half
+// h holds row r + h, so the phase of each of the 64 pixels is taken once.
+// Modes: kFusedMid as above; kFusedFirst takes the phases from `phase`
+// ([ny][nx], radians: the loop's start) and runs the forward only;
+// kFusedLast runs the adjoint only and writes arg g to `phase`.
 template <int G, bool kReduce>
 __device__ __forceinline__ void fused_range(
-    int N, long b0, long b1, const GLOBAL u32x4* __restrict__ pixtab,
+    int mode, int N, int nx, int ny, int tiles_x, float* __restrict__ phase,
+    long b0, long b1, const GLOBAL u32x4* __restrict__ pixtab,
     const GLOBAL u32x4* __restrict__ spotrec,
     const GLOBAL u32x4* __restrict__ offtab,
     const GLOBAL u32x4* __restrict__ yrec,
@@ -2030,76 +2116,65 @@ __device__ __forceinline__ void fused_range(
   const unsigned m3 = h ? 0u : kBf16MinusOne;
   const rsrc_t rs = make_rsrc(spotrec, (unsigned long)NB * G * 64 * 16);
   const rsrc_t ry = make_rsrc(yrec, (unsigned long)NB * 64 * 16);
-  for (long b = b0; b < b1;) {
+  // tile column and row of the current tile, stepped with it
+  int tx = (int)((b0 / kBlkPerTile) % tiles_x);
+  int ty = (int)((b0 / kBlkPerTile) / tiles_x);
+  for (long b = b0; b < b1; b += 2) {
     const long t = b / kBlkPerTile;
-    const int r0 = (int)(b - t * kBlkPerTile);
-    const int r1 = (int)min((long)kBlkPerTile, r0 + (b1 - b));
+    const int r = (int)(b - t * kBlkPerTile);
+    if (r == 0 && b != b0 && ++tx == tiles_x) {
+      tx = 0;
+      ++ty;
+    }
     const rsrc_t rx = make_rsrc(pixtab + t * G * 2 * kTile,
                                 (unsigned long)G * 2 * kTile * 16);
     const rsrc_t ro = make_rsrc(offtab + t * 2 * NP, (unsigned long)2 * NP * 16);
     const rsrc_t ra = make_rsrc(amp_t + t * kTile, (unsigned long)kTile * 4);
-    for (int r = r0; r < r1; ++r) {
-      u32x4 X[G];
+    u32x4 X0[G], X1[G];
 #pragma unroll
-      for (int g = 0; g < G; ++g)
-        X[g] = bload4(rx, off_pix, (unsigned)(g * 2 * kTile + r * 32) * 16u);
-      // adjoint: g(x) = sum_k |y_k| exp(2 pi i (tau_k(x) + psi_k))
-      float ar[4] = {0.0f, 0.0f, 0.0f, 0.0f}, ai[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-      for (int nb = 0; nb < NB; ++nb) {
-        u32x4 S[G];
-#pragma unroll
-        for (int g = 0; g < G - 1; ++g)
-          S[g] = bload4(rs, off_spot, (unsigned)(nb * G + g) * 64u * 16u);
-        u32x4 last = bload4(ro, off_ot, (unsigned)nb * 32u * 16u);
-        const u32x4 yv = bload4(ry, off_spot, (unsigned)nb * 64u * 16u);
-        floatx4 w[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) w[j] = ym4[nb * 8 + 2 * j + h];
-        __builtin_amdgcn_sched_barrier(0);  // loads before the products
-        last[2] |= yv[0];
-        last[3] |= yv[1];
-        S[G - 1] = last;
-        const floatx16 th = phase_block<G>(S, X);
-        accumulate_rows<kReduce>(th, w, ar, ai);
-      }
-      const float gr = join_halves((ar[0] + ar[1]) + (ar[2] + ar[3]));
-      const float gi = join_halves((ai[0] + ai[1]) + (ai[2] + ai[3]));
-      // the pixel's next phase (as the adjoint's epilogue writes it) in
-      // the last group of its record
-      const u32x4 rec = nearfield_record(u32x2{X[G - 1][0], X[G - 1][1]},
-                                         rad_to_turns(atan2f(gi, gr)));
-      if (h == 0) {
-        X[G - 1][2] = rec[2];
-        X[G - 1][3] = rec[3];
-      }
-      // forward of the next iteration: E_k += sum_x A(x) exp(-2 pi i
-      // (tau_k(x) - phi(x))) over the block's 32 pixels
-      floatx4 a[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        a[j] = __builtin_bit_cast(
-            floatx4, bload4(ra, off_amp, (unsigned)(r * 32 + 8 * j) * 4u));
-      for (int nb = 0; nb < NB; ++nb) {
-        u32x4 S[G];
-#pragma unroll
-        for (int g = 0; g < G - 1; ++g)
-          S[g] = bload4(rs, off_spot, (unsigned)(nb * G + g) * 64u * 16u);
-        u32x4 last = bload4(ro, off_ot, (unsigned)nb * 32u * 16u);
-        float2 o = acc_s[nb * kWave + lane];
-        __builtin_amdgcn_sched_barrier(0);
-        last[2] |= m2;
-        last[3] |= m3;
-        S[G - 1] = last;
-        const floatx16 th = phase_block<G>(X, S);
-        float fr[4] = {0.0f, 0.0f, 0.0f, 0.0f}, fi[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        accumulate_rows<kReduce>(th, a, fr, fi);
-        o.x += (fr[0] + fr[1]) + (fr[2] + fr[3]);
-        o.y += (fi[0] + fi[1]) + (fi[2] + fi[3]);
-        acc_s[nb * kWave + lane] = o;
-      }
+    for (int g = 0; g < G; ++g) {
+      X0[g] = bload4(rx, off_pix, (unsigned)(g * 2 * kTile + r * 32) * 16u);
+      X1[g] = bload4(rx, off_pix, (unsigned)(g * 2 * kTile + r * 32 + 32) * 16u);
     }
-    b += r1 - r0;
+    // the lane's pixel after the adjoint's join: row r + h, column q
+    const int pix = (r + h) * 32 + q;
+    const int pi = tx * kTileW + pix % kTileW;
+    const int pj = ty * kTileH + pix / kTileW;
+    const bool inside = pi < nx && pj < ny;
+    const long pp = (long)pj * nx + pi;
+    float turns = 0.0f;
+    if (mode == kFusedFirst) {
+      if (inside) turns = rad_to_turns(phase[pp]);
+    } else {
+      const float2 gv = adjoint_pair<G, kReduce>(NB, X0, X1, rs, ro, ry, ym4,
+                                                 off_spot, off_ot, h);
+      const float ang = atan2f(gv.y, gv.x);  // atan2(0, 0) = 0
+      if (mode == kFusedLast) {
+        if (inside) phase[pp] = ang;
+        continue;
+      }
+      turns = rad_to_turns(ang);
+    }
+    // the pixel's phase (as the adjoint's epilogue writes it) in the last
+    // group of its record: half 0's words for row r stay, row r + 1's move
+    // from half 1 to half 0
+    unsigned ph[3];
+    split3f(turns, ph);
+    const unsigned w2 = ph[0] | (ph[1] << 16), w3 = ph[2] | (kBf16One << 16);
+    const auto s2 = __builtin_amdgcn_permlane32_swap(w2, w2, false, false);
+    const auto s3 = __builtin_amdgcn_permlane32_swap(w3, w3, false, false);
+    if (h == 0) {
+      X0[G - 1][2] = w2;
+      X0[G - 1][3] = w3;
+      X1[G - 1][2] = s2[1];
+      X1[G - 1][3] = s3[1];
+    }
+    // forward of the next iteration over the pair's 64 pixels
+    forward_pair<G, kReduce>(NB, r, X0, X1, rs, ro, ra, off_spot, off_ot,
+                             off_amp, m2, m3, acc_s, lane);
   }
+  if (mode == kFusedLast) return;
+  // E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))) of the range
   for (int nb = 0; nb < NB; ++nb) {
     const float2 o = acc_s[nb * kWave + lane];
     const float er = join_halves(o.x), ei = -join_halves(o.y);
@@ -2110,11 +2185,12 @@ __device__ __forceinline__ void fused_range(
 
 // Fused launch of a batch: each wave takes units {holo, range} from the
 // queues (as the forward) and runs fused_range over the range, writing the
-// range's row of forward partial sums.
+// range's row of forward partial sums (mode: see fused_range).
 template <int G, bool kReduce>
 __global__ __launch_bounds__(kBlock) void k_batch_fused(
     const HoloDesc* __restrict__ hd, const int4* __restrict__ items,
-    const int* __restrict__ qoff, int* __restrict__ ctr, int np_max) {
+    const int* __restrict__ qoff, int* __restrict__ ctr, int np_max,
+    int mode) {
   extern __shared__ float lds[];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   float* const base = lds + (long)wave * fused_lds_floats(np_max);
@@ -2123,7 +2199,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused(
     const long b0 = (long)it.y * d.L;
     const long b1 = min(b0 + d.L, d.n_blk);
     fused_range<G, kReduce>(
-        d.N, b0, b1, as_global(d.pixtab), as_global(d.spotrec),
+        mode, d.N, d.nx, d.ny, d.tiles_x, d.phase, b0, b1,
+        as_global(d.pixtab), as_global(d.spotrec),
         as_global(reinterpret_cast<const u32x4*>(d.offtab)),
         as_global(reinterpret_cast<const u32x4*>(d.ypol)), as_global(d.amp_t),
         base, reinterpret_cast<float2*>(base + np_max),
@@ -2132,12 +2209,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused(
 }
 
 template <int G, bool kReduce>
-static hipError_t bfus_g(int grid, int np_max, const HoloDesc* d,
+static hipError_t bfus_g(int grid, int np_max, int mode, const HoloDesc* d,
                          const int4* items, const int* qoff, int* ctr,
                          hipStream_t s) {
   const size_t lds = (size_t)(kBlock / kWave) * fused_lds_floats(np_max) * 4;
   hipLaunchKernelGGL((k_batch_fused<G, kReduce>), dim3(grid), dim3(kBlock),
-                     lds, s, d, items, qoff, ctr, np_max);
+                     lds, s, d, items, qoff, ctr, np_max, mode);
   return hipGetLastError();
 }
 
@@ -2154,14 +2231,17 @@ static int fus_blocks_per_cu(int np_max) {
 }
 
 hipError_t launch_batch_fused(int G, bool reduce, int grid, int np_max,
-                              const HoloDesc* d, const int4* items,
+                              int mode, const HoloDesc* d, const int4* items,
                               const int* qoff, int* ctr, hipStream_t s) {
-  if (np_max < 32 || np_max > kFusedSpots || np_max % 32) return hipErrorInvalidValue;
+  if (np_max < 32 || np_max > kFusedSpots || np_max % 32 ||
+      mode < kFusedFirst || mode > kFusedLast)
+    return hipErrorInvalidValue;
   switch (G) {
-#define X(n)                                                                 \
-  case n:                                                                    \
-    return reduce ? bfus_g<n, true>(grid, np_max, d, items, qoff, ctr, s)    \
-                  : bfus_g<n, false>(grid, np_max, d, items, qoff, ctr, s);
+#define X(n)                                                              \
+  case n:                                                                 \
+    return reduce                                                         \
+               ? bfus_g<n, true>(grid, np_max, mode, d, items, qoff, ctr, s) \
+               : bfus_g<n, false>(grid, np_max, mode, d, items, qoff, ctr, s);
     ASH_G_CASES(X)
 #undef X
     default:

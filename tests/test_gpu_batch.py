@@ -176,7 +176,8 @@ def test_batch_tuning_table(A, batch_case, tmp_path):
     # these members are small: the tuner sets both forms' parameters (range
     # lengths; chunk and resident blocks per CU of the one-launch form) and
     # keeps the faster form
-    assert all(L in (16, 32, 64, 128, 256, 512) for L in inf["range_blocks"])
+    cands = (4, 8, 16, 32, 64, 128) if inf["fused"] else (16, 32, 64, 128, 256, 512)
+    assert all(L in cands for L in inf["range_blocks"])
     assert all(L in (4, 8, 16, 32) for L in inf["chunk"])
     rows = [l.split() for l in open(path) if not l.startswith("#")]
     assert sum(r[0] == "persist" for r in rows) == inf["shapes"]
