@@ -82,6 +82,9 @@ __device__ __forceinline__ GLOBAL T* as_global(T* p) {
 // zeros.
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit dword access
+// A lane offset past every resource's extent (extents stay below 2^31
+// bytes): its buffer loads return zeros.
+constexpr unsigned kOutOfRange = 0x80000000u;
 
 template <typename T>
 __device__ __forceinline__ rsrc_t make_rsrc(const GLOBAL T* base,
@@ -932,13 +935,20 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 // Two values as bf16 pieces, packed two per word (x0 in the low half):
 // hi rounds to nearest even, the remainder x - hi is exact, and lo is its
-// rounding, so x = hi + lo + O(2^-17 |x|).
-__device__ __forceinline__ void split2(float x0, float x1, unsigned& hi,
+// rounding, so x = hi + lo + O(2^-17 |x|).  Each remainder is one bf16 dot
+// product, x + (-1) hi + 0 hi': its products are exact and its result is
+// representable, so it carries no rounding.  The selector pairs {-1, 0}
+// and {0, -1} (n0, n1: bf16 bits 0x0000BF80, 0xBF800000) are held in
+// registers by the caller, never folded into the instruction as constants.
+__device__ __forceinline__ void split2(float x0, float x1, unsigned n0,
+                                       unsigned n1, unsigned& hi,
                                        unsigned& lo) {
-  hi = __builtin_bit_cast(unsigned,
-                          __builtin_convertvector(float2v{x0, x1}, bf16x2));
-  const float r0 = x0 - __uint_as_float(hi << 16);
-  const float r1 = x1 - __uint_as_float(hi & 0xFFFF0000u);
+  const bf16x2 h = __builtin_convertvector(float2v{x0, x1}, bf16x2);
+  const float r0 = __builtin_amdgcn_fdot2_f32_bf16(
+      h, __builtin_bit_cast(bf16x2, n0), x0, false);
+  const float r1 = __builtin_amdgcn_fdot2_f32_bf16(
+      h, __builtin_bit_cast(bf16x2, n1), x1, false);
+  hi = __builtin_bit_cast(unsigned, h);
   lo = __builtin_bit_cast(unsigned,
                           __builtin_convertvector(float2v{r0, r1}, bf16x2));
 }
@@ -998,9 +1008,10 @@ hipError_t launch_build_momtab(const Geom& b, const int32_t* d_pow,
 
 // Moments of one wave: the 32 spots of spot block mb over pixel blocks
 // [b0, b1).  RT tiles of 32 moment rows; out: [2D][NP] (re, -im) sums.
-template <int G, int RT>
+// kReduce as for the transforms.
+template <int G, int RT, bool kReduce>
 __device__ __forceinline__ void moments_range(
-    int N, int D2, int mb, long b0, long b1, bool reduce,
+    int N, int D2, int mb, long b0, long b1,
     const GLOBAL u32x4* __restrict__ pixtab, const GLOBAL u32x4* __restrict__ nf,
     const GLOBAL u32x4* __restrict__ spotrec,
     const GLOBAL u32x4* __restrict__ offtab,
@@ -1015,6 +1026,10 @@ __device__ __forceinline__ void moments_range(
   for (int g = 0; g < G - 1; ++g) S[g] = sb[lane_spot + g * 64];
   const unsigned m2 = h ? 0u : (kBf16MinusOne | (kBf16MinusOne << 16));
   const unsigned m3 = h ? 0u : kBf16MinusOne;
+  // split2's selector pairs, in vector registers (an empty asm statement
+  // hides their values from constant folding)
+  unsigned sel0 = kBf16MinusOne, sel1 = kBf16MinusOne << 16;
+  asm volatile("" : "+v"(sel0), "+v"(sel1));
   floatx16 are[RT], aim[RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -1033,8 +1048,8 @@ __device__ __forceinline__ void moments_range(
                                 (unsigned long)G * 2 * kTile * 16);
     const rsrc_t rn = make_rsrc(nf + t * kBlkPerTile * 64,
                                 (unsigned long)kBlkPerTile * 64 * 16);
-    const rsrc_t rt_ = make_rsrc(momtab + t * kBlkPerTile * 4 * D2,
-                                 (unsigned long)kBlkPerTile * 4 * D2 * 16);
+    const rsrc_t rm = make_rsrc(momtab + t * kBlkPerTile * 4 * D2,
+                                (unsigned long)kBlkPerTile * 4 * D2 * 16);
     for (int r = r0; r < r1; ++r) {
       u32x4 X[G];
 #pragma unroll
@@ -1042,17 +1057,16 @@ __device__ __forceinline__ void moments_range(
         X[g] = bload4(rx, lane_pix * 16u,
                       (unsigned)(g * 2 * kTile + r * 32) * 16u);
       X[G - 1] = bload4(rn, lane_spot * 16u, (unsigned)r * 64u * 16u);
-      // moment rows 32 rt + q of this lane; rows past 2D are zero
+      // moment rows 32 rt + q of this lane; rows past 2D load zeros
       u32x4 A[RT][2];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
           const int row = 32 * rt + q;
-          A[rt][kb] = row < D2
-                          ? bload4(rt_, (unsigned)((kb * 2 + h) * D2 + row) * 16u,
-                                   (unsigned)r * 4u * D2 * 16u)
-                          : u32x4{0u, 0u, 0u, 0u};
+          A[rt][kb] = bload4(
+              rm, row < D2 ? (unsigned)((kb * 2 + h) * D2 + row) * 16u : kOutOfRange,
+              (unsigned)r * 4u * D2 * 16u);
         }
       const floatx16 th = phase_block<G>(X, S);
       u32x4 ch[2], cl[2], sh[2], sl[2];
@@ -1061,14 +1075,15 @@ __device__ __forceinline__ void moments_range(
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
           float t0 = th[8 * kb + 2 * w], t1 = th[8 * kb + 2 * w + 1];
-          if (reduce) {
+          if (kReduce) {
             t0 = __builtin_amdgcn_fractf(t0);
             t1 = __builtin_amdgcn_fractf(t1);
           }
           unsigned a0, a1, b0w, b1w;
-          split2(__builtin_amdgcn_cosf(t0), __builtin_amdgcn_cosf(t1), a0, a1);
-          split2(__builtin_amdgcn_sinf(t0), __builtin_amdgcn_sinf(t1), b0w,
-                 b1w);
+          split2(__builtin_amdgcn_cosf(t0), __builtin_amdgcn_cosf(t1), sel0,
+                 sel1, a0, a1);
+          split2(__builtin_amdgcn_sinf(t0), __builtin_amdgcn_sinf(t1), sel0,
+                 sel1, b0w, b1w);
           ch[kb][w] = a0;
           cl[kb][w] = a1;
           sh[kb][w] = b0w;
@@ -1097,9 +1112,9 @@ __device__ __forceinline__ void moments_range(
 }
 
 // Waves and ranges are laid out over the XCDs as in k_forward.
-template <int G, int RT>
+template <int G, int RT, bool kReduce>
 __global__ __launch_bounds__(kBlock) void k_moments(
-    int N, int D2, long n_blk, int groups, int reduce,
+    int N, int D2, long n_blk, int groups,
     const u32x4* __restrict__ pixtab, const unsigned* __restrict__ nf_t,
     const u32x4* __restrict__ spotrec, const unsigned* __restrict__ offtab,
     const u32x4* __restrict__ momtab, float2* __restrict__ partial) {
@@ -1111,8 +1126,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(
   if (v >= (long)(groups / kXcds) * n_mb) return;  // wave-uniform exit
   const int gi = (int)(v / n_mb) * kXcds + xcd;
   const int mb = (int)(v % n_mb);
-  moments_range<G, RT>(N, D2, mb, n_blk * gi / groups,
-                       n_blk * (gi + 1) / groups, reduce != 0,
+  moments_range<G, RT, kReduce>(N, D2, mb, n_blk * gi / groups,
+                                n_blk * (gi + 1) / groups,
                        as_global(pixtab),
                        as_global(reinterpret_cast<const u32x4*>(nf_t)),
                        as_global(spotrec),
@@ -1130,8 +1145,10 @@ static hipError_t mom_g(const Geom& b, int N, int groups, hipStream_t s,
   const long per_xcd = (long)(groups / kXcds) * n_mb;
   const long blocks_per_xcd =
       (per_xcd + kBlock / kWave - 1) / (kBlock / kWave);
-  hipLaunchKernelGGL((k_moments<G, RT>), dim3((unsigned)(blocks_per_xcd * kXcds)),
-                     dim3(kBlock), 0, s, N, 2 * b.D, n_blk, groups, b.reduce,
+  auto* const kern =
+      b.reduce ? k_moments<G, RT, true> : k_moments<G, RT, false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(blocks_per_xcd * kXcds)),
+                     dim3(kBlock), 0, s, N, 2 * b.D, n_blk, groups,
                      reinterpret_cast<const u32x4*>(pixtab), nf_t,
                      reinterpret_cast<const u32x4*>(spotrec), offtab,
                      reinterpret_cast<const u32x4*>(momtab),
@@ -1163,8 +1180,8 @@ hipError_t launch_moments(const Geom& b, int N, int groups,
 template <int G, int RT>
 static int mom_blocks_per_cu() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_moments<G, RT>,
-                                                   kBlock, 0) != hipSuccess) {
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, k_moments<G, RT, false>, kBlock, 0) != hipSuccess) {
     (void)hipGetLastError();
     return 1;
   }
