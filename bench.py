@@ -20,6 +20,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -451,7 +452,8 @@ def bench_coef(args, d):
     value = N * P * n_calls * args.steps / T
     ms_avg = prof["forward"][0] / max(prof["forward"][1], 1)
     groups = info["groups"]
-    kname = "k_moments<%d, %d>" % (groups, 2 if 2 * D > 32 else 1)
+    kname = "k_moments<%d, %d, %s>" % (groups, 2 if 2 * D > 32 else 1,
+                                        "true" if info["range_reduce"] else "false")
     F = 6 * D + 3       # phase 2D, reduction 1, sin + cos, 4D moment flops
     traffic, traffic_src = profiled_traffic("coefgrad1024", kname,
                                             "coef_grad_kernels")
@@ -958,9 +960,15 @@ def bench_batch(args, holos):
         launches = prof[dom][1] // shapes
         ms_avg = prof[dom][0] / max(launches, 1)
         evals_launch = evals
-    traffic, traffic_src = (profiled_traffic(args.workload, kname,
-                                             summary="batch_kernels")
-                            if shapes == 1 else (None, None))
+    # the unit timed spans one launch of every record shape: its traffic is
+    # the sum of the shapes' kernels' traffic per launch
+    parts = [profiled_traffic(args.workload,
+                              re.sub(r"<\d+,", "<%d," % g, kname, count=1),
+                              summary="batch_kernels")
+             for g in (info["groups"] or [groups])]
+    traffic = (sum(t for t, _ in parts)
+               if parts and all(t is not None for t, _ in parts) else None)
+    traffic_src = parts[0][1] if parts else None
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
