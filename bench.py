@@ -49,7 +49,7 @@ def flops_per_eval(D):
 # overlap on this chip).
 ISSUE = {}
 SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
-# BASELINE's slot model: 256 CUs x 64 lanes x 2.4 GHz FP32 issue slots/s
+# FP32 issue slots of the vector units: 256 CUs x 64 lanes x 2.4 GHz
 SLOT_RATE = 256 * 64 * 2.4e9
 
 
@@ -140,9 +140,10 @@ def issue_model(evals_per_s, groups, cycles=None):
 
 
 def slot_model(evals_per_s, D, cycles=None):
-    """BASELINE's slot model of '% FP32 VALU peak': per evaluation (D + 4)/2
-    packed-FMA slots + 1 range reduction + r_sin + r_cos, r = the measured
-    transcendental cost in FMA slots, against 256 x 64 x 2.4e9 slots/s."""
+    """The vector-unit slot model of '% FP32 VALU peak': per evaluation
+    (D + 4)/2 packed-FMA slots + 1 range reduction + r_sin + r_cos, r = the
+    measured transcendental cost in FMA slots, against 256 x 64 x 2.4e9
+    slots/s (it prices the phase multiply-adds on the vector unit)."""
     c = cycles or ISSUE
     r = c["trans"] / c["fma"]
     s_eval = (D + 4) / 2.0 + 1.0 + 2.0 * r

@@ -73,9 +73,9 @@ def test_wgs_and_transforms_replay_bitwise(A):
 
 def test_adam_and_coefficient_gradient_replay_bitwise(A):
     """The on-device Adam descent, the moment transform and the gradient in
-    the coefficients captured once (after an eager warm-up that allocates
-    the context's gradient buffers) and replayed, each replay equal to the
-    eager calls bitwise."""
+    the coefficients captured once (after the usual warm-up on a side
+    stream) and replayed, each replay equal to an eager run of the same
+    calls bitwise."""
     nx, ny, N = 128, 96, 40
     modes = [1, 2, 3, 4, 5, 7, 12]
     rng = np.random.default_rng(77)

@@ -181,6 +181,18 @@ def _window_axes_swapped(mp):
                 lambda w, ix, iy, dwx, dwy, win: wc(w, iy, ix, dwy, dwx, win))
 
 
+def _spread_sample_std(mp):
+    ws = owgs.wgs_stats
+
+    def wrong(E, t, amp):
+        st = np.array(ws(E, t, amp), dtype=np.float64)
+        I = np.abs(np.asarray(E)) ** 2 / np.asarray(t, dtype=np.float64) ** 2
+        mu = np.mean(I)
+        st[2] = np.std(I, ddof=1) / mu if mu > 0 else 0.0
+        return st
+    _patch_both(mp, owgs, "wgs_stats", wrong)
+
+
 def _principal_trailing(mp):
     def wrong(w, basis, K):
         w = np.asarray(w, dtype=np.float64)
@@ -210,6 +222,7 @@ MUTATIONS = {
     "windowed Strehl of amplitudes, not intensities": _strehl_amplitudes,
     "window offsets on swapped axes": _window_axes_swapped,
     "principal modes from the trailing singular vectors": _principal_trailing,
+    "intensity spread with the sample standard deviation": _spread_sample_std,
 }
 
 
