@@ -2098,12 +2098,13 @@ __device__ __forceinline__ void forward_pair(
 // spot block's records are loaded once for both rows, whose products form
 // two independent matrix-core chains; after the adjoint's join, lane half
 // h holds row r + h, so the phase of each of the 64 pixels is taken once.
-// Modes: kFusedMid as above; kFusedFirst takes the phases from `phase`
-// ([ny][nx], radians: the loop's start) and runs the forward only;
+// Modes (a template parameter, so that each kernel holds only its own
+// path's registers): kFusedMid as above; kFusedFirst takes the phases from
+// `phase` ([ny][nx], radians: the loop's start) and runs the forward only;
 // kFusedLast runs the adjoint only and writes arg g to `phase`.
-template <int G, bool kReduce>
+template <int G, bool kReduce, int kMode>
 __device__ __forceinline__ void fused_range(
-    int mode, int N, int nx, int ny, int tiles_x, float* __restrict__ phase,
+    int N, int nx, int ny, int tiles_x, float* __restrict__ phase,
     long b0, long b1, const GLOBAL u32x4* __restrict__ pixtab,
     const GLOBAL u32x4* __restrict__ spotrec,
     const GLOBAL u32x4* __restrict__ offtab,
@@ -2160,13 +2161,13 @@ __device__ __forceinline__ void fused_range(
     const bool inside = pi < nx && pj < ny;
     const long pp = (long)pj * nx + pi;
     float turns = 0.0f;
-    if (mode == kFusedFirst) {
+    if (kMode == kFusedFirst) {
       if (inside) turns = rad_to_turns(phase[pp]);
     } else {
       const float2 gv = adjoint_pair<G, kReduce>(NB, X0, X1, rs, ro, ry, ym4,
                                                  off_spot, off_ot, h);
       const float ang = atan2f(gv.y, gv.x);  // atan2(0, 0) = 0
-      if (mode == kFusedLast) {
+      if (kMode == kFusedLast) {
         if (inside) phase[pp] = ang;
         continue;
       }
@@ -2190,7 +2191,7 @@ __device__ __forceinline__ void fused_range(
     forward_pair<G, kReduce>(NB, r, X0, X1, rs, ro, ra, off_spot, off_ot,
                              off_amp, m2, m3, acc_s, lane);
   }
-  if (mode == kFusedLast) return;
+  if (kMode == kFusedLast) return;
   // E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))) of the range
   for (int nb = 0; nb < NB; ++nb) {
     const float2 o = acc_s[nb * kWave + lane];
@@ -2203,11 +2204,10 @@ __device__ __forceinline__ void fused_range(
 // Fused launch of a batch: each wave takes units {holo, range} from the
 // queues (as the forward) and runs fused_range over the range, writing the
 // range's row of forward partial sums (mode: see fused_range).
-template <int G, bool kReduce>
+template <int G, bool kReduce, int kMode>
 __global__ __launch_bounds__(kBlock) void k_batch_fused(
     const HoloDesc* __restrict__ hd, const int4* __restrict__ items,
-    const int* __restrict__ qoff, int* __restrict__ ctr, int np_max,
-    int mode) {
+    const int* __restrict__ qoff, int* __restrict__ ctr, int np_max) {
   extern __shared__ float lds[];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   float* const base = lds + (long)wave * fused_lds_floats(np_max);
@@ -2215,8 +2215,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused(
     const HoloDesc& d = hd[it.x];
     const long b0 = (long)it.y * d.L;
     const long b1 = min(b0 + d.L, d.n_blk);
-    fused_range<G, kReduce>(
-        mode, d.N, d.nx, d.ny, d.tiles_x, d.phase, b0, b1,
+    fused_range<G, kReduce, kMode>(
+        d.N, d.nx, d.ny, d.tiles_x, d.phase, b0, b1,
         as_global(d.pixtab), as_global(d.spotrec),
         as_global(reinterpret_cast<const u32x4*>(d.offtab)),
         as_global(reinterpret_cast<const u32x4*>(d.ypol)), as_global(d.amp_t),
@@ -2230,8 +2230,11 @@ static hipError_t bfus_g(int grid, int np_max, int mode, const HoloDesc* d,
                          const int4* items, const int* qoff, int* ctr,
                          hipStream_t s) {
   const size_t lds = (size_t)(kBlock / kWave) * fused_lds_floats(np_max) * 4;
-  hipLaunchKernelGGL((k_batch_fused<G, kReduce>), dim3(grid), dim3(kBlock),
-                     lds, s, d, items, qoff, ctr, np_max, mode);
+  auto* const kern = mode == kFusedFirst ? k_batch_fused<G, kReduce, kFusedFirst>
+                     : mode == kFusedMid ? k_batch_fused<G, kReduce, kFusedMid>
+                                         : k_batch_fused<G, kReduce, kFusedLast>;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, d, items, qoff,
+                     ctr, np_max);
   return hipGetLastError();
 }
 
@@ -2239,8 +2242,9 @@ template <int G, bool kReduce>
 static int fus_blocks_per_cu(int np_max) {
   const size_t lds = (size_t)(kBlock / kWave) * fused_lds_floats(np_max) * 4;
   int n = 0;
+  // the middle mode's kernel, which runs every iteration but the last
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &n, k_batch_fused<G, kReduce>, kBlock, lds) != hipSuccess) {
+          &n, k_batch_fused<G, kReduce, kFusedMid>, kBlock, lds) != hipSuccess) {
     (void)hipGetLastError();
     return 1;
   }
