@@ -526,7 +526,8 @@ typedef struct ash_batch_info {
   int32_t groups[4];        /* matrix-core groups of the first 4 shapes    */
   int32_t range_blocks[4];  /* their forward range lengths (fused: for a
                                hologram of one 32-spot block)             */
-  int64_t items;            /* forward + adjoint work items                */
+  int64_t items;            /* work items of the per-phase launches:
+                               forward + adjoint, or fused units          */
   double evals_per_transform;  /* sum over holograms of N * P              */
   int32_t one_launch;       /* 1: the one-launch form (see ash_batch_wgs)  */
   int32_t chunk[4];         /* its pixel blocks per forward unit, per shape*/
