@@ -949,7 +949,7 @@ def bench_batch(args, holos):
         # 2 n_iter transforms of its holograms (the first only a forward,
         # the last only an adjoint); the unit timed is a launch of all
         # shapes, with the work of the average launch
-        kname = "k_batch_fused<%d, false>" % groups
+        kname = "k_batch_fused<%d, false, 1>" % groups
         launches = prof["adjoint"][1] // shapes
         ms_avg = prof["adjoint"][0] / max(launches, 1)
         evals_launch = 2.0 * evals * n_iter / (n_iter + 1)
@@ -962,11 +962,21 @@ def bench_batch(args, holos):
         ms_avg = prof[dom][0] / max(launches, 1)
         evals_launch = evals
     # the unit timed spans one launch of every record shape: its traffic is
-    # the sum of the shapes' kernels' traffic per launch
-    parts = [profiled_traffic(args.workload,
-                              re.sub(r"<\d+,", "<%d," % g, kname, count=1),
-                              summary="batch_kernels")
-             for g in (info["groups"] or [groups])]
+    # the sum of the shapes' kernels' traffic per launch (fused: the first,
+    # middle and last launches weighted 1 : n_iter - 1 : 1)
+    parts = []
+    for g in (info["groups"] or [groups]):
+        name = re.sub(r"<\d+,", "<%d," % g, kname, count=1)
+        if info["fused"]:
+            modes = [profiled_traffic(args.workload, name[:-2] + "%d>" % m,
+                                      summary="batch_kernels") for m in (0, 1, 2)]
+            t = (None if any(x is None for x, _ in modes) else
+                 (modes[0][0] + (n_iter - 1) * modes[1][0] + modes[2][0])
+                 / (n_iter + 1))
+            parts.append((t, modes[1][1]))
+        else:
+            parts.append(profiled_traffic(args.workload, name,
+                                          summary="batch_kernels"))
     traffic = (sum(t for t, _ in parts)
                if parts and all(t is not None for t, _ in parts) else None)
     traffic_src = parts[0][1] if parts else None
