@@ -114,6 +114,22 @@ const char* ash_strerror(int code);
 /* Detail of the last error on ctx (static per context; "" if none). */
 const char* ash_last_error(const ash_ctx* ctx);
 
+/* Failure injection, for tests of the error paths (process-wide):
+ *   ASH_INJECT_ALLOC    the next `count` device allocations made by any
+ *                       context or batch fail as if the device were out of
+ *                       memory: the call returns ASH_ENOMEM and leaves the
+ *                       object valid (what it was setting up is unset, and
+ *                       repeating the call succeeds);
+ *   ASH_INJECT_BARRIER  the next `count` one-launch batch calls start with
+ *                       their barrier error flag set: every barrier gives
+ *                       up at once, nothing waits, and the call returns
+ *                       ASH_EHIP as for a barrier past its time limit.
+ * count 0 disarms.  Returns ASH_OK or ASH_EINVAL (unknown `what`, count
+ * < 0). */
+#define ASH_INJECT_ALLOC 1
+#define ASH_INJECT_BARRIER 2
+int ash_inject_failure(int what, int count);
+
 /* Create a context on HIP device `device`, enqueueing on `stream` (a
  * hipStream_t, NULL = the device's null stream).  *out receives the handle. */
 int ash_create(ash_ctx** out, int device, void* stream);

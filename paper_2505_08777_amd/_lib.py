@@ -84,6 +84,7 @@ def _load():
         "ash_version": (I, []),
         "ash_strerror": (ctypes.c_char_p, [I]),
         "ash_last_error": (ctypes.c_char_p, [P]),
+        "ash_inject_failure": (I, [I, I]),
         "ash_create": (I, [ctypes.POINTER(P), I, P]),
         "ash_destroy": (I, [P]),
         "ash_set_stream": (I, [P, P]),
@@ -136,6 +137,20 @@ lib = _load()
 
 def strerror(code):
     return lib.ash_strerror(code).decode()
+
+
+INJECT_ALLOC = 1
+INJECT_BARRIER = 2
+
+
+def inject_failure(what, count=1):
+    """Arm `count` injected failures of kind `what` (INJECT_ALLOC: device
+    allocations fail as out of memory; INJECT_BARRIER: one-launch batch
+    calls start with their barrier flag set); count 0 disarms.  For tests
+    of the error paths."""
+    rc = lib.ash_inject_failure(int(what), int(count))
+    if rc != 0:
+        raise ValueError("ash_inject_failure: %s" % strerror(rc))
 
 
 def check(code, where, ctx=None):

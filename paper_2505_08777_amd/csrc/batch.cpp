@@ -146,7 +146,8 @@ int bgrow(ash_batch* b, T** p, size_t* cap, size_t need, const char* what) {
   if (need <= *cap) return ASH_OK;
   bfree(*p);
   *cap = 0;
-  if (hipMalloc(reinterpret_cast<void**>(p), need * sizeof(T)) != hipSuccess) {
+  if (injected_alloc_failure() ||
+      hipMalloc(reinterpret_cast<void**>(p), need * sizeof(T)) != hipSuccess) {
     (void)hipGetLastError();
     *p = nullptr;
     return bfail(b, ASH_ENOMEM, std::string("out of device memory for ") + what);
@@ -652,6 +653,9 @@ int run_persist(ash_batch* b, int n_iter, float power) {
   int* err = b->d_pctr + b->pholo.size() * kCtrPad;
   BCHK(b, hipMemsetAsync(b->d_pctr, 0, n_ctr * sizeof(int), b->stream),
        "clearing barrier counters");
+  if (injected_barrier_failure())  // the flag set: every barrier gives up
+    BCHK(b, hipMemsetAsync(err, 0x01, sizeof(int), b->stream),
+         "setting the barrier flag");
   for (const Cls& c : b->cls) {
     BCHK(b, btimed(b, ASH_PROF_FORWARD, [&] {
            return launch_batch_persist(c.G, c.reduce != 0, c.p_grid, c.p_lds,
@@ -665,8 +669,9 @@ int run_persist(ash_batch* b, int n_iter, float power) {
                          b->stream), "reading the barrier flag");
   BCHK(b, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   if (flag)
-    return bfail(b, ASH_EHIP, "a barrier of the one-launch batch exceeded "
-                              "its time limit; results are incomplete");
+    return bfail(b, ASH_EHIP, "a barrier of the one-launch batch gave up "
+                              "(its time limit, or an injected failure); "
+                              "results are incomplete");
   return ASH_OK;
 }
 
@@ -689,7 +694,8 @@ int tune_persist(ash_batch* b, float* const* phase_dev,
   };
   for (size_t h = 0; h < H && !rc; ++h) {
     const size_t P = (size_t)b->m[h]->basis.g.nx * b->m[h]->basis.g.ny;
-    if (hipMalloc(reinterpret_cast<void**>(&ph[h]), P * sizeof(float)) !=
+    if (injected_alloc_failure() ||
+        hipMalloc(reinterpret_cast<void**>(&ph[h]), P * sizeof(float)) !=
             hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&W[h]),
                   b->m[h]->spots.N * sizeof(float)) != hipSuccess) {
@@ -846,7 +852,8 @@ int ash_batch_create(ash_batch** out, int H, ash_ctx* const* members,
     if (members[h]->spots.N > kFusedSpots) b->fused = false;
   for (auto& c : b->cls) c.L = b->fused ? kDefaultFusedRange : kDefaultRange;
   if (!rc) {
-    if (hipMalloc(reinterpret_cast<void**>(&b->d_desc),
+    if (injected_alloc_failure() ||
+        hipMalloc(reinterpret_cast<void**>(&b->d_desc),
                   H * sizeof(HoloDesc)) != hipSuccess) {
       (void)hipGetLastError();
       b->d_desc = nullptr;

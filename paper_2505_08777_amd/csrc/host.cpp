@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <new>
 #include <string>
@@ -18,6 +19,26 @@
 #include "internal.h"
 
 using namespace ash;
+
+namespace {
+
+// Armed failure injections (ash_inject_failure), process-wide.
+std::atomic<int> g_inject_alloc{0};
+std::atomic<int> g_inject_barrier{0};
+
+bool consume(std::atomic<int>& armed) {
+  int n = armed.load();
+  while (n > 0 && !armed.compare_exchange_weak(n, n - 1)) {
+  }
+  return n > 0;
+}
+
+}  // namespace
+
+namespace ash {
+bool injected_alloc_failure() { return consume(g_inject_alloc); }
+bool injected_barrier_failure() { return consume(g_inject_barrier); }
+}  // namespace ash
 
 namespace {
 
@@ -107,6 +128,11 @@ template <typename T>
 int dalloc(ash_ctx* c, T** p, size_t count, const char* what) {
   *p = nullptr;
   if (count == 0) count = 1;
+  if (injected_alloc_failure()) {
+    c->err = std::string("out of device memory allocating ") + what +
+             " (injected)";
+    return ASH_ENOMEM;
+  }
   hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
   if (e != hipSuccess) {
     *p = nullptr;
@@ -227,6 +253,20 @@ constexpr float kMaxPhaseBound = 256.0f;
 extern "C" {
 
 int ash_version(void) { return 100; }
+
+int ash_inject_failure(int what, int count) {
+  if (count < 0) return ASH_EINVAL;
+  switch (what) {
+    case ASH_INJECT_ALLOC:
+      g_inject_alloc.store(count);
+      return ASH_OK;
+    case ASH_INJECT_BARRIER:
+      g_inject_barrier.store(count);
+      return ASH_OK;
+    default:
+      return ASH_EINVAL;
+  }
+}
 
 const char* ash_strerror(int code) {
   switch (code) {

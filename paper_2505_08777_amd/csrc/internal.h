@@ -245,6 +245,11 @@ hipError_t launch_batch_update(int H, const HoloDesc* d, float power,
                                hipStream_t s);
 // Resident blocks per CU of the persistent kernels.
 int batch_blocks_per_cu(int G, bool reduce, bool forward);
+// Armed failure injections (ash_inject_failure): each call consumes one
+// armed failure of its kind if any is left and then returns true.
+bool injected_alloc_failure();
+bool injected_barrier_failure();
+
 // Fused adjoint and next forward (per-phase form, members of at most
 // kFusedSpots spots): units {holo, range, 0, 0} in 8 per-XCD queues like the
 // forward's; np_max is the largest padded spot count of the launch's

@@ -108,3 +108,99 @@ def test_error_codes_and_unchanged_state(A):
     assert torch.equal(E0, E1)
     _say("  last error:", L.ash_last_error(h).decode())
     c.close()
+
+
+def _small_set(A, nx, ny, N, seed):
+    rng = np.random.default_rng(seed)
+    w = rng.normal(0, 0.5, size=(N, 3))
+    w[:, 0] = np.pi * rng.uniform(-0.4 * ny, 0.4 * ny, N) * (min(nx, ny) / 2) / ny
+    w[:, 1] = np.pi * rng.uniform(-0.4 * nx, 0.4 * nx, N) * (min(nx, ny) / 2) / nx
+    amp = torch.tensor(rng.uniform(0.2, 1.0, size=(ny, nx)), dtype=torch.float32,
+                       device="cuda")
+    ph = torch.tensor(rng.uniform(-np.pi, np.pi, size=(ny, nx)),
+                      dtype=torch.float32, device="cuda")
+    return w, amp, ph
+
+
+def test_injected_allocation_failures(A):
+    """Device allocations made to fail (ash_inject_failure) return ASH_ENOMEM
+    from the set-up calls and from batch creation; the objects stay valid,
+    and repeating the calls gives bitwise the results of a context that
+    never failed."""
+    from paper_2505_08777_amd import _lib
+    nx, ny, modes = 96, 64, [1, 2, 4]
+    w, amp, ph = _small_set(A, nx, ny, 40, 11)
+    ref = A.Context(0)
+    ref.set_basis(nx, ny, modes=modes, amp=amp)
+    ref.set_spots(w)
+    E_ref = ref.forward(phase=ph).clone()
+    c = A.Context(0)
+    try:
+        A.inject_failure(A.INJECT_ALLOC, 1)
+        with pytest.raises(A.AshError) as ei:
+            c.set_basis(nx, ny, modes=modes, amp=amp)
+        assert ei.value.code == _lib.ENOMEM and "injected" in str(ei.value)
+        _say("  ", ei.value)
+        c.set_basis(nx, ny, modes=modes, amp=amp)
+        A.inject_failure(A.INJECT_ALLOC, 1)
+        with pytest.raises(A.AshError) as ei:
+            c.set_spots(w)
+        assert ei.value.code == _lib.ENOMEM
+        c.set_spots(w)
+        assert torch.equal(c.forward(phase=ph), E_ref)
+        A.inject_failure(A.INJECT_ALLOC, 1)
+        with pytest.raises(A.AshError) as ei:
+            A.Batch([c, ref])
+        assert ei.value.code == _lib.ENOMEM
+        b = A.Batch([c, ref])
+        b.set_form(False)  # per-hologram work units: equal members, equal bits
+        phs = [ph.clone(), ph.clone()]
+        b.wgs(phs, 2)
+        assert torch.equal(phs[0], phs[1])
+        b.close()
+    finally:
+        A.inject_failure(A.INJECT_ALLOC, 0)
+    c.close()
+    ref.close()
+
+
+def test_injected_barrier_failure(A):
+    """A one-launch batch call whose barriers give up (their error flag set
+    from the host before the launch, so nothing waits) returns ASH_EHIP
+    with the barrier's message; the batch stays usable, and its next call
+    equals bitwise a batch that never failed."""
+    from paper_2505_08777_amd import _lib
+    sizes = [(96, 64, 40, 21), (64, 64, 7, 22), (128, 96, 90, 23)]
+    ctxs, starts = [], []
+    for nx, ny, N, seed in sizes:
+        w, amp, ph = _small_set(A, nx, ny, N, seed)
+        c = A.Context(0)
+        c.set_basis(nx, ny, modes=[1, 2, 4], amp=amp)
+        c.set_spots(w)
+        ctxs.append(c)
+        starts.append(ph)
+    clean = A.Batch(ctxs)
+    clean.set_form(True)
+    ph_c = [p.clone() for p in starts]
+    W_c = [torch.ones(n, device="cuda") for _, _, n, _ in sizes]
+    clean.wgs(ph_c, 3, weights=W_c)
+    b = A.Batch(ctxs)
+    b.set_form(True)
+    try:
+        A.inject_failure(A.INJECT_BARRIER, 1)
+        with pytest.raises(A.AshError) as ei:
+            b.wgs([p.clone() for p in starts], 3,
+                  weights=[torch.ones(n, device="cuda") for _, _, n, _ in sizes])
+        assert ei.value.code == _lib.EHIP and "barrier" in str(ei.value)
+        _say("  ", ei.value)
+    finally:
+        A.inject_failure(A.INJECT_BARRIER, 0)
+    ph_b = [p.clone() for p in starts]
+    W_b = [torch.ones(n, device="cuda") for _, _, n, _ in sizes]
+    b.wgs(ph_b, 3, weights=W_b)
+    for x, y in zip(ph_b + W_b, ph_c + W_c):
+        assert torch.equal(x, y)
+    b.close()
+    clean.close()
+    for c in ctxs:
+        c.close()
