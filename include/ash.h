@@ -188,6 +188,19 @@ int ash_principal_modes(int N, int D, int n_mono, const int32_t* mono_pow,
                         int* D_out, double* sigma, double* mono_out,
                         double* w_out);
 
+/* Checks of the ash_set_basis / ash_set_spots arguments without a context
+ * or device (host-only code, also built without HIP): the code, and in
+ * *detail (static storage, may be NULL) the message, that those calls
+ * return for the same arguments before they touch the device (the source
+ * amplitude, read from the device, and the spots' phase bound, computed
+ * there, are checked by the calls themselves).  ASH_OK, ASH_EINVAL or
+ * ASH_EUNSUPPORTED. */
+int ash_check_basis(int nx, int ny, double cx, double cy, double R, int D,
+                    int n_mono, const int32_t* mono_pow,
+                    const double* mono_coef, const char** detail);
+int ash_check_spots(int N, int D, const double* w, const float* target,
+                    const char** detail);
+
 /* Define the SLM and the basis.
  *   nx, ny     SLM size in pixels (1 .. ASH_MAX_SIDE).
  *   cx, cy, R  pupil centre (pixels) and unit radius (pixels, > 0).

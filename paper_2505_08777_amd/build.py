@@ -15,7 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libash.so")
 
-SOURCES = ["host.cpp", "batch.cpp", "principal.cpp", "kernels.hip"]
+SOURCES = ["host.cpp", "validate.cpp", "batch.cpp", "principal.cpp",
+           "kernels.hip"]
 # the issue-rate microbenchmarks behind the transforms' issue ceiling
 UBENCH_SOURCES = ["ubench.hip"]
 UBENCH_LIB = os.path.join(PKG, "libash_ubench.so")

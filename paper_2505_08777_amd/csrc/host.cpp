@@ -427,27 +427,12 @@ int ash_set_basis(ash_ctx* c, int nx, int ny, double cx, double cy, double R,
                   const double* mono_coef, const float* amp_dev) {
   if (!c) return ASH_EINVAL;
   c->err.clear();
-  if (nx < 1 || ny < 1 || nx > ASH_MAX_SIDE || ny > ASH_MAX_SIDE)
-    return fail(c, nx < 1 || ny < 1 ? ASH_EINVAL : ASH_EUNSUPPORTED,
-                "nx, ny out of range");
-  if (!isfinite(cx) || !isfinite(cy) || !isfinite(R) || !(R > 0.0))
-    return fail(c, ASH_EINVAL, "cx, cy must be finite and R > 0");
-  if (D < 1 || n_mono < 1 || !mono_pow || !mono_coef)
-    return fail(c, ASH_EINVAL, "D, n_mono must be >= 1, tables non-null");
-  if (D > ASH_MAX_MODES || n_mono > ASH_MAX_MONOMIALS)
-    return fail(c, ASH_EUNSUPPORTED, "too many modes or monomials");
-  for (int k = 0; k < n_mono; ++k) {
-    const int p = mono_pow[2 * k], q = mono_pow[2 * k + 1];
-    if (p < 0 || q < 0) return fail(c, ASH_EINVAL, "negative exponent");
-    if (p + q > ASH_MAX_DEGREE)
-      return fail(c, ASH_EUNSUPPORTED, "monomial degree too high");
-    for (int k2 = 0; k2 < k; ++k2)
-      if (mono_pow[2 * k2] == p && mono_pow[2 * k2 + 1] == q)
-        return fail(c, ASH_EINVAL, "repeated monomial");
+  {
+    const char* why = "";
+    const int rc0 = ash_check_basis(nx, ny, cx, cy, R, D, n_mono, mono_pow,
+                                    mono_coef, &why);
+    if (rc0) return fail(c, rc0, why);
   }
-  for (long k = 0; k < (long)D * n_mono; ++k)
-    if (!isfinite(mono_coef[k]))
-      return fail(c, ASH_EINVAL, "non-finite basis coefficient");
 
   Basis b;
   Geom& g = b.g;
@@ -597,22 +582,18 @@ int ash_set_spots(ash_ctx* c, int N, const double* w_host,
   if (!c) return ASH_EINVAL;
   c->err.clear();
   if (!c->has_basis) return fail(c, ASH_ENOTREADY, "set the basis first");
-  if (N < 1 || !w_host) return fail(c, ASH_EINVAL, "N >= 1 and w required");
-  if (N > ASH_MAX_SPOTS) return fail(c, ASH_EUNSUPPORTED, "too many spots");
   Geom& g = c->basis.g;
+  const char* why = "";
+  int rc = ash_check_spots(N, g.D, w_host, target_host, &why);
+  if (rc) return fail(c, rc, why);
   const size_t nw = (size_t)N * g.D;
-  for (size_t k = 0; k < nw; ++k)
-    if (!isfinite(w_host[k]))
-      return fail(c, ASH_EINVAL, "non-finite spot coefficient");
   std::vector<float> t(N, 1.0f);
   double tn2 = 0.0;
   for (int k = 0; k < N; ++k) {
     if (target_host) t[k] = target_host[k];
-    if (!isfinite(t[k]) || !(t[k] > 0.0f))
-      return fail(c, ASH_EINVAL, "targets must be finite and > 0");
     tn2 += (double)t[k] * t[k];
   }
-  int rc = use_device(c);
+  rc = use_device(c);
   if (rc) return rc;
   c->has_spots = false;
   Buffers& B = c->buf;

@@ -110,6 +110,86 @@ def test_null_context_and_arguments():
     assert lib.ash_version() >= 100
 
 
+def _check_basis(nx, ny, cx, cy, R, D, pw, cf):
+    lib = _lib.lib
+    lib.ash_check_basis.restype = ctypes.c_int
+    lib.ash_check_basis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_char_p)]
+    why = ctypes.c_char_p()
+    n_mono = 0 if pw is None else pw.shape[0]
+    rc = lib.ash_check_basis(nx, ny, cx, cy, R, D, n_mono,
+                             None if pw is None else pw.ctypes.data,
+                             None if cf is None else cf.ctypes.data,
+                             ctypes.byref(why))
+    return rc, why.value.decode()
+
+
+def _check_spots(N, D, w, t):
+    lib = _lib.lib
+    lib.ash_check_spots.restype = ctypes.c_int
+    lib.ash_check_spots.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_char_p)]
+    why = ctypes.c_char_p()
+    rc = lib.ash_check_spots(N, D, None if w is None else w.ctypes.data,
+                             None if t is None else t.ctypes.data,
+                             ctypes.byref(why))
+    return rc, why.value.decode()
+
+
+def test_setup_argument_checks_without_a_device():
+    """ash_check_basis / ash_check_spots (the checks ash_set_basis and
+    ash_set_spots run first) return every documented code on the CPU."""
+    pw, cf = zernike_table_np([1, 2, 4])
+    assert _check_basis(64, 48, 32.0, 24.0, 24.0, 3, pw, cf) == (_lib.OK, "")
+    bad = [
+        ((0, 48, 32.0, 24.0, 24.0, 3, pw, cf), _lib.EINVAL, "out of range"),
+        ((70000, 48, 32.0, 24.0, 24.0, 3, pw, cf), _lib.EUNSUPPORTED, "out of range"),
+        ((64, 48, 32.0, 24.0, 0.0, 3, pw, cf), _lib.EINVAL, "R > 0"),
+        ((64, 48, float("nan"), 24.0, 24.0, 3, pw, cf), _lib.EINVAL, "finite"),
+        ((64, 48, 32.0, 24.0, 24.0, 3, None, cf), _lib.EINVAL, "non-null"),
+        ((64, 48, 32.0, 24.0, 24.0, 0, pw, cf), _lib.EINVAL, "D, n_mono"),
+        ((64, 48, 32.0, 24.0, 24.0, 40, pw, np.zeros((40, pw.shape[0]))),
+         _lib.EUNSUPPORTED, "too many"),
+    ]
+    neg = pw.copy()
+    neg[1, 0] = -1
+    bad.append(((64, 48, 32.0, 24.0, 24.0, 3, neg, cf), _lib.EINVAL, "negative"))
+    rep = pw.copy()
+    rep[1] = rep[0]
+    bad.append(((64, 48, 32.0, 24.0, 24.0, 3, rep, cf), _lib.EINVAL, "repeated"))
+    high = np.array([[13, 0]], np.int32)
+    bad.append(((64, 48, 32.0, 24.0, 24.0, 1, high, np.ones((1, 1))),
+                _lib.EUNSUPPORTED, "degree"))
+    nan = cf.copy()
+    nan[2, 0] = np.nan
+    bad.append(((64, 48, 32.0, 24.0, 24.0, 3, pw, nan), _lib.EINVAL, "non-finite"))
+    for args, code, text in bad:
+        rc, why = _check_basis(*args)
+        assert rc == code and text in why, (args[:6], rc, why)
+    w = np.random.default_rng(1).normal(size=(5, 3))
+    t = np.ones(5, np.float32)
+    assert _check_spots(5, 3, w, t) == (_lib.OK, "")
+    assert _check_spots(5, 3, w, None) == (_lib.OK, "")
+    assert _check_spots(0, 3, w, t)[0] == _lib.EINVAL
+    assert _check_spots(5, 3, None, t)[0] == _lib.EINVAL
+    assert _check_spots(_lib.MAX_SPOTS + 1, 3, w, t)[0] == _lib.EUNSUPPORTED
+    wn = w.copy()
+    wn[4, 2] = np.inf
+    assert _check_spots(5, 3, wn, t) == (_lib.EINVAL, "non-finite spot coefficient")
+    for tv in (0.0, -1.0, np.nan):
+        tb = t.copy()
+        tb[3] = tv
+        assert _check_spots(5, 3, w, tb)[0] == _lib.EINVAL
+
+
+def zernike_table_np(modes):
+    from paper_2505_08777_amd.basis import zernike_table
+    pw, cf = zernike_table(modes)
+    return np.ascontiguousarray(pw, np.int32), np.ascontiguousarray(cf, np.float64)
+
+
 def test_create_without_gpu_reports_hip_error():
     import torch
     if torch.cuda.is_available():
