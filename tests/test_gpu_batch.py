@@ -375,6 +375,46 @@ def test_batch64small_fused(A):
         c.close()
 
 
+def test_fused_edges(A):
+    """Fused launches at their edges: a member of exactly 512 spots (the
+    largest the fused form takes, 40 KB of LDS per block), one spot, 33
+    spots (one spot into a second block), a range-reduced record shape and
+    an odd range length loaded from a table; three iterations of every
+    member against its own run."""
+    specs = [
+        (160, 96, 512, [1, 2, 3, 4, 5, 7, 12], 0.4, 1.0, False, None),
+        (64, 48, 1, [1, 2, 4], 0.3, 1.0, False, None),
+        (96, 80, 33, [1, 2, 3, 4, 5, 7, 12], 0.6, 1.0, False, None),
+        (48, 40, 70, [1, 2, 4, 7], 0.7, 9.0, False, None),
+    ]
+    holos = [_holo(s, 900 + i) for i, s in enumerate(specs)]
+    ctxs = [_ctx(A, h) for h in holos]
+    assert any(c.info()["range_reduce"] for c in ctxs)
+    b = A.Batch(ctxs)
+    b.set_form(False)
+    assert b.info()["fused"]
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "odd.txt")
+        with open(path, "w") as f:
+            for inf in (c.info() for c in ctxs):
+                f.write("%d %d 7 0.0\n" % (inf["groups"], inf["range_reduce"]))
+        b.load_tuning(path)
+    assert all(L == 8 for L in b.info()["range_blocks"])  # made even
+    ph_b = [_cu(h["phi"]) for h in holos]
+    W_b = [torch.ones(h["w"].shape[0], device="cuda") for h in holos]
+    b.wgs(ph_b, 3, weights=W_b)
+    torch.cuda.synchronize()
+    for h, c, pb, wb in zip(holos, ctxs, ph_b, W_b):
+        ph = _cu(h["phi"])
+        _, W, E, _ = c.wgs(ph, 3)
+        err = _batch_vs_alone(c, h["t"], pb, wb, ph, W, E, "fused edge", 3)
+        _say("  %dx%d, %d spots: phase, weights" % (h["nx"], h["ny"], h["w"].shape[0]), err)
+    b.close()
+    for c in ctxs:
+        c.close()
+
+
 def test_batch64_uses_phase_launches(A):
     """Members with more spots than the one-launch form holds run as one
     launch per phase (the batch64 test covers their results)."""
