@@ -458,11 +458,13 @@ int ash_get_info(const ash_ctx* ctx, ash_info* out);
  * launches): one cooperative launch per record shape runs every iteration
  * of its holograms.  Each resident block owns a contiguous range of one
  * hologram's 32-pixel blocks (the blocks shared out over the holograms in
- * proportion to their work) and, per iteration, adds up its range's
- * forward sums, meets the hologram's other blocks at a barrier (a counter
- * per hologram), computes the whole hologram's weight update from all
- * blocks' sums, and runs the adjoint of its range.  Its pixel blocks per
- * forward unit (chunk) and resident blocks per CU are tuned.
+ * proportion to their work, in pairs) and, per iteration, runs fused rows
+ * over its range (the adjoint of the last spot fields and the forward of
+ * the new phases, its four waves taking pairs of pixel blocks), meets the
+ * hologram's other blocks at a barrier (a counter per hologram), and
+ * computes the whole hologram's weight update from all blocks' sums; a
+ * last pass of adjoint rows writes the phase.  Its resident blocks per CU
+ * are tuned.
  *
  * Launches per phase (any members): each phase of an iteration is one
  * persistent launch over the work items of all holograms of a record
@@ -528,12 +530,12 @@ int ash_batch_wgs(ash_batch* batch, float* const* phase_dev,
  * plus its reduction for range lengths of 16, 32, 64, 128, 256 and 512
  * pixel blocks (fused: an adjoint-and-forward launch for 4, 8, 16, 32, 64
  * and 128) and keeps the fastest; when the one-launch form is possible,
- * times two iterations of it for chunks of 4, 8, 16 and 32 pixel blocks and
- * 1 up to the most resident blocks per CU that fit, keeps the fastest, times
+ * times two iterations of it for 1 up to the most resident blocks per CU
+ * that fit, keeps the fastest, times
  * two iterations of the per-phase form, and selects the faster form.  The
  * timed iterations run on copies of the phases (the caller's are left
  * untouched).  The table written to table_out (if not NULL) holds lines
- * "groups range_reduce range_blocks ms", "persist groups range_reduce chunk
+ * "groups range_reduce range_blocks ms", "one_launch groups range_reduce
  * blocks_per_cu ms_per_iteration" and "form one_launch ms_per_iteration".
  * Errors: ASH_EINVAL (null phases, unwritable file), ASH_ENOTREADY,
  * ASH_ENOMEM, ASH_EHIP. */
@@ -559,7 +561,6 @@ typedef struct ash_batch_info {
                                forward + adjoint, or fused units          */
   double evals_per_transform;  /* sum over holograms of N * P              */
   int32_t one_launch;       /* 1: the one-launch form (see ash_batch_wgs)  */
-  int32_t chunk[4];         /* its pixel blocks per forward unit, per shape*/
   int32_t blocks_per_cu[4]; /* its resident blocks per CU (grid / CUs)     */
   int32_t grid[4];          /* its blocks per launch                       */
   int32_t fused;            /* 1: per-phase iterations fuse the adjoint

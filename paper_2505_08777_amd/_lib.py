@@ -61,7 +61,6 @@ class BatchInfo(ctypes.Structure):
                 ("items", ctypes.c_int64),
                 ("evals_per_transform", ctypes.c_double),
                 ("one_launch", ctypes.c_int32),
-                ("chunk", ctypes.c_int32 * 4),
                 ("blocks_per_cu", ctypes.c_int32 * 4),
                 ("grid", ctypes.c_int32 * 4),
                 ("fused", ctypes.c_int32)]

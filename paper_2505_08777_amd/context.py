@@ -544,7 +544,6 @@ class Batch:
                 "items": out.items,
                 "evals_per_transform": out.evals_per_transform,
                 "one_launch": bool(out.one_launch),
-                "chunk": list(out.chunk)[:min(n, 4)],
                 "blocks_per_cu": list(out.blocks_per_cu)[:min(n, 4)],
                 "grid": list(out.grid)[:min(n, 4)],
                 "fused": bool(out.fused)}

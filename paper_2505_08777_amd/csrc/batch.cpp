@@ -28,10 +28,7 @@ constexpr int kTuneCandidates[] = {16, 32, 64, 128, 256, 512};
 // (one of B blocks takes about 1/B of it), untuned and the candidates.
 constexpr int kDefaultFusedRange = 16;
 constexpr int kFusedCandidates[] = {4, 8, 16, 32, 64, 128};
-// One-launch form: pixel blocks per forward unit (untuned), the candidates
-// of the tuner, and the iterations it times per candidate.
-constexpr int kDefaultChunk = 8;
-constexpr int kChunkCandidates[] = {4, 8, 16, 32};
+// One-launch form: the iterations the tuner times per candidate.
 constexpr int kPersistTuneIters = 2;
 // Relative cost of a pixel block's adjoint epilogue (butterfly over the
 // spots, arg g, next nearfield record) in 32 x 32 evaluation blocks.
@@ -48,7 +45,6 @@ struct Cls {
   int fwd_grid = 0, adj_grid = 0, fus_grid = 0;
   int np_max = 32;  // largest padded spot count of its holograms
   // one-launch form
-  int chunk = kDefaultChunk;  // pixel blocks per forward unit
   int bpc = 0;                // resident blocks per CU (0: as many as fit)
   int p_grid = 0;             // blocks of its launch
   size_t p_lds = 0;           // dynamic LDS per block
@@ -228,7 +224,8 @@ int plan_persist(ash_batch* b) {
   for (auto& c : b->cls) {
     int maxN = 1;
     for (int h : c.holos) maxN = std::max(maxN, b->m[h]->spots.N);
-    c.p_lds = persist_lds_bytes(maxN);
+    c.np_max = std::max(32, (maxN + 31) / 32 * 32);
+    c.p_lds = persist_lds_bytes(c.np_max);
     int occ = persist_blocks_per_cu(c.G, c.reduce != 0, c.p_lds);
     if (occ <= 0) return bfail(b, ASH_EUNSUPPORTED, "no resident block fits");
     if (c.bpc > 0) occ = std::min(occ, c.bpc);
@@ -245,13 +242,14 @@ int plan_persist(ash_batch* b) {
     const int Hc = (int)c.holos.size();
     if (Hc > c.p_grid)
       return bfail(b, ASH_EUNSUPPORTED, "more holograms than resident blocks");
-    // blocks per hologram: at least one, at most one per pixel block, the
-    // rest by largest remainder of the proportional share
+    // blocks per hologram: at least one, at most one per pair of pixel
+    // blocks (the fused rows take them in pairs), the rest by largest
+    // remainder of the proportional share
     std::vector<long> nb(Hc, 1);
     std::vector<std::pair<double, int>> rem;
     long given = Hc;
     for (int i = 0; i < Hc; ++i) {
-      const long cap = (long)b->m[c.holos[i]]->basis.g.n_tiles * kBlkPerTile;
+      const long cap = (long)b->m[c.holos[i]]->basis.g.n_tiles * kBlkPerTile / 2;
       const double share = (double)(c.p_grid - Hc) * work[i] / total;
       const long extra = std::min(cap - 1, (long)floor(share));
       nb[i] += extra;
@@ -264,7 +262,7 @@ int plan_persist(ash_batch* b) {
     });
     for (size_t r = 0; r < rem.size() && given < c.p_grid; ++r) {
       const int i = rem[r].second;
-      const long cap = (long)b->m[c.holos[i]]->basis.g.n_tiles * kBlkPerTile;
+      const long cap = (long)b->m[c.holos[i]]->basis.g.n_tiles * kBlkPerTile / 2;
       if (nb[i] < cap) {
         ++nb[i];
         ++given;
@@ -280,7 +278,6 @@ int plan_persist(ash_batch* b) {
       Buffers& B = m->buf;
       PHolo d;
       d.pixtab = reinterpret_cast<const u32x4*>(B.pixtab);
-      d.nf_t = B.field_t;
       d.spotrec = reinterpret_cast<const u32x4*>(B.spotrec);
       d.offtab = B.offtab;
       d.amp_t = B.amp_t;
@@ -301,12 +298,13 @@ int plan_persist(ash_batch* b) {
       d.ctr = reinterpret_cast<int*>((size_t)b->pholo.size() * kCtrPad);
       rows += (size_t)2 * nb[i] * d.N;
       yblk += (size_t)nb[i] * NP * 9;
+      const long pairs = d.n_blk / 2;  // n_blk is a whole number of tiles
       for (long j = 0; j < nb[i]; ++j) {
         PBlock pb;
         pb.holo = i;
         pb.j = (int)j;
-        pb.b0 = d.n_blk * j / nb[i];
-        pb.b1 = d.n_blk * (j + 1) / nb[i];
+        pb.b0 = 2 * (pairs * j / nb[i]);
+        pb.b1 = 2 * (pairs * (j + 1) / nb[i]);
         b->pblk.push_back(pb);
       }
       b->pholo.push_back(d);
@@ -661,7 +659,7 @@ int run_persist(ash_batch* b, int n_iter, float power) {
            return launch_batch_persist(c.G, c.reduce != 0, c.p_grid, c.p_lds,
                                        b->d_pholo + c.p_holo,
                                        b->d_pblk + c.p_blk, n_iter, power,
-                                       c.chunk, err, b->stream);
+                                       c.np_max, err, b->stream);
          }), "batch launch");
   }
   int flag = 0;
@@ -675,8 +673,8 @@ int run_persist(ash_batch* b, int n_iter, float power) {
   return ASH_OK;
 }
 
-// Tuner of the one-launch form: per record shape, every (chunk, resident
-// blocks per CU) pair times one launch of kPersistTuneIters iterations on
+// Tuner of the one-launch form: per record shape, every count of resident
+// blocks per CU times one launch of kPersistTuneIters iterations on
 // copies of the caller's phases (unit weights), and the fastest is kept.
 int tune_persist(ash_batch* b, float* const* phase_dev,
                  std::vector<float>* best_ms) {
@@ -713,11 +711,10 @@ int tune_persist(ash_batch* b, float* const* phase_dev,
     Cls& c = b->cls[k];
     const int max_bpc = persist_blocks_per_cu(
         c.G, c.reduce != 0, c.p_lds ? c.p_lds : persist_lds_bytes(kPersistSpots));
-    int best_chunk = c.chunk, best_bpc = c.bpc;
+    int best_bpc = c.bpc;
     float best_t = -1.0f;
-    for (int chunk : kChunkCandidates) {
+    {
       for (int bpc = 1; bpc <= max_bpc && !rc; ++bpc) {
-        c.chunk = chunk;
         c.bpc = bpc;
         if ((rc = plan_persist(b))) break;
         if ((rc = upload_persist(b, ph.data(), W.data()))) break;
@@ -739,7 +736,7 @@ int tune_persist(ash_batch* b, float* const* phase_dev,
             hipEventRecord(e0, b->stream) != hipSuccess ||
             launch_batch_persist(c.G, c.reduce != 0, c.p_grid, c.p_lds,
                                  b->d_pholo + c.p_holo, b->d_pblk + c.p_blk,
-                                 kPersistTuneIters, 1.0f, c.chunk, err,
+                                 kPersistTuneIters, 1.0f, c.np_max, err,
                                  b->stream) != hipSuccess ||
             hipEventRecord(e1, b->stream) != hipSuccess ||
             hipEventSynchronize(e1) != hipSuccess ||
@@ -756,13 +753,10 @@ int tune_persist(ash_batch* b, float* const* phase_dev,
         }
         if (best_t < 0.0f || ms < best_t) {
           best_t = ms;
-          best_chunk = chunk;
           best_bpc = bpc;
         }
       }
-      if (rc) break;
     }
-    c.chunk = best_chunk;
     c.bpc = best_bpc;
     (*best_ms)[k] = best_t / kPersistTuneIters;
   }
@@ -1000,8 +994,8 @@ int ash_batch_tune(ash_batch* b, float* const* phase_dev,
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (!rc) rc = plan(b);
-  // the one-launch form: its chunk and blocks per CU, then the faster of
-  // the two forms
+  // the one-launch form: its blocks per CU, then the faster of the two
+  // forms
   std::vector<float> pms;
   if (!rc && b->persist) {
     rc = tune_persist(b, phase_dev, &pms);
@@ -1018,11 +1012,11 @@ int ash_batch_tune(ash_batch* b, float* const* phase_dev,
       fprintf(f, "%d %d %d %.4f\n", b->cls[k].G, b->cls[k].reduce,
               b->cls[k].L, best_ms[k]);
     if (b->persist) {
-      fprintf(f, "# persist groups range_reduce chunk blocks_per_cu "
+      fprintf(f, "# one_launch groups range_reduce blocks_per_cu "
                  "ms_per_iteration\n");
       for (size_t k = 0; k < b->cls.size(); ++k)
-        fprintf(f, "persist %d %d %d %d %.4f\n", b->cls[k].G,
-                b->cls[k].reduce, b->cls[k].chunk, b->cls[k].bpc, pms[k]);
+        fprintf(f, "one_launch %d %d %d %.4f\n", b->cls[k].G,
+                b->cls[k].reduce, b->cls[k].bpc, pms[k]);
       fprintf(f, "# form (1: one launch, 0: launches per phase), "
                  "ms_per_iteration of the launches per phase\n");
       fprintf(f, "form %d %.4f\n", b->one_launch ? 1 : 0, pms.back());
@@ -1046,11 +1040,10 @@ int ash_batch_load_tuning(ash_batch* b, const char* table_in) {
       b->one_launch = b->persist && L == 1;
       continue;
     }
-    if (sscanf(line, "persist %d %d %d %d", &G, &red, &L, &bpc) == 4) {
-      if (L < 1 || L > (1 << 20) || bpc < 0 || bpc > 64) continue;
+    if (sscanf(line, "one_launch %d %d %d", &G, &red, &bpc) == 3) {
+      if (bpc < 0 || bpc > 64) continue;
       for (auto& c : b->cls)
         if (c.G == G && c.reduce == red) {
-          c.chunk = L;
           c.bpc = bpc;
           ++n_set;
         }
@@ -1095,7 +1088,6 @@ int ash_batch_get_info(const ash_batch* b, ash_batch_info* out) {
   out->one_launch = b->one_launch ? 1 : 0;
   out->fused = b->fused ? 1 : 0;
   for (size_t k = 0; k < b->cls.size() && k < 4; ++k) {
-    out->chunk[k] = b->cls[k].chunk;
     out->blocks_per_cu[k] = b->one_launch ? b->cls[k].p_grid / b->n_cu : 0;
     out->grid[k] = b->one_launch ? b->cls[k].p_grid : 0;
   }

@@ -265,16 +265,16 @@ int fused_blocks_per_cu(int G, bool reduce, int np_max);
 
 // ---- batched form in one launch (holograms of at most kPersistSpots) ----
 // Every block owns a contiguous range of one hologram's 32-pixel blocks and
-// runs all iterations: the forward over its range (partial sums per block),
-// a barrier with the hologram's other blocks, the weight update of the
+// runs all iterations: fused rows over its range (the adjoint of the last
+// spot fields, then the forward of the new phases, partial sums per block),
+// a barrier with the hologram's other blocks, and the weight update of the
 // whole hologram from all blocks' partial sums (every block computes it,
-// the same way, so no second barrier is needed), and the adjoint of its
-// range.
+// the same way, so no second barrier is needed).  After the last update a
+// pass of adjoint rows writes the phase.
 constexpr int kPersistSpots = 512;
 
 struct PHolo {
   const u32x4* pixtab;
-  unsigned* nf_t;          // nearfield records (built from `phase` first)
   const u32x4* spotrec;
   const unsigned* offtab;
   const float* amp_t;
@@ -293,12 +293,14 @@ struct PBlock {
   int holo, j;
   long b0, b1;
 };
-// Units of a block's forward: (chunk of `chunk` pixel blocks, spot block),
-// taken by its waves in turn.  `err` is set when a barrier waits longer
-// than its time limit (then every block leaves the loop).
+// Each block's pixel-block range (an even number of pixel blocks) is split
+// over its four waves in pairs; every iteration is one pass of fused rows
+// (adjoint of the last fields, forward of the new phases).  `np_max` is the
+// batch's largest spot count rounded up to 32.  `err` is set when a barrier
+// waits longer than its time limit (then every block leaves the loop).
 hipError_t launch_batch_persist(int G, bool reduce, int grid, size_t lds,
                                 const PHolo* hd, const PBlock* blks,
-                                int n_iter, float power, int chunk, int* err,
+                                int n_iter, float power, int np_max, int* err,
                                 hipStream_t s);
 // Resident blocks per CU of the persistent kernel with `lds` bytes of
 // dynamic LDS, and its LDS need for N spots.

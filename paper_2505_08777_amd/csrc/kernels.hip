@@ -755,7 +755,7 @@ __device__ __forceinline__ void accumulate(const floatx16& th, float m,
 // lane half its part of the nearfield record's last group, another the
 // magnitude of the lane's pixel (the same for both halves).
 // E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))).
-template <int G, bool kReduce, bool kAdd = false>
+template <int G, bool kReduce>
 __device__ __forceinline__ void forward_range(
     int N, int mb, long b0, long b1, const GLOBAL u32x4* __restrict__ pixtab,
     const GLOBAL u32x4* __restrict__ nf, const GLOBAL float* __restrict__ mag,
@@ -813,14 +813,7 @@ __device__ __forceinline__ void forward_range(
   }
   bfly_reduce(er, ei, q);
   const int ko = mb * 32 + mfma_row(bfly_index(q), h);
-  if ((q & 1) == 0 && ko < N) {
-    if (kAdd) {  // the wave's own running sums (each spot one lane)
-      const float2 o = row[ko];
-      row[ko] = make_float2(o.x + er[0], o.y + ei[0]);
-    } else {
-      row[ko] = make_float2(er[0], ei[0]);
-    }
-  }
+  if ((q & 1) == 0 && ko < N) row[ko] = make_float2(er[0], ei[0]);
 }
 
 // Forward of one hologram: wave = 32 spots x a contiguous range of pixel
@@ -2358,8 +2351,9 @@ constexpr unsigned long long kBarrierTicks = 1000000000ull;  // 10 s at 100 MHz
 size_t persist_lds_bytes(int N) {
   const int NP = (N + 31) / 32 * 32;
   // per-wave forward sums [4][NP] float2 (reused for the fields E in the
-  // update) and the weights [NP]
-  return (size_t)NP * (4 * 8 + 4);
+  // update), the weights [NP], and each wave's fused-range LDS
+  return (size_t)NP * (4 * 8 + 4) +
+         (size_t)(kBlock / kWave) * fused_lds_floats(NP) * 4;
 }
 
 // Wait until the counter reaches `target` (thread 0); false on error.
@@ -2392,10 +2386,18 @@ __device__ __forceinline__ bool persist_barrier(int* ctr, int target,
   return ok != 0;
 }
 
+// Waves per SIMD the register allocator must allow: left to itself it gives
+// the one-launch kernel a few more registers than the fused launch's (the
+// iteration loop keeps the block's state live) and lands one occupancy step
+// lower.  At these targets G = 1, 2, 4 and 5 fit without spills; G = 3 and G = 6 spill
+// a few values of the per-iteration set-up, outside the range loops.
+constexpr int persist_waves(int G) { return G <= 3 ? 4 : G <= 6 ? 3 : 1; }
+
 template <int G, bool kReduce>
-__global__ __launch_bounds__(kBlock) void k_batch_persist(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(persist_waves(G)))) void k_batch_persist(
     const PHolo* __restrict__ hd, const PBlock* __restrict__ blks, int n_iter,
-    float power, int chunk, int* __restrict__ err) {
+    float power, int np_max, int* __restrict__ err) {
   extern __shared__ float lds[];
   __shared__ float sh[4 * kBlock / kWave];
   const int bi = blockIdx.x;
@@ -2403,14 +2405,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_persist(
   const int j = __builtin_amdgcn_readfirstlane(blks[bi].j);
   const long b0 = blks[bi].b0, b1 = blks[bi].b1;
   const PHolo& d = hd[holo];
-  const int N = d.N, NP = (N + 31) / 32 * 32, n_mb = NP / 32;
+  const int N = d.N, NP = (N + 31) / 32 * 32;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   float2* wrow = reinterpret_cast<float2*>(lds);  // [4][NP]
   float* Ws = lds + 8 * NP;                         // [NP]
+  // each wave's fused-range LDS (spot magnitudes, running forward sums)
+  float* const fl = lds + 9 * np_max + (long)wave * fused_lds_floats(np_max);
   unsigned* yb = d.yblk + (long)j * NP * 9;
-  // the block's weights, its spot-field records past N (zero) and the
-  // nearfield records of its pixels from the start phase
+  // the block's weights and its spot-field records past N (zero)
   for (int k = tid; k < N; k += kBlock) Ws[k] = d.W[k];
   for (int k = N + tid; k < NP; k += kBlock) {
     u32x4* y4 = reinterpret_cast<u32x4*>(yb) + (long)(k / 32) * 64 + k % 32;
@@ -2418,30 +2421,32 @@ __global__ __launch_bounds__(kBlock) void k_batch_persist(
     y4[32] = u32x4{0u, 0u, 0u, 0u};
     reinterpret_cast<float*>(yb)[(long)NP * 8 + k] = 0.0f;
   }
-  for (long gid = b0 * 32 + tid; gid < b1 * 32; gid += kBlock)
-    make_field_at(d.nx, d.ny, d.tiles_x, G, gid, d.phase, nullptr, d.amp_t,
-                  d.pixtab, reinterpret_cast<u32x4*>(d.nf_t), nullptr);
   __threadfence_block();
   __syncthreads();
-  const long rows = b1 - b0;
-  const long n_chunks = (rows + chunk - 1) / chunk;
-  for (int it = 0; it < n_iter; ++it) {
-    // forward: units (chunk, spot block) in turn over the four waves; each
-    // wave adds its units' sums into its own row
-    for (int k = tid; k < 4 * NP; k += kBlock) wrow[k] = make_float2(0.f, 0.f);
-    __syncthreads();
-    for (long u = wave; u < n_chunks * n_mb; u += kBlock / kWave) {
-      const long c = u / n_mb;
-      const int mb = (int)(u - c * n_mb);
-      const long r0 = b0 + c * chunk;
-      const long r1 = r0 + chunk < b1 ? r0 + chunk : b1;
-      forward_range<G, kReduce, true>(
-          N, mb, r0, r1, as_global(d.pixtab),
-          as_global(reinterpret_cast<const u32x4*>(d.nf_t)),
-          as_global(d.amp_t), as_global(d.spotrec),
-          as_global(reinterpret_cast<const u32x4*>(d.offtab)),
-          wrow + (long)wave * NP);
+  // the wave's share of the block's pixel blocks, in whole pairs
+  const long pairs = (b1 - b0) / 2;
+  const long w0 = b0 + 2 * (pairs * wave / (kBlock / kWave));
+  const long w1 = b0 + 2 * (pairs * (wave + 1) / (kBlock / kWave));
+  float2* const my_row = wrow + (long)wave * NP;
+  const GLOBAL u32x4* const ycur = as_global(reinterpret_cast<const u32x4*>(yb));
+  for (int it = 0; it <= n_iter; ++it) {
+    // fused ranges over the wave's pixel blocks: the forward of the start
+    // phases; then each iteration's adjoint with the next forward; after
+    // the last update the adjoint alone, which writes the phases
+#define FUSED_ARGS                                                         \
+  N, d.nx, d.ny, d.tiles_x, d.phase, w0, w1, as_global(d.pixtab),          \
+      as_global(d.spotrec),                                                \
+      as_global(reinterpret_cast<const u32x4*>(d.offtab)), ycur,           \
+      as_global(d.amp_t), fl, reinterpret_cast<float2*>(fl + np_max), my_row
+    if (it == n_iter) {
+      fused_range<G, kReduce, kFusedLast>(FUSED_ARGS);
+      break;
     }
+    if (it == 0)
+      fused_range<G, kReduce, kFusedFirst>(FUSED_ARGS);
+    else
+      fused_range<G, kReduce, kFusedMid>(FUSED_ARGS);
+#undef FUSED_ARGS
     __syncthreads();
     float2* rows_it = d.rows + (long)(it & 1) * d.n_blocks * N;
     for (int k = tid; k < N; k += kBlock) {  // the waves' sums in order
@@ -2461,22 +2466,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_persist(
                              nullptr, nullptr, kPhaseFree);
     __threadfence_block();
     __syncthreads();
-    // adjoint of the block's pixel blocks: the next nearfield, or the
-    // phase after the last iteration
-    AdjOut o;
-    o.outs = it == n_iter - 1 ? kOutPhase : kOutField;
-    o.phase = d.phase;
-    o.nf_t = d.nf_t;
-    for (long b = b0 + wave; b < b1; b += kBlock / kWave)
-      adjoint_row<G, kReduce>(
-          N, d.nx, d.ny, d.tiles_x, (int)(b / kBlkPerTile),
-          (int)(b % kBlkPerTile) * 32, 0, as_global(d.pixtab),
-          as_global(d.spotrec),
-          as_global(reinterpret_cast<const u32x4*>(d.offtab)),
-          as_global(reinterpret_cast<const u32x4*>(yb)), as_global(d.amp_t),
-          o);
-    __threadfence_block();
-    __syncthreads();
   }
   if (j == 0)
     for (int k = tid; k < N; k += kBlock) d.W[k] = Ws[k];
@@ -2485,9 +2474,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_persist(
 template <int G, bool kReduce>
 static hipError_t bpersist_g(int grid, size_t lds, const PHolo* hd,
                              const PBlock* blks, int n_iter, float power,
-                             int chunk, int* err, hipStream_t s) {
+                             int np_max, int* err, hipStream_t s) {
   void* args[] = {(void*)&hd, (void*)&blks, (void*)&n_iter, (void*)&power,
-                  (void*)&chunk, (void*)&err};
+                  (void*)&np_max, (void*)&err};
   return hipLaunchCooperativeKernel(
       reinterpret_cast<const void*>(&k_batch_persist<G, kReduce>),
       dim3(grid), dim3(kBlock), args, (unsigned)lds, s);
@@ -2495,16 +2484,19 @@ static hipError_t bpersist_g(int grid, size_t lds, const PHolo* hd,
 
 hipError_t launch_batch_persist(int G, bool reduce, int grid, size_t lds,
                                 const PHolo* hd, const PBlock* blks,
-                                int n_iter, float power, int chunk, int* err,
+                                int n_iter, float power, int np_max, int* err,
                                 hipStream_t s) {
   if (grid <= 0) return hipSuccess;
+  if (n_iter < 1 || np_max < 32 || np_max > kPersistSpots || np_max % 32 ||
+      lds < persist_lds_bytes(np_max))
+    return hipErrorInvalidValue;
   switch (G) {
 #define X(n)                                                                \
   case n:                                                                   \
     return reduce ? bpersist_g<n, true>(grid, lds, hd, blks, n_iter, power, \
-                                        chunk, err, s)                      \
+                                        np_max, err, s)                     \
                   : bpersist_g<n, false>(grid, lds, hd, blks, n_iter, power,\
-                                         chunk, err, s);
+                                         np_max, err, s);
     ASH_G_CASES(X)
 #undef X
     default:
