@@ -908,9 +908,9 @@ def bench_batch(args, holos):
             if f[0] == "form":
                 forms["chosen"] = "one_launch" if f[1] == "1" else "per_phase"
                 forms["per_phase_ms_per_iteration"] = float(f[2])
-            if f[0] == "persist":
+            if f[0] == "one_launch":
                 forms.setdefault("one_launch_ms_per_iteration", 0.0)
-                forms["one_launch_ms_per_iteration"] += float(f[5])
+                forms["one_launch_ms_per_iteration"] += float(f[4])
     if args.form != "tuned":
         b.set_form(args.form == "one_launch")
     info = b.info()

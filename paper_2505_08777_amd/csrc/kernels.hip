@@ -795,19 +795,27 @@ __device__ __forceinline__ void forward_range(
     const rsrc_t rn = make_rsrc(nf + t * kBlkPerTile * 64,
                                 (unsigned long)kBlkPerTile * 64 * 16);
     const rsrc_t rm = make_rsrc(mag + t * kTile, (unsigned long)kTile * 4);
-    for (int r = r0; r < r1; ++r) {
-      u32x4 X[G];
+    // two register sets take turns: one block's products run while the
+    // next block's records load into the other set
+    u32x4 XA[G], XB[G];
+    float mA, mB;
+    auto load = [&](u32x4* X, float& m, int r) {
 #pragma unroll
       for (int g = 0; g < G - 1; ++g)
         X[g] = bload4(rx, off_pix, (unsigned)(g * 2 * kTile + r * 32) * 16u);
       X[G - 1] = bload4(rn, off_spot, (unsigned)r * 64u * 16u);
-      const float m = bload1f(rm, off_q, (unsigned)r * 32u * 4u);
-      // all of the block's loads go out before its products (left to
-      // itself the scheduler reuses a load's registers and waits on it
-      // between the products)
+      m = bload1f(rm, off_q, (unsigned)r * 32u * 4u);
+    };
+    load(XA, mA, r0);
+    for (int r = r0; r < r1; r += 2) {
+      load(XB, mB, min(r + 1, r1 - 1));
       __builtin_amdgcn_sched_barrier(0);
-      const floatx16 th = phase_block<G>(S, X);
-      accumulate<true, kReduce>(th, m, er, ei);
+      accumulate<true, kReduce>(phase_block<G>(S, XA), mA, er, ei);
+      if (r + 1 < r1) {
+        load(XA, mA, min(r + 2, r1 - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        accumulate<true, kReduce>(phase_block<G>(S, XB), mB, er, ei);
+      }
     }
     b += r1 - r0;
   }
