@@ -530,11 +530,12 @@ int ash_batch_wgs(ash_batch* batch, float* const* phase_dev,
  * plus its reduction for range lengths of 16, 32, 64, 128, 256 and 512
  * pixel blocks (fused: an adjoint-and-forward launch for 4, 8, 16, 32, 64
  * and 128) and keeps the fastest; when the one-launch form is possible,
- * times two iterations of it for 1 up to the most resident blocks per CU
- * that fit, keeps the fastest, times
- * two iterations of the per-phase form, and selects the faster form.  The
- * timed iterations run on copies of the phases (the caller's are left
- * untouched).  The table written to table_out (if not NULL) holds lines
+ * costs it for 1 up to the most resident blocks per CU that fit, keeps the
+ * cheapest, costs the per-phase form, and selects the cheaper form.  A
+ * form's cost is the time of one more iteration (runs of 2 and 6
+ * iterations, their time difference over 4), so that the first forward
+ * and last adjoint of a call do not weigh.  The timed iterations run on
+ * copies of the phases (the caller's are left untouched).  The table written to table_out (if not NULL) holds lines
  * "groups range_reduce range_blocks ms", "one_launch groups range_reduce
  * blocks_per_cu ms_per_iteration" and "form one_launch ms_per_iteration".
  * Errors: ASH_EINVAL (null phases, unwritable file), ASH_ENOTREADY,

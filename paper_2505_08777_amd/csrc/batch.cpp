@@ -28,8 +28,9 @@ constexpr int kTuneCandidates[] = {16, 32, 64, 128, 256, 512};
 // (one of B blocks takes about 1/B of it), untuned and the candidates.
 constexpr int kDefaultFusedRange = 16;
 constexpr int kFusedCandidates[] = {4, 8, 16, 32, 64, 128};
-// One-launch form: the iterations the tuner times per candidate.
-constexpr int kPersistTuneIters = 2;
+// The tuner's two run lengths (iterations) per one-launch candidate and
+// per form.
+constexpr int kTuneItersShort = 2, kTuneItersLong = 6;
 // Relative cost of a pixel block's adjoint epilogue (butterfly over the
 // spots, arg g, next nearfield record) in 32 x 32 evaluation blocks.
 constexpr double kEpilogueBlocks = 1.25;
@@ -95,6 +96,8 @@ struct ash_batch {
   float2* d_prows = nullptr;
   unsigned* d_pyblk = nullptr;
   int* d_pctr = nullptr;  // per member barrier counter, then the error flag
+  bool pholo_on_device = false;  // d_pholo holds pholo as it stands
+  int* h_flag = nullptr;         // pinned host copy of the error flag
   size_t cap_pholo = 0, cap_pblk = 0, cap_prows = 0, cap_pyblk = 0,
          cap_pctr = 0;
   // timing
@@ -218,6 +221,7 @@ std::vector<std::vector<int>> lpt(const std::vector<double>& work) {
 // counters.
 int plan_persist(ash_batch* b) {
   b->pholo.clear();
+  b->pholo_on_device = false;
   b->pblk.clear();
   b->pmember.clear();
   size_t rows = 0, yblk = 0;
@@ -632,21 +636,33 @@ int counters(ash_batch* b, size_t launches, int** out) {
 // Upload the one-launch descriptors with this call's phase and weight
 // pointers, and zero the barrier counters and the error flag.
 int upload_persist(ash_batch* b, float* const* phase, float* const* W) {
+  bool same = b->pholo_on_device;
   for (size_t i = 0; i < b->pholo.size(); ++i) {
     const int h = b->pmember[i];
+    same = same && b->pholo[i].phase == phase[h] && b->pholo[i].W == W[h];
     b->pholo[i].phase = phase[h];
     b->pholo[i].W = W[h];
   }
+  if (same) return ASH_OK;  // the last call's arrays: nothing to send
   BCHK(b, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   BCHK(b, hipMemcpy(b->d_pholo, b->pholo.data(),
                     b->pholo.size() * sizeof(PHolo), hipMemcpyHostToDevice),
        "uploading descriptors");
+  b->pholo_on_device = true;
   return ASH_OK;
 }
 
 // One launch per record shape runs all n_iter iterations of its holograms;
 // then the stream is synchronised and the barriers' error flag read.
 int run_persist(ash_batch* b, int n_iter, float power) {
+  if (!b->h_flag &&
+      (injected_alloc_failure() ||
+       hipHostMalloc(reinterpret_cast<void**>(&b->h_flag), sizeof(int),
+                     hipHostMallocDefault) != hipSuccess)) {
+    (void)hipGetLastError();
+    b->h_flag = nullptr;
+    return bfail(b, ASH_ENOMEM, "out of pinned host memory for the flag");
+  }
   const size_t n_ctr = (b->pholo.size() + 1) * kCtrPad;
   int* err = b->d_pctr + b->pholo.size() * kCtrPad;
   BCHK(b, hipMemsetAsync(b->d_pctr, 0, n_ctr * sizeof(int), b->stream),
@@ -662,11 +678,10 @@ int run_persist(ash_batch* b, int n_iter, float power) {
                                        c.np_max, err, b->stream);
          }), "batch launch");
   }
-  int flag = 0;
-  BCHK(b, hipMemcpyAsync(&flag, err, sizeof(int), hipMemcpyDeviceToHost,
+  BCHK(b, hipMemcpyAsync(b->h_flag, err, sizeof(int), hipMemcpyDeviceToHost,
                          b->stream), "reading the barrier flag");
   BCHK(b, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-  if (flag)
+  if (*b->h_flag)
     return bfail(b, ASH_EHIP, "a barrier of the one-launch batch gave up "
                               "(its time limit, or an injected failure); "
                               "results are incomplete");
@@ -674,8 +689,12 @@ int run_persist(ash_batch* b, int n_iter, float power) {
 }
 
 // Tuner of the one-launch form: per record shape, every count of resident
-// blocks per CU times one launch of kPersistTuneIters iterations on
-// copies of the caller's phases (unit weights), and the fastest is kept.
+// blocks per CU is timed on copies of the caller's phases (unit weights),
+// and the cheapest kept; then the launches per phase are timed the same
+// way and the cheaper form is kept.  A cost is the time of one more
+// iteration: the difference of runs of kTuneItersShort and kTuneItersLong
+// iterations over their difference, so that the first forward and the
+// last adjoint, which both forms add once per call, weigh nothing.
 int tune_persist(ash_batch* b, float* const* phase_dev,
                  std::vector<float>* best_ms) {
   const size_t H = b->m.size();
@@ -704,89 +723,95 @@ int tune_persist(ash_batch* b, float* const* phase_dev,
   if (!rc && (hipEventCreate(&e0) != hipSuccess ||
               hipEventCreate(&e1) != hipSuccess))
     rc = bfail(b, ASH_EHIP, "hipEventCreate");
-  best_ms->assign(b->cls.size(), 0.0f);
   const std::vector<float> ones(kPersistSpots, 1.0f);
-  int* err = nullptr;
+  // fresh copies of the caller's phases and unit weights
+  auto copy_inputs = [&]() {
+    for (size_t h = 0; h < H; ++h) {
+      const size_t P = (size_t)b->m[h]->basis.g.nx * b->m[h]->basis.g.ny;
+      if (hipMemcpyAsync(ph[h], phase_dev[h], P * sizeof(float),
+                         hipMemcpyDeviceToDevice, b->stream) != hipSuccess ||
+          hipMemcpyAsync(W[h], ones.data(), b->m[h]->spots.N * sizeof(float),
+                         hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        return bfail(b, ASH_EHIP, "copying tuning inputs");
+    }
+    return (int)ASH_OK;
+  };
+  auto elapsed = [&](float* ms) {
+    if (hipEventRecord(e1, b->stream) != hipSuccess ||
+        hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess) {
+      (void)hipGetLastError();
+      return bfail(b, ASH_EHIP, "timing a tuning run");
+    }
+    return (int)ASH_OK;
+  };
+  // one launch of record shape c for n iterations (planned and uploaded)
+  auto time_one = [&](const Cls& c, int n, float* ms) {
+    int r = copy_inputs();
+    if (r) return r;
+    int* err = b->d_pctr + b->pholo.size() * kCtrPad;
+    if (hipMemsetAsync(b->d_pctr, 0,
+                       (b->pholo.size() + 1) * kCtrPad * sizeof(int),
+                       b->stream) != hipSuccess ||
+        hipEventRecord(e0, b->stream) != hipSuccess ||
+        launch_batch_persist(c.G, c.reduce != 0, c.p_grid, c.p_lds,
+                             b->d_pholo + c.p_holo, b->d_pblk + c.p_blk, n,
+                             1.0f, c.np_max, err, b->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return bfail(b, ASH_EHIP, "launching a one-launch candidate");
+    }
+    if ((r = elapsed(ms))) return r;
+    int flag = 0;
+    if (hipMemcpy(&flag, err, sizeof(int), hipMemcpyDeviceToHost) !=
+            hipSuccess || flag)
+      return bfail(b, ASH_EHIP, "a tuning launch's barrier timed out");
+    return (int)ASH_OK;
+  };
+  // the launches per phase of every record shape for n iterations
+  auto time_phase = [&](int n, float* ms) {
+    int r = copy_inputs();
+    int* ctr = nullptr;
+    if (!r) r = upload_desc(b, ph.data(), W.data());
+    if (!r) r = counters(b, n + 1, &ctr);
+    if (!r && hipEventRecord(e0, b->stream) != hipSuccess)
+      r = bfail(b, ASH_EHIP, "hipEventRecord");
+    if (!r) r = enqueue_iterations(b, ph.data(), n, 1.0f, ctr);
+    if (!r) r = elapsed(ms);
+    return r;
+  };
+  constexpr int kShort = kTuneItersShort, kLong = kTuneItersLong;
+  best_ms->assign(b->cls.size(), 0.0f);
   for (size_t k = 0; k < b->cls.size() && !rc; ++k) {
     Cls& c = b->cls[k];
     const int max_bpc = persist_blocks_per_cu(
         c.G, c.reduce != 0, c.p_lds ? c.p_lds : persist_lds_bytes(kPersistSpots));
     int best_bpc = c.bpc;
     float best_t = -1.0f;
-    {
-      for (int bpc = 1; bpc <= max_bpc && !rc; ++bpc) {
-        c.bpc = bpc;
-        if ((rc = plan_persist(b))) break;
-        if ((rc = upload_persist(b, ph.data(), W.data()))) break;
-        err = b->d_pctr + b->pholo.size() * kCtrPad;
-        for (size_t h = 0; h < H && !rc; ++h) {
-          const size_t P = (size_t)b->m[h]->basis.g.nx * b->m[h]->basis.g.ny;
-          if (hipMemcpyAsync(ph[h], phase_dev[h], P * sizeof(float),
-                             hipMemcpyDeviceToDevice, b->stream) != hipSuccess ||
-              hipMemcpyAsync(W[h], ones.data(),
-                             b->m[h]->spots.N * sizeof(float),
-                             hipMemcpyHostToDevice, b->stream) != hipSuccess)
-            rc = bfail(b, ASH_EHIP, "copying tuning inputs");
-        }
-        if (rc) break;
-        float ms = 0.0f;
-        if (hipMemsetAsync(b->d_pctr, 0,
-                           (b->pholo.size() + 1) * kCtrPad * sizeof(int),
-                           b->stream) != hipSuccess ||
-            hipEventRecord(e0, b->stream) != hipSuccess ||
-            launch_batch_persist(c.G, c.reduce != 0, c.p_grid, c.p_lds,
-                                 b->d_pholo + c.p_holo, b->d_pblk + c.p_blk,
-                                 kPersistTuneIters, 1.0f, c.np_max, err,
-                                 b->stream) != hipSuccess ||
-            hipEventRecord(e1, b->stream) != hipSuccess ||
-            hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-          (void)hipGetLastError();
-          rc = bfail(b, ASH_EHIP, "timing a one-launch candidate");
-          break;
-        }
-        int flag = 0;
-        if (hipMemcpy(&flag, err, sizeof(int), hipMemcpyDeviceToHost) !=
-                hipSuccess || flag) {
-          rc = bfail(b, ASH_EHIP, "a tuning launch's barrier timed out");
-          break;
-        }
-        if (best_t < 0.0f || ms < best_t) {
-          best_t = ms;
-          best_bpc = bpc;
-        }
+    for (int bpc = 1; bpc <= max_bpc && !rc; ++bpc) {
+      c.bpc = bpc;
+      float t0 = 0.0f, t1 = 0.0f;
+      if ((rc = plan_persist(b)) ||
+          (rc = upload_persist(b, ph.data(), W.data())) ||
+          (rc = time_one(c, kShort, &t0)) || (rc = time_one(c, kLong, &t1)))
+        break;
+      const float t = (t1 - t0) / (kLong - kShort);
+      if (best_t < 0.0f || t < best_t) {
+        best_t = t;
+        best_bpc = bpc;
       }
     }
     c.bpc = best_bpc;
-    (*best_ms)[k] = best_t / kPersistTuneIters;
+    (*best_ms)[k] = best_t;
   }
-  // the same iterations in launches per phase, on the same copies, with
-  // the range lengths tuned before: the faster form is kept
-  float ms_phase = 0.0f;
-  if (!rc) {
-    int* ctr = nullptr;
-    for (size_t h = 0; h < H && !rc; ++h) {
-      const size_t P = (size_t)b->m[h]->basis.g.nx * b->m[h]->basis.g.ny;
-      if (hipMemcpyAsync(ph[h], phase_dev[h], P * sizeof(float),
-                         hipMemcpyDeviceToDevice, b->stream) != hipSuccess ||
-          hipMemcpyAsync(W[h], ones.data(), b->m[h]->spots.N * sizeof(float),
-                         hipMemcpyHostToDevice, b->stream) != hipSuccess)
-        rc = bfail(b, ASH_EHIP, "copying tuning inputs");
-    }
-    if (!rc) rc = upload_desc(b, ph.data(), W.data());
-    if (!rc) rc = counters(b, kPersistTuneIters + 1, &ctr);
-    if (!rc && hipEventRecord(e0, b->stream) != hipSuccess)
-      rc = bfail(b, ASH_EHIP, "hipEventRecord");
-    if (!rc) rc = enqueue_iterations(b, ph.data(), kPersistTuneIters, 1.0f, ctr);
-    if (!rc && (hipEventRecord(e1, b->stream) != hipSuccess ||
-                hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms_phase, e0, e1) != hipSuccess))
-      rc = bfail(b, ASH_EHIP, "timing the phase launches");
-  }
+  // the same iterations in launches per phase, with the range lengths
+  // tuned before: the cheaper form is kept
+  float p0 = 0.0f, p1 = 0.0f;
+  if (!rc) rc = time_phase(kShort, &p0);
+  if (!rc) rc = time_phase(kLong, &p1);
   if (!rc) {
     float ms_one = 0.0f;
     for (float x : *best_ms) ms_one += x;
-    ms_phase /= kPersistTuneIters;
+    const float ms_phase = (p1 - p0) / (kLong - kShort);
     b->one_launch = ms_one <= ms_phase;
     best_ms->push_back(ms_phase);
   }
@@ -879,6 +904,7 @@ int ash_batch_destroy(ash_batch* b) {
   bfree(b->d_prows);
   bfree(b->d_pyblk);
   bfree(b->d_pctr);
+  if (b->h_flag) (void)hipHostFree(b->h_flag);
   for (auto& r : b->prof) {
     (void)hipEventDestroy(r.start);
     (void)hipEventDestroy(r.stop);

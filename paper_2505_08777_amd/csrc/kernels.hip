@@ -218,14 +218,29 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
 // Compensated sum of the n complex values p[0], p[stride], ... in index
 // order.  The loads go out eight at a time, so their latencies overlap; the
 // additions keep the serial order, so the result does not depend on it.
+// A value written by another block of the same launch, read at device
+// scope: the load goes to the level where the accelerator dies' caches are
+// coherent and invalidates nothing.
+__device__ __forceinline__ float2 load_device_scope(const float2* p) {
+  const unsigned long long u =
+      __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(float2, u);
+}
+
+template <bool kDeviceScope = false>
 __device__ __forceinline__ float2 kahan_sum_strided(
     const float2* __restrict__ p, long stride, int n) {
   float sr = 0.0f, si = 0.0f, cr = 0.0f, ci = 0.0f;
   for (int q = 0; q < n; q += 8) {
     float2 v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      v[u] = q + u < n ? p[(long)(q + u) * stride] : make_float2(0.0f, 0.0f);
+    for (int u = 0; u < 8; ++u) {
+      const float2* a = p + (long)(q + u) * stride;
+      v[u] = q + u >= n     ? make_float2(0.0f, 0.0f)
+             : kDeviceScope ? load_device_scope(a)
+                            : *a;
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       if (q + u < n) {
@@ -1326,9 +1341,10 @@ hipError_t launch_reduce(int N, const FwdPlan& p, const float* partial,
   return hipGetLastError();
 }
 
+template <bool kDeviceScope = false>
 __device__ __forceinline__ float2 sum_slices(const float2* __restrict__ red,
                                              int slices, int N, int k) {
-  return kahan_sum_strided(red + k, N, slices);
+  return kahan_sum_strided<kDeviceScope>(red + k, N, slices);
 }
 
 __global__ void k_finish_E(int N, int slices, const float2* __restrict__ red,
@@ -1417,8 +1433,9 @@ __device__ void block_reduce4(float* v, float* sh) {
 // meas: amplitudes that replace |E_k| in the weight update (experimental
 // feedback), or null.  phase_mode: kPhaseFree projects onto arg E_k;
 // kPhaseStore also stores arg E_k (turns) in fixph; kPhaseFixed projects
-// onto the stored phases (phase-fixed weighted GS).
-template <int NT = kUpd>
+// onto the stored phases (phase-fixed weighted GS).  kDeviceScope: red was
+// written by other blocks of the same launch (read at device scope).
+template <int NT = kUpd, bool kDeviceScope = false>
 __device__ __forceinline__ void wgs_update_block(
     int N, int slices, const float2* __restrict__ red,
     const float* __restrict__ t, float t_norm, float* __restrict__ W,
@@ -1437,7 +1454,7 @@ __device__ __forceinline__ void wgs_update_block(
   float s_a2 = 0.0f, s_I = 0.0f, mx = 0.0f, mn = INFINITY, s_m2 = 0.0f;
   for (int k = tid; k < N; k += blockDim.x) {
     const float tk = t[k];
-    const float2 e = sum_slices(red, slices, N, k);
+    const float2 e = sum_slices<kDeviceScope>(red, slices, N, k);
     if (one) {
       e1 = e;
       t1 = tk;
@@ -2347,12 +2364,17 @@ hipError_t launch_batch_update(int H, const HoloDesc* d, float power,
 
 // ---------------------------------------------------------------------------
 // Batched form in one launch.  The blocks of a hologram meet once per
-// iteration at a barrier (a counter per hologram; release before the count,
-// acquire after it, at device scope, so that the partial sums written on
-// any accelerator die are seen on the others).  The launch is cooperative,
-// so all blocks are resident and every block reaches every barrier; a
-// barrier that waits longer than kBarrierTicks sets *err and every block
-// leaves, so the kernel ends in any case.
+// iteration at a barrier (a counter per hologram).  A block's partial sums
+// are released to device scope (its accelerator die's L2 written back)
+// before it counts itself in; the counter is polled, and the other blocks'
+// sums read after it, with device-scope loads, which are coherent across
+// the dies and invalidate no cache, so the L2s keep the records that the
+// blocks still computing read.  The loads of the sums are issued after the
+// poll that saw the full count returned (they follow it in program order
+// behind a workgroup barrier), so they see the sums.  The launch is
+// cooperative, so all blocks are resident and every block reaches every
+// barrier; a barrier that waits longer than kBarrierTicks sets *err and
+// every block leaves, so the kernel ends in any case.
 // ---------------------------------------------------------------------------
 constexpr unsigned long long kBarrierTicks = 1000000000ull;  // 10 s at 100 MHz
 
@@ -2370,11 +2392,11 @@ __device__ __forceinline__ bool persist_barrier(int* ctr, int target,
   __shared__ int ok;
   __syncthreads();  // the block's writes are done
   if (threadIdx.x == 0) {
-    __threadfence();  // release at device scope
-    atomicAdd(ctr, 1);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int good = 1;
     const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
-    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE,
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         good = 0;
@@ -2390,15 +2412,15 @@ __device__ __forceinline__ bool persist_barrier(int* ctr, int target,
     ok = good;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return ok != 0;
 }
 
 // Waves per SIMD the register allocator must allow: left to itself it gives
 // the one-launch kernel a few more registers than the fused launch's (the
 // iteration loop keeps the block's state live) and lands one occupancy step
-// lower.  At these targets G = 1, 2, 4 and 5 fit without spills; G = 3 and G = 6 spill
-// a few values of the per-iteration set-up, outside the range loops.
+// lower.  At these targets G = 1, 2, 4 and 5 fit without spills; G = 3
+// and G = 6 spill a few values of the per-iteration set-up, outside the
+// range loops.
 constexpr int persist_waves(int G) { return G <= 3 ? 4 : G <= 6 ? 3 : 1; }
 
 template <int G, bool kReduce>
@@ -2469,9 +2491,10 @@ __attribute__((amdgpu_waves_per_eu(persist_waves(G)))) void k_batch_persist(
     if (!persist_barrier(d.ctr, d.n_blocks * (it + 1), err)) return;
     // the weight update of the whole hologram from all blocks' sums, into
     // this block's weights and spot-field records
-    wgs_update_block<kBlock>(N, d.n_blocks, rows_it, d.target, d.t_norm, Ws,
-                             power, 0.0f, yb, wrow, nullptr, nullptr, sh,
-                             nullptr, nullptr, kPhaseFree);
+    wgs_update_block<kBlock, true>(N, d.n_blocks, rows_it, d.target,
+                                   d.t_norm, Ws, power, 0.0f, yb, wrow,
+                                   nullptr, nullptr, sh, nullptr, nullptr,
+                                   kPhaseFree);
     __threadfence_block();
     __syncthreads();
   }

@@ -4,9 +4,11 @@ was (a later valid call gives bitwise the same result as before the bad
 one)."""
 
 import ctypes
+import math
 import sys
 
 import numpy as np
+
 import pytest
 
 torch = pytest.importorskip("torch")
@@ -157,6 +159,21 @@ def test_injected_allocation_failures(A):
         phs = [ph.clone(), ph.clone()]
         b.wgs(phs, 2)
         assert torch.equal(phs[0], phs[1])
+        # the one-launch form's pinned flag: its failure comes before any
+        # launch (the phases are untouched), and the next call runs
+        b.set_form(True)
+        A.inject_failure(A.INJECT_ALLOC, 1)
+        p_fail = [ph.clone(), ph.clone()]
+        with pytest.raises(A.AshError) as ei:
+            b.wgs(p_fail, 2)
+        assert ei.value.code == _lib.ENOMEM
+        assert torch.equal(p_fail[0], ph) and torch.equal(p_fail[1], ph)
+        p_a, p_b = [ph.clone(), ph.clone()], [ph.clone(), ph.clone()]
+        b.wgs(p_a, 2)
+        b.wgs(p_b, 2)
+        assert all(torch.equal(x, y) for x, y in zip(p_a, p_b))
+        d = torch.remainder(p_a[0] - phs[0] + math.pi, 2 * math.pi) - math.pi
+        assert d.abs().median().item() < 1e-4  # the per-phase form's step
         b.close()
     finally:
         A.inject_failure(A.INJECT_ALLOC, 0)
