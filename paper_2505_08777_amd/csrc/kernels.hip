@@ -1066,15 +1066,17 @@ __device__ __forceinline__ void moments_range(
                                 (unsigned long)kBlkPerTile * 64 * 16);
     const rsrc_t rm = make_rsrc(momtab + t * kBlkPerTile * 4 * D2,
                                 (unsigned long)kBlkPerTile * 4 * D2 * 16);
-    for (int r = r0; r < r1; ++r) {
-      u32x4 X[G];
+    // where it costs no occupancy (one moment tile, 3 or 4 groups), two
+    // register sets take turns: one block's products run while the next
+    // block's records and moment rows load into the other set
+    u32x4 XA[G], XB[G], AA[RT][2], AB[RT][2];
+    auto load = [&](u32x4* X, u32x4 (*A)[2], int r) {
 #pragma unroll
       for (int g = 0; g < G - 1; ++g)
         X[g] = bload4(rx, lane_pix * 16u,
                       (unsigned)(g * 2 * kTile + r * 32) * 16u);
       X[G - 1] = bload4(rn, lane_spot * 16u, (unsigned)r * 64u * 16u);
       // moment rows 32 rt + q of this lane; rows past 2D load zeros
-      u32x4 A[RT][2];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -1084,6 +1086,8 @@ __device__ __forceinline__ void moments_range(
               rm, row < D2 ? (unsigned)((kb * 2 + h) * D2 + row) * 16u : kOutOfRange,
               (unsigned)r * 4u * D2 * 16u);
         }
+    };
+    auto block = [&](const u32x4* X, u32x4 (*A)[2]) {
       const floatx16 th = phase_block<G>(X, S);
       u32x4 ch[2], cl[2], sh[2], sl[2];
 #pragma unroll
@@ -1114,6 +1118,24 @@ __device__ __forceinline__ void moments_range(
           aim[rt] = mfma_bf16(A[rt][kb], sh[kb], aim[rt]);
           aim[rt] = mfma_bf16(A[rt][kb], sl[kb], aim[rt]);
         }
+    };
+    if constexpr (RT == 1 && G >= 3 && G <= 4) {
+      load(XA, AA, r0);
+      for (int r = r0; r < r1; r += 2) {
+        load(XB, AB, min(r + 1, r1 - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        block(XA, AA);
+        if (r + 1 < r1) {
+          load(XA, AA, min(r + 2, r1 - 1));
+          __builtin_amdgcn_sched_barrier(0);
+          block(XB, AB);
+        }
+      }
+    } else {
+      for (int r = r0; r < r1; ++r) {
+        load(XA, AA, r);
+        block(XA, AA);
+      }
     }
     b += r1 - r0;
   }
