@@ -44,6 +44,7 @@
 #include <math.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -761,6 +762,7 @@ __device__ __forceinline__ void accumulate(const floatx16& th, float m,
     si[i] = fmaf(ms, __builtin_amdgcn_sinf(r), si[i]);
   }
 }
+
 
 // Forward sum of one wave: the 32 spots of spot block mb over the pixel
 // blocks [b0, b1) (tile rows, tile order).  Operand A is the spot record,
@@ -2037,14 +2039,23 @@ __device__ __forceinline__ float join_halves(float x) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// The values of a lane that hold spot rows below n_valid (1..32): value i
+// holds row 8 (i / 4) + 4h + i % 4 in lane half h, so values i < 4k hold
+// rows < 8k in both halves.
+__device__ __forceinline__ int valid_values(int n_valid) {
+  return 4 * ((min(n_valid, 32) + 7) / 8);
+}
+
 // Sum, with per-value weights w, of w cos(2 pi theta) and w sin(2 pi theta)
-// over one 32x32 block of phases (16 per lane) into four running pairs.
-template <bool kReduce>
+// over one 32x32 block of phases (16 per lane) into four running pairs;
+// kN < 16: the first kN values only, for a block whose later rows are
+// padding (spots past N).
+template <bool kReduce, int kN = 16>
 __device__ __forceinline__ void accumulate_rows(const floatx16& th,
                                                 const floatx4* w, float* sr,
                                                 float* si) {
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < kN; ++i) {
     const float r = kReduce ? __builtin_amdgcn_fractf(th[i]) : th[i];
     const float m = w[i >> 2][i & 3];
     sr[i & 3] = fmaf(m, __builtin_amdgcn_cosf(r), sr[i & 3]);
@@ -2052,16 +2063,21 @@ __device__ __forceinline__ void accumulate_rows(const floatx16& th,
   }
 }
 
+
 // Adjoint of a pair of pixel blocks (records X0: row r, X1: row r + 1)
 // over NB spot blocks: on return lane half h holds g(x) of pixel q of row
-// r + h.  The magnitudes of the spot rows come from ym4 (LDS).
+// r + h.  The magnitudes of the spot rows come from ym4 (LDS).  nv_last:
+// the values of the last spot block that hold spots (valid_values).
 template <int G, bool kReduce>
 __device__ __forceinline__ float2 adjoint_pair(
-    int NB, const u32x4* X0, const u32x4* X1, rsrc_t rs, rsrc_t ro, rsrc_t ry,
-    const floatx4* ym4, unsigned off_spot, unsigned off_ot, int h) {
+    int NB, int nv_last, const u32x4* X0, const u32x4* X1, rsrc_t rs,
+    rsrc_t ro, rsrc_t ry, const floatx4* ym4, unsigned off_spot,
+    unsigned off_ot, int h) {
   float ar[4] = {0.0f, 0.0f, 0.0f, 0.0f}, ai[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   float br[4] = {0.0f, 0.0f, 0.0f, 0.0f}, bi[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  for (int nb = 0; nb < NB; ++nb) {
+  // spot block nb, its first kN values (the rest are padding rows)
+  auto block = [&](int nb, auto kn) {
+    constexpr int kN = decltype(kn)::value;
     u32x4 S[G];
 #pragma unroll
     for (int g = 0; g < G - 1; ++g)
@@ -2077,9 +2093,20 @@ __device__ __forceinline__ float2 adjoint_pair(
     S[G - 1] = last;
     const floatx16 th0 = phase_block<G>(S, X0);
     const floatx16 th1 = phase_block<G>(S, X1);
-    accumulate_rows<kReduce>(th0, w, ar, ai);
-    accumulate_rows<kReduce>(th1, w, br, bi);
-  }
+    accumulate_rows<kReduce, kN>(th0, w, ar, ai);
+    accumulate_rows<kReduce, kN>(th1, w, br, bi);
+  };
+  for (int nb = 0; nb < NB - 1; ++nb)
+    block(nb, std::integral_constant<int, 16>());
+  // the last block: only the values that hold spots
+  if (nv_last == 16)
+    block(NB - 1, std::integral_constant<int, 16>());
+  else if (nv_last == 12)
+    block(NB - 1, std::integral_constant<int, 12>());
+  else if (nv_last == 8)
+    block(NB - 1, std::integral_constant<int, 8>());
+  else
+    block(NB - 1, std::integral_constant<int, 4>());
   const auto jr = __builtin_amdgcn_permlane32_swap(
       __float_as_uint((ar[0] + ar[1]) + (ar[2] + ar[3])),
       __float_as_uint((br[0] + br[1]) + (br[2] + br[3])), false, false);
@@ -2154,6 +2181,8 @@ __device__ __forceinline__ void fused_range(
   const int lane = threadIdx.x & (kWave - 1);
   const int h = lane >> 5, q = lane & 31;
   const int NB = (N + 31) / 32, NP = NB * 32;
+  const int nv_last =
+      __builtin_amdgcn_readfirstlane(valid_values(N - (NB - 1) * 32));
   const GLOBAL float* __restrict__ ymag =
       reinterpret_cast<const GLOBAL float*>(yrec + (long)NB * 64);
   for (int k = lane; k < NP; k += kWave) ymag_s[k] = ymag[k];
@@ -2204,8 +2233,8 @@ __device__ __forceinline__ void fused_range(
     if (kMode == kFusedFirst) {
       if (inside) turns = rad_to_turns(phase[pp]);
     } else {
-      const float2 gv = adjoint_pair<G, kReduce>(NB, X0, X1, rs, ro, ry, ym4,
-                                                 off_spot, off_ot, h);
+      const float2 gv = adjoint_pair<G, kReduce>(NB, nv_last, X0, X1, rs, ro,
+                                                 ry, ym4, off_spot, off_ot, h);
       const float ang = atan2f(gv.y, gv.x);  // atan2(0, 0) = 0
       if (kMode == kFusedLast) {
         if (inside) phase[pp] = ang;
@@ -2244,8 +2273,14 @@ __device__ __forceinline__ void fused_range(
 // Fused launch of a batch: each wave takes units {holo, range} from the
 // queues (as the forward) and runs fused_range over the range, writing the
 // range's row of forward partial sums (mode: see fused_range).
+// Waves per SIMD the register allocator must allow the fused launches (and
+// the one-launch kernel, which runs the same rows): 4 up to G = 3, 3 up to
+// G = 6; left to itself the compiler lands one step lower.
+constexpr int fused_waves(int G) { return G <= 3 ? 4 : G <= 6 ? 3 : 1; }
+
 template <int G, bool kReduce, int kMode>
-__global__ __launch_bounds__(kBlock) void k_batch_fused(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(fused_waves(G)))) void k_batch_fused(
     const HoloDesc* __restrict__ hd, const int4* __restrict__ items,
     const int* __restrict__ qoff, int* __restrict__ ctr, int np_max) {
   extern __shared__ float lds[];
