@@ -378,14 +378,17 @@ def test_batch64small_fused(A):
 def test_fused_edges(A):
     """Fused launches at their edges: a member of exactly 512 spots (the
     largest the fused form takes, 40 KB of LDS per block), one spot, 33
-    spots (one spot into a second block), a range-reduced record shape and
-    an odd range length loaded from a table; three iterations of every
-    member against its own run."""
+    spots (one spot into a second block), last spot blocks of 6, 16 and 24
+    spots (the adjoint takes 4, 8 and 12 of a lane's 16 values there), a
+    range-reduced record shape and an odd range length loaded from a
+    table; three iterations of every member against its own run."""
     specs = [
         (160, 96, 512, [1, 2, 3, 4, 5, 7, 12], 0.4, 1.0, False, None),
         (64, 48, 1, [1, 2, 4], 0.3, 1.0, False, None),
         (96, 80, 33, [1, 2, 3, 4, 5, 7, 12], 0.6, 1.0, False, None),
         (48, 40, 70, [1, 2, 4, 7], 0.7, 9.0, False, None),
+        (64, 64, 48, [1, 2, 4], 0.5, 1.0, False, None),
+        (80, 64, 88, [1, 2, 3, 4, 5, 7, 12], 0.5, 1.0, False, None),
     ]
     holos = [_holo(s, 900 + i) for i, s in enumerate(specs)]
     ctxs = [_ctx(A, h) for h in holos]
@@ -404,12 +407,19 @@ def test_fused_edges(A):
     ph_b = [_cu(h["phi"]) for h in holos]
     W_b = [torch.ones(h["w"].shape[0], device="cuda") for h in holos]
     b.wgs(ph_b, 3, weights=W_b)
+    # the same members in the one-launch form, which runs the same rows
+    b.set_form(True)
+    ph_o = [_cu(h["phi"]) for h in holos]
+    W_o = [torch.ones(h["w"].shape[0], device="cuda") for h in holos]
+    b.wgs(ph_o, 3, weights=W_o)
     torch.cuda.synchronize()
-    for h, c, pb, wb in zip(holos, ctxs, ph_b, W_b):
+    for h, c, pb, wb, po, wo in zip(holos, ctxs, ph_b, W_b, ph_o, W_o):
         ph = _cu(h["phi"])
         _, W, E, _ = c.wgs(ph, 3)
         err = _batch_vs_alone(c, h["t"], pb, wb, ph, W, E, "fused edge", 3)
         _say("  %dx%d, %d spots: phase, weights" % (h["nx"], h["ny"], h["w"].shape[0]), err)
+        err = _batch_vs_alone(c, h["t"], po, wo, ph, W, E, "one-launch edge", 3)
+        _say("    one launch: phase, weights", err)
     b.close()
     for c in ctxs:
         c.close()
