@@ -2273,9 +2273,12 @@ __device__ __forceinline__ void fused_range(
 // Fused launch of a batch: each wave takes units {holo, range} from the
 // queues (as the forward) and runs fused_range over the range, writing the
 // range's row of forward partial sums (mode: see fused_range).
-// Waves per SIMD the register allocator must allow the fused launches (and
-// the one-launch kernel, which runs the same rows): 4 up to G = 3, 3 up to
-// G = 6; left to itself the compiler lands one step lower.
+// Waves per SIMD the register allocator must allow the fused launches and
+// the one-launch kernel, which runs the same rows: 4 up to G = 3, 3 up to
+// G = 6; left to itself the compiler lands one step lower.  At these
+// targets a few values spill at some G (the one-launch kernel at G = 2, 3,
+// 5 and 6, the fused middle launch at G = 3 and 6), outside the loops over
+// spot blocks.
 constexpr int fused_waves(int G) { return G <= 3 ? 4 : G <= 6 ? 3 : 1; }
 
 template <int G, bool kReduce, int kMode>
@@ -2472,17 +2475,10 @@ __device__ __forceinline__ bool persist_barrier(int* ctr, int target,
   return ok != 0;
 }
 
-// Waves per SIMD the register allocator must allow: left to itself it gives
-// the one-launch kernel a few more registers than the fused launch's (the
-// iteration loop keeps the block's state live) and lands one occupancy step
-// lower.  At these targets G = 1, 2, 4 and 5 fit without spills; G = 3
-// and G = 6 spill a few values of the per-iteration set-up, outside the
-// range loops.
-constexpr int persist_waves(int G) { return G <= 3 ? 4 : G <= 6 ? 3 : 1; }
 
 template <int G, bool kReduce>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(persist_waves(G)))) void k_batch_persist(
+__attribute__((amdgpu_waves_per_eu(fused_waves(G)))) void k_batch_persist(
     const PHolo* __restrict__ hd, const PBlock* __restrict__ blks, int n_iter,
     float power, int np_max, int* __restrict__ err) {
   extern __shared__ float lds[];
