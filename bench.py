@@ -963,11 +963,15 @@ def bench_batch(args, holos):
         evals_launch = evals
     # the unit timed spans one launch of every record shape: its traffic is
     # the sum of the shapes' kernels' traffic per launch (fused: the first,
-    # middle and last launches weighted 1 : n_iter - 1 : 1)
+    # middle and last launches weighted 1 : n_iter - 1 : 1; one launch: the
+    # whole call, from the one-launch form's own summary)
     parts = []
     for g in (info["groups"] or [groups]):
         name = re.sub(r"<\d+,", "<%d," % g, kname, count=1)
-        if info["fused"]:
+        if info["one_launch"]:
+            parts.append(profiled_traffic(args.workload, name,
+                                          summary="one_launch_kernels"))
+        elif info["fused"]:
             modes = [profiled_traffic(args.workload, name[:-2] + "%d>" % m,
                                       summary="batch_kernels") for m in (0, 1, 2)]
             t = (None if any(x is None for x, _ in modes) else
