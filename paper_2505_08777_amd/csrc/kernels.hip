@@ -772,7 +772,7 @@ __device__ __forceinline__ void accumulate(const floatx16& th, float m,
 // lane half its part of the nearfield record's last group, another the
 // magnitude of the lane's pixel (the same for both halves).
 // E_k = sum_x A(x) exp(-2 pi i (tau_k(x) - phi(x))).
-template <int G, bool kReduce>
+template <int G, bool kReduce, bool kTwoSets>
 __device__ __forceinline__ void forward_range(
     int N, int mb, long b0, long b1, const GLOBAL u32x4* __restrict__ pixtab,
     const GLOBAL u32x4* __restrict__ nf, const GLOBAL float* __restrict__ mag,
@@ -812,8 +812,10 @@ __device__ __forceinline__ void forward_range(
     const rsrc_t rn = make_rsrc(nf + t * kBlkPerTile * 64,
                                 (unsigned long)kBlkPerTile * 64 * 16);
     const rsrc_t rm = make_rsrc(mag + t * kTile, (unsigned long)kTile * 4);
-    // two register sets take turns: one block's products run while the
-    // next block's records load into the other set
+    // kTwoSets: two register sets take turns, one block's products running
+    // while the next block's records load into the other set; otherwise
+    // (where the second set would cost a wave per SIMD) each block's loads
+    // go out before its products
     u32x4 XA[G], XB[G];
     float mA, mB;
     auto load = [&](u32x4* X, float& m, int r) {
@@ -823,15 +825,23 @@ __device__ __forceinline__ void forward_range(
       X[G - 1] = bload4(rn, off_spot, (unsigned)r * 64u * 16u);
       m = bload1f(rm, off_q, (unsigned)r * 32u * 4u);
     };
-    load(XA, mA, r0);
-    for (int r = r0; r < r1; r += 2) {
-      load(XB, mB, min(r + 1, r1 - 1));
-      __builtin_amdgcn_sched_barrier(0);
-      accumulate<true, kReduce>(phase_block<G>(S, XA), mA, er, ei);
-      if (r + 1 < r1) {
-        load(XA, mA, min(r + 2, r1 - 1));
+    if constexpr (kTwoSets) {
+      load(XA, mA, r0);
+      for (int r = r0; r < r1; r += 2) {
+        load(XB, mB, min(r + 1, r1 - 1));
         __builtin_amdgcn_sched_barrier(0);
-        accumulate<true, kReduce>(phase_block<G>(S, XB), mB, er, ei);
+        accumulate<true, kReduce>(phase_block<G>(S, XA), mA, er, ei);
+        if (r + 1 < r1) {
+          load(XA, mA, min(r + 2, r1 - 1));
+          __builtin_amdgcn_sched_barrier(0);
+          accumulate<true, kReduce>(phase_block<G>(S, XB), mB, er, ei);
+        }
+      }
+    } else {
+      for (int r = r0; r < r1; ++r) {
+        load(XA, mA, r);
+        __builtin_amdgcn_sched_barrier(0);
+        accumulate<true, kReduce>(phase_block<G>(S, XA), mA, er, ei);
       }
     }
     b += r1 - r0;
@@ -862,7 +872,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(
   if (v >= (long)(groups / kXcds) * n_mb) return;  // wave-uniform exit
   const int gi = (int)(v / n_mb) * kXcds + xcd;  // pixel range
   const int mb = (int)(v % n_mb);                // spot block
-  forward_range<G, kReduce>(N, mb, n_blk * gi / groups,
+  // two register sets where they keep this kernel's waves per SIMD
+  forward_range<G, kReduce, G == 3 || G == 6>(N, mb, n_blk * gi / groups,
                             n_blk * (gi + 1) / groups, as_global(pixtab),
                             as_global(reinterpret_cast<const u32x4*>(nf_t)),
                             as_global(mag), as_global(spotrec),
@@ -1949,7 +1960,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(
     const HoloDesc& d = hd[it.x];
     const long b0 = (long)it.y * d.L;
     const long b1 = min(b0 + d.L, d.n_blk);
-    forward_range<G, kReduce>(
+    // two register sets where they keep this kernel's waves per SIMD
+    forward_range<G, kReduce, G <= 3 || G == 5 || G == 9>(
         d.N, it.z, b0, b1, as_global(d.pixtab),
         as_global(reinterpret_cast<const u32x4*>(d.nf_t)), as_global(d.amp_t),
         as_global(d.spotrec),
