@@ -751,15 +751,22 @@ __device__ __forceinline__ int mfma_row(int i, int h) {
 // sine and cosine take turns and reduce exactly by themselves over
 // |theta| <= 256; kReduce = false skips the explicit fract where the host
 // has bounded every phase of the set-up well inside that domain.
-template <bool kNegSin, bool kReduce>
+// kInit: the sums start here (sr = m cos, si = sgn m sin: the same
+// roundings as adding to zeros, without the zeroing moves).
+template <bool kNegSin, bool kReduce, bool kInit = false>
 __device__ __forceinline__ void accumulate(const floatx16& th, float m,
                                            float* sr, float* si) {
   const float ms = kNegSin ? -m : m;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const float r = kReduce ? __builtin_amdgcn_fractf(th[i]) : th[i];
-    sr[i] = fmaf(m, __builtin_amdgcn_cosf(r), sr[i]);
-    si[i] = fmaf(ms, __builtin_amdgcn_sinf(r), si[i]);
+    if (kInit) {
+      sr[i] = m * __builtin_amdgcn_cosf(r);
+      si[i] = ms * __builtin_amdgcn_sinf(r);
+    } else {
+      sr[i] = fmaf(m, __builtin_amdgcn_cosf(r), sr[i]);
+      si[i] = fmaf(ms, __builtin_amdgcn_sinf(r), si[i]);
+    }
   }
 }
 
@@ -1831,13 +1838,12 @@ __device__ __forceinline__ void adjoint_row(
   // whole blocks with zero records.
   const GLOBAL u32x4* __restrict__ ot_t = offtab + (long)tile * 2 * NP;
   float gr[16], gi[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) gr[i] = gi[i] = 0.0f;
   const unsigned off_spot = lane_spot * 16u, off_ot = lane_ot * 16u;
   const rsrc_t rs = make_rsrc(spotrec, (unsigned long)NB * G * 64 * 16);
   const rsrc_t ro = make_rsrc(ot_t, (unsigned long)2 * NP * 16);
   const rsrc_t ry = make_rsrc(yrec, (unsigned long)NB * 64 * 16);
-  for (int nb = 0; nb < NB; ++nb) {
+  // spot block nb; the first one starts the sums
+  auto block = [&](int nb, auto init) {
     u32x4 S[G];
 #pragma unroll
     for (int gg = 0; gg < G - 1; ++gg)
@@ -1850,8 +1856,10 @@ __device__ __forceinline__ void adjoint_row(
     S[G - 1] = last;
     const float m = __uint_as_float(yv[2]);
     const floatx16 th = phase_block<G>(X, S);
-    accumulate<false, kReduce>(th, m, gr, gi);
-  }
+    accumulate<false, kReduce, decltype(init)::value>(th, m, gr, gi);
+  };
+  block(0, std::true_type());
+  for (int nb = 1; nb < NB; ++nb) block(nb, std::false_type());
   adjoint_epilogue<G>(gr, gi, nx, ny, tiles_x, tile, p0, wv, pixtab, amp_t, o);
 }
 
