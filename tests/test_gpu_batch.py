@@ -348,6 +348,34 @@ def test_batch64small_one_launch(A):
         c.close()
 
 
+def test_batch64small_deterministic(A):
+    """Both batched forms sum their partial rows in a fixed order, so two
+    calls from the same start give bitwise the same phases and weights:
+    20 iterations of the 64 small holograms in each form (in the one-launch
+    form, 20 barriers per hologram whose partial sums every block reads
+    from the others)."""
+    holos = workloads.make("batch64small")
+    ctxs = _members(A, holos)
+    b = A.Batch(ctxs)
+    for one_launch in (True, False):
+        b.set_form(one_launch)
+        runs = []
+        for _ in range(2):
+            ph = [_cu(d["phi0"]) for d in holos]
+            W = [torch.ones(d["w"].shape[0], device="cuda") for d in holos]
+            b.wgs(ph, 20, weights=W)
+            torch.cuda.synchronize()
+            runs.append((ph, W))
+        (p1, w1), (p2, w2) = runs
+        assert all(torch.equal(x, y) for x, y in zip(p1, p2)), one_launch
+        assert all(torch.equal(x, y) for x, y in zip(w1, w2)), one_launch
+        _say("form %s: two calls bitwise equal" %
+             ("one launch" if one_launch else "per phase"))
+    b.close()
+    for c in ctxs:
+        c.close()
+
+
 def test_batch64small_fused(A):
     """The same 64 holograms in launches per phase, where every iteration
     after the first fuses the adjoint with the next forward: three
