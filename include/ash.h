@@ -532,8 +532,8 @@ int ash_batch_wgs(ash_batch* batch, float* const* phase_dev,
  * and 128) and keeps the fastest; when the one-launch form is possible,
  * costs it for 1 up to the most resident blocks per CU that fit, keeps the
  * cheapest, costs the per-phase form, and selects the cheaper form.  A
- * form's cost is the time of one more iteration (runs of 2 and 6
- * iterations, their time difference over 4), so that the first forward
+ * form's cost is the time of one more iteration (runs of 2 and 22
+ * iterations, their time difference over 20), so that the first forward
  * and last adjoint of a call do not weigh.  The timed iterations run on
  * copies of the phases (the caller's are left untouched).  The table written to table_out (if not NULL) holds lines
  * "groups range_reduce range_blocks ms", "one_launch groups range_reduce

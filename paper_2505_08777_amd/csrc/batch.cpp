@@ -29,8 +29,11 @@ constexpr int kTuneCandidates[] = {16, 32, 64, 128, 256, 512};
 constexpr int kDefaultFusedRange = 16;
 constexpr int kFusedCandidates[] = {4, 8, 16, 32, 64, 128};
 // The tuner's two run lengths (iterations) per one-launch candidate and
-// per form.
-constexpr int kTuneItersShort = 2, kTuneItersLong = 6;
+// per form.  The long run is as long as a typical call: the one-launch
+// form's cost per iteration grows with the run (its holograms fall out of
+// step, and the slowest one's barriers set the end), so that a short run
+// would favour it.
+constexpr int kTuneItersShort = 2, kTuneItersLong = 22;
 // Relative cost of a pixel block's adjoint epilogue (butterfly over the
 // spots, arg g, next nearfield record) in 32 x 32 evaluation blocks.
 constexpr double kEpilogueBlocks = 1.25;
@@ -789,10 +792,13 @@ int tune_persist(ash_batch* b, float* const* phase_dev,
     float best_t = -1.0f;
     for (int bpc = 1; bpc <= max_bpc && !rc; ++bpc) {
       c.bpc = bpc;
+      // an untimed launch first: the first launch of a kernel also loads
+      // its code, which would inflate the short run
       float t0 = 0.0f, t1 = 0.0f;
       if ((rc = plan_persist(b)) ||
           (rc = upload_persist(b, ph.data(), W.data())) ||
-          (rc = time_one(c, kShort, &t0)) || (rc = time_one(c, kLong, &t1)))
+          (rc = time_one(c, 1, &t0)) || (rc = time_one(c, kShort, &t0)) ||
+          (rc = time_one(c, kLong, &t1)))
         break;
       const float t = (t1 - t0) / (kLong - kShort);
       if (best_t < 0.0f || t < best_t) {
@@ -806,6 +812,7 @@ int tune_persist(ash_batch* b, float* const* phase_dev,
   // the same iterations in launches per phase, with the range lengths
   // tuned before: the cheaper form is kept
   float p0 = 0.0f, p1 = 0.0f;
+  if (!rc) rc = time_phase(1, &p0);  // untimed, as above
   if (!rc) rc = time_phase(kShort, &p0);
   if (!rc) rc = time_phase(kLong, &p1);
   if (!rc) {
